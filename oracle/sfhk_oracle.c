@@ -1,0 +1,625 @@
+/*
+ * sfhk_oracle.c -- plain, slow, FP64 CPU oracle for the strong-field Herman-Kluk (SFHK) hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg. It shares no code with the HIP library and never calls it.
+ *
+ * Method (Tran, Truong, Goetz, Le, SFHK for high-harmonic generation):
+ *   Hamiltonian H = p^2/2 + V_a(q) + q.E(t) and Hamilton's equations ....... App. A
+ *   action S = int (p.qdot - H) dt ........................................... App. A
+ *   stability (monodromy) equations through the Hessian of H ................ App. A
+ *   HK prefactor C = sqrt det[(dp/dp0 + dq/dq0 - 2i g dq/dp0 - dp/dq0/(2i g))/2]  App. A (C_HK)
+ *   Kay removal of trajectories with |C|^2 > D_t ............................. Sec. III.A
+ *   dipole matrix element <psi0|z|p,q,gamma> over GTOs ....................... App. C.1
+ *   D(t) = -<psi0 e^{i Ip t}|z|psi_c(t)> + c.c. summed over trajectories ..... Eq. (2), App. C.1
+ *     (the bra's e^{i Ip t} is conjugated: each term carries e^{i (S - Ip t)})
+ *   Hann window and Fourier transform ........................................ App. D
+ *
+ * The integrator is the classical four-stage Runge-Kutta scheme with a fixed step (the paper
+ * does not name the trajectory integrator; the fixed-step RK4 reading is documented with the
+ * other readings of the paper). Because near-core trajectories are chaotic, every operation on
+ * the trajectory path (equations of motion, RK4 combination, det G, Kay test, square-root branch)
+ * is written as one IEEE operation per step, with fused multiply-adds written out explicitly as
+ * fma(), so that its rounding is fixed: the "arithmetic contract" that the GPU path implements
+ * independently. Compile with -ffp-contract=off.
+ */
+#include "sfhk_oracle.h"
+
+#include <complex.h>
+#include <math.h>
+#include <pthread.h>
+#include <quadmath.h>
+#include <stdlib.h>
+#include <string.h>
+#include <unistd.h>
+
+#define NY 43 /* q(3) p(3) M(36: 6 columns of (Q(3), P(3))) S(1) */
+#define IY_S 42
+
+/* ------------------------------------------------------------------------------------------ */
+/* correctly rounded exponential: binary128 evaluation rounded once to binary64               */
+/* ------------------------------------------------------------------------------------------ */
+double or_exp_cr(double x) { return (double)expq((__float128)x); }
+
+/* ------------------------------------------------------------------------------------------ */
+/* laser field (Sec. II.B field equation with the sin^2 envelope; E = -dA/dt, App. A)          */
+/* ------------------------------------------------------------------------------------------ */
+double or_field_A(double t, double e0, double omega, double T, double cep) {
+  if (fabs(t) > 0.5 * T) return 0.0;
+  double c = cos(M_PI * t / T);
+  return -(e0 / omega) * c * c * sin(omega * t + cep);
+}
+
+double or_field_E(double t, double e0, double omega, double T, double cep) {
+  if (fabs(t) > 0.5 * T) return 0.0;
+  double c = cos(M_PI * t / T);
+  return e0 * c * c * cos(omega * t + cep) -
+         (e0 * M_PI / (omega * T)) * sin(2.0 * M_PI * t / T) * sin(omega * t + cep);
+}
+
+/* antiderivative of cos^2(pi t/T) sin(omega t + cep): cos^2 = (1 + cos(W t))/2, W = 2 pi/T */
+static double cos2sin_antideriv(double t, double omega, double T, double cep) {
+  double W = 2.0 * M_PI / T;
+  return -cos(omega * t + cep) / (2.0 * omega) -
+         cos((omega + W) * t + cep) / (4.0 * (omega + W)) -
+         cos((omega - W) * t + cep) / (4.0 * (omega - W));
+}
+
+double or_field_intA(double t, double e0, double omega, double T, double cep) {
+  double ta = -0.5 * T;
+  if (t <= ta) return 0.0;
+  double tt = t > 0.5 * T ? 0.5 * T : t;
+  return -(e0 / omega) *
+         (cos2sin_antideriv(tt, omega, T, cep) - cos2sin_antideriv(ta, omega, T, cep));
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* central potentials: grad V = g q, Hess V = g I + c q q^T                                   */
+/* ------------------------------------------------------------------------------------------ */
+static void pot_gc(const or_potential* pot, const double* q, double* V, double* g, double* c) {
+  double r2 = q[0] * q[0];
+  r2 = fma(q[1], q[1], r2);
+  r2 = fma(q[2], q[2], r2);
+  switch (pot->kind) {
+    case 1: { /* soft-core Coulomb: V = -Z u, u = (r^2+a)^(-1/2) */
+      double Z = pot->z_inf;
+      double s = r2 + pot->soft2;
+      double rho = sqrt(s);
+      double u = 1.0 / rho;
+      double u2 = u * u;
+      double u3 = u2 * u;
+      double u5 = u3 * u2;
+      *V = -(Z * u);
+      *g = Z * u3;                  /* dV/dr / r = Z u^3 */
+      *c = (-3.0 * Z) * u5;         /* (V'' - V'/r) / r^2 = -3 Z u^5 */
+      return;
+    }
+    case 2: { /* screened: V = -Z(r)/rho, Z(r) = z_inf + z_in exp(-r/r_scr), rho = sqrt(r^2+a) */
+      double r = sqrt(r2);
+      double s = r2 + pot->soft2;
+      double rho = sqrt(s);
+      double ir = 1.0 / rho;
+      double ir2 = ir * ir;
+      double ir3 = ir2 * ir;
+      double e = or_exp_cr(-(r / pot->r_scr));
+      double ez = pot->z_in * e;            /* z_in exp(-r/r_scr) */
+      double Z = pot->z_inf + ez;
+      double d1 = ez / pot->r_scr;          /* -Z'(r) */
+      double d2 = d1 / pot->r_scr;          /*  Z''(r) */
+      *V = -(Z * ir);
+      /* V'(r) = d1/rho + Z r / rho^3 */
+      double vp = fma(Z * r, ir3, d1 * ir);
+      /* V''(r) = -d2/rho - 2 d1 r/rho^3 + Z (a - 2 r^2)/rho^5 */
+      double w1 = fma(-2.0, r2, pot->soft2);
+      double ta = d2 * ir;
+      double tb = (d1 * r) * ir3;
+      double tc = ((Z * w1) * ir3) * ir2;
+      double vpp = tc - fma(2.0, tb, ta);
+      if (r > 0.0) {
+        *g = vp / r;
+        *c = (vpp - *g) / r2;
+      } else { /* r == 0 exactly (measure zero): finite isotropic choice */
+        *g = vpp;
+        *c = 0.0;
+      }
+      return;
+    }
+    case 3: { /* harmonic */
+      double w2 = pot->omega_ho * pot->omega_ho;
+      *V = (0.5 * w2) * r2;
+      *g = w2;
+      *c = 0.0;
+      return;
+    }
+    default:
+      *V = 0.0;
+      *g = 0.0;
+      *c = 0.0;
+      return;
+  }
+}
+
+void or_potential_eval(const or_potential* pot, const double q[3], double* V, double grad[3],
+                       double hess[9]) {
+  double g, c;
+  pot_gc(pot, q, V, &g, &c);
+  for (int i = 0; i < 3; ++i) {
+    grad[i] = g * q[i];
+    for (int k = 0; k < 3; ++k) {
+      double ci = c * q[i];
+      hess[3 * i + k] = (i == k) ? fma(ci, q[i], g) : ci * q[k];
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* right-hand side of the 43 ODEs (App. A): qdot = p, pdot = -grad V - E z^,                  */
+/* Qdot_j = P_j, Pdot_j = -Hess V . Q_j, Sdot = p^2/2 - V - z E                               */
+/* ------------------------------------------------------------------------------------------ */
+static void rhs(const or_potential* pot, double E, const double* y, double* k) {
+  const double* q = y;
+  const double* p = y + 3;
+  double V, g, c;
+  pot_gc(pot, q, &V, &g, &c);
+  /* Hessian g I + c q q^T, symmetric */
+  double cx = c * q[0], cy = c * q[1], cz = c * q[2];
+  double H[3][3];
+  H[0][0] = fma(cx, q[0], g);
+  H[1][1] = fma(cy, q[1], g);
+  H[2][2] = fma(cz, q[2], g);
+  H[0][1] = H[1][0] = cx * q[1];
+  H[0][2] = H[2][0] = cx * q[2];
+  H[1][2] = H[2][1] = cy * q[2];
+
+  k[0] = p[0];
+  k[1] = p[1];
+  k[2] = p[2];
+  k[3] = -(g * q[0]);
+  k[4] = -(g * q[1]);
+  k[5] = -fma(g, q[2], E);
+  for (int j = 0; j < 6; ++j) {
+    const double* Q = y + 6 + 6 * j;
+    const double* P = Q + 3;
+    double* kQ = k + 6 + 6 * j;
+    double* kP = kQ + 3;
+    for (int i = 0; i < 3; ++i) {
+      kQ[i] = P[i];
+      double t = H[i][0] * Q[0];
+      t = fma(H[i][1], Q[1], t);
+      t = fma(H[i][2], Q[2], t);
+      kP[i] = -t;
+    }
+  }
+  double p2 = p[0] * p[0];
+  p2 = fma(p[1], p[1], p2);
+  p2 = fma(p[2], p[2], p2);
+  double L = fma(0.5, p2, -V);
+  L = fma(-q[2], E, L);
+  k[IY_S] = L;
+}
+
+/* one classical RK4 step; ea, eb, ec = E at t, t + h/2, t + h */
+static void rk4_step(const or_potential* pot, double ea, double eb, double ec, double h,
+                     double* y) {
+  double k1[NY], k2[NY], k3[NY], k4[NY], ys[NY];
+  double h2 = 0.5 * h;
+  double h6 = h / 6.0;
+  rhs(pot, ea, y, k1);
+  for (int i = 0; i < NY; ++i) ys[i] = fma(h2, k1[i], y[i]);
+  rhs(pot, eb, ys, k2);
+  for (int i = 0; i < NY; ++i) ys[i] = fma(h2, k2[i], y[i]);
+  rhs(pot, eb, ys, k3);
+  for (int i = 0; i < NY; ++i) ys[i] = fma(h, k3[i], y[i]);
+  rhs(pot, ec, ys, k4);
+  for (int i = 0; i < NY; ++i) {
+    double acc = fma(2.0, k2[i], k1[i]);
+    acc = fma(2.0, k3[i], acc);
+    acc = acc + k4[i];
+    y[i] = fma(h6, acc, y[i]);
+  }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* HK prefactor (App. A, C_HK): G = (M_pp + M_qq)/2 + i (M_pq/(4 gamma) - gamma M_qp)         */
+/* ------------------------------------------------------------------------------------------ */
+typedef struct {
+  double re, im;
+} cpx;
+
+static cpx cmul(cpx a, cpx b) {
+  cpx r;
+  r.re = fma(a.re, b.re, -(a.im * b.im));
+  r.im = fma(a.re, b.im, a.im * b.re);
+  return r;
+}
+static cpx csub2(cpx a, cpx b) {
+  cpx r = {a.re - b.re, a.im - b.im};
+  return r;
+}
+static cpx cadd2(cpx a, cpx b) {
+  cpx r = {a.re + b.re, a.im + b.im};
+  return r;
+}
+
+/* element (i,k) of a block of M: column k (or 3+k) of M, row i of its Q (or P) part */
+#define M_QQ(m, i, k) ((m)[6 * (k) + (i)])
+#define M_PQ(m, i, k) ((m)[6 * (k) + 3 + (i)])
+#define M_QP(m, i, k) ((m)[6 * (3 + (k)) + (i)])
+#define M_PP(m, i, k) ((m)[6 * (3 + (k)) + 3 + (i)])
+
+void or_hk_det(const double* m, double gamma, double det[2]) {
+  double inv4g = 1.0 / (4.0 * gamma);
+  cpx G[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) {
+      G[i][k].re = 0.5 * (M_PP(m, i, k) + M_QQ(m, i, k));
+      G[i][k].im = fma(M_PQ(m, i, k), inv4g, -(gamma * M_QP(m, i, k)));
+    }
+  /* cofactor expansion along the first row */
+  cpx m0 = csub2(cmul(G[1][1], G[2][2]), cmul(G[1][2], G[2][1]));
+  cpx m1 = csub2(cmul(G[1][0], G[2][2]), cmul(G[1][2], G[2][0]));
+  cpx m2 = csub2(cmul(G[1][0], G[2][1]), cmul(G[1][1], G[2][0]));
+  cpx d = cadd2(csub2(cmul(G[0][0], m0), cmul(G[0][1], m1)), cmul(G[0][2], m2));
+  det[0] = d.re;
+  det[1] = d.im;
+}
+
+/* principal square root: branch cut on the negative real axis */
+static cpx csqrt_principal(cpx z, double mod) {
+  cpx r;
+  double t = sqrt(0.5 * (mod + fabs(z.re)));
+  if (t == 0.0) {
+    r.re = 0.0;
+    r.im = 0.0;
+  } else if (z.re >= 0.0) {
+    r.re = t;
+    r.im = z.im / (2.0 * t);
+  } else {
+    r.re = fabs(z.im) / (2.0 * t);
+    r.im = copysign(t, z.im);
+  }
+  return r;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* <psi0|z|p,q,gamma> over GTOs (App. C.1), overall constant 1                                 */
+/* ------------------------------------------------------------------------------------------ */
+static double complex overlap_c(const or_ground* gs, double gamma, double cut, const double* q,
+                                const double* p) {
+  double p2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+  double q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+  double pq = p[0] * q[0] + p[1] * q[1] + p[2] * q[2];
+  double complex a = 2.0 * gamma * q[2] + I * p[2];
+  double complex sum = 0.0;
+  for (int j = 0; j < gs->n_prim; ++j) {
+    double al = gs->alpha[j];
+    double ga = gamma + al;
+    double complex ex = (-p2 - 4.0 * al * (gamma * q2 + I * pq)) / (4.0 * ga);
+    if (creal(ex) < -cut) continue; /* primitive negligible: skip rule */
+    if (gs->l == 0)
+      sum += gs->coef[j] * pow(ga, -2.5) * cexp(ex);
+    else
+      sum += gs->coef[j] * pow(ga, -3.5) * cexp(ex) * (a * a + 2.0 * ga);
+  }
+  return gs->l == 0 ? a * sum : sum;
+}
+
+void or_overlap(const or_ground* gs, double gamma, double cut, const double q[3],
+                const double p[3], double out[2]) {
+  double complex o = overlap_c(gs, gamma, cut, q, p);
+  out[0] = creal(o);
+  out[1] = cimag(o);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* one trajectory: birth, propagation, per-step HK integrand                                   */
+/* ------------------------------------------------------------------------------------------ */
+static int64_t birth_step(const or_grid* g, double t0) {
+  /* nearest grid step, ties to the lower index, clamped to [0, n_steps] */
+  double u = (t0 - g->t_a) / g->h;
+  double n = ceil(u - 0.5);
+  if (!(n >= 0.0)) n = 0.0;
+  if (n > (double)g->n_steps) n = (double)g->n_steps;
+  return (int64_t)n;
+}
+
+typedef struct {
+  /* outputs of run_traj for the caller */
+  int64_t n0, death, evaluated;
+  int nonfinite;
+  double y[NY];
+  cpx c;
+} traj_out;
+
+/* per-step callback sink: either a long double accumulator or a recorder */
+typedef struct {
+  long double* acc_re;
+  long double* acc_im;
+  double* y_rec;
+  double* c_rec;
+  double* f_rec;
+  double* o_rec;
+  double* det_rec;
+  int8_t* alive_rec;
+} sink;
+
+static void run_traj(const or_potential* pot, const or_ground* gs, const or_hk* hk,
+                     const or_grid* g, double t0, const double* q0, const double* p0,
+                     double complex w, sink* sk, traj_out* out) {
+  double y[NY];
+  memset(y, 0, sizeof(y));
+  for (int i = 0; i < 3; ++i) {
+    y[i] = q0[i];
+    y[3 + i] = p0[i];
+  }
+  for (int j = 0; j < 6; ++j) y[6 + 6 * j + j] = 1.0; /* M = identity */
+  y[IY_S] = 0.0;
+  int64_t n0 = birth_step(g, t0);
+  double kay2 = hk->kay_max * hk->kay_max;
+  cpx cprev = {1.0, 0.0};
+  double sgn = 1.0;
+  out->n0 = n0;
+  out->death = -1;
+  out->evaluated = 0;
+  out->nonfinite = 0;
+  out->c = cprev;
+  for (int64_t n = n0; n <= g->n_steps; ++n) {
+    out->evaluated++;
+    double det[2];
+    or_hk_det(y + 6, hk->gamma, det);
+    double a2 = det[0] * det[0];
+    a2 = fma(det[1], det[1], a2);
+    int finite = 1;
+    for (int i = 0; i < 6; ++i) finite &= isfinite(y[i]) ? 1 : 0;
+    finite &= isfinite(y[IY_S]) ? 1 : 0;
+    if (sk->det_rec) {
+      sk->det_rec[2 * n] = det[0];
+      sk->det_rec[2 * n + 1] = det[1];
+    }
+    if (!(a2 <= kay2) || !finite) { /* Kay removal (or non-finite state): dead from step n */
+      out->death = n;
+      out->nonfinite = (!finite || isnan(a2)) ? 1 : 0;
+      break;
+    }
+    cpx dz = {det[0], det[1]};
+    cpx c = csqrt_principal(dz, sqrt(a2));
+    double dot = fma(c.im, cprev.im, c.re * cprev.re);
+    if (sgn * dot < 0.0) sgn = -sgn;
+    cpx C = {sgn * c.re, sgn * c.im};
+    cprev = C;
+    out->c = C;
+
+    double complex o = overlap_c(gs, hk->gamma, hk->overlap_cut, y, y + 3);
+    double tn = g->t_a + (double)n * g->h;
+    /* the ground state psi0 e^{i Ip t} sits in the bra of <Psi|z|Psi>, so it enters as e^{-i Ip t} */
+    double complex f = w * (C.re + I * C.im) * o * cexp(I * (y[IY_S] - gs->ip * tn));
+    if (sk->acc_re) {
+      sk->acc_re[n] += creall(f);
+      sk->acc_im[n] += cimagl(f);
+    }
+    if (sk->y_rec) {
+      memcpy(sk->y_rec + (size_t)n * NY, y, sizeof(y));
+      sk->c_rec[2 * n] = C.re;
+      sk->c_rec[2 * n + 1] = C.im;
+      sk->f_rec[2 * n] = creal(f);
+      sk->f_rec[2 * n + 1] = cimag(f);
+      sk->o_rec[2 * n] = creal(o);
+      sk->o_rec[2 * n + 1] = cimag(o);
+      sk->alive_rec[n] = 1;
+    }
+    if (n < g->n_steps)
+      rk4_step(pot, g->e_half[2 * n], g->e_half[2 * n + 1], g->e_half[2 * n + 2], g->h, y);
+  }
+  memcpy(out->y, y, sizeof(y));
+}
+
+static double complex default_weight(const double* q0, const double* p0, int64_t n) {
+  double pq = p0[0] * q0[0] + p0[1] * q0[1] + p0[2] * q0[2];
+  return cexp(I * pq) / (double)n;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* many trajectories, threaded over contiguous blocks, long double accumulation               */
+/* ------------------------------------------------------------------------------------------ */
+typedef struct {
+  const or_potential* pot;
+  const or_ground* gs;
+  const or_hk* hk;
+  const or_grid* g;
+  int64_t n_traj, lo, hi;
+  const double *t0, *q0, *p0, *w;
+  long double *acc_re, *acc_im;
+  or_diag* diag;
+  or_stats st;
+} job_t;
+
+static void* worker(void* arg) {
+  job_t* jb = (job_t*)arg;
+  sink sk;
+  memset(&sk, 0, sizeof(sk));
+  sk.acc_re = jb->acc_re;
+  sk.acc_im = jb->acc_im;
+  int64_t N = jb->n_traj;
+  for (int64_t j = jb->lo; j < jb->hi; ++j) {
+    double q0[3] = {jb->q0[j], jb->q0[N + j], jb->q0[2 * N + j]};
+    double p0[3] = {jb->p0[j], jb->p0[N + j], jb->p0[2 * N + j]};
+    double complex w = jb->w ? (jb->w[j] + I * jb->w[N + j]) : default_weight(q0, p0, N);
+    traj_out to;
+    run_traj(jb->pot, jb->gs, jb->hk, jb->g, jb->t0[j], q0, p0, w, &sk, &to);
+    jb->st.steps_evaluated += to.evaluated;
+    if (to.death >= 0) {
+      if (to.nonfinite)
+        jb->st.nonfinite_removed++;
+      else
+        jb->st.kay_removed++;
+    }
+    or_diag* d = jb->diag;
+    if (d) {
+      if (d->n0) d->n0[j] = to.n0;
+      if (d->death) d->death[j] = to.death;
+      if (d->y_final)
+        for (int i = 0; i < NY; ++i) d->y_final[(size_t)i * N + j] = to.y[i];
+      if (d->c_final) {
+        d->c_final[j] = to.c.re;
+        d->c_final[N + j] = to.c.im;
+      }
+    }
+  }
+  return NULL;
+}
+
+int or_propagate(const or_potential* pot, const or_ground* gs, const or_hk* hk,
+                 const or_grid* grid, int64_t n_traj, const double* t0, const double* q0,
+                 const double* p0, const double* w, int n_threads, double* f_out,
+                 or_diag* diag, or_stats* stats) {
+  if (n_traj < 0 || grid->n_steps < 0 || !(grid->h > 0.0) || !(hk->gamma > 0.0)) return -1;
+  if (gs->l != 0 && gs->l != 1) return -1;
+  int64_t nb = grid->n_steps + 1;
+  if (n_threads <= 0) n_threads = (int)sysconf(_SC_NPROCESSORS_ONLN);
+  if (n_threads < 1) n_threads = 1;
+  if (n_traj < n_threads) n_threads = n_traj > 0 ? (int)n_traj : 1;
+  job_t* jobs = (job_t*)calloc((size_t)n_threads, sizeof(job_t));
+  pthread_t* th = (pthread_t*)calloc((size_t)n_threads, sizeof(pthread_t));
+  long double* acc = (long double*)calloc((size_t)n_threads * 2 * nb, sizeof(long double));
+  if (!jobs || !th || !acc) {
+    free(jobs);
+    free(th);
+    free(acc);
+    return -2;
+  }
+  for (int t = 0; t < n_threads; ++t) {
+    job_t* jb = &jobs[t];
+    jb->pot = pot;
+    jb->gs = gs;
+    jb->hk = hk;
+    jb->g = grid;
+    jb->n_traj = n_traj;
+    jb->lo = n_traj * t / n_threads;
+    jb->hi = n_traj * (t + 1) / n_threads;
+    jb->t0 = t0;
+    jb->q0 = q0;
+    jb->p0 = p0;
+    jb->w = w;
+    jb->acc_re = acc + (size_t)t * 2 * nb;
+    jb->acc_im = jb->acc_re + nb;
+    jb->diag = diag;
+  }
+  for (int t = 1; t < n_threads; ++t) pthread_create(&th[t], NULL, worker, &jobs[t]);
+  worker(&jobs[0]);
+  for (int t = 1; t < n_threads; ++t) pthread_join(th[t], NULL);
+  or_stats st = {0, 0, 0};
+  for (int64_t n = 0; n < nb; ++n) {
+    long double sr = 0.0L, si = 0.0L;
+    for (int t = 0; t < n_threads; ++t) {
+      sr += jobs[t].acc_re[n];
+      si += jobs[t].acc_im[n];
+    }
+    f_out[n] = (double)sr;
+    f_out[nb + n] = (double)si;
+  }
+  for (int t = 0; t < n_threads; ++t) {
+    st.steps_evaluated += jobs[t].st.steps_evaluated;
+    st.kay_removed += jobs[t].st.kay_removed;
+    st.nonfinite_removed += jobs[t].st.nonfinite_removed;
+  }
+  if (stats) *stats = st;
+  free(jobs);
+  free(th);
+  free(acc);
+  return 0;
+}
+
+int or_trajectory(const or_potential* pot, const or_ground* gs, const or_hk* hk,
+                  const or_grid* grid, double t0, const double q0[3], const double p0[3],
+                  const double w[2], double* y_rec, double* c_rec, double* f_rec, double* o_rec,
+                  double* det_rec, int8_t* alive_rec) {
+  if (grid->n_steps < 0 || !(grid->h > 0.0) || !(hk->gamma > 0.0)) return -1;
+  int64_t nb = grid->n_steps + 1;
+  memset(y_rec, 0, sizeof(double) * NY * nb);
+  memset(c_rec, 0, sizeof(double) * 2 * nb);
+  memset(f_rec, 0, sizeof(double) * 2 * nb);
+  memset(o_rec, 0, sizeof(double) * 2 * nb);
+  memset(det_rec, 0, sizeof(double) * 2 * nb);
+  memset(alive_rec, 0, nb);
+  sink sk;
+  memset(&sk, 0, sizeof(sk));
+  sk.y_rec = y_rec;
+  sk.c_rec = c_rec;
+  sk.f_rec = f_rec;
+  sk.o_rec = o_rec;
+  sk.det_rec = det_rec;
+  sk.alive_rec = alive_rec;
+  traj_out to;
+  run_traj(pot, gs, hk, grid, t0, q0, p0, w[0] + I * w[1], &sk, &to);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* dipole, output grid, spectrum                                                               */
+/* ------------------------------------------------------------------------------------------ */
+void or_dipole(const double* f, int64_t n_steps, double* d_out) {
+  for (int64_t n = 0; n <= n_steps; ++n) d_out[n] = -2.0 * f[n];
+}
+
+void or_resample(const double* d, int64_t n_steps, int64_t n_out, double* out) {
+  for (int64_t k = 0; k < n_out; ++k) {
+    /* t_k sits at fractional step u = k n_steps / n_out (exact integer arithmetic) */
+    int64_t num = k * n_steps;
+    int64_t i = num / n_out;
+    int64_t rem = num % n_out;
+    double frac = (double)rem / (double)n_out;
+    out[k] = (i >= n_steps) ? d[n_steps] : d[i] + frac * (d[i + 1] - d[i]);
+  }
+}
+
+int or_spectrum(const double* d, int64_t n, double t_first, double dt, double tau_h,
+                int64_t n_fft, double* omega_out, double* power_out, double* x_out) {
+  if (n_fft <= 0) n_fft = n;
+  if (n < 1 || n_fft < n || !(dt > 0.0) || !(tau_h > 0.0)) return -1;
+  double* xw = (double*)malloc(sizeof(double) * n_fft);
+  double* tc = (double*)malloc(sizeof(double) * n_fft);
+  double* ts = (double*)malloc(sizeof(double) * n_fft);
+  if (!xw || !tc || !ts) {
+    free(xw);
+    free(tc);
+    free(ts);
+    return -2;
+  }
+  for (int64_t i = 0; i < n_fft; ++i) {
+    if (i < n) {
+      double t = t_first + (double)i * dt;
+      double win = fabs(t) >= tau_h ? 0.0 : 0.5 * (1.0 + cos(M_PI * t / tau_h));
+      xw[i] = d[i] * win;
+    } else {
+      xw[i] = 0.0;
+    }
+    /* twiddle exp(2 pi i m / n_fft), m reduced exactly */
+    double ang = 2.0 * M_PI * (double)i / (double)n_fft;
+    tc[i] = cos(ang);
+    ts[i] = sin(ang);
+  }
+  for (int64_t k = 0; k <= n_fft / 2; ++k) {
+    long double sr = 0.0L, si = 0.0L;
+    for (int64_t i = 0; i < n; ++i) {
+      int64_t m = (int64_t)(((__int128)k * i) % n_fft);
+      sr += (long double)xw[i] * tc[m];
+      si += (long double)xw[i] * ts[m];
+    }
+    double omega = 2.0 * M_PI * (double)k / ((double)n_fft * dt);
+    /* exp(i omega t_first) shifts the time origin from sample 0 to t = 0 */
+    double ph = omega * t_first;
+    double cr = cos(ph), ci = sin(ph);
+    double xr = dt * ((double)sr * cr - (double)si * ci);
+    double xi = dt * ((double)sr * ci + (double)si * cr);
+    if (omega_out) omega_out[k] = omega;
+    if (power_out) power_out[k] = xr * xr + xi * xi;
+    if (x_out) {
+      x_out[2 * k] = xr;
+      x_out[2 * k + 1] = xi;
+    }
+  }
+  free(xw);
+  free(tc);
+  free(ts);
+  return 0;
+}

@@ -1,0 +1,74 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case plants one mistake in a copy of the oracle's source (on the CPU), builds it, and runs
+the pin tests against that build: they must fail. A case whose mutant passes every pin names a
+part of the oracle that nothing outside it checks.
+"""
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "sfhk_oracle.c")
+HDR = os.path.join(ROOT, "oracle", "sfhk_oracle.h")
+PINS = os.path.join(ROOT, "tests", "test_oracle_pins.py")
+
+MUTANTS = {
+    "G imaginary part sign": ("G[i][k].im = fma(M_PQ(m, i, k), inv4g, -(gamma * M_QP(m, i, k)));",
+                              "G[i][k].im = -fma(M_PQ(m, i, k), inv4g, -(gamma * M_QP(m, i, k)));"),
+    "1/(2 gamma) for 1/(4 gamma)": ("double inv4g = 1.0 / (4.0 * gamma);",
+                                    "double inv4g = 1.0 / (2.0 * gamma);"),
+    "gamma dq/dp0 term doubled": ("-(gamma * M_QP(m, i, k))", "-(2.0 * gamma * M_QP(m, i, k))"),
+    "Hessian force sign": ("kP[i] = -t;", "kP[i] = t;"),
+    "field dropped from the action": ("L = fma(-q[2], E, L);", "L = L;"),
+    "field force sign": ("k[5] = -fma(g, q[2], E);", "k[5] = -fma(g, q[2], -E);"),
+    "RK4 weight of k3": ("acc = fma(2.0, k3[i], acc);", "acc = acc + k3[i];"),
+    "RK4 stage-3 time": ("rhs(pot, eb, ys, k3);", "rhs(pot, ea, ys, k3);"),
+    "overlap phase conjugated": ("(gamma * q2 + I * pq)", "(gamma * q2 - I * pq)"),
+    "overlap s-wave power": ("pow(ga, -2.5)", "pow(ga, -1.5)"),
+    "overlap p-wave bracket": ("(a * a + 2.0 * ga)", "(a * a + ga)"),
+    "no branch tracking": ("if (sgn * dot < 0.0) sgn = -sgn;", ""),
+    "screened V' drops Z'": ("double vp = fma(Z * r, ir3, d1 * ir);", "double vp = Z * r * ir3;"),
+    "screened V'' factor": ("double vpp = tc - fma(2.0, tb, ta);", "double vpp = tc - fma(1.0, tb, ta);"),
+    "softcore Hessian factor": ("*c = (-3.0 * Z) * u5;", "*c = (-2.0 * Z) * u5;"),
+    "Kay test on |det|^2": ("if (!(a2 <= kay2) || !finite)", "if (!(a2 <= hk->kay_max) || !finite)"),
+    "birth ties to upper": ("double n = ceil(u - 0.5);", "double n = floor(u + 0.5);"),
+    "dipole sign": ("d_out[n] = -2.0 * f[n];", "d_out[n] = 2.0 * f[n];"),
+    "Hann window sign": ("0.5 * (1.0 + cos(M_PI * t / tau_h))", "0.5 * (1.0 - cos(M_PI * t / tau_h))"),
+    "resample neighbour": ("d[i] + frac * (d[i + 1] - d[i])", "d[i] + frac * (d[i] - d[i])"),
+    "Ip phase sign": ("cexp(I * (y[IY_S] - gs->ip * tn))", "cexp(I * (y[IY_S] + gs->ip * tn))"),
+    "default weight sign": ("return cexp(I * pq) / (double)n;", "return cexp(-I * pq) / (double)n;"),
+    "exp not correctly rounded": ("return (double)expq((__float128)x);",
+                                  "return (double)(float)expq((__float128)x);"),
+}
+
+
+def _run_mutant(name, old, new, tmp):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"{name}: snippet not found exactly once"
+    d = os.path.join(tmp, name.replace(" ", "_").replace("/", "_").replace("'", ""))
+    os.makedirs(d, exist_ok=True)
+    open(os.path.join(d, "sfhk_oracle.c"), "w").write(src.replace(old, new))
+    open(os.path.join(d, "sfhk_oracle.h"), "w").write(open(HDR).read())
+    lib = os.path.join(d, "libmut.so")
+    subprocess.run(["gcc", "-O2", "-mfma", "-ffp-contract=off", "-fPIC", "-shared",
+                    "-std=gnu11", "-w", "-o", lib, os.path.join(d, "sfhk_oracle.c"),
+                    "-lquadmath", "-lm", "-lpthread"], check=True)
+    env = dict(os.environ, SFHK_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, "-m", "pytest", PINS, "-x", "-q", "-p", "no:cacheprovider",
+                        "-W", "ignore"], cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=600)
+    return name, r.returncode
+
+
+def test_every_planted_mistake_fails_a_pin():
+    with tempfile.TemporaryDirectory() as tmp:
+        with cf.ThreadPoolExecutor(max_workers=4) as ex:
+            futs = [ex.submit(_run_mutant, n, o, w, tmp) for n, (o, w) in MUTANTS.items()]
+            results = dict(f.result() for f in futs)
+    survivors = [n for n, rc in results.items() if rc == 0]
+    assert not survivors, f"mutants not caught by any pin: {survivors}"
