@@ -1,0 +1,155 @@
+"""Benchmark of the SFHK hot path on one MI355X.
+
+One step = one pass of the whole path over one synthetic instance whose inputs are already in
+HBM: job creation (birth snapping, initial state), propagation of every trajectory (RK4 of the 43
+ODEs, HK prefactor, Kay removal, dipole integrand, per-step reduction), the fixed-order reduction
+into d(t) with resampling, and the Hann-windowed spectrum.
+
+Workload: screened SAE potential, 1600 nm, 1.5e14 W/cm^2, 8-cycle sin^2 pulse, 1024 birth times x
+1024 Gaussian phase-space samples (2^20 trajectories), gamma = 0.5, RK4 dt = 0.05, FP64, dipole
+resampled onto 2^15 points.
+
+Prints one JSON line. The CPU baseline is the plain oracle on a bounded sample of the same
+workload (it is test infrastructure; the product path never calls it).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CUs x 2.4 GHz x 128 FP64 operations per CU-clock
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp64"], default="fp64")
+    ap.add_argument("--n-birth", type=int, default=1024)
+    ap.add_argument("--n-per-birth", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-births", type=int, default=16,
+                    help="birth groups (spread over the pulse) in the oracle's sample")
+    ap.add_argument("--cpu-per-birth", type=int, default=64)
+    return ap.parse_args()
+
+
+def cpu_baseline(inst, n_births, n_per):
+    """Oracle trajectory-steps/s on a bounded sample: n_births birth groups spread evenly over
+    the pulse, the first n_per samples of each."""
+    from oracle import oracle as O  # test infrastructure: the CPU-baseline leg only
+    from tests.common import run_oracle
+    O.build(force=False)
+    stride = max(1, inst.n_birth // n_births)
+    births = list(range(0, inst.n_birth, stride))[:n_births]
+    from paper_2601_17164_amd import inputs as I
+    sub = I.config1_birth_subset(inst, births, n_per)
+    threads = min(os.cpu_count() or 1, 16)
+    t = time.perf_counter()
+    r = run_oracle(sub, n_threads=threads)
+    dt = time.perf_counter() - t
+    return {"value": r.steps_evaluated / dt, "unit": "trajectory-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{len(births)} birth groups x {n_per} samples = {sub.n_traj} trajectories "
+                      f"({r.steps_evaluated} trajectory-steps, {dt:.1f} s)"}
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU path (sharding "
+                                   "by birth groups with one reduction of d(t)) is not built",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_2601_17164_amd import flops, inputs as I, sfhk
+
+    inst = I.config1(n_birth=a.n_birth, n_per_birth=a.n_per_birth)
+    dev = torch.device("cuda:0")
+    arrays = sfhk.to_device(inst, "cuda:0")
+    ctx = sfhk.Context(0)
+    stream = torch.cuda.current_stream()
+    T = inst.grid.h * inst.grid.n_steps
+    n_out = inst.n_out
+    dt_out = T / n_out
+
+    def step(ev):
+        job = sfhk.make_job(ctx, inst, arrays)
+        ev[0].record(stream)
+        done = job.propagate(0)
+        ev[1].record(stream)
+        assert done
+        d = job.dipole()
+        om, pw, _ = sfhk.spectrum(d, inst.grid.t_a, dt_out, T / 2)
+        return job, pw
+
+    for _ in range(a.warmup):
+        job, pw = step([torch.cuda.Event(enable_timing=True) for _ in range(2)])
+        torch.cuda.synchronize()
+        job.close()
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(a.steps)]
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    marks[0].record(stream)
+    for k in range(a.steps):
+        job, pw = step(evs[k])
+        marks[k + 1].record(stream)
+        stats.append(job.stats(stream))  # synchronises the stream
+        job.close()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    steps_eval = sum(s.steps_evaluated for s in stats)
+    kern_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
+    lat_ms = np.array([marks[k].elapsed_time(marks[k + 1]) for k in range(a.steps)])
+    s0 = stats[0]
+    fl = flops.flops(inst.potential.kind, inst.ground.l, s0.steps_evaluated, s0.prims_evaluated)
+    achieved = fl / (kern_ms.mean() * 1e-3) / 1e12
+    out = {
+        "metric": "HK trajectory-steps/s (3D, w/ monodromy) at 1 GPU; p50/p99 spectrum latency",
+        "value": steps_eval / wall,
+        "unit": "trajectory-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": wall / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "screened-SAE 1600nm 1.5e14 W/cm2 8-cycle, "
+                               f"{inst.n_birth}x{inst.n_per_birth} trajectories, dt 0.05, "
+                               "2^15-point dipole, FP64",
+                   "n_traj": inst.n_traj, "n_steps": inst.grid.n_steps,
+                   "trajectory_steps_per_step": s0.steps_evaluated},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
+                       "p99": float(np.percentile(lat_ms, 99))},
+        "roofline": {"bound": "alu", "kernel": "k_propagate_fp64 (screened)",
+                     "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "kernel_ms": float(kern_ms.mean()),
+                     "flop_per_launch": fl},
+        "stats": {"kay_removed": s0.kay_removed, "nonfinite_removed": s0.nonfinite_removed,
+                  "prims_per_step": s0.prims_evaluated / max(1, s0.steps_evaluated)},
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inst, a.cpu_births, a.cpu_per_birth)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * sfhk.h -- C ABI of the MI355X (gfx950) hot path of the semiclassical strong-field Herman-Kluk
+ * (SFHK) method for high-harmonic generation (Tran, Truong, Goetz, Le).
+ *
+ * The hot path: many independent classical trajectories, each integrating Hamilton's equations of
+ * H = p^2/2 + V_a(q) + q.E(t) together with its 6x6 stability (monodromy) matrix and its action
+ * (App. A); per time step the Herman-Kluk prefactor and phase of each coherent-state trajectory
+ * times the GTO dipole matrix element <psi0|z|p_t,q_t,gamma> (App. C.1), summed into the induced
+ * dipole D(t) = -<psi0 e^{i Ip t}|z|psi_c(t)> + c.c. (Eq. 2); then the Hann-windowed Fourier
+ * transform of D(t) (App. D).
+ *
+ * Conventions of every entry point:
+ *  - Atomic units. Pointers are DEVICE pointers unless stated otherwise; the caller owns them.
+ *  - Calls are asynchronous on the given HIP stream (hipStream_t passed as void*; NULL = the null
+ *    stream) unless stated otherwise; results are ready when the stream reaches that point.
+ *  - Errors are returned as negative sfhk_status codes; nothing throws across the ABI. The text of
+ *    the most recent error on the calling thread is available from sfhk_last_error().
+ *  - A context is used from one host thread at a time. Jobs of one context may be propagated from
+ *    that thread on any stream; calls that touch the same job must be ordered by the caller.
+ */
+#ifndef SFHK_H
+#define SFHK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SFHK_OK = 0,
+  SFHK_E_INVALID = -1,  /* an argument is out of range (message names it) */
+  SFHK_E_NOMEM = -2,    /* device allocation failed */
+  SFHK_E_DEVICE = -3,   /* a HIP runtime call failed */
+  SFHK_E_NOT_DONE = -4, /* sfhk_propagate stopped after max_steps; call again to continue */
+  SFHK_E_BUDGET = -5    /* the job does not fit in the context's remaining HBM budget */
+} sfhk_status;
+
+/* Atomic model potential V_a (App. A, Hamiltonian of the HK propagation):
+ *   SFHK_POT_NONE      V = 0 (laser-only motion)
+ *   SFHK_POT_SOFTCORE  V = -z_inf / sqrt(r^2 + soft2)
+ *   SFHK_POT_SCREENED  V = -(z_inf + z_in exp(-r / r_scr)) / sqrt(r^2 + soft2)
+ *   SFHK_POT_HARMONIC  V = omega_ho^2 r^2 / 2 (closed-form test case) */
+typedef enum { SFHK_POT_NONE = 0, SFHK_POT_SOFTCORE = 1, SFHK_POT_SCREENED = 2, SFHK_POT_HARMONIC = 3 } sfhk_pot_kind;
+
+typedef enum { SFHK_FP64 = 0, SFHK_FP32_MIXED = 1 } sfhk_precision;
+
+typedef struct {
+  int32_t kind;
+  double z_inf, z_in, r_scr, soft2, omega_ho;
+} sfhk_potential;
+
+/* Ground state psi0 as GTOs (App. B.1/C.1): l = 0: sum_j coef_j exp(-alpha_j r^2);
+ * l = 1: z sum_j coef_j exp(-alpha_j r^2). alpha/coef are HOST arrays of n_prim <= SFHK_MAX_PRIM
+ * entries, read during sfhk_job_create. ip is the ionization potential I_p. */
+#define SFHK_MAX_PRIM 8
+typedef struct {
+  int32_t l;
+  int32_t n_prim;
+  const double* alpha;
+  const double* coef;
+  double ip;
+} sfhk_ground;
+
+/* Time grid and laser field (Sec. II.B field, linear polarisation along z): t_n = t_a + n h,
+ * n = 0..n_steps. e_half is a DEVICE array of 2*n_steps + 1 values E_z(t_a + m h / 2), read during
+ * sfhk_job_create (copied; the caller may free it afterwards). */
+typedef struct {
+  double t_a;
+  double h;
+  int64_t n_steps;
+  const double* e_half;
+} sfhk_grid;
+
+/* Method parameters:
+ *   gamma        coherent-state width (App. A), > 0
+ *   kay_max      Kay removal limit D_t on |C|^2 (Sec. III.A): a trajectory stops contributing
+ *                from the first step where |det G| > kay_max (also when its state is not finite)
+ *   overlap_cut  a GTO primitive is skipped when the real part of its exponent is < -overlap_cut
+ *   r_fp64       SFHK_FP32_MIXED only: steps that start at r < r_fp64 run in FP64
+ *   precision    sfhk_precision
+ *   n_out        0: dipole on the step grid (n_steps + 1 points); > 0: linearly resampled onto
+ *                t_k = t_a + k (n_steps h) / n_out, k = 0..n_out-1 */
+typedef struct {
+  double gamma;
+  double kay_max;
+  double overlap_cut;
+  double r_fp64;
+  int32_t precision;
+  int64_t n_out;
+} sfhk_params;
+
+typedef struct {
+  int64_t n_traj;
+  int64_t n_steps;
+  int64_t steps_evaluated;   /* (trajectory, t_n) pairs evaluated so far, removal steps included */
+  int64_t steps_fp64;        /* of which evaluated after an FP64 step (SFHK_FP32_MIXED) */
+  int64_t kay_removed;
+  int64_t nonfinite_removed;
+  int64_t tiles_total;
+  int64_t tiles_done;
+  int64_t prims_evaluated;   /* GTO primitives evaluated in the dipole integrand (the rest were
+                                skipped by overlap_cut) */
+} sfhk_stats;
+
+typedef struct sfhk_ctx sfhk_ctx;
+typedef struct sfhk_job sfhk_job;
+
+/* Create a context on HIP device `device` whose jobs may hold at most hbm_budget_bytes of device
+ * memory in total (0: no limit). Synchronous. */
+sfhk_status sfhk_ctx_create(int device, size_t hbm_budget_bytes, sfhk_ctx** out);
+void sfhk_ctx_destroy(sfhk_ctx* ctx);
+/* Bytes of device memory currently held by the context's jobs. */
+size_t sfhk_ctx_bytes_in_use(const sfhk_ctx* ctx);
+
+/* Device bytes a job of this shape will hold (the admission test of a serving loop). */
+size_t sfhk_job_footprint(int64_t n_traj, int64_t n_steps, int64_t n_out, int32_t precision);
+
+/* Create a job: n_traj trajectories born at times t0[n_traj] with initial phase-space samples
+ * q0[3][n_traj], p0[3][n_traj] (SoA, DEVICE) and complex Monte-Carlo/birth weights
+ * w[2][n_traj] (re block then im block, DEVICE) or NULL for w_j = exp(i p0.q0)/n_traj (the
+ * e^{i p0.q0} factor of the continuum wavefunction at the tunnel exit, App. A).
+ * Each trajectory is born on the grid step nearest to t0 (ties to the lower step), with
+ * M = I and S = 0. t0 must lie in [t_a, t_a + n_steps h]. Reads t0 synchronously (the host orders
+ * trajectories by birth step); the other inputs are read on `stream` before the call returns its
+ * status, after which the caller may free all inputs.
+ * Errors: SFHK_E_INVALID (gamma <= 0, h <= 0, n_steps < 1, n_traj < 1, l not 0/1, n_prim not in
+ * 1..SFHK_MAX_PRIM, precision unknown, n_out < 0, t0 outside the grid, NULL pointers),
+ * SFHK_E_BUDGET, SFHK_E_NOMEM, SFHK_E_DEVICE. Non-finite samples are not errors: the trajectory
+ * is removed at its birth step and counted in nonfinite_removed. */
+sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk_ground* ground,
+                            const sfhk_grid* grid, const sfhk_params* params, int64_t n_traj,
+                            const double* t0, const double* q0, const double* p0, const double* w,
+                            void* stream, sfhk_job** out);
+void sfhk_job_destroy(sfhk_job* job);
+
+/* Propagate the job's trajectories (RK4 steps of the 43 ODEs, HK prefactor, Kay removal, dipole
+ * integrand, per-step reduction) by at most max_steps steps each (max_steps <= 0: to the end of
+ * the grid). Returns SFHK_OK when every trajectory has reached the end of the grid,
+ * SFHK_E_NOT_DONE when some have not (call again to continue: state stays in HBM between calls and
+ * the result is identical to one uninterrupted call). Asynchronous on `stream`; the completion
+ * status is known on the host without waiting for the kernels. */
+sfhk_status sfhk_propagate(sfhk_job* job, int64_t max_steps, void* stream);
+
+/* Propagate several jobs of one context in a single kernel launch (jobs may differ in size,
+ * pulse, potential and precision). Same semantics per job as sfhk_propagate; returns
+ * SFHK_E_NOT_DONE if any job is unfinished. */
+sfhk_status sfhk_propagate_many(sfhk_job* const* jobs, int32_t n_jobs, int64_t max_steps,
+                                void* stream);
+
+/* Reduce the job's per-tile partial sums in a fixed order into F(t_n) = sum_j f_j(t_n) and write
+ * d_out = -2 Re F (Eq. 2: "+ c.c." with the leading minus) on the job's output grid (n_out points,
+ * or n_steps + 1 when n_out = 0). f_out (nullable) receives F on the step grid as
+ * [2][n_steps+1] (re block then im block). Requires a finished job (else SFHK_E_NOT_DONE). */
+sfhk_status sfhk_dipole(sfhk_job* job, double* d_out, double* f_out, void* stream);
+
+/* Number of points sfhk_dipole writes to d_out. */
+int64_t sfhk_job_n_out(const sfhk_job* job);
+
+/* Hann-windowed Fourier transform (App. D): with t_n = t_first + n dt and d zero-padded to
+ * n_fft samples (n_fft = 0: n),
+ *   X_k = dt sum_n d_n W_H(t_n) exp(i omega_k t_n),  W_H(t) = (1 + cos(pi t / tau_h)) / 2 for
+ *   |t| < tau_h and 0 otherwise,  omega_k = 2 pi k / (n_fft dt),  k = 0..n_fft/2.
+ * Writes omega_out[k], power_out[k] = |X_k|^2 and (nullable) x_out[2k], x_out[2k+1] = X_k.
+ * Stateless. Errors: SFHK_E_INVALID for n < 1, n_fft < n, dt <= 0 or tau_h <= 0. */
+sfhk_status sfhk_spectrum(const double* d, int64_t n, double t_first, double dt, double tau_h,
+                          int64_t n_fft, double* omega_out, double* power_out, double* x_out,
+                          void* stream);
+
+/* Counters of the job (synchronises `stream` first). */
+sfhk_status sfhk_job_stats(sfhk_job* job, sfhk_stats* out, void* stream);
+
+/* Per-trajectory state in the caller's original trajectory order (for checks and checkpoints):
+ * y_out[43][n_traj] = q(3) p(3) M (6 columns of Q(3) P(3)) S at the last step evaluated (the
+ * removal step for removed trajectories), c_out[2][n_traj] = HK prefactor C at the last accepted
+ * step, death_out[n_traj] = removal step or -1 (int64). Any output may be NULL. DEVICE pointers. */
+sfhk_status sfhk_job_trajectories(sfhk_job* job, double* y_out, double* c_out, int64_t* death_out,
+                                  void* stream);
+
+/* Text of the most recent error on the calling thread ("" if none). */
+const char* sfhk_last_error(void);
+const char* sfhk_status_string(sfhk_status s);
+
+/* Correctly rounded binary64 exp of x[n] into y[n] (the exponential the screened potential uses;
+ * exported so it can be checked against an independent correctly rounded evaluation). */
+sfhk_status sfhk_exp_cr(const double* x, double* y, int64_t n, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFHK_H */

@@ -1,0 +1,872 @@
+// sfhk.hip -- HIP kernels and host runtime of the SFHK hot path (gfx950), behind include/sfhk.h.
+//
+// Layout in HBM (per job):
+//   trajectories are ordered by birth step (stable) and padded to tiles of 64 lanes; tile t holds
+//   sorted trajectories 64t..64t+63, so tiles are ordered longest first;
+//   state y[43][n_pad] (SoA, FP64): q(3) p(3) M(6 columns of Q(3) P(3)) S; aux[5][n_pad]:
+//   C_prev (re, im), w (re, im), branch sign; n0[n_pad], death[n_pad] (int32);
+//   one partial row per tile: the wave-reduced dipole integrand F_tile(t_n) for
+//   n = tile_n0 .. n_steps (complex FP64), written 64 steps at a time by one coalesced store.
+// Reduction order is fixed (tile order inside groups of 64 tiles, then group order), so the dipole
+// is bitwise reproducible for a given input.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/sfhk.h"
+#include "sfhk_device.hpp"
+
+using namespace sfhk;
+
+namespace {
+
+constexpr int kTile = 64;           // trajectories per tile = lanes per wave
+constexpr int kReduceGroup = 64;    // tiles per first-level reduction group
+constexpr int kNY = 43;
+
+thread_local std::string g_err;
+
+sfhk_status fail(sfhk_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(e_ == hipErrorOutOfMemory ? SFHK_E_NOMEM : SFHK_E_DEVICE,            \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+  } while (0)
+
+// ------------------------------------------------------------------------------------------------
+// device-side job description
+// ------------------------------------------------------------------------------------------------
+struct GtoConst {
+  int l, n_prim;
+  double A[SFHK_MAX_PRIM];   // 1 / (4 (gamma + alpha_j))
+  double B[SFHK_MAX_PRIM];   // alpha_j gamma / (gamma + alpha_j)
+  double D[SFHK_MAX_PRIM];   // alpha_j / (gamma + alpha_j)
+  double N[SFHK_MAX_PRIM];   // c_j (gamma + alpha_j)^(-5/2) (l = 0) or ^(-7/2) (l = 1)
+  double G2[SFHK_MAX_PRIM];  // 2 (gamma + alpha_j)
+  double two_gamma, ip;
+};
+
+struct JobDev {
+  PotParams pot;
+  GtoConst gto;
+  double gamma, inv4g, kay2, cut;
+  double t_a, h, h2, h6;
+  int n_steps;
+  int n_tiles;
+  long long n_pad;
+  const double* e_half;
+  double* y;
+  double* aux;
+  int* n0;
+  int* death;
+  int* tile_n0;
+  int* tile_next;
+  int* tile_last;
+  long long* row_off;
+  double2* part;
+  unsigned long long* counters;  // steps_evaluated, kay_removed, nonfinite_removed, steps_fp64,
+                                 // GTO primitives evaluated
+};
+
+// ------------------------------------------------------------------------------------------------
+// wave-level sum (butterfly: every lane ends with the same, order-independent-by-symmetry value)
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// <psi0|z|p,q,gamma> over GTOs (App. C.1, overall constant 1); tolerance-level arithmetic (it does
+// not feed back into the trajectory)
+__device__ __forceinline__ cplx overlap(const GtoConst& G, double cut, const double* q,
+                                        const double* p, unsigned int& n_eval) {
+  double p2 = SFHK_FMA(p[2], p[2], SFHK_FMA(p[1], p[1], p[0] * p[0]));
+  double q2 = SFHK_FMA(q[2], q[2], SFHK_FMA(q[1], q[1], q[0] * q[0]));
+  double pq = SFHK_FMA(p[2], q[2], SFHK_FMA(p[1], q[1], p[0] * q[0]));
+  cplx a = {G.two_gamma * q[2], p[2]};
+  cplx sum = {0.0, 0.0};
+  cplx a2 = cmul(a, a);
+  for (int j = 0; j < G.n_prim; ++j) {
+    double re = -SFHK_FMA(p2, G.A[j], q2 * G.B[j]);
+    if (re >= -cut) {
+      ++n_eval;
+      double im = -(pq * G.D[j]);
+      double e = exp(re) * G.N[j];
+      double s, c;
+      sincos(im, &s, &c);
+      cplx E = {e * c, e * s};
+      if (G.l == 0) {
+        sum.re += E.re;
+        sum.im += E.im;
+      } else {
+        cplx b = {a2.re + G.G2[j], a2.im};
+        cplx t = cmul(E, b);
+        sum.re += t.re;
+        sum.im += t.im;
+      }
+    }
+  }
+  return G.l == 0 ? cmul(a, sum) : sum;
+}
+
+// ------------------------------------------------------------------------------------------------
+// initialisation: gather the sorted samples into the SoA state
+// ------------------------------------------------------------------------------------------------
+__global__ void k_init(JobDev J, const long long* __restrict__ perm, long long n_traj,
+                       const double* __restrict__ q0, const double* __restrict__ p0,
+                       const double* __restrict__ w) {
+  long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= J.n_pad) return;
+  long long np = J.n_pad;
+  long long o = perm[s];
+  double* y = J.y;
+  double q[3] = {0, 0, 0}, p[3] = {0, 0, 0}, wr = 0.0, wi = 0.0;
+  if (o >= 0) {
+    for (int i = 0; i < 3; ++i) {
+      q[i] = q0[i * n_traj + o];
+      p[i] = p0[i * n_traj + o];
+    }
+    if (w) {
+      wr = w[o];
+      wi = w[n_traj + o];
+    } else {  // exp(i p0.q0) / n
+      double pq = p[0] * q[0] + p[1] * q[1] + p[2] * q[2];
+      double sn, cs;
+      sincos(pq, &sn, &cs);
+      wr = cs / (double)n_traj;
+      wi = sn / (double)n_traj;
+    }
+  }
+  for (int i = 0; i < 3; ++i) {
+    y[i * np + s] = q[i];
+    y[(3 + i) * np + s] = p[i];
+  }
+  for (int c = 0; c < 36; ++c) y[(6 + c) * np + s] = (c % 7 == 0) ? 1.0 : 0.0;  // M = I
+  y[42 * np + s] = 0.0;
+  J.aux[0 * np + s] = 1.0;  // C_prev
+  J.aux[1 * np + s] = 0.0;
+  J.aux[2 * np + s] = wr;
+  J.aux[3 * np + s] = wi;
+  J.aux[4 * np + s] = 1.0;  // branch sign
+  J.death[s] = (o >= 0) ? -1 : -2;
+}
+
+// ------------------------------------------------------------------------------------------------
+// propagation, FP64: one wave per tile, one trajectory per lane
+// ------------------------------------------------------------------------------------------------
+template <int KIND>
+__global__ __launch_bounds__(64) void k_propagate_fp64(const JobDev* __restrict__ jobs,
+                                                       int max_steps) {
+  const JobDev& J = jobs[0];
+  const int tile = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int n_begin = J.tile_next[tile];
+  const int N = J.n_steps;
+  if (n_begin > N) return;
+  const int n_stop = (max_steps > 0) ? min(N, n_begin + max_steps - 1) : N;
+  const long long np = J.n_pad;
+  const long long s = (long long)tile * kTile + lane;
+
+  Traj T;
+  const double* y = J.y;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T.q[i] = y[i * np + s];
+    T.p[i] = y[(3 + i) * np + s];
+  }
+#pragma unroll
+  for (int c = 0; c < 36; ++c) T.M[c] = y[(6 + c) * np + s];
+  T.S = y[42 * np + s];
+  cplx cprev = {J.aux[s], J.aux[np + s]};
+  const cplx w = {J.aux[2 * np + s], J.aux[3 * np + s]};
+  double sgn = J.aux[4 * np + s];
+  const int n0l = J.n0[s];
+  int death = J.death[s];
+  bool alive = death == -1;
+
+  const int t0 = J.tile_n0[tile];
+  const long long roff = J.row_off[tile];
+  double2* __restrict__ part = J.part;
+  const double* __restrict__ eh = J.e_half;
+  const double gamma = J.gamma, inv4g = J.inv4g, kay2 = J.kay2, cut = J.cut;
+  const double h = J.h, h2 = J.h2, h6 = J.h6, t_a = J.t_a, ip = J.gto.ip;
+
+  double buf_re = 0.0, buf_im = 0.0;
+  int slot_lo = (n_begin - t0) & 63;
+  unsigned int evals = 0, kay = 0, nonfin = 0, prims = 0;
+  int n = n_begin;
+  int last_written = n_begin - 1;
+  for (; n <= n_stop; ++n) {
+    const bool active = alive && n >= n0l;
+    double fr = 0.0, fi = 0.0;
+    if (active) {
+      ++evals;
+      cplx d = hk_det(T.M, gamma, inv4g);
+      double a2 = d.re * d.re;
+      a2 = SFHK_FMA(d.im, d.im, a2);
+      bool finite = isfinite(T.q[0]) && isfinite(T.q[1]) && isfinite(T.q[2]) &&
+                    isfinite(T.p[0]) && isfinite(T.p[1]) && isfinite(T.p[2]) && isfinite(T.S);
+      if (!(a2 <= kay2) || !finite) {
+        alive = false;
+        death = n;
+        if (!finite || isnan(a2))
+          ++nonfin;
+        else
+          ++kay;
+      } else {
+        cplx c = csqrt_principal(d, sqrt(a2));
+        double dot = SFHK_FMA(c.im, cprev.im, c.re * cprev.re);
+        if (sgn * dot < 0.0) sgn = -sgn;
+        cplx C = {sgn * c.re, sgn * c.im};
+        cprev = C;
+        cplx O = overlap(J.gto, cut, T.q, T.p, prims);
+        double tn = t_a + (double)n * h;
+        double ph = T.S - ip * tn;
+        double sp, cp;
+        sincos(ph, &sp, &cp);
+        cplx f = cmul(cmul(w, C), cmul(O, cplx{cp, sp}));
+        fr = f.re;
+        fi = f.im;
+      }
+    }
+    fr = wave_sum(fr);
+    fi = wave_sum(fi);
+    const int slot = (n - t0) & 63;
+    if (lane == slot) {
+      buf_re = fr;
+      buf_im = fi;
+    }
+    if (slot == 63 || n == n_stop) {
+      const long long base = roff + (n - slot - t0);
+      if (lane >= slot_lo && lane <= slot) part[base + lane] = make_double2(buf_re, buf_im);
+      slot_lo = 0;
+    }
+    last_written = n;
+    if (active && alive && n < N) rk4_step<KIND>(J.pot, T, eh[2 * n], eh[2 * n + 1], eh[2 * n + 2], h, h2, h6);
+    if (!__any(alive)) {  // every lane removed: the rest of the row is zero
+      if (slot != 63 && n != n_stop) {
+        const long long base = roff + (n - slot - t0);
+        if (lane >= slot_lo && lane <= slot) part[base + lane] = make_double2(buf_re, buf_im);
+      }
+      ++n;
+      break;
+    }
+  }
+  // write back
+  double* yw = J.y;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    yw[i * np + s] = T.q[i];
+    yw[(3 + i) * np + s] = T.p[i];
+  }
+#pragma unroll
+  for (int c = 0; c < 36; ++c) yw[(6 + c) * np + s] = T.M[c];
+  yw[42 * np + s] = T.S;
+  J.aux[s] = cprev.re;
+  J.aux[np + s] = cprev.im;
+  J.aux[4 * np + s] = sgn;
+  J.death[s] = death;
+  const bool finished = !__any(alive) || n > N;
+  if (lane == 0) {
+    J.tile_next[tile] = finished ? N + 1 : n;
+    J.tile_last[tile] = last_written;
+  }
+  // counters: one atomic per wave
+  double ev = wave_sum((double)evals), ka = wave_sum((double)kay), nf = wave_sum((double)nonfin);
+  double pr = wave_sum((double)prims);
+  if (lane == 0) {
+    atomicAdd(&J.counters[0], (unsigned long long)ev);
+    atomicAdd(&J.counters[1], (unsigned long long)ka);
+    atomicAdd(&J.counters[2], (unsigned long long)nf);
+    atomicAdd(&J.counters[4], (unsigned long long)pr);
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// reduction of the partial rows (fixed order) and the dipole
+// ------------------------------------------------------------------------------------------------
+__global__ void k_reduce_groups(JobDev J, double2* __restrict__ gsum) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = blockIdx.y;
+  if (n > J.n_steps) return;
+  const int t_lo = g * kReduceGroup;
+  const int t_hi = min(J.n_tiles, t_lo + kReduceGroup);
+  double sr = 0.0, si = 0.0;
+  for (int t = t_lo; t < t_hi; ++t) {
+    const int a = J.tile_n0[t];
+    if (a > n) break;  // tiles are sorted by birth step
+    if (n <= J.tile_last[t]) {
+      double2 v = J.part[J.row_off[t] + (n - a)];
+      sr += v.x;
+      si += v.y;
+    }
+  }
+  gsum[(long long)g * (J.n_steps + 1) + n] = make_double2(sr, si);
+}
+
+__global__ void k_reduce_final(int n_steps, int n_groups, const double2* __restrict__ gsum,
+                               double* __restrict__ d, double* __restrict__ f_out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n > n_steps) return;
+  double sr = 0.0, si = 0.0;
+  for (int g = 0; g < n_groups; ++g) {
+    double2 v = gsum[(long long)g * (n_steps + 1) + n];
+    sr += v.x;
+    si += v.y;
+  }
+  d[n] = -2.0 * sr;
+  if (f_out) {
+    f_out[n] = sr;
+    f_out[n_steps + 1 + n] = si;
+  }
+}
+
+__global__ void k_resample(const double* __restrict__ d, long long n_steps, long long n_out,
+                           double* __restrict__ out) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_out) return;
+  long long num = k * n_steps;
+  long long i = num / n_out;
+  long long rem = num - i * n_out;
+  double frac = (double)rem / (double)n_out;
+  out[k] = (i >= n_steps) ? d[n_steps] : d[i] + frac * (d[i + 1] - d[i]);
+}
+
+// ------------------------------------------------------------------------------------------------
+// trajectories in the caller's order
+// ------------------------------------------------------------------------------------------------
+__global__ void k_scatter_traj(JobDev J, const long long* __restrict__ perm, long long n_traj,
+                               double* __restrict__ y_out, double* __restrict__ c_out,
+                               long long* __restrict__ death_out) {
+  long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= J.n_pad) return;
+  long long o = perm[s];
+  if (o < 0) return;
+  if (y_out)
+    for (int c = 0; c < kNY; ++c) y_out[c * n_traj + o] = J.y[c * J.n_pad + s];
+  if (c_out) {
+    c_out[o] = J.aux[s];
+    c_out[n_traj + o] = J.aux[J.n_pad + s];
+  }
+  if (death_out) death_out[o] = J.death[s];
+}
+
+// ------------------------------------------------------------------------------------------------
+// spectrum: Hann window and direct Fourier sum with exact index reduction k n mod n_fft
+// ------------------------------------------------------------------------------------------------
+__global__ void k_window(const double* __restrict__ d, long long n, long long n_fft, double t_first,
+                         double dt, double tau_h, double* __restrict__ xw, double2* __restrict__ tw) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_fft) return;
+  double v = 0.0;
+  if (i < n) {
+    double t = t_first + (double)i * dt;
+    double win = fabs(t) >= tau_h ? 0.0 : 0.5 * (1.0 + cos(M_PI * t / tau_h));
+    v = d[i] * win;
+  }
+  xw[i] = v;
+  double s, c;
+  sincospi(2.0 * (double)i / (double)n_fft, &s, &c);
+  tw[i] = make_double2(c, s);
+}
+
+__global__ __launch_bounds__(256) void k_dft(const double* __restrict__ xw, const double2* __restrict__ tw,
+                                             long long n, long long n_fft, double t_first, double dt,
+                                             double* __restrict__ omega_out, double* __restrict__ power_out,
+                                             double* __restrict__ x_out) {
+  __shared__ double xs[1024];
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nk = n_fft / 2 + 1;
+  double sr = 0.0, si = 0.0;
+  long long m = 0;  // k * i mod n_fft
+  const long long kk = k < nk ? k : 0;
+  for (long long base = 0; base < n; base += 1024) {
+    const int cnt = (int)min((long long)1024, n - base);
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) xs[i] = xw[base + i];
+    __syncthreads();
+    double cr = 0.0, ci = 0.0;
+    for (int i = 0; i < cnt; ++i) {
+      double2 t = tw[m];
+      cr = SFHK_FMA(xs[i], t.x, cr);
+      ci = SFHK_FMA(xs[i], t.y, ci);
+      m += kk;
+      if (m >= n_fft) m -= n_fft;
+    }
+    sr += cr;
+    si += ci;
+  }
+  if (k >= nk) return;
+  const double omega = 2.0 * M_PI * (double)k / ((double)n_fft * dt);
+  double s, c;
+  sincos(omega * t_first, &s, &c);
+  const double xr = dt * (sr * c - si * s);
+  const double xi = dt * (sr * s + si * c);
+  if (omega_out) omega_out[k] = omega;
+  if (power_out) power_out[k] = xr * xr + xi * xi;
+  if (x_out) {
+    x_out[2 * k] = xr;
+    x_out[2 * k + 1] = xi;
+  }
+}
+
+__global__ void k_exp_cr(const double* __restrict__ x, double* __restrict__ y, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = exp_cr(x[i]);
+}
+
+}  // namespace
+
+// ================================================================================================
+// host runtime
+// ================================================================================================
+struct sfhk_ctx {
+  int device;
+  size_t budget;
+  size_t in_use = 0;
+  std::mutex mu;
+};
+
+struct sfhk_job {
+  sfhk_ctx* ctx = nullptr;
+  JobDev host{};               // host copy of the device descriptor
+  JobDev* dev = nullptr;       // device copy
+  int kind = 0;
+  int precision = 0;
+  long long n_traj = 0;
+  long long n_out = 0;
+  long long* perm = nullptr;   // [n_pad] sorted slot -> original index (-1: padding)
+  double* dbuf = nullptr;      // [n_steps+1] dipole on the step grid
+  double2* gsum = nullptr;     // [n_groups][n_steps+1]
+  size_t bytes = 0;
+  std::vector<void*> allocs;
+  std::vector<int> tile_n0_host;
+  long long steps_done = 0;    // steps requested so far (uniform across tiles)
+  bool done = false;
+};
+
+namespace {
+
+size_t footprint_parts(long long n_traj, long long n_steps, long long n_out,
+                       const std::vector<int>* tile_n0, long long* part_elems) {
+  long long n_pad = (n_traj + kTile - 1) / kTile * kTile;
+  long long n_tiles = n_pad / kTile;
+  long long pe = 0;
+  if (tile_n0) {
+    for (int a : *tile_n0) pe += n_steps - a + 1;
+  } else {
+    pe = n_tiles * (n_steps + 1);  // upper bound
+  }
+  if (part_elems) *part_elems = pe;
+  long long n_groups = (n_tiles + kReduceGroup - 1) / kReduceGroup;
+  size_t b = 0;
+  b += (size_t)n_pad * kNY * 8 + (size_t)n_pad * 5 * 8 + (size_t)n_pad * 8 * 2;  // y, aux, n0+death, perm
+  b += (size_t)n_tiles * (4 * 3 + 8);
+  b += (size_t)pe * 16;
+  b += (size_t)(2 * n_steps + 1) * 8;
+  b += (size_t)(n_steps + 1) * 8 + (size_t)n_groups * (n_steps + 1) * 16;
+  b += 64;
+  (void)n_out;
+  return b;
+}
+
+template <typename T>
+sfhk_status job_alloc(sfhk_job* j, T** p, size_t count) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(T) + 16);
+  if (e != hipSuccess) return fail(SFHK_E_NOMEM, "hipMalloc failed for a job buffer");
+  j->allocs.push_back(q);
+  *p = (T*)q;
+  return SFHK_OK;
+}
+
+void job_free(sfhk_job* j) {
+  for (void* p : j->allocs) (void)hipFree(p);
+  j->allocs.clear();
+}
+
+int blocks_for(long long n, int t) { return (int)((n + t - 1) / t); }
+
+sfhk_status launch_propagate(sfhk_job* j, int n_tiles_unfinished, int max_steps, hipStream_t st) {
+  dim3 grid(n_tiles_unfinished), block(kTile);
+  switch (j->kind) {
+    case SFHK_POT_NONE:
+      hipLaunchKernelGGL(k_propagate_fp64<POT_NONE>, grid, block, 0, st, j->dev, max_steps);
+      break;
+    case SFHK_POT_SOFTCORE:
+      hipLaunchKernelGGL(k_propagate_fp64<POT_SOFTCORE>, grid, block, 0, st, j->dev, max_steps);
+      break;
+    case SFHK_POT_SCREENED:
+      hipLaunchKernelGGL(k_propagate_fp64<POT_SCREENED>, grid, block, 0, st, j->dev, max_steps);
+      break;
+    case SFHK_POT_HARMONIC:
+      hipLaunchKernelGGL(k_propagate_fp64<POT_HARMONIC>, grid, block, 0, st, j->dev, max_steps);
+      break;
+    default:
+      return fail(SFHK_E_INVALID, "unknown potential kind");
+  }
+  HIP_TRY(hipGetLastError());
+  return SFHK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sfhk_last_error(void) { return g_err.c_str(); }
+
+const char* sfhk_status_string(sfhk_status s) {
+  switch (s) {
+    case SFHK_OK: return "ok";
+    case SFHK_E_INVALID: return "invalid argument";
+    case SFHK_E_NOMEM: return "out of device memory";
+    case SFHK_E_DEVICE: return "HIP runtime error";
+    case SFHK_E_NOT_DONE: return "not done";
+    case SFHK_E_BUDGET: return "HBM budget exceeded";
+  }
+  return "unknown status";
+}
+
+sfhk_status sfhk_ctx_create(int device, size_t hbm_budget_bytes, sfhk_ctx** out) {
+  if (!out) return fail(SFHK_E_INVALID, "out is NULL");
+  int n = 0;
+  HIP_TRY(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(SFHK_E_INVALID, "device index out of range");
+  HIP_TRY(hipSetDevice(device));
+  sfhk_ctx* c = new sfhk_ctx();
+  c->device = device;
+  c->budget = hbm_budget_bytes;
+  *out = c;
+  return SFHK_OK;
+}
+
+void sfhk_ctx_destroy(sfhk_ctx* ctx) { delete ctx; }
+
+size_t sfhk_ctx_bytes_in_use(const sfhk_ctx* ctx) { return ctx ? ctx->in_use : 0; }
+
+size_t sfhk_job_footprint(int64_t n_traj, int64_t n_steps, int64_t n_out, int32_t precision) {
+  (void)precision;
+  if (n_traj < 1 || n_steps < 1) return 0;
+  return footprint_parts(n_traj, n_steps, n_out, nullptr, nullptr);
+}
+
+int64_t sfhk_job_n_out(const sfhk_job* job) {
+  if (!job) return 0;
+  return job->n_out > 0 ? job->n_out : (int64_t)job->host.n_steps + 1;
+}
+
+sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk_ground* ground,
+                            const sfhk_grid* grid, const sfhk_params* params, int64_t n_traj,
+                            const double* t0, const double* q0, const double* p0, const double* w,
+                            void* stream, sfhk_job** out) {
+  if (!ctx || !pot || !ground || !grid || !params || !t0 || !q0 || !p0 || !out)
+    return fail(SFHK_E_INVALID, "NULL argument");
+  if (!(params->gamma > 0.0)) return fail(SFHK_E_INVALID, "gamma must be > 0");
+  if (!(grid->h > 0.0)) return fail(SFHK_E_INVALID, "h must be > 0");
+  if (grid->n_steps < 1 || grid->n_steps > (1LL << 30)) return fail(SFHK_E_INVALID, "n_steps out of range");
+  if (!grid->e_half) return fail(SFHK_E_INVALID, "e_half is NULL");
+  if (n_traj < 1 || n_traj > (1LL << 31)) return fail(SFHK_E_INVALID, "n_traj out of range");
+  if (ground->l != 0 && ground->l != 1) return fail(SFHK_E_INVALID, "ground-state l must be 0 or 1");
+  if (ground->n_prim < 1 || ground->n_prim > SFHK_MAX_PRIM || !ground->alpha || !ground->coef)
+    return fail(SFHK_E_INVALID, "n_prim must be in 1..SFHK_MAX_PRIM with alpha/coef given");
+  if (pot->kind < SFHK_POT_NONE || pot->kind > SFHK_POT_HARMONIC)
+    return fail(SFHK_E_INVALID, "unknown potential kind");
+  if (pot->kind == SFHK_POT_SCREENED && !(pot->r_scr > 0.0))
+    return fail(SFHK_E_INVALID, "r_scr must be > 0");
+  if (params->precision != SFHK_FP64 && params->precision != SFHK_FP32_MIXED)
+    return fail(SFHK_E_INVALID, "unknown precision");
+  if (params->n_out < 0) return fail(SFHK_E_INVALID, "n_out must be >= 0");
+  for (int j = 0; j < ground->n_prim; ++j)
+    if (!(ground->alpha[j] > 0.0)) return fail(SFHK_E_INVALID, "GTO exponents must be > 0");
+
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const long long N = n_traj;
+  const int NS = (int)grid->n_steps;
+
+  // birth steps on the host: nearest grid step, ties to the lower one (same arithmetic as the
+  // definition: u = (t0 - t_a)/h, n0 = ceil(u - 1/2))
+  std::vector<double> t0h(N);
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipMemcpy(t0h.data(), t0, N * sizeof(double), hipMemcpyDeviceToHost));
+  std::vector<int> n0h(N);
+  const double t_b = grid->t_a + (double)NS * grid->h;
+  for (long long i = 0; i < N; ++i) {
+    double t = t0h[i];
+    if (!(t >= grid->t_a - 0.5 * grid->h && t <= t_b + 0.5 * grid->h))
+      return fail(SFHK_E_INVALID, "t0[" + std::to_string(i) + "] outside the time grid");
+    double u = (t - grid->t_a) / grid->h;
+    double nn = std::ceil(u - 0.5);
+    if (!(nn >= 0.0)) nn = 0.0;
+    if (nn > (double)NS) nn = (double)NS;
+    n0h[i] = (int)nn;
+  }
+  std::vector<long long> order(N);
+  std::iota(order.begin(), order.end(), 0LL);
+  std::stable_sort(order.begin(), order.end(), [&](long long a, long long b) { return n0h[a] < n0h[b]; });
+  const long long n_pad = (N + kTile - 1) / kTile * kTile;
+  const int n_tiles = (int)(n_pad / kTile);
+  std::vector<long long> perm(n_pad, -1);
+  std::vector<int> n0s(n_pad, NS + 1);
+  for (long long s = 0; s < N; ++s) {
+    perm[s] = order[s];
+    n0s[s] = n0h[order[s]];
+  }
+  std::vector<int> tile_n0(n_tiles), tile_next(n_tiles), tile_last(n_tiles);
+  std::vector<long long> row_off(n_tiles);
+  long long off = 0;
+  for (int t = 0; t < n_tiles; ++t) {
+    tile_n0[t] = n0s[(long long)t * kTile];
+    tile_next[t] = tile_n0[t];
+    tile_last[t] = tile_n0[t] - 1;
+    row_off[t] = off;
+    off += NS - tile_n0[t] + 1;
+  }
+  long long part_elems = 0;
+  size_t bytes = footprint_parts(N, NS, params->n_out, &tile_n0, &part_elems);
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->budget && ctx->in_use + bytes > ctx->budget)
+      return fail(SFHK_E_BUDGET, "job needs " + std::to_string(bytes) + " bytes; budget left " +
+                                     std::to_string(ctx->budget - ctx->in_use));
+    ctx->in_use += bytes;
+  }
+
+  sfhk_job* j = new sfhk_job();
+  j->ctx = ctx;
+  j->kind = pot->kind;
+  j->precision = params->precision;
+  j->n_traj = N;
+  j->n_out = params->n_out;
+  j->bytes = bytes;
+  j->tile_n0_host = tile_n0;
+  JobDev& H = j->host;
+  H.pot = {pot->z_inf, pot->z_in, pot->r_scr, pot->soft2, pot->omega_ho};
+  const double g = params->gamma;
+  H.gto.l = ground->l;
+  H.gto.n_prim = ground->n_prim;
+  for (int k = 0; k < ground->n_prim; ++k) {
+    const double a = ground->alpha[k];
+    const double ga = g + a;
+    H.gto.A[k] = 1.0 / (4.0 * ga);
+    H.gto.B[k] = a * g / ga;
+    H.gto.D[k] = a / ga;
+    H.gto.N[k] = ground->coef[k] * std::pow(ga, ground->l == 0 ? -2.5 : -3.5);
+    H.gto.G2[k] = 2.0 * ga;
+  }
+  H.gto.two_gamma = 2.0 * g;
+  H.gto.ip = ground->ip;
+  H.gamma = g;
+  H.inv4g = 1.0 / (4.0 * g);
+  H.kay2 = params->kay_max * params->kay_max;
+  H.cut = params->overlap_cut;
+  H.t_a = grid->t_a;
+  H.h = grid->h;
+  H.h2 = 0.5 * grid->h;
+  H.h6 = grid->h / 6.0;
+  H.n_steps = NS;
+  H.n_tiles = n_tiles;
+  H.n_pad = n_pad;
+
+  auto cleanup = [&](sfhk_status s) {
+    job_free(j);
+    {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      ctx->in_use -= bytes;
+    }
+    delete j;
+    return s;
+  };
+  sfhk_status rc;
+  double* e_half = nullptr;
+  if ((rc = job_alloc(j, &e_half, 2 * (size_t)NS + 1)) || (rc = job_alloc(j, &H.y, (size_t)n_pad * kNY)) ||
+      (rc = job_alloc(j, &H.aux, (size_t)n_pad * 5)) || (rc = job_alloc(j, &H.n0, (size_t)n_pad)) ||
+      (rc = job_alloc(j, &H.death, (size_t)n_pad)) || (rc = job_alloc(j, &H.tile_n0, (size_t)n_tiles)) ||
+      (rc = job_alloc(j, &H.tile_next, (size_t)n_tiles)) || (rc = job_alloc(j, &H.tile_last, (size_t)n_tiles)) ||
+      (rc = job_alloc(j, &H.row_off, (size_t)n_tiles)) || (rc = job_alloc(j, &H.part, (size_t)part_elems)) ||
+      (rc = job_alloc(j, &H.counters, 8)) || (rc = job_alloc(j, &j->perm, (size_t)n_pad)) ||
+      (rc = job_alloc(j, &j->dbuf, (size_t)NS + 1)) ||
+      (rc = job_alloc(j, &j->gsum, (size_t)((n_tiles + kReduceGroup - 1) / kReduceGroup) * (NS + 1))) ||
+      (rc = job_alloc(j, &j->dev, 1)))
+    return cleanup(rc);
+  H.e_half = e_half;
+#define TRY_C(expr)                                                              \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess) return cleanup(fail(SFHK_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_))); \
+  } while (0)
+  TRY_C(hipMemcpyAsync(e_half, grid->e_half, (2 * (size_t)NS + 1) * sizeof(double), hipMemcpyDeviceToDevice, st));
+  TRY_C(hipMemcpyAsync(j->perm, perm.data(), n_pad * sizeof(long long), hipMemcpyHostToDevice, st));
+  TRY_C(hipMemcpyAsync(H.n0, n0s.data(), n_pad * sizeof(int), hipMemcpyHostToDevice, st));
+  TRY_C(hipMemcpyAsync(H.tile_n0, tile_n0.data(), n_tiles * sizeof(int), hipMemcpyHostToDevice, st));
+  TRY_C(hipMemcpyAsync(H.tile_next, tile_next.data(), n_tiles * sizeof(int), hipMemcpyHostToDevice, st));
+  TRY_C(hipMemcpyAsync(H.tile_last, tile_last.data(), n_tiles * sizeof(int), hipMemcpyHostToDevice, st));
+  TRY_C(hipMemcpyAsync(H.row_off, row_off.data(), n_tiles * sizeof(long long), hipMemcpyHostToDevice, st));
+  TRY_C(hipMemsetAsync(H.counters, 0, 8 * sizeof(unsigned long long), st));
+  TRY_C(hipMemcpyAsync(j->dev, &H, sizeof(JobDev), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_init, dim3(blocks_for(n_pad, 256)), dim3(256), 0, st, H, j->perm, N, q0, p0, w);
+  TRY_C(hipGetLastError());
+  // the host vectors above are about to go out of scope: finish the copies before returning
+  TRY_C(hipStreamSynchronize(st));
+#undef TRY_C
+  *out = j;
+  return SFHK_OK;
+}
+
+void sfhk_job_destroy(sfhk_job* job) {
+  if (!job) return;
+  (void)hipSetDevice(job->ctx->device);
+  (void)hipDeviceSynchronize();
+  job_free(job);
+  {
+    std::lock_guard<std::mutex> lk(job->ctx->mu);
+    job->ctx->in_use -= job->bytes;
+  }
+  delete job;
+}
+
+// number of tiles that still have steps left after `done` steps have been requested
+static int unfinished_tiles(const sfhk_job* j, long long done) {
+  const int NS = j->host.n_steps;
+  // tiles are sorted by birth step ascending: a tile with birth a is finished once a + done > NS
+  const std::vector<int>& a = j->tile_n0_host;
+  int lo = 0, hi = (int)a.size();
+  while (lo < hi) {
+    int mid = (lo + hi) / 2;
+    if ((long long)a[mid] + done <= NS) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+sfhk_status sfhk_propagate(sfhk_job* job, int64_t max_steps, void* stream) {
+  if (!job) return fail(SFHK_E_INVALID, "job is NULL");
+  if (job->done) return SFHK_OK;
+  HIP_TRY(hipSetDevice(job->ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int NS = job->host.n_steps;
+  const int nt = unfinished_tiles(job, job->steps_done);
+  if (nt > 0) {
+    int ms = (max_steps <= 0 || max_steps > NS + 1) ? 0 : (int)max_steps;
+    sfhk_status rc = launch_propagate(job, nt, ms, st);
+    if (rc) return rc;
+  }
+  job->steps_done += (max_steps <= 0) ? (long long)NS + 1 : max_steps;
+  if (unfinished_tiles(job, job->steps_done) == 0) {
+    job->done = true;
+    return SFHK_OK;
+  }
+  return SFHK_E_NOT_DONE;
+}
+
+sfhk_status sfhk_propagate_many(sfhk_job* const* jobs, int32_t n_jobs, int64_t max_steps, void* stream) {
+  if (!jobs || n_jobs < 0) return fail(SFHK_E_INVALID, "bad job list");
+  sfhk_status agg = SFHK_OK;
+  for (int i = 0; i < n_jobs; ++i) {
+    sfhk_status rc = sfhk_propagate(jobs[i], max_steps, stream);
+    if (rc == SFHK_E_NOT_DONE) agg = SFHK_E_NOT_DONE;
+    else if (rc != SFHK_OK) return rc;
+  }
+  return agg;
+}
+
+sfhk_status sfhk_dipole(sfhk_job* job, double* d_out, double* f_out, void* stream) {
+  if (!job || !d_out) return fail(SFHK_E_INVALID, "NULL argument");
+  if (!job->done) return fail(SFHK_E_NOT_DONE, "job is not finished");
+  HIP_TRY(hipSetDevice(job->ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const JobDev& H = job->host;
+  const int n_groups = (H.n_tiles + kReduceGroup - 1) / kReduceGroup;
+  dim3 g1(blocks_for(H.n_steps + 1, 256), n_groups);
+  hipLaunchKernelGGL(k_reduce_groups, g1, dim3(256), 0, st, H, job->gsum);
+  HIP_TRY(hipGetLastError());
+  double* d_step = job->n_out > 0 ? job->dbuf : d_out;
+  hipLaunchKernelGGL(k_reduce_final, dim3(blocks_for(H.n_steps + 1, 256)), dim3(256), 0, st,
+                     H.n_steps, n_groups, (const double2*)job->gsum, d_step, f_out);
+  HIP_TRY(hipGetLastError());
+  if (job->n_out > 0) {
+    hipLaunchKernelGGL(k_resample, dim3(blocks_for(job->n_out, 256)), dim3(256), 0, st,
+                       (const double*)job->dbuf, (long long)H.n_steps, (long long)job->n_out, d_out);
+    HIP_TRY(hipGetLastError());
+  }
+  return SFHK_OK;
+}
+
+sfhk_status sfhk_spectrum(const double* d, int64_t n, double t_first, double dt, double tau_h,
+                          int64_t n_fft, double* omega_out, double* power_out, double* x_out,
+                          void* stream) {
+  if (n_fft == 0) n_fft = n;
+  if (!d || n < 1 || n_fft < n || !(dt > 0.0) || !(tau_h > 0.0))
+    return fail(SFHK_E_INVALID, "spectrum: need d, n >= 1, n_fft >= n, dt > 0, tau_h > 0");
+  hipStream_t st = (hipStream_t)stream;
+  double* xw = nullptr;
+  double2* tw = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&xw, n_fft * sizeof(double), st));
+  HIP_TRY(hipMallocAsync((void**)&tw, n_fft * sizeof(double2), st));
+  hipLaunchKernelGGL(k_window, dim3(blocks_for(n_fft, 256)), dim3(256), 0, st, d, (long long)n,
+                     (long long)n_fft, t_first, dt, tau_h, xw, tw);
+  HIP_TRY(hipGetLastError());
+  const long long nk = n_fft / 2 + 1;
+  hipLaunchKernelGGL(k_dft, dim3(blocks_for(nk, 256)), dim3(256), 0, st, (const double*)xw,
+                     (const double2*)tw, (long long)n_fft, (long long)n_fft, t_first, dt, omega_out,
+                     power_out, x_out);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipFreeAsync(xw, st));
+  HIP_TRY(hipFreeAsync(tw, st));
+  return SFHK_OK;
+}
+
+sfhk_status sfhk_job_stats(sfhk_job* job, sfhk_stats* out, void* stream) {
+  if (!job || !out) return fail(SFHK_E_INVALID, "NULL argument");
+  HIP_TRY(hipSetDevice(job->ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  unsigned long long c[8] = {0};
+  HIP_TRY(hipMemcpyAsync(c, job->host.counters, sizeof(c), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  out->n_traj = job->n_traj;
+  out->n_steps = job->host.n_steps;
+  out->steps_evaluated = (int64_t)c[0];
+  out->kay_removed = (int64_t)c[1];
+  out->nonfinite_removed = (int64_t)c[2];
+  out->steps_fp64 = (int64_t)c[3];
+  out->prims_evaluated = (int64_t)c[4];
+  out->tiles_total = job->host.n_tiles;
+  out->tiles_done = job->host.n_tiles - unfinished_tiles(job, job->steps_done);
+  return SFHK_OK;
+}
+
+sfhk_status sfhk_job_trajectories(sfhk_job* job, double* y_out, double* c_out, int64_t* death_out,
+                                  void* stream) {
+  if (!job) return fail(SFHK_E_INVALID, "job is NULL");
+  HIP_TRY(hipSetDevice(job->ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_scatter_traj, dim3(blocks_for(job->host.n_pad, 256)), dim3(256), 0, st,
+                     job->host, (const long long*)job->perm, (long long)job->n_traj, y_out, c_out,
+                     (long long*)death_out);
+  HIP_TRY(hipGetLastError());
+  return SFHK_OK;
+}
+
+sfhk_status sfhk_exp_cr(const double* x, double* y, int64_t n, void* stream) {
+  if (!x || !y || n < 0) return fail(SFHK_E_INVALID, "bad exp_cr arguments");
+  if (n == 0) return SFHK_OK;
+  hipLaunchKernelGGL(k_exp_cr, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, x, y, (long long)n);
+  HIP_TRY(hipGetLastError());
+  return SFHK_OK;
+}
+
+}  // extern "C"

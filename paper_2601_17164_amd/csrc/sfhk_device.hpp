@@ -1,0 +1,395 @@
+// sfhk_device.hpp -- device arithmetic of the SFHK hot path (gfx950, FP64).
+//
+// Rounding contract. Trajectories of the near-core workloads are chaotic: one rounding difference
+// in q, p or the monodromy grows to O(1) within the pulse. Every operation on the trajectory path
+// (equations of motion, RK4 combination, det G, Kay test, square-root branch) is therefore written
+// as an explicit sequence of IEEE-754 binary64 operations with round-to-nearest-even: +, -, *, /,
+// sqrt, and __builtin_fma where a fused multiply-add is part of the sequence. This file must be
+// compiled with -ffp-contract=off so the compiler adds no fusion of its own. gfx950's binary64
+// division and square root are correctly rounded, and the screened potential's exponential is the
+// correctly rounded exp below, so a CPU implementation of the same sequence agrees bit for bit.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "exp_table.inc"
+
+#define SFHK_FMA(a, b, c) __builtin_fma((a), (b), (c))
+
+namespace sfhk {
+
+// ----------------------------------------------------------------------------------------------
+// correctly rounded exp(x) (table-driven reduction of Tang 1989, double-double evaluation with a
+// rounding test; a second, more accurate double-double evaluation when the first cannot decide)
+// ----------------------------------------------------------------------------------------------
+struct dd {
+  double hi, lo;
+};
+
+__device__ __forceinline__ dd two_prod(double a, double b) {
+  double p = a * b;
+  return {p, SFHK_FMA(a, b, -p)};
+}
+__device__ __forceinline__ dd fast_two_sum(double a, double b) {  // |a| >= |b|
+  double s = a + b;
+  return {s, b - (s - a)};
+}
+__device__ __forceinline__ dd two_sum(double a, double b) {
+  double s = a + b;
+  double bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+__device__ __forceinline__ dd dd_mul(dd a, dd b) {
+  dd p = two_prod(a.hi, b.hi);
+  double t = SFHK_FMA(a.hi, b.lo, a.lo * b.hi) + p.lo;
+  return fast_two_sum(p.hi, t);
+}
+__device__ __forceinline__ dd dd_add(dd a, dd b) {
+  dd s = two_sum(a.hi, b.hi);
+  dd t = two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = fast_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return fast_two_sum(s.hi, s.lo);
+}
+
+// Round y = (s + t) * 2^m, known to relative accuracy err_rel, to binary64. Returns false when
+// the error interval straddles a rounding boundary (the caller then needs a better y).
+__device__ __forceinline__ bool exp_round(double s, double t, int m, double err_rel, double* out) {
+  double e = err_rel * s;
+  if (m > -1022 || (m == -1022 && s >= 1.0)) {  // normal result: scaling by 2^m is exact
+    double a = s + (t + e);
+    double b = s + (t - e);
+    if (a != b) return false;
+    *out = ldexp(a, m);
+    return true;
+  }
+  // subnormal result: round y * 2^(m+1074) to an integer count of 2^-1074
+  int K = m + 1074;
+  if (K < -2) {
+    *out = 0.0;
+    return true;
+  }
+  double S1 = ldexp(s, K);  // exact
+  double T1 = ldexp(t, K);
+  double E1 = ldexp(e, K);
+  double n = rint(S1);
+  double d = (S1 - n) + T1;  // in [-0.5 - T1, 0.5 + T1]
+  double ad = fabs(d);
+  if (fabs(ad - 0.5) <= E1 + 0x1p-52) return false;
+  if (ad > 0.5) n += (d > 0.0 ? 1.0 : -1.0);
+  *out = ldexp(n, -1074);
+  return true;
+}
+
+__device__ __noinline__ double exp_cr_slow(double rh, double rl, double th, double tl, int m) {
+  // exp(r) by Horner in double-double to degree 13 (truncation < 2^-120 for |r| < 2^-8.4)
+  dd r = fast_two_sum(rh, rl);
+  dd c = {sfhk_inv_fact[26], sfhk_inv_fact[27]};
+  for (int n = 12; n >= 0; --n) {
+    c = dd_mul(c, r);
+    c = dd_add(c, dd{sfhk_inv_fact[2 * n], sfhk_inv_fact[2 * n + 1]});
+  }
+  dd y = dd_mul(dd{th, tl}, c);
+  double out;
+  if (exp_round(y.hi, y.lo, m, 0x1p-100, &out)) return out;
+  exp_round(y.hi, y.lo, m, 0.0, &out);  // undecidable at 2^-100: nearest of the 106-bit value
+  return out;
+}
+
+__device__ __forceinline__ double exp_cr(double x) {
+  if (!(x <= 709.79)) return x + x;  // +inf for large x, NaN propagates (x + x keeps NaN)
+  if (x < -745.2) return 0.0;
+  double kd = rint(x * SFHK_EXP_INV_L);
+  int k = (int)kd;
+  int j = k & 127;
+  int m = k >> 7;
+  // r = x - k ln2/128 as rh + rl (k*L1, k*L2 exact; x - k*L1 exact)
+  double t1 = SFHK_FMA(-kd, SFHK_EXP_L1, x);
+  double u2 = kd * SFHK_EXP_L2;
+  dd r0 = two_sum(t1, -u2);
+  double rh = r0.hi;
+  double rl = SFHK_FMA(-kd, SFHK_EXP_L3, r0.lo);
+  dd rr = fast_two_sum(rh, rl);
+  rh = rr.hi;
+  rl = rr.lo;
+  // exp(r) - 1 - r_hi ~ r_lo + r_hi r_lo + r_hi^2 (1/2 + r_hi/6 + ... + r_hi^4/720)
+  double c = SFHK_FMA(rh, 0x1.6c16c16c16c17p-10, 0x1.1111111111111p-7);
+  c = SFHK_FMA(rh, c, 0x1.5555555555555p-5);
+  c = SFHK_FMA(rh, c, 0x1.5555555555555p-3);
+  c = SFHK_FMA(rh, c, 0.5);
+  double p = (rh * rh) * c;
+  double lo = rl + SFHK_FMA(rh, rl, p);
+  dd e1 = fast_two_sum(1.0, rh);
+  double el = e1.lo + lo;
+  double th = sfhk_exp_tab[2 * j];
+  double tl = sfhk_exp_tab[2 * j + 1];
+  dd y = two_prod(th, e1.hi);
+  double yl = y.lo + SFHK_FMA(th, el, tl * e1.hi);
+  dd s = fast_two_sum(y.hi, yl);
+  double out;
+  if (exp_round(s.hi, s.lo, m, 0x1p-65, &out)) return out;
+  return exp_cr_slow(rh, rl, th, tl, m);
+}
+
+// ----------------------------------------------------------------------------------------------
+// atomic model potential V_a (App. A): central, grad V = g q, Hess V = g I + c q q^T
+// ----------------------------------------------------------------------------------------------
+enum PotKind : int { POT_NONE = 0, POT_SOFTCORE = 1, POT_SCREENED = 2, POT_HARMONIC = 3 };
+
+struct PotParams {
+  double z_inf, z_in, r_scr, soft2, omega_ho;
+};
+
+template <int KIND>
+__device__ __forceinline__ void pot_gc(const PotParams& P, double x, double y, double z, double& V,
+                                       double& g, double& c) {
+  double r2 = x * x;
+  r2 = SFHK_FMA(y, y, r2);
+  r2 = SFHK_FMA(z, z, r2);
+  if constexpr (KIND == POT_SOFTCORE) {
+    // V = -Z u, u = (r^2 + a)^(-1/2); dV/dr / r = Z u^3; (V'' - V'/r)/r^2 = -3 Z u^5
+    double s = r2 + P.soft2;
+    double rho = sqrt(s);
+    double u = 1.0 / rho;
+    double u2 = u * u;
+    double u3 = u2 * u;
+    double u5 = u3 * u2;
+    V = -(P.z_inf * u);
+    g = P.z_inf * u3;
+    c = (-3.0 * P.z_inf) * u5;
+  } else if constexpr (KIND == POT_SCREENED) {
+    // V = -Z(r)/rho, Z = z_inf + z_in exp(-r/r_scr), rho = (r^2 + a)^(1/2)
+    double r = sqrt(r2);
+    double s = r2 + P.soft2;
+    double rho = sqrt(s);
+    double ir = 1.0 / rho;
+    double ir2 = ir * ir;
+    double ir3 = ir2 * ir;
+    double e = exp_cr(-(r / P.r_scr));
+    double ez = P.z_in * e;
+    double Z = P.z_inf + ez;
+    double d1 = ez / P.r_scr;  // -Z'
+    double d2 = d1 / P.r_scr;  //  Z''
+    V = -(Z * ir);
+    double vp = SFHK_FMA(Z * r, ir3, d1 * ir);           // V'
+    double w1 = SFHK_FMA(-2.0, r2, P.soft2);             // a - 2 r^2
+    double ta = d2 * ir;
+    double tb = (d1 * r) * ir3;
+    double tc = ((Z * w1) * ir3) * ir2;
+    double vpp = tc - SFHK_FMA(2.0, tb, ta);             // V''
+    if (r > 0.0) {
+      g = vp / r;
+      c = (vpp - g) / r2;
+    } else {
+      g = vpp;
+      c = 0.0;
+    }
+  } else if constexpr (KIND == POT_HARMONIC) {
+    double w2 = P.omega_ho * P.omega_ho;
+    V = (0.5 * w2) * r2;
+    g = w2;
+    c = 0.0;
+  } else {
+    V = 0.0;
+    g = 0.0;
+    c = 0.0;
+  }
+}
+
+struct Hess3 {
+  double h00, h11, h22, h01, h02, h12;
+};
+
+__device__ __forceinline__ Hess3 hess_from(double g, double c, double x, double y, double z) {
+  double cx = c * x, cy = c * y, cz = c * z;
+  Hess3 H;
+  H.h00 = SFHK_FMA(cx, x, g);
+  H.h11 = SFHK_FMA(cy, y, g);
+  H.h22 = SFHK_FMA(cz, z, g);
+  H.h01 = cx * y;
+  H.h02 = cx * z;
+  H.h12 = cy * z;
+  return H;
+}
+
+// (H v)_i with the row order of the contract: H_i0 v0, then + H_i1 v1, then + H_i2 v2
+__device__ __forceinline__ void hess_mv(const Hess3& H, double v0, double v1, double v2, double& t0,
+                                        double& t1, double& t2) {
+  t0 = H.h00 * v0;
+  t0 = SFHK_FMA(H.h01, v1, t0);
+  t0 = SFHK_FMA(H.h02, v2, t0);
+  t1 = H.h01 * v0;
+  t1 = SFHK_FMA(H.h11, v1, t1);
+  t1 = SFHK_FMA(H.h12, v2, t1);
+  t2 = H.h02 * v0;
+  t2 = SFHK_FMA(H.h12, v1, t2);
+  t2 = SFHK_FMA(H.h22, v2, t2);
+}
+
+// ----------------------------------------------------------------------------------------------
+// one classical RK4 step of the 43 ODEs (App. A): qdot = p, pdot = -grad V - E z^,
+// Qdot_j = P_j, Pdot_j = -Hess V Q_j, Sdot = p^2/2 - V - z E. The (q, p, S) stages run first and
+// leave the four stage Hessians; the six monodromy columns then take their RK4 step with them.
+// Every component sees exactly the operation sequence of a plain 43-component RK4:
+//   ys = fma(c, k, y); acc = fma(2, k2, k1); acc = fma(2, k3, acc); acc += k4; y = fma(h/6, acc, y)
+// ----------------------------------------------------------------------------------------------
+struct Traj {
+  double q[3], p[3], S;
+  double M[36];  // 6 columns (Q(3), P(3)): column j = d(q_t, p_t)/d z_j, z = (q0, p0)
+};
+
+template <int KIND>
+__device__ __forceinline__ void qps_rhs(const PotParams& P, const double* q, const double* p,
+                                        double E, double* kp, double& kS, Hess3& H) {
+  double V, g, c;
+  pot_gc<KIND>(P, q[0], q[1], q[2], V, g, c);
+  H = hess_from(g, c, q[0], q[1], q[2]);
+  kp[0] = -(g * q[0]);
+  kp[1] = -(g * q[1]);
+  kp[2] = -SFHK_FMA(g, q[2], E);
+  double p2 = p[0] * p[0];
+  p2 = SFHK_FMA(p[1], p[1], p2);
+  p2 = SFHK_FMA(p[2], p[2], p2);
+  double L = SFHK_FMA(0.5, p2, -V);
+  kS = SFHK_FMA(-q[2], E, L);
+}
+
+template <int KIND>
+__device__ __forceinline__ void rk4_step(const PotParams& P, Traj& T, double ea, double eb, double ec,
+                                         double h, double h2, double h6) {
+  Hess3 H1, H2, H3, H4;
+  {
+    double accq[3], accp[3], accS, ysq[3], ysp[3], ysS, kp[3], kS;
+    // stage 1
+    qps_rhs<KIND>(P, T.q, T.p, ea, kp, kS, H1);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      accq[i] = T.p[i];
+      accp[i] = kp[i];
+      ysq[i] = SFHK_FMA(h2, T.p[i], T.q[i]);
+      ysp[i] = SFHK_FMA(h2, kp[i], T.p[i]);
+    }
+    accS = kS;
+    ysS = SFHK_FMA(h2, kS, T.S);
+    // stage 2
+    qps_rhs<KIND>(P, ysq, ysp, eb, kp, kS, H2);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double kq = ysp[i];
+      accq[i] = SFHK_FMA(2.0, kq, accq[i]);
+      accp[i] = SFHK_FMA(2.0, kp[i], accp[i]);
+      ysq[i] = SFHK_FMA(h2, kq, T.q[i]);
+      ysp[i] = SFHK_FMA(h2, kp[i], T.p[i]);
+    }
+    accS = SFHK_FMA(2.0, kS, accS);
+    ysS = SFHK_FMA(h2, kS, T.S);
+    // stage 3
+    qps_rhs<KIND>(P, ysq, ysp, eb, kp, kS, H3);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double kq = ysp[i];
+      accq[i] = SFHK_FMA(2.0, kq, accq[i]);
+      accp[i] = SFHK_FMA(2.0, kp[i], accp[i]);
+      ysq[i] = SFHK_FMA(h, kq, T.q[i]);
+      ysp[i] = SFHK_FMA(h, kp[i], T.p[i]);
+    }
+    accS = SFHK_FMA(2.0, kS, accS);
+    ysS = SFHK_FMA(h, kS, T.S);
+    (void)ysS;
+    // stage 4
+    qps_rhs<KIND>(P, ysq, ysp, ec, kp, kS, H4);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      accq[i] = accq[i] + ysp[i];
+      accp[i] = accp[i] + kp[i];
+      T.q[i] = SFHK_FMA(h6, accq[i], T.q[i]);
+      T.p[i] = SFHK_FMA(h6, accp[i], T.p[i]);
+    }
+    accS = accS + kS;
+    T.S = SFHK_FMA(h6, accS, T.S);
+  }
+  // monodromy columns
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    double* Q = T.M + 6 * j;
+    double* Pc = Q + 3;
+    double aQ[3], aP[3], sQ[3], sP[3], t[3];
+    hess_mv(H1, Q[0], Q[1], Q[2], t[0], t[1], t[2]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double kP = -t[i];
+      aQ[i] = Pc[i];
+      aP[i] = kP;
+      sQ[i] = SFHK_FMA(h2, Pc[i], Q[i]);
+      sP[i] = SFHK_FMA(h2, kP, Pc[i]);
+    }
+    hess_mv(H2, sQ[0], sQ[1], sQ[2], t[0], t[1], t[2]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double kQ = sP[i], kP = -t[i];
+      aQ[i] = SFHK_FMA(2.0, kQ, aQ[i]);
+      aP[i] = SFHK_FMA(2.0, kP, aP[i]);
+      sQ[i] = SFHK_FMA(h2, kQ, Q[i]);
+      sP[i] = SFHK_FMA(h2, kP, Pc[i]);
+    }
+    hess_mv(H3, sQ[0], sQ[1], sQ[2], t[0], t[1], t[2]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double kQ = sP[i], kP = -t[i];
+      aQ[i] = SFHK_FMA(2.0, kQ, aQ[i]);
+      aP[i] = SFHK_FMA(2.0, kP, aP[i]);
+      sQ[i] = SFHK_FMA(h, kQ, Q[i]);
+      sP[i] = SFHK_FMA(h, kP, Pc[i]);
+    }
+    hess_mv(H4, sQ[0], sQ[1], sQ[2], t[0], t[1], t[2]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      aQ[i] = aQ[i] + sP[i];
+      aP[i] = aP[i] + (-t[i]);
+      Q[i] = SFHK_FMA(h6, aQ[i], Q[i]);
+      Pc[i] = SFHK_FMA(h6, aP[i], Pc[i]);
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------------------------
+// HK prefactor (App. A): G = (M_pp + M_qq)/2 + i (M_pq / (4 gamma) - gamma M_qp), det G by
+// cofactors along the first row; complex product (a b)_re = fma(a.re, b.re, -(a.im b.im)),
+// (a b)_im = fma(a.re, b.im, a.im b.re)
+// ----------------------------------------------------------------------------------------------
+struct cplx {
+  double re, im;
+};
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  return {SFHK_FMA(a.re, b.re, -(a.im * b.im)), SFHK_FMA(a.re, b.im, a.im * b.re)};
+}
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
+
+__device__ __forceinline__ cplx hk_det(const double* M, double gamma, double inv4g) {
+  cplx G[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double mqq = M[6 * k + i], mpq = M[6 * k + 3 + i];
+      double mqp = M[6 * (3 + k) + i], mpp = M[6 * (3 + k) + 3 + i];
+      G[i][k].re = 0.5 * (mpp + mqq);
+      G[i][k].im = SFHK_FMA(mpq, inv4g, -(gamma * mqp));
+    }
+  cplx m0 = csub(cmul(G[1][1], G[2][2]), cmul(G[1][2], G[2][1]));
+  cplx m1 = csub(cmul(G[1][0], G[2][2]), cmul(G[1][2], G[2][0]));
+  cplx m2 = csub(cmul(G[1][0], G[2][1]), cmul(G[1][1], G[2][0]));
+  return cadd(csub(cmul(G[0][0], m0), cmul(G[0][1], m1)), cmul(G[0][2], m2));
+}
+
+// principal square root (cut on the negative real axis), modulus supplied
+__device__ __forceinline__ cplx csqrt_principal(cplx z, double mod) {
+  double t = sqrt(0.5 * (mod + fabs(z.re)));
+  if (t == 0.0) return {0.0, 0.0};
+  if (z.re >= 0.0) return {t, z.im / (2.0 * t)};
+  return {fabs(z.im) / (2.0 * t), copysign(t, z.im)};
+}
+
+}  // namespace sfhk

@@ -1,0 +1,300 @@
+"""Thin ctypes binding of ``libsfhk.so`` (the C ABI declared in ``include/sfhk.h``).
+
+Argument marshalling only: every step of the hot path (trajectory propagation with monodromy and
+action, HK prefactor, Kay removal, dipole integrand, reduction, spectrum) runs in the HIP kernels
+of the library. PyTorch provides device memory and the HIP stream. The library must have been
+built (``python -m paper_2601_17164_amd.build``); importing this module on a machine without it
+raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsfhk.so")
+
+SFHK_OK, SFHK_E_INVALID, SFHK_E_NOMEM, SFHK_E_DEVICE, SFHK_E_NOT_DONE, SFHK_E_BUDGET = (
+    0, -1, -2, -3, -4, -5)
+SFHK_FP64, SFHK_FP32_MIXED = 0, 1
+SFHK_MAX_PRIM = 8
+
+
+class SfhkError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: status {status} ({msg})")
+        self.status = status
+
+
+class _Potential(ct.Structure):
+    _fields_ = [("kind", ct.c_int32), ("z_inf", ct.c_double), ("z_in", ct.c_double),
+                ("r_scr", ct.c_double), ("soft2", ct.c_double), ("omega_ho", ct.c_double)]
+
+
+class _Ground(ct.Structure):
+    _fields_ = [("l", ct.c_int32), ("n_prim", ct.c_int32), ("alpha", ct.POINTER(ct.c_double)),
+                ("coef", ct.POINTER(ct.c_double)), ("ip", ct.c_double)]
+
+
+class _Grid(ct.Structure):
+    _fields_ = [("t_a", ct.c_double), ("h", ct.c_double), ("n_steps", ct.c_int64),
+                ("e_half", ct.c_void_p)]
+
+
+class _Params(ct.Structure):
+    _fields_ = [("gamma", ct.c_double), ("kay_max", ct.c_double), ("overlap_cut", ct.c_double),
+                ("r_fp64", ct.c_double), ("precision", ct.c_int32), ("n_out", ct.c_int64)]
+
+
+class _Stats(ct.Structure):
+    _fields_ = [("n_traj", ct.c_int64), ("n_steps", ct.c_int64), ("steps_evaluated", ct.c_int64),
+                ("steps_fp64", ct.c_int64), ("kay_removed", ct.c_int64),
+                ("nonfinite_removed", ct.c_int64), ("tiles_total", ct.c_int64),
+                ("tiles_done", ct.c_int64), ("prims_evaluated", ct.c_int64)]
+
+
+_lib = None
+
+# exported symbols and their signatures (restype, argtypes)
+_VP = ct.c_void_p
+_SIGS = {
+    "sfhk_ctx_create": (ct.c_int, [ct.c_int, ct.c_size_t, ct.POINTER(_VP)]),
+    "sfhk_ctx_destroy": (None, [_VP]),
+    "sfhk_ctx_bytes_in_use": (ct.c_size_t, [_VP]),
+    "sfhk_job_footprint": (ct.c_size_t, [ct.c_int64, ct.c_int64, ct.c_int64, ct.c_int32]),
+    "sfhk_job_create": (ct.c_int, [_VP, ct.POINTER(_Potential), ct.POINTER(_Ground),
+                                   ct.POINTER(_Grid), ct.POINTER(_Params), ct.c_int64, _VP, _VP,
+                                   _VP, _VP, _VP, ct.POINTER(_VP)]),
+    "sfhk_job_destroy": (None, [_VP]),
+    "sfhk_propagate": (ct.c_int, [_VP, ct.c_int64, _VP]),
+    "sfhk_propagate_many": (ct.c_int, [ct.POINTER(_VP), ct.c_int32, ct.c_int64, _VP]),
+    "sfhk_dipole": (ct.c_int, [_VP, _VP, _VP, _VP]),
+    "sfhk_job_n_out": (ct.c_int64, [_VP]),
+    "sfhk_spectrum": (ct.c_int, [_VP, ct.c_int64, ct.c_double, ct.c_double, ct.c_double,
+                                 ct.c_int64, _VP, _VP, _VP, _VP]),
+    "sfhk_job_stats": (ct.c_int, [_VP, ct.POINTER(_Stats), _VP]),
+    "sfhk_job_trajectories": (ct.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "sfhk_last_error": (ct.c_char_p, []),
+    "sfhk_status_string": (ct.c_char_p, [ct.c_int]),
+    "sfhk_exp_cr": (ct.c_int, [_VP, _VP, ct.c_int64, _VP]),
+}
+
+
+def exported_symbols() -> list:
+    return sorted(_SIGS)
+
+
+def lib():
+    """Load libsfhk.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2601_17164_amd.build` (no CPU fallback exists)")
+        L = ct.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status not in (SFHK_OK, SFHK_E_NOT_DONE):
+        msg = lib().sfhk_last_error().decode(errors="replace")
+        raise SfhkError(status, where, msg)
+    return status
+
+
+def _stream_ptr(stream: Optional[torch.cuda.Stream]):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ct.c_void_p(s.cuda_stream)
+
+
+def _dptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    return ct.c_void_p(t.data_ptr())
+
+
+class Context:
+    """sfhk_ctx: a device and an HBM budget for the jobs it holds."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        h = _VP()
+        _check(lib().sfhk_ctx_create(int(device), int(hbm_budget_bytes), ct.byref(h)),
+               "sfhk_ctx_create")
+        self.handle = h
+        self.device = int(device)
+
+    def bytes_in_use(self) -> int:
+        return int(lib().sfhk_ctx_bytes_in_use(self.handle))
+
+    def close(self):
+        if self.handle:
+            lib().sfhk_ctx_destroy(self.handle)
+            self.handle = _VP()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def job_footprint(n_traj: int, n_steps: int, n_out: int = 0, precision: int = SFHK_FP64) -> int:
+    return int(lib().sfhk_job_footprint(int(n_traj), int(n_steps), int(n_out), int(precision)))
+
+
+@dataclass
+class Stats:
+    n_traj: int
+    n_steps: int
+    steps_evaluated: int
+    steps_fp64: int
+    kay_removed: int
+    nonfinite_removed: int
+    tiles_total: int
+    tiles_done: int
+    prims_evaluated: int
+
+
+class Job:
+    """sfhk_job: one SFHK instance (its trajectories' state, partial sums and field table live in
+    HBM until the job is closed)."""
+
+    def __init__(self, ctx: Context, potential, ground, grid_t_a: float, grid_h: float,
+                 n_steps: int, e_half: torch.Tensor, t0: torch.Tensor, q0: torch.Tensor,
+                 p0: torch.Tensor, w: Optional[torch.Tensor] = None, gamma: float = 0.5,
+                 kay_max: float = 1e30, overlap_cut: float = 60.0, r_fp64: float = 2.0,
+                 precision: int = SFHK_FP64, n_out: int = 0,
+                 stream: Optional[torch.cuda.Stream] = None):
+        alpha = np.ascontiguousarray(ground.alpha, dtype=np.float64)
+        coef = np.ascontiguousarray(ground.coef, dtype=np.float64)
+        pot = _Potential(int(potential.kind), float(potential.z_inf), float(potential.z_in),
+                         float(potential.r_scr), float(potential.soft2), float(potential.omega_ho))
+        gs = _Ground(int(ground.l), len(alpha), alpha.ctypes.data_as(ct.POINTER(ct.c_double)),
+                     coef.ctypes.data_as(ct.POINTER(ct.c_double)), float(ground.ip))
+        grid = _Grid(float(grid_t_a), float(grid_h), int(n_steps), _dptr(e_half))
+        prm = _Params(float(gamma), float(kay_max), float(overlap_cut), float(r_fp64),
+                      int(precision), int(n_out))
+        n = int(t0.shape[0])
+        for name, t, shp in (("t0", t0, (n,)), ("q0", q0, (3, n)), ("p0", p0, (3, n))):
+            if tuple(t.shape) != shp or t.dtype != torch.float64:
+                raise ValueError(f"{name} must be float64 of shape {shp}")
+        if w is not None and (tuple(w.shape) != (2, n) or w.dtype != torch.float64):
+            raise ValueError("w must be float64 of shape (2, n) (re, im)")
+        h = _VP()
+        _check(lib().sfhk_job_create(ctx.handle, ct.byref(pot), ct.byref(gs), ct.byref(grid),
+                                     ct.byref(prm), n, _dptr(t0), _dptr(q0), _dptr(p0), _dptr(w),
+                                     _stream_ptr(stream), ct.byref(h)), "sfhk_job_create")
+        self.handle = h
+        self.ctx = ctx
+        self.n_traj = n
+        self.n_steps = int(n_steps)
+        self.t_a = float(grid_t_a)
+        self.h = float(grid_h)
+
+    @property
+    def n_out(self) -> int:
+        return int(lib().sfhk_job_n_out(self.handle))
+
+    def propagate(self, max_steps: int = 0, stream=None) -> bool:
+        """Returns True when every trajectory reached the end of the grid."""
+        rc = _check(lib().sfhk_propagate(self.handle, int(max_steps), _stream_ptr(stream)),
+                    "sfhk_propagate")
+        return rc == SFHK_OK
+
+    def dipole(self, want_f: bool = False, stream=None):
+        dev = torch.device("cuda", self.ctx.device)
+        d = torch.empty(self.n_out, dtype=torch.float64, device=dev)
+        f = torch.empty(2, self.n_steps + 1, dtype=torch.float64, device=dev) if want_f else None
+        _check(lib().sfhk_dipole(self.handle, _dptr(d), _dptr(f), _stream_ptr(stream)),
+               "sfhk_dipole")
+        return (d, f) if want_f else d
+
+    def stats(self, stream=None) -> Stats:
+        s = _Stats()
+        _check(lib().sfhk_job_stats(self.handle, ct.byref(s), _stream_ptr(stream)),
+               "sfhk_job_stats")
+        return Stats(s.n_traj, s.n_steps, s.steps_evaluated, s.steps_fp64, s.kay_removed,
+                     s.nonfinite_removed, s.tiles_total, s.tiles_done,
+                     s.prims_evaluated)
+
+    def trajectories(self, stream=None):
+        dev = torch.device("cuda", self.ctx.device)
+        y = torch.empty(43, self.n_traj, dtype=torch.float64, device=dev)
+        c = torch.empty(2, self.n_traj, dtype=torch.float64, device=dev)
+        death = torch.empty(self.n_traj, dtype=torch.int64, device=dev)
+        _check(lib().sfhk_job_trajectories(self.handle, _dptr(y), _dptr(c), _dptr(death),
+                                           _stream_ptr(stream)), "sfhk_job_trajectories")
+        return y, c, death
+
+    def close(self):
+        if self.handle:
+            lib().sfhk_job_destroy(self.handle)
+            self.handle = _VP()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def propagate_many(jobs: Sequence[Job], max_steps: int = 0, stream=None) -> bool:
+    arr = (_VP * len(jobs))(*[j.handle for j in jobs])
+    rc = _check(lib().sfhk_propagate_many(arr, len(jobs), int(max_steps), _stream_ptr(stream)),
+                "sfhk_propagate_many")
+    return rc == SFHK_OK
+
+
+def spectrum(d: torch.Tensor, t_first: float, dt: float, tau_h: float, n_fft: int = 0,
+             stream=None):
+    """Hann-windowed Fourier transform of d on the device: returns (omega, power, X complex)."""
+    n = int(d.shape[0])
+    nf = int(n_fft) if n_fft else n
+    nk = nf // 2 + 1
+    om = torch.empty(nk, dtype=torch.float64, device=d.device)
+    pw = torch.empty(nk, dtype=torch.float64, device=d.device)
+    x = torch.empty(nk, 2, dtype=torch.float64, device=d.device)
+    _check(lib().sfhk_spectrum(_dptr(d), n, float(t_first), float(dt), float(tau_h), nf,
+                               _dptr(om), _dptr(pw), _dptr(x), _stream_ptr(stream)),
+           "sfhk_spectrum")
+    return om, pw, torch.view_as_complex(x)
+
+
+def exp_cr(x: torch.Tensor, stream=None) -> torch.Tensor:
+    y = torch.empty_like(x)
+    _check(lib().sfhk_exp_cr(_dptr(x), _dptr(y), int(x.numel()), _stream_ptr(stream)),
+           "sfhk_exp_cr")
+    return y
+
+
+# ------------------------------------------------------------------------------------------------
+# convenience: one instance (see inputs.Instance) end to end on the device
+# ------------------------------------------------------------------------------------------------
+def to_device(inst, device="cuda:0"):
+    """Upload an instance's field table and samples (float64) to the device."""
+    dev = torch.device(device)
+    f = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    w = None
+    if inst.w is not None:
+        w = f(np.stack([np.real(inst.w), np.imag(inst.w)]))
+    return dict(e_half=f(inst.e_half), t0=f(inst.t0), q0=f(inst.q0), p0=f(inst.p0), w=w)
+
+
+def make_job(ctx: Context, inst, dev_arrays=None, precision=SFHK_FP64, n_out=None, stream=None,
+             r_fp64=2.0) -> Job:
+    a = dev_arrays if dev_arrays is not None else to_device(inst, f"cuda:{ctx.device}")
+    return Job(ctx, inst.potential, inst.ground, inst.grid.t_a, inst.grid.h, inst.grid.n_steps,
+               a["e_half"], a["t0"], a["q0"], a["p0"], a["w"], inst.gamma, inst.kay_max,
+               inst.overlap_cut, r_fp64, precision, inst.n_out if n_out is None else n_out,
+               stream)
