@@ -40,7 +40,21 @@ def _args():
     ap.add_argument("--cpu-births", type=int, default=16,
                     help="birth groups (spread over the pulse) in the oracle's sample")
     ap.add_argument("--cpu-per-birth", type=int, default=64)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes (calibrates the "
+                         "HBM traffic counters) and exit")
     return ap.parse_args()
+
+
+def copy_probe(nbytes):
+    import torch
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 8}), flush=True)
 
 
 def cpu_baseline(inst, n_births, n_per):
@@ -70,6 +84,9 @@ def main():
                                    "by birth groups with one reduction of d(t)) is not built",
                           "n_gpus": a.gpus}))
         sys.exit(2)
+    if a.copy_probe:
+        copy_probe(a.copy_probe)
+        return
     import torch
     from paper_2601_17164_amd import flops, inputs as I, sfhk
 

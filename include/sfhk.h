@@ -182,9 +182,13 @@ sfhk_status sfhk_job_trajectories(sfhk_job* job, double* y_out, double* c_out, i
 const char* sfhk_last_error(void);
 const char* sfhk_status_string(sfhk_status s);
 
-/* Correctly rounded binary64 exp of x[n] into y[n] (the exponential the screened potential uses;
- * exported so it can be checked against an independent correctly rounded evaluation). */
-sfhk_status sfhk_exp_cr(const double* x, double* y, int64_t n, void* stream);
+/* y[i] = exp(x[i]) for i < n, evaluated exactly as inside the screened potential: Cody-Waite
+ * reduction x = k ln2 + r (ln2 split into a 32-significant-bit head and a rounded tail, both
+ * applied with fused multiply-adds), the degree-13 Taylor polynomial of exp(r) in Horner form
+ * with fused multiply-adds, then scaling by 2^k; 0 for x < -708. Within about one ulp of exp.
+ * Exported so the sequence can be checked against an independent implementation. DEVICE
+ * pointers; asynchronous on `stream`. */
+sfhk_status sfhk_potential_exp(const double* x, double* y, int64_t n, void* stream);
 
 #ifdef __cplusplus
 }

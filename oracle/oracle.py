@@ -79,6 +79,8 @@ def lib():
         D, P = ct.c_double, ct.POINTER(ct.c_double)
         L.or_exp_cr.restype = D
         L.or_exp_cr.argtypes = [D]
+        L.or_exp_cw.restype = D
+        L.or_exp_cw.argtypes = [D]
         for nm in ("or_field_A", "or_field_E", "or_field_intA"):
             getattr(L, nm).restype = D
             getattr(L, nm).argtypes = [D, D, D, D, D]
@@ -145,6 +147,11 @@ class Ground:
 
 def exp_cr(x: float) -> float:
     return lib().or_exp_cr(float(x))
+
+
+def exp_cw(x: float) -> float:
+    """The exponential the screened potential uses (Cody-Waite + degree-13 Taylor)."""
+    return lib().or_exp_cw(float(x))
 
 
 def field_A(t, e0, omega, T, cep=0.0):

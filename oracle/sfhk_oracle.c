@@ -37,9 +37,39 @@
 #define IY_S 42
 
 /* ------------------------------------------------------------------------------------------ */
-/* correctly rounded exponential: binary128 evaluation rounded once to binary64               */
+/* correctly rounded exponential: binary128 evaluation rounded once to binary64 (the reference */
+/* the contract's exponential below is checked against)                                       */
 /* ------------------------------------------------------------------------------------------ */
 double or_exp_cr(double x) { return (double)expq((__float128)x); }
+
+/* ------------------------------------------------------------------------------------------ */
+/* the exponential of the rounding contract (screened potential): Cody-Waite argument          */
+/* reduction x = k ln2 + r with ln2 split as LN2_HI + LN2_LO (LN2_HI has 32 significant bits,  */
+/* so k LN2_HI is exact), exp(r) by the degree-13 Taylor polynomial in Horner form with fused   */
+/* multiply-adds, then scaling by 2^k. Results below 2^-1021 are flushed to zero (x < -708).    */
+/* ------------------------------------------------------------------------------------------ */
+#define EXPC_INV_LN2 1.4426950408889634          /* 1/ln 2 rounded to binary64 */
+#define EXPC_LN2_HI 0x1.62e42feep-1               /* ln 2 truncated to 32 significant bits */
+#define EXPC_LN2_LO 0x1.a39ef35793c76p-33         /* ln 2 - EXPC_LN2_HI rounded to binary64 */
+
+double or_exp_cw(double x) {
+  if (x != x) return x;
+  if (x < -708.0) return 0.0;
+  if (x > 709.0) return HUGE_VAL;
+  double k = rint(x * EXPC_INV_LN2);
+  double r = fma(-k, EXPC_LN2_HI, x);
+  r = fma(-k, EXPC_LN2_LO, r);
+  /* 1/n!, n = 0..13, each the correctly rounded quotient */
+  double inv_fact[14];
+  double f = 1.0;
+  for (int n = 0; n < 14; ++n) {
+    if (n > 0) f *= (double)n; /* n! is exact in binary64 for n <= 18 */
+    inv_fact[n] = 1.0 / f;
+  }
+  double p = inv_fact[13];
+  for (int n = 12; n >= 0; --n) p = fma(p, r, inv_fact[n]);
+  return ldexp(p, (int)k);
+}
 
 /* ------------------------------------------------------------------------------------------ */
 /* laser field (Sec. II.B field equation with the sin^2 envelope; E = -dA/dt, App. A)          */
@@ -101,11 +131,12 @@ static void pot_gc(const or_potential* pot, const double* q, double* V, double* 
       double ir = 1.0 / rho;
       double ir2 = ir * ir;
       double ir3 = ir2 * ir;
-      double e = or_exp_cr(-(r / pot->r_scr));
+      double inv_rs = 1.0 / pot->r_scr;
+      double e = or_exp_cw(-(r * inv_rs));
       double ez = pot->z_in * e;            /* z_in exp(-r/r_scr) */
       double Z = pot->z_inf + ez;
-      double d1 = ez / pot->r_scr;          /* -Z'(r) */
-      double d2 = d1 / pot->r_scr;          /*  Z''(r) */
+      double d1 = ez * inv_rs;              /* -Z'(r) */
+      double d2 = d1 * inv_rs;              /*  Z''(r) */
       *V = -(Z * ir);
       /* V'(r) = d1/rho + Z r / rho^3 */
       double vp = fma(Z * r, ir3, d1 * ir);
@@ -116,8 +147,9 @@ static void pot_gc(const or_potential* pot, const double* q, double* V, double* 
       double tc = ((Z * w1) * ir3) * ir2;
       double vpp = tc - fma(2.0, tb, ta);
       if (r > 0.0) {
-        *g = vp / r;
-        *c = (vpp - *g) / r2;
+        double inv_r = 1.0 / r;
+        *g = vp * inv_r;
+        *c = (vpp - *g) * (inv_r * inv_r);
       } else { /* r == 0 exactly (measure zero): finite isotropic choice */
         *g = vpp;
         *c = 0.0;

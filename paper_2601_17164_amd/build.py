@@ -17,18 +17,18 @@ HIPCC_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}"
                "-Wno-unused-command-line-argument"]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     src = os.path.join(CSRC, "sfhk.hip")
-    tmp = LIB + ".tmp"
-    cmd = ["hipcc", *HIPCC_FLAGS, "-o", tmp, src]
+    tmp = out + ".tmp"
+    cmd = ["hipcc", *HIPCC_FLAGS, *[f"-D{d}" for d in defines], "-o", tmp, src]
     r = subprocess.run(cmd, capture_output=True, text=True)
-    out = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
+    log = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({r.returncode}):\n{out}")
-    if verbose and out.strip():
-        print(out, file=sys.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+        raise RuntimeError(f"hipcc failed ({r.returncode}):\n{log}")
+    if verbose and log.strip():
+        print(log, file=sys.stderr)
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -58,9 +58,11 @@ struct GtoConst {
   double N[SFHK_MAX_PRIM];   // c_j (gamma + alpha_j)^(-5/2) (l = 0) or ^(-7/2) (l = 1)
   double G2[SFHK_MAX_PRIM];  // 2 (gamma + alpha_j)
   double two_gamma, ip;
+  double Amin, Bmin, cut_hi;  // all-primitives-skipped bound (see overlap_all_skipped)
 };
 
 struct JobDev {
+  int kind;
   PotParams pot;
   GtoConst gto;
   double gamma, inv4g, kay2, cut;
@@ -91,12 +93,19 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// <psi0|z|p,q,gamma> over GTOs (App. C.1, overall constant 1); tolerance-level arithmetic (it does
-// not feed back into the trajectory)
+// ------------------------------------------------------------------------------------------------
+// dipole element <psi0|z|p,q,gamma> over GTOs (App. C.1, overall constant 1). Tolerance-level
+// arithmetic: it does not feed back into the trajectory.
+// ------------------------------------------------------------------------------------------------
+// Every primitive is skipped when p^2 A_j + q^2 B_j > cut for all j. Since A_j >= A_min and
+// B_j >= B_min, p^2 A_min + q^2 B_min > cut (1 + 1e-12) implies it; the margin covers rounding.
+__device__ __forceinline__ bool overlap_all_skipped(const GtoConst& G, double p2, double q2) {
+  return SFHK_FMA(p2, G.Amin, q2 * G.Bmin) > G.cut_hi;
+}
+
 __device__ __forceinline__ cplx overlap(const GtoConst& G, double cut, const double* q,
-                                        const double* p, unsigned int& n_eval) {
-  double p2 = SFHK_FMA(p[2], p[2], SFHK_FMA(p[1], p[1], p[0] * p[0]));
-  double q2 = SFHK_FMA(q[2], q[2], SFHK_FMA(q[1], q[1], q[0] * q[0]));
+                                        const double* p, double p2, double q2,
+                                        unsigned int& n_eval) {
   double pq = SFHK_FMA(p[2], q[2], SFHK_FMA(p[1], q[1], p[0] * q[0]));
   cplx a = {G.two_gamma * q[2], p[2]};
   cplx sum = {0.0, 0.0};
@@ -169,11 +178,41 @@ __global__ void k_init(JobDev J, const long long* __restrict__ perm, long long n
 // ------------------------------------------------------------------------------------------------
 // propagation, FP64: one wave per tile, one trajectory per lane
 // ------------------------------------------------------------------------------------------------
-template <int KIND>
-__global__ __launch_bounds__(64) void k_propagate_fp64(const JobDev* __restrict__ jobs,
-                                                       int max_steps) {
-  const JobDev& J = jobs[0];
-  const int tile = blockIdx.x;
+// Per step every lane writes its integrand f_j(t_n) to an LDS ring of kRing steps; when the ring is
+// full (or the launch ends) the wave sums each step's 64 values in a fixed order (four interleaved
+// quarters of 16 lanes, then the quarters pairwise) and one lane per step writes the tile's
+// partial row. The wave is the whole workgroup, so the ring needs no cross-wave synchronisation.
+constexpr int kRing = 16;                // = kTile / 4: four lanes sum each buffered step
+constexpr int kRingStride = kTile + 4;   // double2 per ring row; the padding staggers the banks
+
+struct WorkItem {
+  int job, tile;
+};
+
+typedef __attribute__((address_space(4))) const double* const_dptr;  // scalar (uniform) loads
+
+__device__ __forceinline__ void flush_ring(double2 (*ring)[kRingStride], int lane, int slot_lo,
+                                           int slot_hi, double2* __restrict__ part,
+                                           long long base) {
+  __syncthreads();
+  const int s = lane >> 2, qq = lane & 3;
+  double sr = 0.0, si = 0.0;
+#pragma unroll
+  for (int i = 0; i < kTile / 4; ++i) {
+    double2 v = ring[s][qq + 4 * i];
+    sr += v.x;
+    si += v.y;
+  }
+  sr += __shfl_xor(sr, 1, 64);
+  si += __shfl_xor(si, 1, 64);
+  sr += __shfl_xor(sr, 2, 64);
+  si += __shfl_xor(si, 2, 64);
+  if (qq == 0 && s >= slot_lo && s <= slot_hi) part[base + s] = make_double2(sr, si);
+  __syncthreads();
+}
+
+__device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const int max_steps,
+                                         double2 (*ring)[kRingStride]) {
   const int lane = threadIdx.x;
   const int n_begin = J.tile_next[tile];
   const int N = J.n_steps;
@@ -196,32 +235,35 @@ __global__ __launch_bounds__(64) void k_propagate_fp64(const JobDev* __restrict_
   const cplx w = {J.aux[2 * np + s], J.aux[3 * np + s]};
   double sgn = J.aux[4 * np + s];
   const int n0l = J.n0[s];
-  int death = J.death[s];
-  bool alive = death == -1;
+  const int death_in = J.death[s];
+  int death = death_in;
+  bool alive = death_in == -1;
 
   const int t0 = J.tile_n0[tile];
   const long long roff = J.row_off[tile];
   double2* __restrict__ part = J.part;
-  const double* __restrict__ eh = J.e_half;
+  const const_dptr eh = (const_dptr)J.e_half;
+  const PotParams P = J.pot;
+  const int kind = J.kind;
   const double gamma = J.gamma, inv4g = J.inv4g, kay2 = J.kay2, cut = J.cut;
   const double h = J.h, h2 = J.h2, h6 = J.h6, t_a = J.t_a, ip = J.gto.ip;
 
-  double buf_re = 0.0, buf_im = 0.0;
-  int slot_lo = (n_begin - t0) & 63;
-  unsigned int evals = 0, kay = 0, nonfin = 0, prims = 0;
+  int slot_lo = (n_begin - t0) % kRing;
+  unsigned int kay = 0, nonfin = 0, prims = 0;
   int n = n_begin;
-  int last_written = n_begin - 1;
+  double ea = eh[2 * n];
   for (; n <= n_stop; ++n) {
-    const bool active = alive && n >= n0l;
+    const int slot = (n - t0) % kRing;
     double fr = 0.0, fi = 0.0;
-    if (active) {
-      ++evals;
+    bool contrib = false;
+    cplx C = {0.0, 0.0};
+    if (alive && n >= n0l) {
       cplx d = hk_det(T.M, gamma, inv4g);
       double a2 = d.re * d.re;
       a2 = SFHK_FMA(d.im, d.im, a2);
       bool finite = isfinite(T.q[0]) && isfinite(T.q[1]) && isfinite(T.q[2]) &&
                     isfinite(T.p[0]) && isfinite(T.p[1]) && isfinite(T.p[2]) && isfinite(T.S);
-      if (!(a2 <= kay2) || !finite) {
+      if (!(a2 <= kay2) || !finite) {  // Kay removal (or a non-finite state) from step n on
         alive = false;
         death = n;
         if (!finite || isnan(a2))
@@ -232,42 +274,47 @@ __global__ __launch_bounds__(64) void k_propagate_fp64(const JobDev* __restrict_
         cplx c = csqrt_principal(d, sqrt(a2));
         double dot = SFHK_FMA(c.im, cprev.im, c.re * cprev.re);
         if (sgn * dot < 0.0) sgn = -sgn;
-        cplx C = {sgn * c.re, sgn * c.im};
+        C = {sgn * c.re, sgn * c.im};
         cprev = C;
-        cplx O = overlap(J.gto, cut, T.q, T.p, prims);
-        double tn = t_a + (double)n * h;
-        double ph = T.S - ip * tn;
-        double sp, cp;
-        sincos(ph, &sp, &cp);
-        cplx f = cmul(cmul(w, C), cmul(O, cplx{cp, sp}));
-        fr = f.re;
-        fi = f.im;
+        contrib = true;
       }
     }
-    fr = wave_sum(fr);
-    fi = wave_sum(fi);
-    const int slot = (n - t0) & 63;
-    if (lane == slot) {
-      buf_re = fr;
-      buf_im = fi;
+    // dipole element: costly only for lanes near the ground state
+    double p2 = SFHK_FMA(T.p[2], T.p[2], SFHK_FMA(T.p[1], T.p[1], T.p[0] * T.p[0]));
+    double q2 = SFHK_FMA(T.q[2], T.q[2], SFHK_FMA(T.q[1], T.q[1], T.q[0] * T.q[0]));
+    const bool need = contrib && !overlap_all_skipped(J.gto, p2, q2);
+    if (__any(need)) {
+      if (need) {
+        cplx O = overlap(J.gto, cut, T.q, T.p, p2, q2, prims);
+        if (O.re != 0.0 || O.im != 0.0) {
+          double tn = t_a + (double)n * h;
+          double ph = T.S - ip * tn;
+          double sp, cp;
+          sincos(ph, &sp, &cp);
+          cplx f = cmul(cmul(w, C), cmul(O, cplx{cp, sp}));
+          fr = f.re;
+          fi = f.im;
+        }
+      }
     }
-    if (slot == 63 || n == n_stop) {
-      const long long base = roff + (n - slot - t0);
-      if (lane >= slot_lo && lane <= slot) part[base + lane] = make_double2(buf_re, buf_im);
+    ring[slot][lane] = make_double2(fr, fi);
+    const bool last = (n == n_stop);
+    if (slot == kRing - 1 || last) {
+      flush_ring(ring, lane, slot_lo, slot, part, roff + (n - slot - t0));
       slot_lo = 0;
     }
-    last_written = n;
-    if (active && alive && n < N) rk4_step<KIND>(J.pot, T, eh[2 * n], eh[2 * n + 1], eh[2 * n + 2], h, h2, h6);
-    if (!__any(alive)) {  // every lane removed: the rest of the row is zero
-      if (slot != 63 && n != n_stop) {
-        const long long base = roff + (n - slot - t0);
-        if (lane >= slot_lo && lane <= slot) part[base + lane] = make_double2(buf_re, buf_im);
-      }
+    if (n < N) {
+      const double eb = eh[2 * n + 1], ec = eh[2 * n + 2];
+      if (alive && n >= n0l) rk4_step(kind, P, T, ea, eb, ec, h, h2, h6);
+      ea = ec;
+    }
+    if (!__any(alive)) {  // every lane removed: the rest of the tile's row stays unwritten
+      if (!(slot == kRing - 1 || last)) flush_ring(ring, lane, slot_lo, slot, part, roff + (n - slot - t0));
       ++n;
       break;
     }
   }
-  // write back
+  // n is now one past the last step processed
   double* yw = J.y;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -284,9 +331,16 @@ __global__ __launch_bounds__(64) void k_propagate_fp64(const JobDev* __restrict_
   const bool finished = !__any(alive) || n > N;
   if (lane == 0) {
     J.tile_next[tile] = finished ? N + 1 : n;
-    J.tile_last[tile] = last_written;
+    J.tile_last[tile] = n - 1;
   }
-  // counters: one atomic per wave
+  // steps evaluated by this lane in this launch: from max(n_begin, n0) to its removal step or the
+  // last step processed
+  int evals = 0;
+  if (death_in == -1) {
+    const int first = max(n_begin, n0l);
+    const int lastn = death >= 0 ? death : n - 1;
+    evals = max(0, lastn - first + 1);
+  }
   double ev = wave_sum((double)evals), ka = wave_sum((double)kay), nf = wave_sum((double)nonfin);
   double pr = wave_sum((double)prims);
   if (lane == 0) {
@@ -295,6 +349,17 @@ __global__ __launch_bounds__(64) void k_propagate_fp64(const JobDev* __restrict_
     atomicAdd(&J.counters[2], (unsigned long long)nf);
     atomicAdd(&J.counters[4], (unsigned long long)pr);
   }
+}
+
+#ifndef SFHK_PROPAGATE_WAVES_PER_EU
+#define SFHK_PROPAGATE_WAVES_PER_EU 2
+#endif
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_PROPAGATE_WAVES_PER_EU)))
+void k_propagate_fp64(
+    const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work, int max_steps) {
+  __shared__ double2 ring[kRing][kRingStride];
+  const WorkItem wi = work[blockIdx.x];
+  run_tile(jobs[wi.job], wi.tile, max_steps, ring);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -425,9 +490,9 @@ __global__ __launch_bounds__(256) void k_dft(const double* __restrict__ xw, cons
   }
 }
 
-__global__ void k_exp_cr(const double* __restrict__ x, double* __restrict__ y, long long n) {
+__global__ void k_exp(const double* __restrict__ x, double* __restrict__ y, long long n) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = exp_cr(x[i]);
+  if (i < n) y[i] = exp_cw(x[i]);
 }
 
 }  // namespace
@@ -440,6 +505,12 @@ struct sfhk_ctx {
   size_t budget;
   size_t in_use = 0;
   std::mutex mu;
+  // staging of sfhk_propagate_many: job descriptors and the combined work list
+  JobDev* many_desc = nullptr;
+  WorkItem* many_work = nullptr;
+  JobDev* many_desc_host = nullptr;  // pinned
+  WorkItem* many_work_host = nullptr;
+  size_t many_desc_cap = 0, many_work_cap = 0;
 };
 
 struct sfhk_job {
@@ -451,6 +522,7 @@ struct sfhk_job {
   long long n_traj = 0;
   long long n_out = 0;
   long long* perm = nullptr;   // [n_pad] sorted slot -> original index (-1: padding)
+  WorkItem* work = nullptr;    // [n_tiles] (0, t): this job's tiles, longest first
   double* dbuf = nullptr;      // [n_steps+1] dipole on the step grid
   double2* gsum = nullptr;     // [n_groups][n_steps+1]
   size_t bytes = 0;
@@ -476,7 +548,7 @@ size_t footprint_parts(long long n_traj, long long n_steps, long long n_out,
   long long n_groups = (n_tiles + kReduceGroup - 1) / kReduceGroup;
   size_t b = 0;
   b += (size_t)n_pad * kNY * 8 + (size_t)n_pad * 5 * 8 + (size_t)n_pad * 8 * 2;  // y, aux, n0+death, perm
-  b += (size_t)n_tiles * (4 * 3 + 8);
+  b += (size_t)n_tiles * (4 * 3 + 8 + sizeof(WorkItem));
   b += (size_t)pe * 16;
   b += (size_t)(2 * n_steps + 1) * 8;
   b += (size_t)(n_steps + 1) * 8 + (size_t)n_groups * (n_steps + 1) * 16;
@@ -502,24 +574,10 @@ void job_free(sfhk_job* j) {
 
 int blocks_for(long long n, int t) { return (int)((n + t - 1) / t); }
 
-sfhk_status launch_propagate(sfhk_job* j, int n_tiles_unfinished, int max_steps, hipStream_t st) {
-  dim3 grid(n_tiles_unfinished), block(kTile);
-  switch (j->kind) {
-    case SFHK_POT_NONE:
-      hipLaunchKernelGGL(k_propagate_fp64<POT_NONE>, grid, block, 0, st, j->dev, max_steps);
-      break;
-    case SFHK_POT_SOFTCORE:
-      hipLaunchKernelGGL(k_propagate_fp64<POT_SOFTCORE>, grid, block, 0, st, j->dev, max_steps);
-      break;
-    case SFHK_POT_SCREENED:
-      hipLaunchKernelGGL(k_propagate_fp64<POT_SCREENED>, grid, block, 0, st, j->dev, max_steps);
-      break;
-    case SFHK_POT_HARMONIC:
-      hipLaunchKernelGGL(k_propagate_fp64<POT_HARMONIC>, grid, block, 0, st, j->dev, max_steps);
-      break;
-    default:
-      return fail(SFHK_E_INVALID, "unknown potential kind");
-  }
+sfhk_status launch_propagate(const JobDev* descs, const WorkItem* work, int n_items, int max_steps,
+                             hipStream_t st) {
+  if (n_items <= 0) return SFHK_OK;
+  hipLaunchKernelGGL(k_propagate_fp64, dim3(n_items), dim3(kTile), 0, st, descs, work, max_steps);
   HIP_TRY(hipGetLastError());
   return SFHK_OK;
 }
@@ -555,7 +613,16 @@ sfhk_status sfhk_ctx_create(int device, size_t hbm_budget_bytes, sfhk_ctx** out)
   return SFHK_OK;
 }
 
-void sfhk_ctx_destroy(sfhk_ctx* ctx) { delete ctx; }
+void sfhk_ctx_destroy(sfhk_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(ctx->many_desc);
+  (void)hipFree(ctx->many_work);
+  (void)hipHostFree(ctx->many_desc_host);
+  (void)hipHostFree(ctx->many_work_host);
+  delete ctx;
+}
 
 size_t sfhk_ctx_bytes_in_use(const sfhk_ctx* ctx) { return ctx ? ctx->in_use : 0; }
 
@@ -656,7 +723,8 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   j->bytes = bytes;
   j->tile_n0_host = tile_n0;
   JobDev& H = j->host;
-  H.pot = {pot->z_inf, pot->z_in, pot->r_scr, pot->soft2, pot->omega_ho};
+  H.pot = {pot->z_inf, pot->z_in, pot->r_scr, pot->soft2, pot->omega_ho,
+           pot->kind == SFHK_POT_SCREENED ? 1.0 / pot->r_scr : 0.0};
   const double g = params->gamma;
   H.gto.l = ground->l;
   H.gto.n_prim = ground->n_prim;
@@ -671,6 +739,14 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   }
   H.gto.two_gamma = 2.0 * g;
   H.gto.ip = ground->ip;
+  H.gto.Amin = H.gto.A[0];
+  H.gto.Bmin = H.gto.B[0];
+  for (int k = 1; k < ground->n_prim; ++k) {
+    H.gto.Amin = std::min(H.gto.Amin, H.gto.A[k]);
+    H.gto.Bmin = std::min(H.gto.Bmin, H.gto.B[k]);
+  }
+  H.gto.cut_hi = params->overlap_cut * (1.0 + 1e-12);
+  H.kind = pot->kind;
   H.gamma = g;
   H.inv4g = 1.0 / (4.0 * g);
   H.kay2 = params->kay_max * params->kay_max;
@@ -700,6 +776,7 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
       (rc = job_alloc(j, &H.tile_next, (size_t)n_tiles)) || (rc = job_alloc(j, &H.tile_last, (size_t)n_tiles)) ||
       (rc = job_alloc(j, &H.row_off, (size_t)n_tiles)) || (rc = job_alloc(j, &H.part, (size_t)part_elems)) ||
       (rc = job_alloc(j, &H.counters, 8)) || (rc = job_alloc(j, &j->perm, (size_t)n_pad)) ||
+      (rc = job_alloc(j, &j->work, (size_t)n_tiles)) ||
       (rc = job_alloc(j, &j->dbuf, (size_t)NS + 1)) ||
       (rc = job_alloc(j, &j->gsum, (size_t)((n_tiles + kReduceGroup - 1) / kReduceGroup) * (NS + 1))) ||
       (rc = job_alloc(j, &j->dev, 1)))
@@ -717,6 +794,9 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   TRY_C(hipMemcpyAsync(H.tile_next, tile_next.data(), n_tiles * sizeof(int), hipMemcpyHostToDevice, st));
   TRY_C(hipMemcpyAsync(H.tile_last, tile_last.data(), n_tiles * sizeof(int), hipMemcpyHostToDevice, st));
   TRY_C(hipMemcpyAsync(H.row_off, row_off.data(), n_tiles * sizeof(long long), hipMemcpyHostToDevice, st));
+  std::vector<WorkItem> work(n_tiles);
+  for (int t = 0; t < n_tiles; ++t) work[t] = {0, t};
+  TRY_C(hipMemcpyAsync(j->work, work.data(), n_tiles * sizeof(WorkItem), hipMemcpyHostToDevice, st));
   TRY_C(hipMemsetAsync(H.counters, 0, 8 * sizeof(unsigned long long), st));
   TRY_C(hipMemcpyAsync(j->dev, &H, sizeof(JobDev), hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL(k_init, dim3(blocks_for(n_pad, 256)), dim3(256), 0, st, H, j->perm, N, q0, p0, w);
@@ -762,7 +842,7 @@ sfhk_status sfhk_propagate(sfhk_job* job, int64_t max_steps, void* stream) {
   const int nt = unfinished_tiles(job, job->steps_done);
   if (nt > 0) {
     int ms = (max_steps <= 0 || max_steps > NS + 1) ? 0 : (int)max_steps;
-    sfhk_status rc = launch_propagate(job, nt, ms, st);
+    sfhk_status rc = launch_propagate(job->dev, job->work, nt, ms, st);
     if (rc) return rc;
   }
   job->steps_done += (max_steps <= 0) ? (long long)NS + 1 : max_steps;
@@ -775,11 +855,66 @@ sfhk_status sfhk_propagate(sfhk_job* job, int64_t max_steps, void* stream) {
 
 sfhk_status sfhk_propagate_many(sfhk_job* const* jobs, int32_t n_jobs, int64_t max_steps, void* stream) {
   if (!jobs || n_jobs < 0) return fail(SFHK_E_INVALID, "bad job list");
+  if (n_jobs == 0) return SFHK_OK;
+  sfhk_ctx* ctx = jobs[0] ? jobs[0]->ctx : nullptr;
+  for (int i = 0; i < n_jobs; ++i)
+    if (!jobs[i] || jobs[i]->ctx != ctx) return fail(SFHK_E_INVALID, "jobs must be non-NULL and share one context");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  // one launch over the unfinished tiles of every job, ordered by steps left (longest first)
+  struct Item {
+    long long left;
+    int job, tile;
+  };
+  std::vector<Item> items;
+  for (int i = 0; i < n_jobs; ++i) {
+    sfhk_job* j = jobs[i];
+    if (j->done) continue;
+    const int NS = j->host.n_steps;
+    const int nt = unfinished_tiles(j, j->steps_done);
+    for (int t = 0; t < nt; ++t) items.push_back({NS + 1 - (j->tile_n0_host[t] + j->steps_done), i, t});
+  }
+  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.left > b.left; });
+  if (!items.empty()) {
+    HIP_TRY(hipStreamSynchronize(st));  // the staging buffers of the previous call are free
+    if (ctx->many_desc_cap < (size_t)n_jobs) {
+      (void)hipFree(ctx->many_desc);
+      (void)hipHostFree(ctx->many_desc_host);
+      ctx->many_desc = nullptr;
+      ctx->many_desc_host = nullptr;
+      ctx->many_desc_cap = 0;
+      HIP_TRY(hipMalloc(&ctx->many_desc, n_jobs * sizeof(JobDev)));
+      HIP_TRY(hipHostMalloc(&ctx->many_desc_host, n_jobs * sizeof(JobDev), hipHostMallocDefault));
+      ctx->many_desc_cap = n_jobs;
+    }
+    if (ctx->many_work_cap < items.size()) {
+      (void)hipFree(ctx->many_work);
+      (void)hipHostFree(ctx->many_work_host);
+      ctx->many_work = nullptr;
+      ctx->many_work_host = nullptr;
+      ctx->many_work_cap = 0;
+      HIP_TRY(hipMalloc(&ctx->many_work, items.size() * sizeof(WorkItem)));
+      HIP_TRY(hipHostMalloc(&ctx->many_work_host, items.size() * sizeof(WorkItem), hipHostMallocDefault));
+      ctx->many_work_cap = items.size();
+    }
+    for (int i = 0; i < n_jobs; ++i) ctx->many_desc_host[i] = jobs[i]->host;
+    for (size_t k = 0; k < items.size(); ++k) ctx->many_work_host[k] = {items[k].job, items[k].tile};
+    HIP_TRY(hipMemcpyAsync(ctx->many_desc, ctx->many_desc_host, n_jobs * sizeof(JobDev), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(ctx->many_work, ctx->many_work_host, items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, st));
+    int ms = (max_steps <= 0 || max_steps > INT32_MAX / 2) ? 0 : (int)max_steps;
+    sfhk_status rc = launch_propagate(ctx->many_desc, ctx->many_work, (int)items.size(), ms, st);
+    if (rc) return rc;
+  }
   sfhk_status agg = SFHK_OK;
   for (int i = 0; i < n_jobs; ++i) {
-    sfhk_status rc = sfhk_propagate(jobs[i], max_steps, stream);
-    if (rc == SFHK_E_NOT_DONE) agg = SFHK_E_NOT_DONE;
-    else if (rc != SFHK_OK) return rc;
+    sfhk_job* j = jobs[i];
+    if (j->done) continue;
+    const int NS = j->host.n_steps;
+    j->steps_done += (max_steps <= 0) ? (long long)NS + 1 : max_steps;
+    if (unfinished_tiles(j, j->steps_done) == 0)
+      j->done = true;
+    else
+      agg = SFHK_E_NOT_DONE;
   }
   return agg;
 }
@@ -861,10 +996,10 @@ sfhk_status sfhk_job_trajectories(sfhk_job* job, double* y_out, double* c_out, i
   return SFHK_OK;
 }
 
-sfhk_status sfhk_exp_cr(const double* x, double* y, int64_t n, void* stream) {
-  if (!x || !y || n < 0) return fail(SFHK_E_INVALID, "bad exp_cr arguments");
+sfhk_status sfhk_potential_exp(const double* x, double* y, int64_t n, void* stream) {
+  if (!x || !y || n < 0) return fail(SFHK_E_INVALID, "bad sfhk_potential_exp arguments");
   if (n == 0) return SFHK_OK;
-  hipLaunchKernelGGL(k_exp_cr, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, x, y, (long long)n);
+  hipLaunchKernelGGL(k_exp, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, x, y, (long long)n);
   HIP_TRY(hipGetLastError());
   return SFHK_OK;
 }

@@ -6,130 +6,51 @@
 // as an explicit sequence of IEEE-754 binary64 operations with round-to-nearest-even: +, -, *, /,
 // sqrt, and __builtin_fma where a fused multiply-add is part of the sequence. This file must be
 // compiled with -ffp-contract=off so the compiler adds no fusion of its own. gfx950's binary64
-// division and square root are correctly rounded, and the screened potential's exponential is the
-// correctly rounded exp below, so a CPU implementation of the same sequence agrees bit for bit.
+// division and square root are correctly rounded, and the screened potential's exponential is a
+// fixed sequence of such operations (exp_cw below), so a CPU implementation of the same sequence
+// agrees bit for bit.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "exp_table.inc"
 
 #define SFHK_FMA(a, b, c) __builtin_fma((a), (b), (c))
 
 namespace sfhk {
 
 // ----------------------------------------------------------------------------------------------
-// correctly rounded exp(x) (table-driven reduction of Tang 1989, double-double evaluation with a
-// rounding test; a second, more accurate double-double evaluation when the first cannot decide)
+// the exponential of the rounding contract (inside the screened potential). Cody-Waite argument
+// reduction x = k ln2 + r, ln2 = kLn2Hi + kLn2Lo with kLn2Hi holding 32 significant bits; exp(r)
+// by the degree-13 Taylor polynomial in Horner form with fused multiply-adds; scaling by 2^k.
+// Results below 2^-1021 are flushed to zero (x < -708), so the scaling is always exact. Within
+// about one ulp of exp; no tables and no memory traffic.
 // ----------------------------------------------------------------------------------------------
-struct dd {
-  double hi, lo;
+struct InvFactorials {
+  double v[14];
+  constexpr InvFactorials() : v() {
+    double f = 1.0;
+    for (int n = 0; n < 14; ++n) {
+      if (n > 0) f *= (double)n;  // n! is exact in binary64 for n <= 18
+      v[n] = 1.0 / f;             // correctly rounded quotient (evaluated by the compiler)
+    }
+  }
 };
+constexpr InvFactorials kInvFact{};
 
-__device__ __forceinline__ dd two_prod(double a, double b) {
-  double p = a * b;
-  return {p, SFHK_FMA(a, b, -p)};
-}
-__device__ __forceinline__ dd fast_two_sum(double a, double b) {  // |a| >= |b|
-  double s = a + b;
-  return {s, b - (s - a)};
-}
-__device__ __forceinline__ dd two_sum(double a, double b) {
-  double s = a + b;
-  double bb = s - a;
-  return {s, (a - (s - bb)) + (b - bb)};
-}
-__device__ __forceinline__ dd dd_mul(dd a, dd b) {
-  dd p = two_prod(a.hi, b.hi);
-  double t = SFHK_FMA(a.hi, b.lo, a.lo * b.hi) + p.lo;
-  return fast_two_sum(p.hi, t);
-}
-__device__ __forceinline__ dd dd_add(dd a, dd b) {
-  dd s = two_sum(a.hi, b.hi);
-  dd t = two_sum(a.lo, b.lo);
-  s.lo += t.hi;
-  s = fast_two_sum(s.hi, s.lo);
-  s.lo += t.lo;
-  return fast_two_sum(s.hi, s.lo);
-}
-
-// Round y = (s + t) * 2^m, known to relative accuracy err_rel, to binary64. Returns false when
-// the error interval straddles a rounding boundary (the caller then needs a better y).
-__device__ __forceinline__ bool exp_round(double s, double t, int m, double err_rel, double* out) {
-  double e = err_rel * s;
-  if (m > -1022 || (m == -1022 && s >= 1.0)) {  // normal result: scaling by 2^m is exact
-    double a = s + (t + e);
-    double b = s + (t - e);
-    if (a != b) return false;
-    *out = ldexp(a, m);
-    return true;
-  }
-  // subnormal result: round y * 2^(m+1074) to an integer count of 2^-1074
-  int K = m + 1074;
-  if (K < -2) {
-    *out = 0.0;
-    return true;
-  }
-  double S1 = ldexp(s, K);  // exact
-  double T1 = ldexp(t, K);
-  double E1 = ldexp(e, K);
-  double n = rint(S1);
-  double d = (S1 - n) + T1;  // in [-0.5 - T1, 0.5 + T1]
-  double ad = fabs(d);
-  if (fabs(ad - 0.5) <= E1 + 0x1p-52) return false;
-  if (ad > 0.5) n += (d > 0.0 ? 1.0 : -1.0);
-  *out = ldexp(n, -1074);
-  return true;
-}
-
-__device__ __noinline__ double exp_cr_slow(double rh, double rl, double th, double tl, int m) {
-  // exp(r) by Horner in double-double to degree 13 (truncation < 2^-120 for |r| < 2^-8.4)
-  dd r = fast_two_sum(rh, rl);
-  dd c = {sfhk_inv_fact[26], sfhk_inv_fact[27]};
-  for (int n = 12; n >= 0; --n) {
-    c = dd_mul(c, r);
-    c = dd_add(c, dd{sfhk_inv_fact[2 * n], sfhk_inv_fact[2 * n + 1]});
-  }
-  dd y = dd_mul(dd{th, tl}, c);
-  double out;
-  if (exp_round(y.hi, y.lo, m, 0x1p-100, &out)) return out;
-  exp_round(y.hi, y.lo, m, 0.0, &out);  // undecidable at 2^-100: nearest of the 106-bit value
-  return out;
-}
-
-__device__ __forceinline__ double exp_cr(double x) {
-  if (!(x <= 709.79)) return x + x;  // +inf for large x, NaN propagates (x + x keeps NaN)
-  if (x < -745.2) return 0.0;
-  double kd = rint(x * SFHK_EXP_INV_L);
-  int k = (int)kd;
-  int j = k & 127;
-  int m = k >> 7;
-  // r = x - k ln2/128 as rh + rl (k*L1, k*L2 exact; x - k*L1 exact)
-  double t1 = SFHK_FMA(-kd, SFHK_EXP_L1, x);
-  double u2 = kd * SFHK_EXP_L2;
-  dd r0 = two_sum(t1, -u2);
-  double rh = r0.hi;
-  double rl = SFHK_FMA(-kd, SFHK_EXP_L3, r0.lo);
-  dd rr = fast_two_sum(rh, rl);
-  rh = rr.hi;
-  rl = rr.lo;
-  // exp(r) - 1 - r_hi ~ r_lo + r_hi r_lo + r_hi^2 (1/2 + r_hi/6 + ... + r_hi^4/720)
-  double c = SFHK_FMA(rh, 0x1.6c16c16c16c17p-10, 0x1.1111111111111p-7);
-  c = SFHK_FMA(rh, c, 0x1.5555555555555p-5);
-  c = SFHK_FMA(rh, c, 0x1.5555555555555p-3);
-  c = SFHK_FMA(rh, c, 0.5);
-  double p = (rh * rh) * c;
-  double lo = rl + SFHK_FMA(rh, rl, p);
-  dd e1 = fast_two_sum(1.0, rh);
-  double el = e1.lo + lo;
-  double th = sfhk_exp_tab[2 * j];
-  double tl = sfhk_exp_tab[2 * j + 1];
-  dd y = two_prod(th, e1.hi);
-  double yl = y.lo + SFHK_FMA(th, el, tl * e1.hi);
-  dd s = fast_two_sum(y.hi, yl);
-  double out;
-  if (exp_round(s.hi, s.lo, m, 0x1p-65, &out)) return out;
-  return exp_cr_slow(rh, rl, th, tl, m);
+__device__ __forceinline__ double exp_cw(double x) {
+  constexpr double kInvLn2 = 0x1.71547652b82fep+0;  // 1/ln2 rounded to binary64
+  constexpr double kLn2Hi = 0x1.62e42feep-1;         // ln2 truncated to 32 significant bits
+  constexpr double kLn2Lo = 0x1.a39ef35793c76p-33;   // ln2 - kLn2Hi rounded to binary64
+  if (x != x) return x;
+  if (x < -708.0) return 0.0;
+  if (x > 709.0) return __builtin_inf();
+  const double k = rint(x * kInvLn2);
+  double r = SFHK_FMA(-k, kLn2Hi, x);
+  r = SFHK_FMA(-k, kLn2Lo, r);
+  double p = kInvFact.v[13];
+#pragma unroll
+  for (int n = 12; n >= 0; --n) p = SFHK_FMA(p, r, kInvFact.v[n]);
+  return ldexp(p, (int)k);
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -139,6 +60,7 @@ enum PotKind : int { POT_NONE = 0, POT_SOFTCORE = 1, POT_SCREENED = 2, POT_HARMO
 
 struct PotParams {
   double z_inf, z_in, r_scr, soft2, omega_ho;
+  double inv_rscr;  // 1 / r_scr (correctly rounded quotient)
 };
 
 template <int KIND>
@@ -166,11 +88,11 @@ __device__ __forceinline__ void pot_gc(const PotParams& P, double x, double y, d
     double ir = 1.0 / rho;
     double ir2 = ir * ir;
     double ir3 = ir2 * ir;
-    double e = exp_cr(-(r / P.r_scr));
+    double e = exp_cw(-(r * P.inv_rscr));
     double ez = P.z_in * e;
     double Z = P.z_inf + ez;
-    double d1 = ez / P.r_scr;  // -Z'
-    double d2 = d1 / P.r_scr;  //  Z''
+    double d1 = ez * P.inv_rscr;  // -Z'
+    double d2 = d1 * P.inv_rscr;  //  Z''
     V = -(Z * ir);
     double vp = SFHK_FMA(Z * r, ir3, d1 * ir);           // V'
     double w1 = SFHK_FMA(-2.0, r2, P.soft2);             // a - 2 r^2
@@ -179,8 +101,9 @@ __device__ __forceinline__ void pot_gc(const PotParams& P, double x, double y, d
     double tc = ((Z * w1) * ir3) * ir2;
     double vpp = tc - SFHK_FMA(2.0, tb, ta);             // V''
     if (r > 0.0) {
-      g = vp / r;
-      c = (vpp - g) / r2;
+      double inv_r = 1.0 / r;
+      g = vp * inv_r;
+      c = (vpp - g) * (inv_r * inv_r);
     } else {
       g = vpp;
       c = 0.0;
@@ -195,6 +118,19 @@ __device__ __forceinline__ void pot_gc(const PotParams& P, double x, double y, d
     g = 0.0;
     c = 0.0;
   }
+}
+
+// kind known only at run time (uniform across the wave): a scalar branch per evaluation
+__device__ __forceinline__ void pot_gc_rt(int kind, const PotParams& P, double x, double y, double z,
+                                          double& V, double& g, double& c) {
+  if (kind == POT_SCREENED)
+    pot_gc<POT_SCREENED>(P, x, y, z, V, g, c);
+  else if (kind == POT_SOFTCORE)
+    pot_gc<POT_SOFTCORE>(P, x, y, z, V, g, c);
+  else if (kind == POT_HARMONIC)
+    pot_gc<POT_HARMONIC>(P, x, y, z, V, g, c);
+  else
+    pot_gc<POT_NONE>(P, x, y, z, V, g, c);
 }
 
 struct Hess3 {
@@ -239,11 +175,10 @@ struct Traj {
   double M[36];  // 6 columns (Q(3), P(3)): column j = d(q_t, p_t)/d z_j, z = (q0, p0)
 };
 
-template <int KIND>
-__device__ __forceinline__ void qps_rhs(const PotParams& P, const double* q, const double* p,
+__device__ __forceinline__ void qps_rhs(int kind, const PotParams& P, const double* q, const double* p,
                                         double E, double* kp, double& kS, Hess3& H) {
   double V, g, c;
-  pot_gc<KIND>(P, q[0], q[1], q[2], V, g, c);
+  pot_gc_rt(kind, P, q[0], q[1], q[2], V, g, c);
   H = hess_from(g, c, q[0], q[1], q[2]);
   kp[0] = -(g * q[0]);
   kp[1] = -(g * q[1]);
@@ -255,14 +190,13 @@ __device__ __forceinline__ void qps_rhs(const PotParams& P, const double* q, con
   kS = SFHK_FMA(-q[2], E, L);
 }
 
-template <int KIND>
-__device__ __forceinline__ void rk4_step(const PotParams& P, Traj& T, double ea, double eb, double ec,
-                                         double h, double h2, double h6) {
+__device__ __forceinline__ void rk4_step(int kind, const PotParams& P, Traj& T, double ea, double eb,
+                                         double ec, double h, double h2, double h6) {
   Hess3 H1, H2, H3, H4;
   {
     double accq[3], accp[3], accS, ysq[3], ysp[3], ysS, kp[3], kS;
     // stage 1
-    qps_rhs<KIND>(P, T.q, T.p, ea, kp, kS, H1);
+    qps_rhs(kind, P, T.q, T.p, ea, kp, kS, H1);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       accq[i] = T.p[i];
@@ -273,7 +207,7 @@ __device__ __forceinline__ void rk4_step(const PotParams& P, Traj& T, double ea,
     accS = kS;
     ysS = SFHK_FMA(h2, kS, T.S);
     // stage 2
-    qps_rhs<KIND>(P, ysq, ysp, eb, kp, kS, H2);
+    qps_rhs(kind, P, ysq, ysp, eb, kp, kS, H2);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       double kq = ysp[i];
@@ -285,7 +219,7 @@ __device__ __forceinline__ void rk4_step(const PotParams& P, Traj& T, double ea,
     accS = SFHK_FMA(2.0, kS, accS);
     ysS = SFHK_FMA(h2, kS, T.S);
     // stage 3
-    qps_rhs<KIND>(P, ysq, ysp, eb, kp, kS, H3);
+    qps_rhs(kind, P, ysq, ysp, eb, kp, kS, H3);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       double kq = ysp[i];
@@ -298,7 +232,7 @@ __device__ __forceinline__ void rk4_step(const PotParams& P, Traj& T, double ea,
     ysS = SFHK_FMA(h, kS, T.S);
     (void)ysS;
     // stage 4
-    qps_rhs<KIND>(P, ysq, ysp, ec, kp, kS, H4);
+    qps_rhs(kind, P, ysq, ysp, ec, kp, kS, H4);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       accq[i] = accq[i] + ysp[i];

@@ -6,7 +6,7 @@ oracle both follow (one RK4 step of the 43 ODEs of App. A, the HK prefactor with
 branch, the GTO dipole element of App. C.1, the phase and the per-step sum of Eq. 2):
 
   right-hand side, (q, p, S) part incl. the potential's gradient and Hessian, per evaluation:
-      soft-core 40, screened 61, harmonic 33, none 30            (x 4 stages)
+      soft-core 40, screened 63, harmonic 33, none 30            (x 4 stages)
   RK4 combination: 13 per component for q, p (6 components), 7 for S    = 85
   monodromy: per column 4 Hessian products (15 each) + 6 x 13 combination = 138   (x 6) = 828
   HK prefactor: G (45), det G (64), |det|^2 (3), sqrt |det| (1), principal sqrt (5),
@@ -20,7 +20,7 @@ all steps on the benchmark workloads, so every evaluated step is priced at the f
 """
 from __future__ import annotations
 
-RHS = {0: 30, 1: 40, 2: 61, 3: 33}
+RHS = {0: 30, 1: 40, 2: 63, 3: 33}
 RK4_QPS = 85
 MONODROMY = 828
 HK = 124

@@ -81,7 +81,7 @@ _SIGS = {
     "sfhk_job_trajectories": (ct.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "sfhk_last_error": (ct.c_char_p, []),
     "sfhk_status_string": (ct.c_char_p, [ct.c_int]),
-    "sfhk_exp_cr": (ct.c_int, [_VP, _VP, ct.c_int64, _VP]),
+    "sfhk_potential_exp": (ct.c_int, [_VP, _VP, ct.c_int64, _VP]),
 }
 
 
@@ -271,10 +271,11 @@ def spectrum(d: torch.Tensor, t_first: float, dt: float, tau_h: float, n_fft: in
     return om, pw, torch.view_as_complex(x)
 
 
-def exp_cr(x: torch.Tensor, stream=None) -> torch.Tensor:
+def potential_exp(x: torch.Tensor, stream=None) -> torch.Tensor:
+    """exp as evaluated inside the screened potential (device)."""
     y = torch.empty_like(x)
-    _check(lib().sfhk_exp_cr(_dptr(x), _dptr(y), int(x.numel()), _stream_ptr(stream)),
-           "sfhk_exp_cr")
+    _check(lib().sfhk_potential_exp(_dptr(x), _dptr(y), int(x.numel()), _stream_ptr(stream)),
+           "sfhk_potential_exp")
     return y
 
 

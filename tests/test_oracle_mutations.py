@@ -42,8 +42,15 @@ MUTANTS = {
     "resample neighbour": ("d[i] + frac * (d[i + 1] - d[i])", "d[i] + frac * (d[i] - d[i])"),
     "Ip phase sign": ("cexp(I * (y[IY_S] - gs->ip * tn))", "cexp(I * (y[IY_S] + gs->ip * tn))"),
     "default weight sign": ("return cexp(I * pq) / (double)n;", "return cexp(-I * pq) / (double)n;"),
-    "exp not correctly rounded": ("return (double)expq((__float128)x);",
-                                  "return (double)(float)expq((__float128)x);"),
+    "exp reference not correctly rounded": ("return (double)expq((__float128)x);",
+                                            "return (double)(float)expq((__float128)x);"),
+    "contract exp drops the ln2 tail": ("r = fma(-k, EXPC_LN2_LO, r);", "r = r;"),
+    "contract exp one degree short": ("double p = inv_fact[13];\n  for (int n = 12;",
+                                      "double p = inv_fact[12];\n  for (int n = 11;"),
+    "screened exponent scale": ("double e = or_exp_cw(-(r * inv_rs));",
+                                "double e = or_exp_cw(-(r * inv_rs * 0.5));"),
+    "screened 1/r^2 in the Hessian": ("*c = (vpp - *g) * (inv_r * inv_r);",
+                                      "*c = (vpp - *g) * inv_r;"),
 }
 
 

@@ -42,6 +42,25 @@ def test_exp_cr_matches_decimal():
     assert bad == 0
 
 
+def test_contract_exp_within_one_ulp_of_exp():
+    """The exponential inside the screened potential (Cody-Waite reduction, degree-13 Taylor
+    polynomial) differs from the correctly rounded exp by at most one ulp over its range, is
+    exact at 0 and flushes to 0 below -708."""
+    ctx = decimal.Context(prec=60)
+    rng = np.random.default_rng(12)
+    xs = np.concatenate([rng.uniform(-708.0, 0.0, 6000), rng.uniform(-1.0, 1.0, 2000),
+                         -rng.uniform(0.0, 50.0, 2000), [-707.99, -0.3465, 0.3466, -1e-300]])
+    worst = 0.0
+    for x in xs:
+        ref = float(ctx.exp(decimal.Decimal(float(x))))
+        got = O.exp_cw(float(x))
+        worst = max(worst, abs(got - ref) / np.spacing(ref))
+    assert worst <= 1.0, worst
+    assert O.exp_cw(0.0) == 1.0 and O.exp_cw(-0.0) == 1.0
+    assert O.exp_cw(-708.5) == 0.0 and O.exp_cw(-1e4) == 0.0
+    assert math.isnan(O.exp_cw(float("nan")))
+
+
 # ------------------------------------------------------------------------------------------
 # laser field
 # ------------------------------------------------------------------------------------------
