@@ -182,13 +182,22 @@ sfhk_status sfhk_job_trajectories(sfhk_job* job, double* y_out, double* c_out, i
 const char* sfhk_last_error(void);
 const char* sfhk_status_string(sfhk_status s);
 
-/* y[i] = exp(x[i]) for i < n, evaluated exactly as inside the screened potential: Cody-Waite
- * reduction x = k ln2 + r (ln2 split into a 32-significant-bit head and a rounded tail, both
- * applied with fused multiply-adds), the degree-13 Taylor polynomial of exp(r) in Horner form
- * with fused multiply-adds, then scaling by 2^k; 0 for x < -708. Within about one ulp of exp.
- * Exported so the sequence can be checked against an independent implementation. DEVICE
- * pointers; asynchronous on `stream`. */
-sfhk_status sfhk_potential_exp(const double* x, double* y, int64_t n, void* stream);
+/* The two elementary functions of the trajectory arithmetic, exported so their operation
+ * sequences can be checked against an independent implementation (DEVICE pointers, y[i] = f(x[i])
+ * for i < n, asynchronous on `stream`; SFHK_E_INVALID for NULL pointers or n < 0).
+ *
+ * sfhk_traj_exp: exp as evaluated inside the screened potential. Cody-Waite reduction
+ * x = k ln2 + r (ln2 split into a 32-significant-bit head and a rounded tail, both applied with
+ * fused multiply-adds), the degree-13 Taylor polynomial of exp(r) in Horner form with fused
+ * multiply-adds, then scaling by 2^k; 0 for x < -708. Within one ulp of exp.
+ *
+ * sfhk_traj_rsqrt: 1/sqrt(x) as used for every square root and reciprocal on the trajectory path.
+ * Bit-pattern seed (magic constant 0x5FE6EB50C7B537A9), three Newton steps
+ * y <- y (3/2 - (x/2) y^2), a final step y + y (1/2 - (x/2) y^2); arguments outside
+ * [2^-1000, 2^1000] are first scaled by an even power of two. Within one ulp of 1/sqrt(x);
+ * 0 -> +inf, +inf -> 0, negative or NaN -> NaN. */
+sfhk_status sfhk_traj_exp(const double* x, double* y, int64_t n, void* stream);
+sfhk_status sfhk_traj_rsqrt(const double* x, double* y, int64_t n, void* stream);
 
 #ifdef __cplusplus
 }

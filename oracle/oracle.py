@@ -81,6 +81,8 @@ def lib():
         L.or_exp_cr.argtypes = [D]
         L.or_exp_cw.restype = D
         L.or_exp_cw.argtypes = [D]
+        L.or_rsqrt_c.restype = D
+        L.or_rsqrt_c.argtypes = [D]
         for nm in ("or_field_A", "or_field_E", "or_field_intA"):
             getattr(L, nm).restype = D
             getattr(L, nm).argtypes = [D, D, D, D, D]
@@ -152,6 +154,11 @@ def exp_cr(x: float) -> float:
 def exp_cw(x: float) -> float:
     """The exponential the screened potential uses (Cody-Waite + degree-13 Taylor)."""
     return lib().or_exp_cw(float(x))
+
+
+def rsqrt_c(x: float) -> float:
+    """The reciprocal square root of the trajectory arithmetic."""
+    return lib().or_rsqrt_c(float(x))
 
 
 def field_A(t, e0, omega, T, cep=0.0):

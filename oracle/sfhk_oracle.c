@@ -72,6 +72,33 @@ double or_exp_cw(double x) {
 }
 
 /* ------------------------------------------------------------------------------------------ */
+/* the reciprocal square root of the rounding contract: the bit-pattern seed of Lomont's       */
+/* "fast inverse square root" for binary64 (magic constant 0x5FE6EB50C7B537A9, relative error  */
+/* below 3.5%), three Newton steps y <- y (3/2 - (x/2) y^2) and a final step written as         */
+/* y + y (1/2 - (x/2) y^2). Within one ulp of 1/sqrt(x). Arguments outside [2^-1000, 2^1000]    */
+/* are scaled by an even power of two first (exact); 0 -> +inf, +inf -> 0, x < 0 or NaN -> NaN. */
+/* ------------------------------------------------------------------------------------------ */
+static double rsqrt_core(double x) {
+  uint64_t b;
+  memcpy(&b, &x, sizeof b);
+  uint64_t s = UINT64_C(0x5FE6EB50C7B537A9) - (b >> 1);
+  double y;
+  memcpy(&y, &s, sizeof y);
+  double h = 0.5 * x;
+  for (int it = 0; it < 3; ++it) y = y * fma(-h, y * y, 1.5);
+  return fma(y, fma(-h, y * y, 0.5), y);
+}
+
+double or_rsqrt_c(double x) {
+  if (x >= 0x1p-1000 && x <= 0x1p1000) return rsqrt_core(x);
+  if (x != x || x < 0.0) return NAN;
+  if (x == 0.0) return HUGE_VAL;
+  if (x == HUGE_VAL) return 0.0;
+  if (x < 0x1p-1000) return rsqrt_core(x * 0x1p1000) * 0x1p500;
+  return rsqrt_core(x * 0x1p-1000) * 0x1p-500;
+}
+
+/* ------------------------------------------------------------------------------------------ */
 /* laser field (Sec. II.B field equation with the sin^2 envelope; E = -dA/dt, App. A)          */
 /* ------------------------------------------------------------------------------------------ */
 double or_field_A(double t, double e0, double omega, double T, double cep) {
@@ -114,8 +141,7 @@ static void pot_gc(const or_potential* pot, const double* q, double* V, double* 
     case 1: { /* soft-core Coulomb: V = -Z u, u = (r^2+a)^(-1/2) */
       double Z = pot->z_inf;
       double s = r2 + pot->soft2;
-      double rho = sqrt(s);
-      double u = 1.0 / rho;
+      double u = or_rsqrt_c(s);
       double u2 = u * u;
       double u3 = u2 * u;
       double u5 = u3 * u2;
@@ -125,10 +151,13 @@ static void pot_gc(const or_potential* pot, const double* q, double* V, double* 
       return;
     }
     case 2: { /* screened: V = -Z(r)/rho, Z(r) = z_inf + z_in exp(-r/r_scr), rho = sqrt(r^2+a) */
-      double r = sqrt(r2);
       double s = r2 + pot->soft2;
-      double rho = sqrt(s);
-      double ir = 1.0 / rho;
+      double ir = or_rsqrt_c(s);           /* 1/rho */
+      double inv_r = 0.0, r = 0.0;
+      if (r2 > 0.0) {
+        inv_r = or_rsqrt_c(r2);
+        r = r2 * inv_r;
+      }
       double ir2 = ir * ir;
       double ir3 = ir2 * ir;
       double inv_rs = 1.0 / pot->r_scr;
@@ -146,8 +175,7 @@ static void pot_gc(const or_potential* pot, const double* q, double* V, double* 
       double tb = (d1 * r) * ir3;
       double tc = ((Z * w1) * ir3) * ir2;
       double vpp = tc - fma(2.0, tb, ta);
-      if (r > 0.0) {
-        double inv_r = 1.0 / r;
+      if (r2 > 0.0) {
         *g = vp * inv_r;
         *c = (vpp - *g) * (inv_r * inv_r);
       } else { /* r == 0 exactly (measure zero): finite isotropic choice */
@@ -296,18 +324,24 @@ void or_hk_det(const double* m, double gamma, double det[2]) {
   det[1] = d.im;
 }
 
-/* principal square root: branch cut on the negative real axis */
+/* principal square root (branch cut on the negative real axis) of z with |z| = mod:
+ * with w = (mod + |Re z|)/2, sqrt z = (sqrt w, Im z / (2 sqrt w)) for Re z >= 0 and
+ * (|Im z| / (2 sqrt w), sign(Im z) sqrt w) otherwise; sqrt w = w rsqrt(w), 1/sqrt w = rsqrt(w) */
 static cpx csqrt_principal(cpx z, double mod) {
   cpx r;
-  double t = sqrt(0.5 * (mod + fabs(z.re)));
-  if (t == 0.0) {
+  double w = 0.5 * (mod + fabs(z.re));
+  if (w == 0.0) {
     r.re = 0.0;
     r.im = 0.0;
-  } else if (z.re >= 0.0) {
+    return r;
+  }
+  double rw = or_rsqrt_c(w);
+  double t = w * rw;
+  if (z.re >= 0.0) {
     r.re = t;
-    r.im = z.im / (2.0 * t);
+    r.im = (0.5 * z.im) * rw;
   } else {
-    r.re = fabs(z.im) / (2.0 * t);
+    r.re = (0.5 * fabs(z.im)) * rw;
     r.im = copysign(t, z.im);
   }
   return r;
@@ -414,7 +448,8 @@ static void run_traj(const or_potential* pot, const or_ground* gs, const or_hk* 
       break;
     }
     cpx dz = {det[0], det[1]};
-    cpx c = csqrt_principal(dz, sqrt(a2));
+    double mod = a2 > 0.0 ? a2 * or_rsqrt_c(a2) : 0.0; /* |det G| */
+    cpx c = csqrt_principal(dz, mod);
     double dot = fma(c.im, cprev.im, c.re * cprev.re);
     if (sgn * dot < 0.0) sgn = -sgn;
     cpx C = {sgn * c.re, sgn * c.im};

@@ -75,6 +75,9 @@ double or_exp_cr(double x);
 /* The exponential inside the screened potential: Cody-Waite reduction, degree-13 Taylor
  * polynomial, scaling by 2^k; zero below x = -708. Within about 1 ulp of exp. */
 double or_exp_cw(double x);
+/* The reciprocal square root of the trajectory arithmetic: bit-pattern seed, three Newton steps
+ * and a refined final step; within one ulp of 1/sqrt(x). */
+double or_rsqrt_c(double x);
 
 /* Laser field of a linearly polarised sin^2 pulse of total duration T centred at t = 0
  * (Sec. II.B, field equation; E = -dA/dt as in App. A):

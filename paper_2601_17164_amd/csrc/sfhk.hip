@@ -133,6 +133,33 @@ __device__ __forceinline__ cplx overlap(const GtoConst& G, double cut, const dou
   return G.l == 0 ? cmul(a, sum) : sum;
 }
 
+// The dipole integrand f = w C O e^{i (S - Ip t_n)} of one lane (0 when every primitive is skipped).
+// Kept out of line: it runs only for lanes near the ground state, and inlined, the constants and
+// temporaries of its exp and sincos would occupy registers for the whole step loop.
+struct Contrib {
+  double re, im;
+  unsigned int n_eval;
+};
+
+__device__ __noinline__ Contrib contribution(const GtoConst* __restrict__ G, double cut, double qx,
+                                             double qy, double qz, double px, double py, double pz,
+                                             double p2, double q2, double S, double tn, double wcr,
+                                             double wci) {
+  const double q[3] = {qx, qy, qz}, p[3] = {px, py, pz};
+  unsigned int n_eval = 0;
+  const cplx O = overlap(*G, cut, q, p, p2, q2, n_eval);
+  Contrib r = {0.0, 0.0, n_eval};
+  if (O.re != 0.0 || O.im != 0.0) {
+    const double ph = S - G->ip * tn;
+    double sp, cp;
+    sincos(ph, &sp, &cp);
+    const cplx f = cmul(cplx{wcr, wci}, cmul(O, cplx{cp, sp}));
+    r.re = f.re;
+    r.im = f.im;
+  }
+  return r;
+}
+
 // ------------------------------------------------------------------------------------------------
 // initialisation: gather the sorted samples into the SoA state
 // ------------------------------------------------------------------------------------------------
@@ -246,7 +273,7 @@ __device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const 
   const PotParams P = J.pot;
   const int kind = J.kind;
   const double gamma = J.gamma, inv4g = J.inv4g, kay2 = J.kay2, cut = J.cut;
-  const double h = J.h, h2 = J.h2, h6 = J.h6, t_a = J.t_a, ip = J.gto.ip;
+  const double h = J.h, h2 = J.h2, h6 = J.h6, t_a = J.t_a;
 
   int slot_lo = (n_begin - t0) % kRing;
   unsigned int kay = 0, nonfin = 0, prims = 0;
@@ -271,7 +298,8 @@ __device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const 
         else
           ++kay;
       } else {
-        cplx c = csqrt_principal(d, sqrt(a2));
+        const double mod = a2 > 0.0 ? a2 * rsqrt_c(a2) : 0.0;  // |det G|
+        cplx c = csqrt_principal(d, mod);
         double dot = SFHK_FMA(c.im, cprev.im, c.re * cprev.re);
         if (sgn * dot < 0.0) sgn = -sgn;
         C = {sgn * c.re, sgn * c.im};
@@ -285,16 +313,12 @@ __device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const 
     const bool need = contrib && !overlap_all_skipped(J.gto, p2, q2);
     if (__any(need)) {
       if (need) {
-        cplx O = overlap(J.gto, cut, T.q, T.p, p2, q2, prims);
-        if (O.re != 0.0 || O.im != 0.0) {
-          double tn = t_a + (double)n * h;
-          double ph = T.S - ip * tn;
-          double sp, cp;
-          sincos(ph, &sp, &cp);
-          cplx f = cmul(cmul(w, C), cmul(O, cplx{cp, sp}));
-          fr = f.re;
-          fi = f.im;
-        }
+        const cplx wC = cmul(w, C);
+        const Contrib cb = contribution(&J.gto, cut, T.q[0], T.q[1], T.q[2], T.p[0], T.p[1],
+                                        T.p[2], p2, q2, T.S, t_a + (double)n * h, wC.re, wC.im);
+        fr = cb.re;
+        fi = cb.im;
+        prims += cb.n_eval;
       }
     }
     ring[slot][lane] = make_double2(fr, fi);
@@ -490,9 +514,10 @@ __global__ __launch_bounds__(256) void k_dft(const double* __restrict__ xw, cons
   }
 }
 
-__global__ void k_exp(const double* __restrict__ x, double* __restrict__ y, long long n) {
+__global__ void k_traj_fn(int which, const double* __restrict__ x, double* __restrict__ y,
+                          long long n) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = exp_cw(x[i]);
+  if (i < n) y[i] = which == 0 ? exp_cw(x[i]) : rsqrt_c(x[i]);
 }
 
 }  // namespace
@@ -996,12 +1021,21 @@ sfhk_status sfhk_job_trajectories(sfhk_job* job, double* y_out, double* c_out, i
   return SFHK_OK;
 }
 
-sfhk_status sfhk_potential_exp(const double* x, double* y, int64_t n, void* stream) {
-  if (!x || !y || n < 0) return fail(SFHK_E_INVALID, "bad sfhk_potential_exp arguments");
+static sfhk_status traj_fn(int which, const double* x, double* y, int64_t n, void* stream) {
+  if (!x || !y || n < 0) return fail(SFHK_E_INVALID, "NULL pointer or negative count");
   if (n == 0) return SFHK_OK;
-  hipLaunchKernelGGL(k_exp, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, x, y, (long long)n);
+  hipLaunchKernelGGL(k_traj_fn, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, which, x,
+                     y, (long long)n);
   HIP_TRY(hipGetLastError());
   return SFHK_OK;
+}
+
+sfhk_status sfhk_traj_exp(const double* x, double* y, int64_t n, void* stream) {
+  return traj_fn(0, x, y, n, stream);
+}
+
+sfhk_status sfhk_traj_rsqrt(const double* x, double* y, int64_t n, void* stream) {
+  return traj_fn(1, x, y, n, stream);
 }
 
 }  // extern "C"

@@ -6,9 +6,9 @@
 // as an explicit sequence of IEEE-754 binary64 operations with round-to-nearest-even: +, -, *, /,
 // sqrt, and __builtin_fma where a fused multiply-add is part of the sequence. This file must be
 // compiled with -ffp-contract=off so the compiler adds no fusion of its own. gfx950's binary64
-// division and square root are correctly rounded, and the screened potential's exponential is a
-// fixed sequence of such operations (exp_cw below), so a CPU implementation of the same sequence
-// agrees bit for bit.
+// division is correctly rounded, and the square roots and the screened potential's exponential
+// are fixed sequences of such operations (rsqrt_c and exp_cw below), so a CPU implementation of
+// the same sequence agrees bit for bit.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -54,6 +54,35 @@ __device__ __forceinline__ double exp_cw(double x) {
 }
 
 // ----------------------------------------------------------------------------------------------
+// the reciprocal square root of the rounding contract: the binary64 bit-pattern seed with magic
+// constant 0x5FE6EB50C7B537A9 (Lomont; relative error below 3.5%), three Newton steps
+// y <- y (3/2 - (x/2) y^2) and a final step y + y (1/2 - (x/2) y^2); within one ulp of 1/sqrt(x).
+// About 16 VALU operations, against about 36 for a correctly rounded sqrt followed by a division.
+// Arguments outside [2^-1000, 2^1000] are scaled by an even power of two first (exact).
+// ----------------------------------------------------------------------------------------------
+__device__ __forceinline__ double rsqrt_core(double x) {
+  const unsigned long long b = __double_as_longlong(x);
+  double y = __longlong_as_double(0x5FE6EB50C7B537A9ULL - (b >> 1));
+  const double h = 0.5 * x;
+#pragma unroll
+  for (int it = 0; it < 3; ++it) y = y * SFHK_FMA(-h, y * y, 1.5);
+  return SFHK_FMA(y, SFHK_FMA(-h, y * y, 0.5), y);
+}
+
+__device__ __forceinline__ double rsqrt_rare(double x) {
+  if (x != x || x < 0.0) return __builtin_nan("");
+  if (x == 0.0) return __builtin_inf();
+  if (x == __builtin_inf()) return 0.0;
+  if (x < 0x1p-1000) return rsqrt_core(x * 0x1p1000) * 0x1p500;
+  return rsqrt_core(x * 0x1p-1000) * 0x1p-500;
+}
+
+__device__ __forceinline__ double rsqrt_c(double x) {
+  if (__builtin_expect(x >= 0x1p-1000 && x <= 0x1p1000, 1)) return rsqrt_core(x);
+  return rsqrt_rare(x);
+}
+
+// ----------------------------------------------------------------------------------------------
 // atomic model potential V_a (App. A): central, grad V = g q, Hess V = g I + c q q^T
 // ----------------------------------------------------------------------------------------------
 enum PotKind : int { POT_NONE = 0, POT_SOFTCORE = 1, POT_SCREENED = 2, POT_HARMONIC = 3 };
@@ -72,8 +101,7 @@ __device__ __forceinline__ void pot_gc(const PotParams& P, double x, double y, d
   if constexpr (KIND == POT_SOFTCORE) {
     // V = -Z u, u = (r^2 + a)^(-1/2); dV/dr / r = Z u^3; (V'' - V'/r)/r^2 = -3 Z u^5
     double s = r2 + P.soft2;
-    double rho = sqrt(s);
-    double u = 1.0 / rho;
+    double u = rsqrt_c(s);
     double u2 = u * u;
     double u3 = u2 * u;
     double u5 = u3 * u2;
@@ -82,10 +110,13 @@ __device__ __forceinline__ void pot_gc(const PotParams& P, double x, double y, d
     c = (-3.0 * P.z_inf) * u5;
   } else if constexpr (KIND == POT_SCREENED) {
     // V = -Z(r)/rho, Z = z_inf + z_in exp(-r/r_scr), rho = (r^2 + a)^(1/2)
-    double r = sqrt(r2);
     double s = r2 + P.soft2;
-    double rho = sqrt(s);
-    double ir = 1.0 / rho;
+    double ir = rsqrt_c(s);  // 1/rho
+    double inv_r = 0.0, r = 0.0;
+    if (r2 > 0.0) {
+      inv_r = rsqrt_c(r2);
+      r = r2 * inv_r;
+    }
     double ir2 = ir * ir;
     double ir3 = ir2 * ir;
     double e = exp_cw(-(r * P.inv_rscr));
@@ -100,11 +131,11 @@ __device__ __forceinline__ void pot_gc(const PotParams& P, double x, double y, d
     double tb = (d1 * r) * ir3;
     double tc = ((Z * w1) * ir3) * ir2;
     double vpp = tc - SFHK_FMA(2.0, tb, ta);             // V''
-    if (r > 0.0) {
-      double inv_r = 1.0 / r;
+    if (r2 > 0.0) {
       g = vp * inv_r;
       c = (vpp - g) * (inv_r * inv_r);
-    } else {
+    } else {  // r = 0 exactly (measure zero): finite isotropic choice
+
       g = vpp;
       c = 0.0;
     }
@@ -318,12 +349,15 @@ __device__ __forceinline__ cplx hk_det(const double* M, double gamma, double inv
   return cadd(csub(cmul(G[0][0], m0), cmul(G[0][1], m1)), cmul(G[0][2], m2));
 }
 
-// principal square root (cut on the negative real axis), modulus supplied
+// principal square root (cut on the negative real axis) of z with |z| = mod: with
+// w = (mod + |Re z|)/2, sqrt w = w rsqrt(w) and 1/(2 sqrt w) = rsqrt(w)/2
 __device__ __forceinline__ cplx csqrt_principal(cplx z, double mod) {
-  double t = sqrt(0.5 * (mod + fabs(z.re)));
-  if (t == 0.0) return {0.0, 0.0};
-  if (z.re >= 0.0) return {t, z.im / (2.0 * t)};
-  return {fabs(z.im) / (2.0 * t), copysign(t, z.im)};
+  const double w = 0.5 * (mod + fabs(z.re));
+  if (w == 0.0) return {0.0, 0.0};
+  const double rw = rsqrt_c(w);
+  const double t = w * rw;
+  if (z.re >= 0.0) return {t, (0.5 * z.im) * rw};
+  return {(0.5 * fabs(z.im)) * rw, copysign(t, z.im)};
 }
 
 }  // namespace sfhk

@@ -81,7 +81,8 @@ _SIGS = {
     "sfhk_job_trajectories": (ct.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "sfhk_last_error": (ct.c_char_p, []),
     "sfhk_status_string": (ct.c_char_p, [ct.c_int]),
-    "sfhk_potential_exp": (ct.c_int, [_VP, _VP, ct.c_int64, _VP]),
+    "sfhk_traj_exp": (ct.c_int, [_VP, _VP, ct.c_int64, _VP]),
+    "sfhk_traj_rsqrt": (ct.c_int, [_VP, _VP, ct.c_int64, _VP]),
 }
 
 
@@ -271,11 +272,19 @@ def spectrum(d: torch.Tensor, t_first: float, dt: float, tau_h: float, n_fft: in
     return om, pw, torch.view_as_complex(x)
 
 
-def potential_exp(x: torch.Tensor, stream=None) -> torch.Tensor:
+def traj_exp(x: torch.Tensor, stream=None) -> torch.Tensor:
     """exp as evaluated inside the screened potential (device)."""
     y = torch.empty_like(x)
-    _check(lib().sfhk_potential_exp(_dptr(x), _dptr(y), int(x.numel()), _stream_ptr(stream)),
-           "sfhk_potential_exp")
+    _check(lib().sfhk_traj_exp(_dptr(x), _dptr(y), int(x.numel()), _stream_ptr(stream)),
+           "sfhk_traj_exp")
+    return y
+
+
+def traj_rsqrt(x: torch.Tensor, stream=None) -> torch.Tensor:
+    """1/sqrt(x) as evaluated on the trajectory path (device)."""
+    y = torch.empty_like(x)
+    _check(lib().sfhk_traj_rsqrt(_dptr(x), _dptr(y), int(x.numel()), _stream_ptr(stream)),
+           "sfhk_traj_rsqrt")
     return y
 
 

@@ -79,9 +79,23 @@ def test_potential_exp_matches_oracle_bitwise(S):
     x = np.concatenate([rng.uniform(-750.0, 0.0, 20000), rng.uniform(-3.0, 3.0, 5000),
                         -rng.uniform(0.0, 200.0, 5000) / 0.6,
                         [0.0, -0.0, -1e-300, -707.99, -708.0, -708.01, -745.2, 709.7, 0.3466]])
-    y = sfhk.potential_exp(torch.from_numpy(x).cuda()).cpu().numpy()
+    y = sfhk.traj_exp(torch.from_numpy(x).cuda()).cpu().numpy()
     ref = np.array([O.exp_cw(v) for v in x])
     assert np.array_equal(y, ref), f"{np.sum(y != ref)} of {len(x)} differ"
+
+
+def test_trajectory_rsqrt_matches_oracle_bitwise(S):
+    """The reciprocal square root of the trajectory arithmetic, device against oracle, over the
+    binary64 range including the scaled and special arguments."""
+    sfhk, ctx, torch = S
+    rng = np.random.default_rng(6)
+    x = np.concatenate([np.exp(rng.uniform(-744.0, 709.0, 20000)), rng.uniform(0.0, 4.0, 10000),
+                        [0.0, -0.0, 5e-324, 2.0 ** -1000, 2.0 ** 1000, 1.7976931348623157e308,
+                         np.inf, -1.0, np.nan, 0.01, 1.0]])
+    y = sfhk.traj_rsqrt(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = np.array([O.rsqrt_c(v) for v in x])
+    same = (y == ref) | (np.isnan(y) & np.isnan(ref))
+    assert same.all(), f"{np.sum(~same)} of {len(x)} differ"
 
 
 def test_config0_full_matches_oracle(S):

@@ -51,6 +51,11 @@ MUTANTS = {
                                 "double e = or_exp_cw(-(r * inv_rs * 0.5));"),
     "screened 1/r^2 in the Hessian": ("*c = (vpp - *g) * (inv_r * inv_r);",
                                       "*c = (vpp - *g) * inv_r;"),
+    "rsqrt: one Newton step short": ("for (int it = 0; it < 3; ++it)", "for (int it = 0; it < 2; ++it)"),
+    "rsqrt: tiny arguments unscaled": ("return rsqrt_core(x * 0x1p1000) * 0x1p500;",
+                                       "return rsqrt_core(x);"),
+    "principal sqrt: imaginary part halved twice": ("r.im = (0.5 * z.im) * rw;",
+                                                    "r.im = (0.25 * z.im) * rw;"),
 }
 
 

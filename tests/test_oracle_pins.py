@@ -61,6 +61,24 @@ def test_contract_exp_within_one_ulp_of_exp():
     assert math.isnan(O.exp_cw(float("nan")))
 
 
+def test_contract_rsqrt_within_one_ulp():
+    """The reciprocal square root of the trajectory arithmetic is within one ulp of 1/sqrt(x)
+    (decimal arithmetic) over the whole binary64 range, and handles the special values."""
+    ctx = decimal.Context(prec=60)
+    rng = np.random.default_rng(13)
+    xs = np.concatenate([np.exp(rng.uniform(-740.0, 709.0, 6000)), rng.uniform(0.01, 4.0, 3000),
+                         [5e-324, 2.2250738585072014e-308, 2.0 ** -1000, 2.0 ** 1000, 1.7976931348623157e308,
+                          1.0, 4.0, 0.25, 0.01]])
+    worst = 0.0
+    for x in xs:
+        ref = float(1 / ctx.sqrt(decimal.Decimal(float(x))))
+        got = O.rsqrt_c(float(x))
+        worst = max(worst, abs(got - ref) / np.spacing(ref))
+    assert worst <= 1.0, worst
+    assert O.rsqrt_c(0.0) == math.inf and O.rsqrt_c(math.inf) == 0.0
+    assert math.isnan(O.rsqrt_c(-1.0)) and math.isnan(O.rsqrt_c(float("nan")))
+
+
 # ------------------------------------------------------------------------------------------
 # laser field
 # ------------------------------------------------------------------------------------------
