@@ -15,6 +15,7 @@ workload (it is test infrastructure; the product path never calls it).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +27,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CUs x 2.4 GHz x 128 FP64 operations per CU-clock
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "propagate_traffic.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("sfhk.hip", "sfhk_device.hpp"):
+        with open(os.path.join(ROOT, "paper_2601_17164_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(n_traj: int):
+    """HBM bytes of one propagate launch from the rocprofv3 FETCH_SIZE/WRITE_SIZE runs recorded
+    with the profile, if they were taken on this kernel source and this workload; else None."""
+    try:
+        with open(TRAFFIC_RECORD) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash() or rec.get("n_traj") != n_traj:
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
 
 
 def _args():
@@ -156,7 +179,8 @@ def main():
                        "p99": float(np.percentile(lat_ms, 99))},
         "roofline": {"bound": "alu", "kernel": "k_propagate_fp64 (screened)",
                      "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": recorded_traffic(inst.n_traj),
                      "kernel_ms": float(kern_ms.mean()),
                      "flop_per_launch": fl},
         "stats": {"kay_removed": s0.kay_removed, "nonfinite_removed": s0.nonfinite_removed,
