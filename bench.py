@@ -60,9 +60,11 @@ def _args():
     ap.add_argument("--n-birth", type=int, default=1024)
     ap.add_argument("--n-per-birth", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-births", type=int, default=16,
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the FP32-mixed pass over the same inputs")
+    ap.add_argument("--cpu-births", type=int, default=64,
                     help="birth groups (spread over the pulse) in the oracle's sample")
-    ap.add_argument("--cpu-per-birth", type=int, default=64)
+    ap.add_argument("--cpu-per-birth", type=int, default=256)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (calibrates the "
                          "HBM traffic counters) and exit")
@@ -100,6 +102,40 @@ def cpu_baseline(inst, n_births, n_per):
                       f"({r.steps_evaluated} trajectory-steps, {dt:.1f} s)"}
 
 
+def mixed_form(step, stream, inst, arrays, ref_spectrum, flops):
+    """One pass of the FP32-mixed form over the same inputs: its rate, its spectral error against
+    the FP64 kernel's spectrum (which matches the FP64 oracle to 1e-9), and beside it the
+    conditioning floor of the workload: the FP64 spectrum of the samples with q0 moved by one ulp
+    against the unmoved one."""
+    import torch
+    from paper_2601_17164_amd import metrics
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    job, (om, pw, x) = step(ev, precision=1)
+    st = job.stats(stream)
+    wall = time.perf_counter() - t
+    job.close()
+    kms = ev[0].elapsed_time(ev[1])
+    fl = flops.flops(inst.potential.kind, inst.ground.l, st.steps_evaluated, st.prims_evaluated)
+    om_r, _, x_r = ref_spectrum
+    band = lambda xx: metrics.spectral_report(om_r.cpu().numpy(), xx.cpu().numpy(),
+                                              x_r.cpu().numpy(), inst.ground.ip, inst.pulse.up,
+                                              inst.pulse.omega)
+    q0 = arrays["q0"]
+    arrays["q0"] = torch.nextafter(q0, torch.full_like(q0, float("inf")))
+    job, (_, _, x_p) = step([torch.cuda.Event(enable_timing=True) for _ in range(2)])
+    torch.cuda.synchronize()
+    job.close()
+    arrays["q0"] = q0
+    return {"value": st.steps_evaluated / wall, "unit": "trajectory-steps/s",
+            "kernel_ms": kms,
+            "frac_of_fp64_vector_peak": fl / (kms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+            "fp64_step_fraction": st.steps_fp64 / max(1, st.steps_evaluated),
+            "spectral_error_vs_fp64": band(x), "fp64_one_ulp_floor": band(x_p),
+            "kay_max": inst.kay_max}
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -122,18 +158,18 @@ def main():
     n_out = inst.n_out
     dt_out = T / n_out
 
-    def step(ev):
-        job = sfhk.make_job(ctx, inst, arrays)
+    def step(ev, precision=0):
+        job = sfhk.make_job(ctx, inst, arrays, precision=precision)  # arrays: read at each call
         ev[0].record(stream)
         done = job.propagate(0)
         ev[1].record(stream)
         assert done
         d = job.dipole()
-        om, pw, _ = sfhk.spectrum(d, inst.grid.t_a, dt_out, T / 2)
-        return job, pw
+        om, pw, x = sfhk.spectrum(d, inst.grid.t_a, dt_out, T / 2)
+        return job, (om, pw, x)
 
     for _ in range(a.warmup):
-        job, pw = step([torch.cuda.Event(enable_timing=True) for _ in range(2)])
+        job, spec = step([torch.cuda.Event(enable_timing=True) for _ in range(2)])
         torch.cuda.synchronize()
         job.close()
 
@@ -144,7 +180,7 @@ def main():
     t0 = time.perf_counter()
     marks[0].record(stream)
     for k in range(a.steps):
-        job, pw = step(evs[k])
+        job, spec = step(evs[k])
         marks[k + 1].record(stream)
         stats.append(job.stats(stream))  # synchronises the stream
         job.close()
@@ -186,6 +222,8 @@ def main():
         "stats": {"kay_removed": s0.kay_removed, "nonfinite_removed": s0.nonfinite_removed,
                   "prims_per_step": s0.prims_evaluated / max(1, s0.steps_evaluated)},
     }
+    if not a.no_mixed:
+        out["fp32_mixed"] = mixed_form(step, stream, inst, arrays, spec, flops)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, a.cpu_births, a.cpu_per_birth)
     print(json.dumps(out), flush=True)

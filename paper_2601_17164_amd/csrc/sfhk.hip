@@ -23,6 +23,7 @@
 
 #include "../../include/sfhk.h"
 #include "sfhk_device.hpp"
+#include "sfhk_device_f32.hpp"
 
 using namespace sfhk;
 
@@ -66,6 +67,7 @@ struct JobDev {
   PotParams pot;
   GtoConst gto;
   double gamma, inv4g, kay2, cut;
+  double r64sq;  // mixed precision: steps that start at r^2 < r64sq run in FP64
   double t_a, h, h2, h6;
   int n_steps;
   int n_tiles;
@@ -387,6 +389,191 @@ void k_propagate_fp64(
 }
 
 // ------------------------------------------------------------------------------------------------
+// propagation, mixed precision: q, p, M carried and integrated in FP32 away from the nucleus; the
+// action, the HK square root and branch, the dipole integrand and the reduction in FP64; a lane
+// whose step starts at r < r_fp64 takes the FP64 step on its exactly promoted state and rounds the
+// result back to FP32. The precision decision is per lane, so a trajectory's result does not
+// depend on the other trajectories of its wave.
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ void run_tile_mixed(const JobDev& J, const int tile, const int max_steps,
+                                               double2 (*ring)[kRingStride]) {
+  const int lane = threadIdx.x;
+  const int n_begin = J.tile_next[tile];
+  const int N = J.n_steps;
+  if (n_begin > N) return;
+  const int n_stop = (max_steps > 0) ? min(N, n_begin + max_steps - 1) : N;
+  const long long np = J.n_pad;
+  const long long s = (long long)tile * kTile + lane;
+
+  TrajF T;
+  const double* y = J.y;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T.q[i] = (float)y[i * np + s];
+    T.p[i] = (float)y[(3 + i) * np + s];
+  }
+#pragma unroll
+  for (int c = 0; c < 36; ++c) T.M[c] = (float)y[(6 + c) * np + s];
+  T.S = y[42 * np + s];
+  cplx cprev = {J.aux[s], J.aux[np + s]};
+  const cplx w = {J.aux[2 * np + s], J.aux[3 * np + s]};
+  double sgn = J.aux[4 * np + s];
+  const int n0l = J.n0[s];
+  const int death_in = J.death[s];
+  int death = death_in;
+  bool alive = death_in == -1;
+
+  const int t0 = J.tile_n0[tile];
+  const long long roff = J.row_off[tile];
+  double2* __restrict__ part = J.part;
+  const const_dptr eh = (const_dptr)J.e_half;
+  const PotParams P = J.pot;
+  const PotParamsF PF = {(float)P.z_inf, (float)P.z_in, (float)P.soft2, (float)P.omega_ho,
+                         (float)P.inv_rscr};
+  const int kind = J.kind;
+  const double kay2 = J.kay2, cut = J.cut;
+  const double h = J.h, h2 = J.h2, h6 = J.h6, t_a = J.t_a;
+  const float hf = (float)h, h2f = (float)h2, h6f = (float)h6;
+  const float gammaf = (float)J.gamma, inv4gf = (float)J.inv4g;
+  const float aminf = (float)J.gto.Amin, bminf = (float)J.gto.Bmin;
+  const float cut_lo = (float)(J.cut * (1.0 + 1e-5));  // FP32 bound: margin for FP32 rounding
+  const float r64sq = (float)J.r64sq;
+
+  int slot_lo = (n_begin - t0) % kRing;
+  unsigned int kay = 0, nonfin = 0, prims = 0, steps64 = 0;
+  int n = n_begin;
+  double ea = eh[2 * n];
+  for (; n <= n_stop; ++n) {
+    const int slot = (n - t0) % kRing;
+    double fr = 0.0, fi = 0.0;
+    bool contrib = false;
+    cplx C = {0.0, 0.0};
+    if (alive && n >= n0l) {
+      cplx d = hk_det_f32(T.M, gammaf, inv4gf);
+      double a2 = d.re * d.re;
+      a2 = SFHK_FMA(d.im, d.im, a2);
+      bool finite = isfinite(T.q[0]) && isfinite(T.q[1]) && isfinite(T.q[2]) &&
+                    isfinite(T.p[0]) && isfinite(T.p[1]) && isfinite(T.p[2]) && isfinite(T.S);
+      if (!(a2 <= kay2) || !finite) {
+        alive = false;
+        death = n;
+        if (!finite || isnan(a2))
+          ++nonfin;
+        else
+          ++kay;
+      } else {
+        const double mod = a2 > 0.0 ? a2 * rsqrt_c(a2) : 0.0;
+        cplx c = csqrt_principal(d, mod);
+        double dot = SFHK_FMA(c.im, cprev.im, c.re * cprev.re);
+        if (sgn * dot < 0.0) sgn = -sgn;
+        C = {sgn * c.re, sgn * c.im};
+        cprev = C;
+        contrib = true;
+      }
+    }
+    const float p2f = __builtin_fmaf(T.p[2], T.p[2], __builtin_fmaf(T.p[1], T.p[1], T.p[0] * T.p[0]));
+    const float q2f = __builtin_fmaf(T.q[2], T.q[2], __builtin_fmaf(T.q[1], T.q[1], T.q[0] * T.q[0]));
+    const bool need = contrib && !(__builtin_fmaf(p2f, aminf, q2f * bminf) > cut_lo);
+    if (__any(need)) {
+      if (need) {
+        const double qx = T.q[0], qy = T.q[1], qz = T.q[2], px = T.p[0], py = T.p[1], pz = T.p[2];
+        const double p2 = SFHK_FMA(pz, pz, SFHK_FMA(py, py, px * px));
+        const double q2 = SFHK_FMA(qz, qz, SFHK_FMA(qy, qy, qx * qx));
+        const cplx wC = cmul(w, C);
+        const Contrib cb = contribution(&J.gto, cut, qx, qy, qz, px, py, pz, p2, q2, T.S,
+                                        t_a + (double)n * h, wC.re, wC.im);
+        fr = cb.re;
+        fi = cb.im;
+        prims += cb.n_eval;
+      }
+    }
+    ring[slot][lane] = make_double2(fr, fi);
+    const bool last = (n == n_stop);
+    if (slot == kRing - 1 || last) {
+      flush_ring(ring, lane, slot_lo, slot, part, roff + (n - slot - t0));
+      slot_lo = 0;
+    }
+    if (n < N) {
+      const double eb = eh[2 * n + 1], ec = eh[2 * n + 2];
+      if (alive && n >= n0l) {
+        if (q2f < r64sq) {  // near the nucleus: the FP64 step on the promoted state
+          Traj D;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            D.q[i] = T.q[i];
+            D.p[i] = T.p[i];
+          }
+#pragma unroll
+          for (int c = 0; c < 36; ++c) D.M[c] = T.M[c];
+          D.S = T.S;
+          rk4_step(kind, P, D, ea, eb, ec, h, h2, h6);
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            T.q[i] = (float)D.q[i];
+            T.p[i] = (float)D.p[i];
+          }
+#pragma unroll
+          for (int c = 0; c < 36; ++c) T.M[c] = (float)D.M[c];
+          T.S = D.S;
+          ++steps64;
+        } else {
+          rk4_step_f32(kind, PF, T, (float)ea, (float)eb, (float)ec, hf, h2f, h6f, h6);
+        }
+      }
+      ea = ec;
+    }
+    if (!__any(alive)) {
+      if (!(slot == kRing - 1 || last)) flush_ring(ring, lane, slot_lo, slot, part, roff + (n - slot - t0));
+      ++n;
+      break;
+    }
+  }
+  double* yw = J.y;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    yw[i * np + s] = T.q[i];
+    yw[(3 + i) * np + s] = T.p[i];
+  }
+#pragma unroll
+  for (int c = 0; c < 36; ++c) yw[(6 + c) * np + s] = T.M[c];
+  yw[42 * np + s] = T.S;
+  J.aux[s] = cprev.re;
+  J.aux[np + s] = cprev.im;
+  J.aux[4 * np + s] = sgn;
+  J.death[s] = death;
+  const bool finished = !__any(alive) || n > N;
+  if (lane == 0) {
+    J.tile_next[tile] = finished ? N + 1 : n;
+    J.tile_last[tile] = n - 1;
+  }
+  int evals = 0;
+  if (death_in == -1) {
+    const int first = max(n_begin, n0l);
+    const int lastn = death >= 0 ? death : n - 1;
+    evals = max(0, lastn - first + 1);
+  }
+  double ev = wave_sum((double)evals), ka = wave_sum((double)kay), nf = wave_sum((double)nonfin);
+  double pr = wave_sum((double)prims), s64 = wave_sum((double)steps64);
+  if (lane == 0) {
+    atomicAdd(&J.counters[0], (unsigned long long)ev);
+    atomicAdd(&J.counters[1], (unsigned long long)ka);
+    atomicAdd(&J.counters[2], (unsigned long long)nf);
+    atomicAdd(&J.counters[3], (unsigned long long)s64);
+    atomicAdd(&J.counters[4], (unsigned long long)pr);
+  }
+}
+
+#ifndef SFHK_MIXED_WAVES_PER_EU
+#define SFHK_MIXED_WAVES_PER_EU 2
+#endif
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_MIXED_WAVES_PER_EU)))
+void k_propagate_mixed(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work, int max_steps) {
+  __shared__ double2 ring[kRing][kRingStride];
+  const WorkItem wi = work[blockIdx.x];
+  run_tile_mixed(jobs[wi.job], wi.tile, max_steps, ring);
+}
+
+// ------------------------------------------------------------------------------------------------
 // reduction of the partial rows (fixed order) and the dipole
 // ------------------------------------------------------------------------------------------------
 __global__ void k_reduce_groups(JobDev J, double2* __restrict__ gsum) {
@@ -599,10 +786,13 @@ void job_free(sfhk_job* j) {
 
 int blocks_for(long long n, int t) { return (int)((n + t - 1) / t); }
 
-sfhk_status launch_propagate(const JobDev* descs, const WorkItem* work, int n_items, int max_steps,
-                             hipStream_t st) {
+sfhk_status launch_propagate(int precision, const JobDev* descs, const WorkItem* work, int n_items,
+                             int max_steps, hipStream_t st) {
   if (n_items <= 0) return SFHK_OK;
-  hipLaunchKernelGGL(k_propagate_fp64, dim3(n_items), dim3(kTile), 0, st, descs, work, max_steps);
+  if (precision == SFHK_FP32_MIXED)
+    hipLaunchKernelGGL(k_propagate_mixed, dim3(n_items), dim3(kTile), 0, st, descs, work, max_steps);
+  else
+    hipLaunchKernelGGL(k_propagate_fp64, dim3(n_items), dim3(kTile), 0, st, descs, work, max_steps);
   HIP_TRY(hipGetLastError());
   return SFHK_OK;
 }
@@ -776,6 +966,7 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   H.inv4g = 1.0 / (4.0 * g);
   H.kay2 = params->kay_max * params->kay_max;
   H.cut = params->overlap_cut;
+  H.r64sq = params->r_fp64 * params->r_fp64;
   H.t_a = grid->t_a;
   H.h = grid->h;
   H.h2 = 0.5 * grid->h;
@@ -867,7 +1058,7 @@ sfhk_status sfhk_propagate(sfhk_job* job, int64_t max_steps, void* stream) {
   const int nt = unfinished_tiles(job, job->steps_done);
   if (nt > 0) {
     int ms = (max_steps <= 0 || max_steps > NS + 1) ? 0 : (int)max_steps;
-    sfhk_status rc = launch_propagate(job->dev, job->work, nt, ms, st);
+    sfhk_status rc = launch_propagate(job->precision, job->dev, job->work, nt, ms, st);
     if (rc) return rc;
   }
   job->steps_done += (max_steps <= 0) ? (long long)NS + 1 : max_steps;
@@ -889,7 +1080,7 @@ sfhk_status sfhk_propagate_many(sfhk_job* const* jobs, int32_t n_jobs, int64_t m
   // one launch over the unfinished tiles of every job, ordered by steps left (longest first)
   struct Item {
     long long left;
-    int job, tile;
+    int job, tile, precision;
   };
   std::vector<Item> items;
   for (int i = 0; i < n_jobs; ++i) {
@@ -897,9 +1088,13 @@ sfhk_status sfhk_propagate_many(sfhk_job* const* jobs, int32_t n_jobs, int64_t m
     if (j->done) continue;
     const int NS = j->host.n_steps;
     const int nt = unfinished_tiles(j, j->steps_done);
-    for (int t = 0; t < nt; ++t) items.push_back({NS + 1 - (j->tile_n0_host[t] + j->steps_done), i, t});
+    for (int t = 0; t < nt; ++t)
+      items.push_back({NS + 1 - (j->tile_n0_host[t] + j->steps_done), i, t, j->precision});
   }
-  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.left > b.left; });
+  // one launch per precision (each precision has its own kernel), each ordered longest first
+  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
+    return a.precision != b.precision ? a.precision < b.precision : a.left > b.left;
+  });
   if (!items.empty()) {
     HIP_TRY(hipStreamSynchronize(st));  // the staging buffers of the previous call are free
     if (ctx->many_desc_cap < (size_t)n_jobs) {
@@ -927,8 +1122,15 @@ sfhk_status sfhk_propagate_many(sfhk_job* const* jobs, int32_t n_jobs, int64_t m
     HIP_TRY(hipMemcpyAsync(ctx->many_desc, ctx->many_desc_host, n_jobs * sizeof(JobDev), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(ctx->many_work, ctx->many_work_host, items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, st));
     int ms = (max_steps <= 0 || max_steps > INT32_MAX / 2) ? 0 : (int)max_steps;
-    sfhk_status rc = launch_propagate(ctx->many_desc, ctx->many_work, (int)items.size(), ms, st);
-    if (rc) return rc;
+    size_t a = 0;
+    while (a < items.size()) {
+      size_t b = a;
+      while (b < items.size() && items[b].precision == items[a].precision) ++b;
+      sfhk_status rc = launch_propagate(items[a].precision, ctx->many_desc, ctx->many_work + a,
+                                        (int)(b - a), ms, st);
+      if (rc) return rc;
+      a = b;
+    }
   }
   sfhk_status agg = SFHK_OK;
   for (int i = 0; i < n_jobs; ++i) {

@@ -1,0 +1,150 @@
+"""The FP32-mixed form (q, p and the monodromy in FP32 away from the nucleus; action, near-nucleus
+steps, HK square root, dipole integrand and reduction in FP64), through the C ABI.
+
+It is held to a stated spectral error against the FP64 oracle (dB over the plateau and cutoff
+bands), and to exact determinism: the same result when repeated, when propagated in chunks and
+when batched with other jobs.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2601_17164_amd import inputs as I, metrics
+from tests.common import rel_l2, require_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+MIXED = 1
+# Stated accuracy of the mixed form against the FP64 oracle, per band (E_dB), at a Kay limit of
+# D_t = 1e4 on |C|^2. det G of a monodromy stretched by a factor lam carries a relative error of
+# order lam^2 eps, so with the monodromy in FP32 (eps = 2^-24) prefactors of trajectories
+# stretched beyond ~1e3 are not resolved; at the workloads' D_t = 1e30 the mixed spectrum is
+# therefore only as close to the FP64 one as the FP64 one is to itself under a 1-ulp change of the
+# samples (both O(1): the workloads are chaotic), which the benchmark reports side by side.
+KAY_MIXED = 1e4
+E_DB_MAX = {"config0": -20.0, "config1-subset": -35.0}
+
+
+@pytest.fixture(scope="module")
+def S():
+    require_gpu()
+    import torch
+    from paper_2601_17164_amd import sfhk
+    ctx = sfhk.Context(0)
+    yield sfhk, ctx, torch
+    ctx.close()
+
+
+def _run(S, inst, precision=MIXED, chunk=0, r_fp64=2.0):
+    sfhk, ctx, torch = S
+    job = sfhk.make_job(ctx, inst, precision=precision, r_fp64=r_fp64)
+    if chunk:
+        while not job.propagate(chunk):
+            pass
+    else:
+        assert job.propagate(0)
+    d, f = job.dipole(want_f=True)
+    y, c, death = job.trajectories()
+    st = job.stats()
+    torch.cuda.synchronize()
+    out = dict(d=d.cpu().numpy(), F=(f[0] + 1j * f[1]).cpu().numpy(), y=y.cpu().numpy(),
+               c=(c[0] + 1j * c[1]).cpu().numpy(), death=death.cpu().numpy(), stats=st)
+    job.close()
+    return out
+
+
+def _spectral(inst, d, d_ref):
+    T = inst.grid.h * inst.grid.n_steps
+    if inst.n_out:
+        dt, n = T / inst.n_out, inst.n_out
+    else:
+        dt, n = inst.grid.h, len(d)
+    om, _, x = O.spectrum(d, inst.grid.t_a, dt, T / 2)
+    _, _, xr = O.spectrum(d_ref, inst.grid.t_a, dt, T / 2)
+    return metrics.spectral_report(om, x, xr, inst.ground.ip, inst.pulse.up, inst.pulse.omega)
+
+
+def _check_against_oracle(S, name, inst):
+    r = run_oracle(inst)
+    g = _run(S, inst)
+    d_ref = O.dipole(r.F)
+    if inst.n_out:
+        d_ref = O.resample(d_ref, inst.n_out)
+    rep = _spectral(inst, g["d"], d_ref)
+    st = g["stats"]
+    drift = metrics.det_monodromy_drift(g["y"])  # at each trajectory's last evaluated step
+    print(f"[{name}] mixed vs FP64 oracle: {rep}; FP64-step fraction "
+          f"{st.steps_fp64 / max(1, st.steps_evaluated):.4f}; |det M - 1| median "
+          f"{np.median(drift):.2e} max {np.max(drift):.2e}; removed {int(np.sum(g['death'] >= 0))}"
+          f"/{len(g['death'])}; rel-L2(F) {rel_l2(g['F'], r.F):.3e}", flush=True)
+    for band, e in rep.items():
+        assert e["E_dB"] is not None and e["E_dB"] <= E_DB_MAX[name], (band, e)
+    assert st.steps_evaluated > 0
+
+
+def test_mixed_config0_spectral_error(S):
+    inst = I.config0()
+    inst.kay_max = KAY_MIXED
+    _check_against_oracle(S, "config0", inst)
+
+
+def test_mixed_config1_subset_spectral_error(S):
+    c1 = I.config1()
+    inst = I.config1_birth_subset(c1, range(0, 1024, 32), 32)
+    inst.kay_max = KAY_MIXED
+    _check_against_oracle(S, "config1-subset", inst)
+
+
+def test_mixed_volkov_closed_form(S):
+    """Laser-only motion in the mixed form: M = [[I, tau I], [0, I]] and C = (1 - i gamma tau)^{3/2}
+    to FP32 accuracy, with every step on the FP32 path (r_fp64 = 0)."""
+    pulse = I.Pulse(800.0, 1e14, 2.0)
+    grid = I.time_grid(pulse, 0.05)
+    e = I.field_table(pulse, grid)
+    inst = I.Instance("volkov", I.Potential(I.POT_NONE, 0, 0, 1, 0, 0), I.gto_h1s(), pulse, grid,
+                      e, np.array([grid.t_a + 100 * grid.h]), np.array([[3.0], [-2.0], [2.5]]),
+                      np.array([[0.1], [0.2], [-0.3]]))
+    g = _run(S, inst, r_fp64=0.0)
+    tau = (grid.n_steps - 100) * grid.h
+    y = g["y"][:, 0]
+    # FP32 accumulation over ~4300 steps: relative error of order steps x 2^-24
+    for j in range(3):
+        assert abs(y[6 + 6 * (3 + j) + j] - tau) < 1e-3 * tau
+        assert abs(y[6 + 6 * j + j] - 1.0) < 1e-5
+    C_ref = (1 + (0.5 * tau) ** 2) ** 0.75 * np.exp(-1.5j * np.arctan(0.5 * tau))
+    assert abs(g["c"][0] - C_ref) / abs(C_ref) < 1e-3
+    assert g["stats"].steps_fp64 == 0
+
+
+def test_mixed_precision_switch(S):
+    """r_fp64 = 0: no FP64 steps; a huge r_fp64: every propagated step is an FP64 step."""
+    inst = I.config0(n_birth=4, n_per_birth=16)
+    a = _run(S, inst, r_fp64=0.0)
+    assert a["stats"].steps_fp64 == 0
+    b = _run(S, inst, r_fp64=1e6)
+    st = b["stats"]
+    removed = int(np.sum(b["death"] >= 0))
+    # every evaluated step except the last of each surviving trajectory and the removal steps
+    survivors = inst.n_traj - removed
+    assert st.steps_fp64 == st.steps_evaluated - survivors - removed
+
+
+def test_mixed_is_deterministic_chunked_and_batched(S):
+    sfhk, ctx, torch = S
+    inst = I.config0(n_birth=16, n_per_birth=32)
+    a = _run(S, inst)
+    b = _run(S, inst)
+    np.testing.assert_array_equal(a["d"], b["d"])
+    c = _run(S, inst, chunk=53)
+    np.testing.assert_array_equal(a["F"], c["F"])
+    np.testing.assert_array_equal(a["y"], c["y"])
+    # in one call with an FP64 job and another mixed job
+    other = I.config0(n_birth=8, n_per_birth=8, seed=9)
+    jobs = [sfhk.make_job(ctx, inst, precision=MIXED), sfhk.make_job(ctx, other, precision=0),
+            sfhk.make_job(ctx, other, precision=MIXED)]
+    while not sfhk.propagate_many(jobs, 200):
+        pass
+    d0 = jobs[0].dipole().cpu().numpy()
+    np.testing.assert_array_equal(d0, a["d"])
+    for j in jobs:
+        j.close()
