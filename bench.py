@@ -65,6 +65,18 @@ def _args():
     ap.add_argument("--cpu-births", type=int, default=64,
                     help="birth groups (spread over the pulse) in the oracle's sample")
     ap.add_argument("--cpu-per-birth", type=int, default=256)
+    ap.add_argument("--batch", action="store_true",
+                    help="instead: the 64-instance uneven batch in one graph-captured launch per "
+                         "precision (FP64 and FP32-mixed), autotuned launch form")
+    ap.add_argument("--batch-size", type=int, default=64)
+    ap.add_argument("--serve", action="store_true",
+                    help="instead: the serving sweep (Poisson arrivals at --rates, FP64 and mixed)")
+    ap.add_argument("--rates", default="5,10,20,50")
+    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--serve-warmup", type=int, default=20)
+    ap.add_argument("--serve-chunk", type=int, default=1024)
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the short serving run of the default benchmark")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (calibrates the "
                          "HBM traffic counters) and exit")
@@ -136,6 +148,83 @@ def mixed_form(step, stream, inst, arrays, ref_spectrum, flops):
             "kay_max": inst.kay_max}
 
 
+def serving_run(ctx, rate, n_req, warmup, precision, chunk, reqs=None, verbose=False):
+    """Poisson arrivals at `rate` of requests drawn from the uneven-batch distribution (request r
+    has seed 4000 + r); returns latency percentiles and throughput over the non-warm-up requests."""
+    from paper_2601_17164_amd import inputs as I, serve, sfhk
+    n = warmup + n_req
+    if reqs is None:
+        reqs = [I.serving_request(k) for k in range(n)]
+    t = serve.poisson_arrivals(rate, n, seed=4000 + int(round(rate * 1000)))
+    requests = [serve.Request(k, float(t[k]), reqs[k]) for k in range(n)]
+    max_tiles = sum(sfhk.tiles_of(x) for x in reqs)
+    srv = serve.Server(ctx, precision=precision, chunk=chunk, workers_per_cu=0,
+                       max_jobs=min(64, n), max_tiles=max_tiles)
+    res = srv.run(requests)
+    srv.close()
+    kept = [r for r in res if r.req_id >= warmup]
+    summ = serve.summarize(kept)
+    summ.update({"offered_rate": rate, "served_rate": len(kept) / summ["span_s"],
+                 "precision": "fp32_mixed" if precision else "fp64", "chunk": chunk})
+    if verbose:
+        print(json.dumps(summ), flush=True)
+    return summ
+
+
+def run_serve(a):
+    import torch
+    from paper_2601_17164_amd import inputs as I, sfhk
+    ctx = sfhk.Context(0)
+    n = a.serve_warmup + a.requests
+    reqs = [I.serving_request(k) for k in range(n)]
+    out = {"metric": "serving: p50/p99 spectrum latency and trajectory-steps/s",
+           "data": "synthetic", "n_gpus": 1, "requests_per_rate": a.requests,
+           "warmup": a.serve_warmup, "runs": []}
+    for prec in (0, 1):
+        for rate in [float(x) for x in a.rates.split(",")]:
+            out["runs"].append(serving_run(ctx, rate, a.requests, a.serve_warmup, prec,
+                                           a.serve_chunk, reqs, verbose=True))
+    print(json.dumps(out), flush=True)
+
+
+def run_batch(a):
+    """The uneven batch: 64 instances (wavelength 800-2000 nm, 0.8-3e14 W/cm^2, 2-10 cycles,
+    potential of either workload, 2^14-2^20 trajectories each), all tiles of all instances in one
+    graph replay, in FP64 and then in the FP32-mixed form."""
+    import torch
+    from paper_2601_17164_amd import autotune, inputs as I, sfhk
+    insts = I.batch_instances(a.batch_size, seed=3)
+    ctx = sfhk.Context(0)
+    arrays = [sfhk.to_device(x, "cuda:0") for x in insts]
+    n_tiles = sum(sfhk.tiles_of(x) for x in insts)
+    out = {"metric": "HK trajectory-steps/s, uneven batch in one graph-captured launch",
+           "unit": "trajectory-steps/s", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": f"{len(insts)} uneven instances", "instances": len(insts),
+                      "trajectories": int(sum(x.n_traj for x in insts)), "tiles": n_tiles}}
+    for prec, name in ((0, "fp64"), (1, "fp32_mixed")):
+        tuned = autotune.tune(ctx, prec, verbose=True)
+        jobs = [sfhk.make_job(ctx, x, arr, precision=prec) for x, arr in zip(insts, arrays)]
+        b = sfhk.Batch(ctx, len(jobs), n_tiles, tuned["chunk"], tuned["workers_per_cu"])
+        b.set_jobs(jobs)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        replays = 1
+        while not b.run():
+            replays += 1
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        st = [j.stats() for j in jobs]
+        steps = sum(x.steps_evaluated for x in st)
+        out[name] = {"value": steps / wall, "seconds": wall, "trajectory_steps": steps,
+                     "replays": replays, "workers_per_cu": tuned["workers_per_cu"],
+                     "chunk": tuned["chunk"], "autotune_rates": tuned["rates"],
+                     "fp64_step_fraction": sum(x.steps_fp64 for x in st) / max(1, steps)}
+        for j in jobs:
+            j.close()
+        b.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -145,6 +234,12 @@ def main():
         sys.exit(2)
     if a.copy_probe:
         copy_probe(a.copy_probe)
+        return
+    if a.batch:
+        run_batch(a)
+        return
+    if a.serve:
+        run_serve(a)
         return
     import torch
     from paper_2601_17164_amd import flops, inputs as I, sfhk
@@ -224,6 +319,9 @@ def main():
     }
     if not a.no_mixed:
         out["fp32_mixed"] = mixed_form(step, stream, inst, arrays, spec, flops)
+    if not a.no_serving:
+        out["serving"] = {name: serving_run(ctx, 5.0, 30, 2, prec, a.serve_chunk)
+                          for prec, name in ((0, "fp64"), (1, "fp32_mixed"))}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, a.cpu_births, a.cpu_per_birth)
     print(json.dumps(out), flush=True)

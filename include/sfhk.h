@@ -149,11 +149,40 @@ sfhk_status sfhk_propagate(sfhk_job* job, int64_t max_steps, void* stream);
 sfhk_status sfhk_propagate_many(sfhk_job* const* jobs, int32_t n_jobs, int64_t max_steps,
                                 void* stream);
 
+/* Batched, graph-captured propagation. A batch owns a job table of fixed capacity (max_jobs
+ * jobs, max_tiles unfinished tiles) at fixed device addresses and a HIP graph captured once at
+ * creation: a queue reset followed by one kernel per precision (FP64 and mixed). Each replay
+ * (sfhk_batch_run) advances every staged unfinished tile by up to max_steps steps (max_steps <= 0:
+ * to the end of its grid), longest tiles first. workers_per_cu > 0: that many single-wave workgroups
+ * per compute unit stay resident and pop tiles from a device-side atomic queue (persistent
+ * form); 0: one workgroup per tile, dispatched by the hardware. The table is rewritten between
+ * replays by sfhk_batch_set_jobs (no re-capture), so jobs can be added and dropped between replays
+ * (continuous batching). Results are identical to sfhk_propagate on each job alone.
+ * Errors: SFHK_E_INVALID (capacity exceeded, jobs of another context, bad sizes), SFHK_E_NOMEM,
+ * SFHK_E_DEVICE. A batch is used from one host thread; the jobs' other calls must be ordered with
+ * its replays by the caller (same stream). */
+typedef struct sfhk_batch sfhk_batch;
+sfhk_status sfhk_batch_create(sfhk_ctx* ctx, int32_t max_jobs, int64_t max_tiles, int64_t max_steps,
+                              int32_t workers_per_cu, sfhk_batch** out);
+/* Stage the unfinished tiles of jobs[0..n_jobs) (synchronises `stream`, then copies the table
+ * asynchronously on it). */
+sfhk_status sfhk_batch_set_jobs(sfhk_batch* batch, sfhk_job* const* jobs, int32_t n_jobs, void* stream);
+/* One graph replay on `stream`. SFHK_OK when every staged job has finished, else SFHK_E_NOT_DONE. */
+sfhk_status sfhk_batch_run(sfhk_batch* batch, void* stream);
+/* Resident workgroups of the persistent form (0 for hardware dispatch). */
+int32_t sfhk_batch_workers(const sfhk_batch* batch);
+void sfhk_batch_destroy(sfhk_batch* batch);
+
 /* Reduce the job's per-tile partial sums in a fixed order into F(t_n) = sum_j f_j(t_n) and write
  * d_out = -2 Re F (Eq. 2: "+ c.c." with the leading minus) on the job's output grid (n_out points,
  * or n_steps + 1 when n_out = 0). f_out (nullable) receives F on the step grid as
  * [2][n_steps+1] (re block then im block). Requires a finished job (else SFHK_E_NOT_DONE). */
 sfhk_status sfhk_dipole(sfhk_job* job, double* d_out, double* f_out, void* stream);
+
+/* 1 once every trajectory of the job has been propagated to the end of the grid by the calls
+ * issued so far (host-side bookkeeping: no synchronisation; the device work completes in stream
+ * order), else 0. */
+int32_t sfhk_job_is_done(const sfhk_job* job);
 
 /* Number of points sfhk_dipole writes to d_out. */
 int64_t sfhk_job_n_out(const sfhk_job* job);

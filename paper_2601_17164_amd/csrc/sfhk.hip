@@ -574,6 +574,83 @@ void k_propagate_mixed(const JobDev* __restrict__ jobs, const WorkItem* __restri
 }
 
 // ------------------------------------------------------------------------------------------------
+// persistent form (batched, graph-captured launches): a fixed number of single-wave workgroups pop
+// tiles from a longest-first work list through one atomic counter per precision segment. The
+// segment sizes live in device memory so the host can rewrite the job table between graph
+// replays without capturing again.
+// ------------------------------------------------------------------------------------------------
+struct BatchDev {
+  int n_items[2];         // per precision segment (0: FP64, 1: mixed)
+  int offset[2];          // first work item of the segment
+  unsigned int next[2];   // queue heads, zeroed at the start of every replay
+};
+
+__global__ void k_batch_reset(BatchDev* __restrict__ B) {
+  if (threadIdx.x < 2) B->next[threadIdx.x] = 0u;
+}
+
+// one tile per call: inlined into the queue loop, the tile loop's register allocation degrades.
+// The LDS ring is declared here, not passed in, so its accesses stay LDS instructions.
+__device__ __noinline__ void tile_call_fp64(const JobDev* J, int tile, int max_steps) {
+  __shared__ double2 ring[kRing][kRingStride];
+  run_tile(*J, tile, max_steps, ring);
+}
+__device__ __noinline__ void tile_call_mixed(const JobDev* J, int tile, int max_steps) {
+  __shared__ double2 ring[kRing][kRingStride];
+  run_tile_mixed(*J, tile, max_steps, ring);
+}
+
+template <int PREC>
+__device__ __forceinline__ void queue_loop(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work,
+                                           BatchDev* __restrict__ B, int max_steps) {
+  const int n_items = B->n_items[PREC];
+  const WorkItem* seg = work + B->offset[PREC];
+  for (;;) {
+    unsigned int it = 0;
+    if (threadIdx.x == 0) it = atomicAdd(&B->next[PREC], 1u);
+    it = __shfl(it, 0, 64);
+    if (it >= (unsigned int)n_items) break;  // every wave of the grid reaches this exit
+    const WorkItem wi = seg[it];
+    if (PREC == 0)
+      tile_call_fp64(jobs + wi.job, wi.tile, max_steps);
+    else
+      tile_call_mixed(jobs + wi.job, wi.tile, max_steps);
+  }
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_PROPAGATE_WAVES_PER_EU)))
+void k_queue_fp64(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work,
+                  BatchDev* __restrict__ B, int max_steps) {
+  queue_loop<0>(jobs, work, B, max_steps);
+}
+
+// hardware-dispatch alternative for graph replays: one workgroup per work item of capacity;
+// workgroups past the segment's current size exit at once
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_PROPAGATE_WAVES_PER_EU)))
+void k_grid_fp64(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work,
+                 const BatchDev* __restrict__ B, int max_steps) {
+  __shared__ double2 ring[kRing][kRingStride];
+  if ((int)blockIdx.x >= B->n_items[0]) return;
+  const WorkItem wi = work[B->offset[0] + blockIdx.x];
+  run_tile(jobs[wi.job], wi.tile, max_steps, ring);
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_MIXED_WAVES_PER_EU)))
+void k_grid_mixed(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work,
+                  const BatchDev* __restrict__ B, int max_steps) {
+  __shared__ double2 ring[kRing][kRingStride];
+  if ((int)blockIdx.x >= B->n_items[1]) return;
+  const WorkItem wi = work[B->offset[1] + blockIdx.x];
+  run_tile_mixed(jobs[wi.job], wi.tile, max_steps, ring);
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_MIXED_WAVES_PER_EU)))
+void k_queue_mixed(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work,
+                   BatchDev* __restrict__ B, int max_steps) {
+  queue_loop<1>(jobs, work, B, max_steps);
+}
+
+// ------------------------------------------------------------------------------------------------
 // reduction of the partial rows (fixed order) and the dipole
 // ------------------------------------------------------------------------------------------------
 __global__ void k_reduce_groups(JobDev J, double2* __restrict__ gsum) {
@@ -742,6 +819,26 @@ struct sfhk_job {
   std::vector<int> tile_n0_host;
   long long steps_done = 0;    // steps requested so far (uniform across tiles)
   bool done = false;
+};
+
+struct sfhk_batch {
+  sfhk_ctx* ctx = nullptr;
+  int max_jobs = 0;
+  long long max_items = 0;
+  int64_t max_steps = 0;
+  int workers_per_cu = 0;
+  int n_workers = 0;
+  hipStream_t cap_stream = nullptr;   // private stream used for the capture
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  JobDev* desc = nullptr;             // device, [max_jobs]
+  WorkItem* work = nullptr;           // device, [max_items]
+  BatchDev* bdev = nullptr;           // device
+  JobDev* desc_host = nullptr;        // pinned staging
+  WorkItem* work_host = nullptr;
+  BatchDev* bdev_host = nullptr;
+  std::vector<sfhk_job*> jobs;
+  bool staged = false;
 };
 
 namespace {
@@ -1145,6 +1242,155 @@ sfhk_status sfhk_propagate_many(sfhk_job* const* jobs, int32_t n_jobs, int64_t m
   }
   return agg;
 }
+
+// ------------------------------------------------------------------------------------------------
+// batched, graph-captured propagation
+// ------------------------------------------------------------------------------------------------
+void sfhk_batch_destroy(sfhk_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->ctx->device);
+  (void)hipDeviceSynchronize();
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  (void)hipFree(b->desc);
+  (void)hipFree(b->work);
+  (void)hipFree(b->bdev);
+  (void)hipHostFree(b->desc_host);
+  (void)hipHostFree(b->work_host);
+  (void)hipHostFree(b->bdev_host);
+  delete b;
+}
+
+sfhk_status sfhk_batch_create(sfhk_ctx* ctx, int32_t max_jobs, int64_t max_tiles, int64_t max_steps,
+                              int32_t workers_per_cu, sfhk_batch** out) {
+  if (!ctx || !out) return fail(SFHK_E_INVALID, "NULL argument");
+  if (max_jobs < 1 || max_tiles < 1 || max_tiles > INT32_MAX)
+    return fail(SFHK_E_INVALID, "max_jobs and max_tiles must be >= 1 (max_tiles < 2^31)");
+  if (workers_per_cu < 0 || workers_per_cu > 64) return fail(SFHK_E_INVALID, "workers_per_cu must be in 0..64");
+  HIP_TRY(hipSetDevice(ctx->device));
+  int cus = 0;
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+  sfhk_batch* b = new sfhk_batch();
+  b->ctx = ctx;
+  b->max_jobs = max_jobs;
+  b->max_items = max_tiles;
+  b->max_steps = max_steps;
+  b->workers_per_cu = workers_per_cu;
+  b->n_workers = workers_per_cu * cus;
+  auto bail = [&](sfhk_status st) {
+    sfhk_batch_destroy(b);
+    return st;
+  };
+#define TRY_B(expr)                                                                               \
+  do {                                                                                            \
+    hipError_t e_ = (expr);                                                                       \
+    if (e_ != hipSuccess)                                                                         \
+      return bail(fail(e_ == hipErrorOutOfMemory ? SFHK_E_NOMEM : SFHK_E_DEVICE,                  \
+                       std::string(#expr) + ": " + hipGetErrorString(e_)));                       \
+  } while (0)
+  TRY_B(hipMalloc(&b->desc, (size_t)max_jobs * sizeof(JobDev)));
+  TRY_B(hipMalloc(&b->work, (size_t)max_tiles * sizeof(WorkItem)));
+  TRY_B(hipMalloc(&b->bdev, sizeof(BatchDev)));
+  TRY_B(hipHostMalloc(&b->desc_host, (size_t)max_jobs * sizeof(JobDev), hipHostMallocDefault));
+  TRY_B(hipHostMalloc(&b->work_host, (size_t)max_tiles * sizeof(WorkItem), hipHostMallocDefault));
+  TRY_B(hipHostMalloc(&b->bdev_host, sizeof(BatchDev), hipHostMallocDefault));
+  TRY_B(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+  std::memset(b->bdev_host, 0, sizeof(BatchDev));
+  TRY_B(hipMemcpyAsync(b->bdev, b->bdev_host, sizeof(BatchDev), hipMemcpyHostToDevice, b->cap_stream));
+  TRY_B(hipStreamSynchronize(b->cap_stream));
+  const int ms = (max_steps <= 0 || max_steps > INT32_MAX / 2) ? 0 : (int)max_steps;
+  // capture: reset the queue heads with a kernel (no memset node), then one kernel per precision
+  TRY_B(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, b->cap_stream, b->bdev);
+  if (workers_per_cu > 0) {
+    hipLaunchKernelGGL(k_queue_fp64, dim3(b->n_workers), dim3(kTile), 0, b->cap_stream,
+                       (const JobDev*)b->desc, (const WorkItem*)b->work, b->bdev, ms);
+    hipLaunchKernelGGL(k_queue_mixed, dim3(b->n_workers), dim3(kTile), 0, b->cap_stream,
+                       (const JobDev*)b->desc, (const WorkItem*)b->work, b->bdev, ms);
+  } else {
+    hipLaunchKernelGGL(k_grid_fp64, dim3((unsigned)max_tiles), dim3(kTile), 0, b->cap_stream,
+                       (const JobDev*)b->desc, (const WorkItem*)b->work, (const BatchDev*)b->bdev, ms);
+    hipLaunchKernelGGL(k_grid_mixed, dim3((unsigned)max_tiles), dim3(kTile), 0, b->cap_stream,
+                       (const JobDev*)b->desc, (const WorkItem*)b->work, (const BatchDev*)b->bdev, ms);
+  }
+  hipError_t le = hipGetLastError();
+  hipGraph_t g = nullptr;
+  hipError_t ce = hipStreamEndCapture(b->cap_stream, &g);
+  b->graph = g;
+  TRY_B(le);
+  TRY_B(ce);
+  TRY_B(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+#undef TRY_B
+  *out = b;
+  return SFHK_OK;
+}
+
+sfhk_status sfhk_batch_set_jobs(sfhk_batch* b, sfhk_job* const* jobs, int32_t n_jobs, void* stream) {
+  if (!b || (!jobs && n_jobs > 0) || n_jobs < 0) return fail(SFHK_E_INVALID, "bad batch or job list");
+  if (n_jobs > b->max_jobs) return fail(SFHK_E_INVALID, "more jobs than the batch was created for");
+  for (int i = 0; i < n_jobs; ++i)
+    if (!jobs[i] || jobs[i]->ctx != b->ctx) return fail(SFHK_E_INVALID, "jobs must be non-NULL and share the batch's context");
+  HIP_TRY(hipSetDevice(b->ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  struct Item {
+    long long left;
+    int job, tile, precision;
+  };
+  std::vector<Item> items;
+  for (int i = 0; i < n_jobs; ++i) {
+    sfhk_job* j = jobs[i];
+    if (j->done) continue;
+    const int NS = j->host.n_steps;
+    const int nt = unfinished_tiles(j, j->steps_done);
+    for (int t = 0; t < nt; ++t)
+      items.push_back({NS + 1 - (j->tile_n0_host[t] + j->steps_done), i, t, j->precision});
+  }
+  if ((long long)items.size() > b->max_items) return fail(SFHK_E_INVALID, "more unfinished tiles than the batch was created for");
+  std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) {
+    return x.precision != y.precision ? x.precision < y.precision : x.left > y.left;
+  });
+  HIP_TRY(hipStreamSynchronize(st));  // earlier copies from the staging buffers have completed
+  BatchDev bd{};
+  int n64 = 0;
+  for (const Item& it : items) n64 += it.precision == SFHK_FP64;
+  bd.n_items[0] = n64;
+  bd.offset[0] = 0;
+  bd.n_items[1] = (int)items.size() - n64;
+  bd.offset[1] = n64;
+  for (int i = 0; i < n_jobs; ++i) b->desc_host[i] = jobs[i]->host;
+  for (size_t k = 0; k < items.size(); ++k) b->work_host[k] = {items[k].job, items[k].tile};
+  *b->bdev_host = bd;
+  if (n_jobs) HIP_TRY(hipMemcpyAsync(b->desc, b->desc_host, n_jobs * sizeof(JobDev), hipMemcpyHostToDevice, st));
+  if (!items.empty())
+    HIP_TRY(hipMemcpyAsync(b->work, b->work_host, items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(b->bdev, b->bdev_host, sizeof(BatchDev), hipMemcpyHostToDevice, st));
+  b->jobs.assign(jobs, jobs + n_jobs);
+  b->staged = true;
+  return SFHK_OK;
+}
+
+sfhk_status sfhk_batch_run(sfhk_batch* b, void* stream) {
+  if (!b) return fail(SFHK_E_INVALID, "batch is NULL");
+  HIP_TRY(hipSetDevice(b->ctx->device));
+  if (!b->staged || b->jobs.empty()) return SFHK_OK;
+  HIP_TRY(hipGraphLaunch(b->exec, (hipStream_t)stream));
+  sfhk_status agg = SFHK_OK;
+  for (sfhk_job* j : b->jobs) {
+    if (j->done) continue;
+    const int NS = j->host.n_steps;
+    j->steps_done += (b->max_steps <= 0) ? (long long)NS + 1 : b->max_steps;
+    if (unfinished_tiles(j, j->steps_done) == 0)
+      j->done = true;
+    else
+      agg = SFHK_E_NOT_DONE;
+  }
+  return agg;
+}
+
+int32_t sfhk_batch_workers(const sfhk_batch* b) { return b ? b->n_workers : 0; }
+
+int32_t sfhk_job_is_done(const sfhk_job* job) { return job && job->done ? 1 : 0; }
 
 sfhk_status sfhk_dipole(sfhk_job* job, double* d_out, double* f_out, void* stream) {
   if (!job || !d_out) return fail(SFHK_E_INVALID, "NULL argument");

@@ -1,0 +1,168 @@
+"""Continuous-batching serving loop for spectrum requests.
+
+Requests (one SFHK instance each) arrive at given times. Between graph replays of one batch,
+arrived requests are admitted in arrival order while their device footprint fits the context's
+HBM budget and the batch's capacity; admitted requests keep their trajectory state in HBM and
+every replay advances all of them by `chunk` steps (one launch per precision over all their tiles,
+longest first). A request that has finished gets its dipole and spectrum computed on the device
+and copied to pinned host memory; its latency runs from arrival to that copy's completion.
+Results are identical to each request propagated alone (the batch path is bitwise equal to it).
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    req_id: int
+    arrival: float          # seconds after the start of the run
+    inst: object            # inputs.Instance
+
+
+@dataclass
+class Result:
+    req_id: int
+    arrival: float
+    admitted: float
+    finished: float
+    n_traj: int
+    steps: int
+    omega: Optional[np.ndarray] = None
+    power: Optional[np.ndarray] = None
+    dipole: Optional[np.ndarray] = None
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+def poisson_arrivals(rate: float, n: int, seed: int) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.cumsum(rng.exponential(1.0 / rate, n))
+
+
+@dataclass
+class _Active:
+    req: Request
+    job: object
+    admitted: float
+
+
+@dataclass
+class _Finishing:
+    req: Request
+    job: object
+    admitted: float
+    event: object
+    omega: object
+    power: object
+    dipole: object
+    steps: int
+
+
+class Server:
+    def __init__(self, ctx, precision: int = 0, chunk: int = 1024, workers_per_cu: int = 0,
+                 max_jobs: int = 64, max_tiles: int = 1 << 20, keep_results: bool = False):
+        from . import sfhk
+        self.sfhk = sfhk
+        self.ctx = ctx
+        self.precision = precision
+        self.keep = keep_results
+        self.max_jobs, self.max_tiles = max_jobs, max_tiles
+        self.batch = sfhk.Batch(ctx, max_jobs, max_tiles, chunk, workers_per_cu)
+
+    def close(self):
+        self.batch.close()
+
+    def run(self, requests: List[Request]) -> List[Result]:
+        import torch
+        sfhk = self.sfhk
+        stream = torch.cuda.current_stream()
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        queue: deque = deque()
+        active: List[_Active] = []
+        finishing: List[_Finishing] = []
+        results: List[Result] = []
+        tiles_active = 0
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0
+        while pending or queue or active or finishing:
+            t = now()
+            while pending and pending[0].arrival <= t:
+                queue.append(pending.popleft())
+            # admission, in arrival order, by HBM footprint and batch capacity
+            while queue and len(active) < self.max_jobs:
+                req = queue[0]
+                nt = sfhk.tiles_of(req.inst)
+                if nt > self.max_tiles:
+                    raise ValueError(f"request {req.req_id} has more tiles than the batch holds")
+                if tiles_active + nt > self.max_tiles:
+                    break
+                try:
+                    job = sfhk.make_job(self.ctx, req.inst, precision=self.precision)
+                except sfhk.SfhkError as e:
+                    if e.status == sfhk.SFHK_E_BUDGET and (active or finishing):
+                        break  # wait for running requests to free HBM
+                    raise      # does not fit even on an idle device
+                queue.popleft()
+                active.append(_Active(req, job, now()))
+                tiles_active += nt
+            # staging the table synchronises the stream: every earlier replay and every finished
+            # request's spectrum copy is complete after it
+            if active:
+                self.batch.set_jobs([a.job for a in active])
+            elif finishing:
+                stream.synchronize()
+            t_sync = now()
+            for f in finishing:
+                st = f.job.stats()
+                results.append(Result(f.req.req_id, f.req.arrival, f.admitted, t_sync,
+                                      f.req.inst.n_traj, st.steps_evaluated,
+                                      None if f.omega is None else f.omega.numpy(),
+                                      f.power.numpy() if self.keep else None,
+                                      None if f.dipole is None else f.dipole.numpy()))
+                f.job.close()
+            finishing = []
+            if active:
+                self.batch.run()
+                still = []
+                for a in active:
+                    if not a.job.done:
+                        still.append(a)
+                        continue
+                    d = a.job.dipole()
+                    inst = a.req.inst
+                    T = inst.grid.h * inst.grid.n_steps
+                    dt = T / inst.n_out if inst.n_out else inst.grid.h
+                    om, pw, _ = sfhk.spectrum(d, inst.grid.t_a, dt, T / 2)
+                    host_pw = torch.empty(pw.shape, dtype=pw.dtype, pin_memory=True)
+                    host_pw.copy_(pw, non_blocking=True)
+                    host_om = host_d = None
+                    if self.keep:
+                        host_om = torch.empty(om.shape, dtype=om.dtype, pin_memory=True)
+                        host_om.copy_(om, non_blocking=True)
+                        host_d = torch.empty(d.shape, dtype=d.dtype, pin_memory=True)
+                        host_d.copy_(d, non_blocking=True)
+                    finishing.append(_Finishing(a.req, a.job, a.admitted, None, host_om, host_pw,
+                                                host_d, 0))
+                    tiles_active -= sfhk.tiles_of(inst)
+                active = still
+            elif not queue and pending and not finishing:
+                time.sleep(max(0.0, min(0.05, pending[0].arrival - now())))
+        return sorted(results, key=lambda r: r.req_id)
+
+
+def summarize(results: List[Result], wall: float = None) -> dict:
+    lat = np.array([r.latency for r in results]) * 1e3
+    steps = sum(r.steps for r in results)
+    span = wall if wall is not None else (max(r.finished for r in results) -
+                                          min(r.arrival for r in results))
+    return {"requests": len(results), "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+            "trajectory_steps_per_s": steps / span, "span_s": span}

@@ -75,10 +75,17 @@ _SIGS = {
     "sfhk_propagate_many": (ct.c_int, [ct.POINTER(_VP), ct.c_int32, ct.c_int64, _VP]),
     "sfhk_dipole": (ct.c_int, [_VP, _VP, _VP, _VP]),
     "sfhk_job_n_out": (ct.c_int64, [_VP]),
+    "sfhk_job_is_done": (ct.c_int32, [_VP]),
     "sfhk_spectrum": (ct.c_int, [_VP, ct.c_int64, ct.c_double, ct.c_double, ct.c_double,
                                  ct.c_int64, _VP, _VP, _VP, _VP]),
     "sfhk_job_stats": (ct.c_int, [_VP, ct.POINTER(_Stats), _VP]),
     "sfhk_job_trajectories": (ct.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "sfhk_batch_create": (ct.c_int, [_VP, ct.c_int32, ct.c_int64, ct.c_int64, ct.c_int32,
+                                     ct.POINTER(_VP)]),
+    "sfhk_batch_set_jobs": (ct.c_int, [_VP, ct.POINTER(_VP), ct.c_int32, _VP]),
+    "sfhk_batch_run": (ct.c_int, [_VP, _VP]),
+    "sfhk_batch_workers": (ct.c_int32, [_VP]),
+    "sfhk_batch_destroy": (None, [_VP]),
     "sfhk_last_error": (ct.c_char_p, []),
     "sfhk_status_string": (ct.c_char_p, [ct.c_int]),
     "sfhk_traj_exp": (ct.c_int, [_VP, _VP, ct.c_int64, _VP]),
@@ -207,6 +214,11 @@ class Job:
     def n_out(self) -> int:
         return int(lib().sfhk_job_n_out(self.handle))
 
+    @property
+    def done(self) -> bool:
+        """All steps issued (no synchronisation)."""
+        return bool(lib().sfhk_job_is_done(self.handle))
+
     def propagate(self, max_steps: int = 0, stream=None) -> bool:
         """Returns True when every trajectory reached the end of the grid."""
         rc = _check(lib().sfhk_propagate(self.handle, int(max_steps), _stream_ptr(stream)),
@@ -255,6 +267,50 @@ def propagate_many(jobs: Sequence[Job], max_steps: int = 0, stream=None) -> bool
     rc = _check(lib().sfhk_propagate_many(arr, len(jobs), int(max_steps), _stream_ptr(stream)),
                 "sfhk_propagate_many")
     return rc == SFHK_OK
+
+
+class Batch:
+    """sfhk_batch: a graph-captured, batched propagation over a job table of fixed capacity.
+    workers_per_cu > 0 selects the persistent (queue) form, 0 hardware dispatch."""
+
+    def __init__(self, ctx: Context, max_jobs: int, max_tiles: int, max_steps: int = 0,
+                 workers_per_cu: int = 8):
+        h = _VP()
+        _check(lib().sfhk_batch_create(ctx.handle, int(max_jobs), int(max_tiles), int(max_steps),
+                                       int(workers_per_cu), ct.byref(h)), "sfhk_batch_create")
+        self.handle = h
+        self.ctx = ctx
+        self._jobs = []
+
+    @property
+    def workers(self) -> int:
+        return int(lib().sfhk_batch_workers(self.handle))
+
+    def set_jobs(self, jobs: Sequence[Job], stream=None):
+        arr = (_VP * max(1, len(jobs)))(*[j.handle for j in jobs])
+        _check(lib().sfhk_batch_set_jobs(self.handle, arr, len(jobs), _stream_ptr(stream)),
+               "sfhk_batch_set_jobs")
+        self._jobs = list(jobs)
+
+    def run(self, stream=None) -> bool:
+        """One graph replay; True when every staged job has finished."""
+        rc = _check(lib().sfhk_batch_run(self.handle, _stream_ptr(stream)), "sfhk_batch_run")
+        return rc == SFHK_OK
+
+    def close(self):
+        if self.handle:
+            lib().sfhk_batch_destroy(self.handle)
+            self.handle = _VP()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tiles_of(inst) -> int:
+    return (inst.n_traj + 63) // 64
 
 
 def spectrum(d: torch.Tensor, t_first: float, dt: float, tau_h: float, n_fft: int = 0,
