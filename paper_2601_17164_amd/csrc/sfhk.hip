@@ -220,6 +220,15 @@ struct WorkItem {
 
 typedef __attribute__((address_space(4))) const double* const_dptr;  // scalar (uniform) loads
 
+// values that are the same in every lane of the wave (per-tile bookkeeping): kept in scalar
+// registers so the step loop's control runs on the scalar unit
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long uniform_i64(long long v) {
+  const unsigned int lo = __builtin_amdgcn_readfirstlane((unsigned int)(unsigned long long)v);
+  const unsigned int hi = __builtin_amdgcn_readfirstlane((unsigned int)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
 __device__ __forceinline__ void flush_ring(double2 (*ring)[kRingStride], int lane, int slot_lo,
                                            int slot_hi, double2* __restrict__ part,
                                            long long base) {
@@ -243,7 +252,7 @@ __device__ __forceinline__ void flush_ring(double2 (*ring)[kRingStride], int lan
 __device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const int max_steps,
                                          double2 (*ring)[kRingStride]) {
   const int lane = threadIdx.x;
-  const int n_begin = J.tile_next[tile];
+  const int n_begin = uniform_i32(J.tile_next[tile]);
   const int N = J.n_steps;
   if (n_begin > N) return;
   const int n_stop = (max_steps > 0) ? min(N, n_begin + max_steps - 1) : N;
@@ -268,8 +277,8 @@ __device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const 
   int death = death_in;
   bool alive = death_in == -1;
 
-  const int t0 = J.tile_n0[tile];
-  const long long roff = J.row_off[tile];
+  const int t0 = uniform_i32(J.tile_n0[tile]);
+  const long long roff = uniform_i64(J.row_off[tile]);
   double2* __restrict__ part = J.part;
   const const_dptr eh = (const_dptr)J.e_half;
   const PotParams P = J.pot;
@@ -398,7 +407,7 @@ void k_propagate_fp64(
 __device__ __forceinline__ void run_tile_mixed(const JobDev& J, const int tile, const int max_steps,
                                                double2 (*ring)[kRingStride]) {
   const int lane = threadIdx.x;
-  const int n_begin = J.tile_next[tile];
+  const int n_begin = uniform_i32(J.tile_next[tile]);
   const int N = J.n_steps;
   if (n_begin > N) return;
   const int n_stop = (max_steps > 0) ? min(N, n_begin + max_steps - 1) : N;
@@ -423,8 +432,8 @@ __device__ __forceinline__ void run_tile_mixed(const JobDev& J, const int tile, 
   int death = death_in;
   bool alive = death_in == -1;
 
-  const int t0 = J.tile_n0[tile];
-  const long long roff = J.row_off[tile];
+  const int t0 = uniform_i32(J.tile_n0[tile]);
+  const long long roff = uniform_i64(J.row_off[tile]);
   double2* __restrict__ part = J.part;
   const const_dptr eh = (const_dptr)J.e_half;
   const PotParams P = J.pot;

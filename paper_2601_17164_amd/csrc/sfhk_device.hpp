@@ -37,20 +37,32 @@ struct InvFactorials {
 };
 constexpr InvFactorials kInvFact{};
 
+// fma(a, b, c) as the three-operand v_fma_f64: under the propagate kernel's register pressure
+// the compiler otherwise emits a copy of the addend plus the two-operand v_fmac_f64 for every
+// Horner step. Same IEEE fused multiply-add, one instruction.
+__device__ __forceinline__ double fma3(double a, double b, double c) {
+  double d;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+
 __device__ __forceinline__ double exp_cw(double x) {
   constexpr double kInvLn2 = 0x1.71547652b82fep+0;  // 1/ln2 rounded to binary64
   constexpr double kLn2Hi = 0x1.62e42feep-1;         // ln2 truncated to 32 significant bits
   constexpr double kLn2Lo = 0x1.a39ef35793c76p-33;   // ln2 - kLn2Hi rounded to binary64
-  if (x != x) return x;
-  if (x < -708.0) return 0.0;
-  if (x > 709.0) return __builtin_inf();
+  // the sequence runs for every x; the three out-of-range cases are selected afterwards
   const double k = rint(x * kInvLn2);
   double r = SFHK_FMA(-k, kLn2Hi, x);
   r = SFHK_FMA(-k, kLn2Lo, r);
   double p = kInvFact.v[13];
 #pragma unroll
-  for (int n = 12; n >= 0; --n) p = SFHK_FMA(p, r, kInvFact.v[n]);
-  return ldexp(p, (int)k);
+  for (int n = 12; n >= 3; --n) p = fma3(p, r, kInvFact.v[n]);
+#pragma unroll
+  for (int n = 2; n >= 0; --n) p = SFHK_FMA(p, r, kInvFact.v[n]);  // 1/2, 1, 1: inline constants
+  double y = ldexp(p, (int)k);
+  y = x < -708.0 ? 0.0 : y;
+  y = x > 709.0 ? __builtin_inf() : y;
+  return x != x ? x : y;
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -77,9 +89,15 @@ __device__ __forceinline__ double rsqrt_rare(double x) {
   return rsqrt_core(x * 0x1p-1000) * 0x1p-500;
 }
 
+// The in-range sequence runs unconditionally; lanes outside [2^-1000, 2^1000] are redone under a
+// wave-uniform test, so the common path has no divergent branch to merge.
 __device__ __forceinline__ double rsqrt_c(double x) {
-  if (__builtin_expect(x >= 0x1p-1000 && x <= 0x1p1000, 1)) return rsqrt_core(x);
-  return rsqrt_rare(x);
+  double y = rsqrt_core(x);
+  const bool rare = !(x >= 0x1p-1000 && x <= 0x1p1000);
+  if (__builtin_expect(__any(rare), 0)) {
+    if (rare) y = rsqrt_rare(x);
+  }
+  return y;
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -112,11 +130,9 @@ __device__ __forceinline__ void pot_gc(const PotParams& P, double x, double y, d
     // V = -Z(r)/rho, Z = z_inf + z_in exp(-r/r_scr), rho = (r^2 + a)^(1/2)
     double s = r2 + P.soft2;
     double ir = rsqrt_c(s);  // 1/rho
-    double inv_r = 0.0, r = 0.0;
-    if (r2 > 0.0) {
-      inv_r = rsqrt_c(r2);
-      r = r2 * inv_r;
-    }
+    const bool pos = r2 > 0.0;
+    const double inv_r = rsqrt_c(r2);   // +inf at r = 0, unused there
+    const double r = pos ? r2 * inv_r : 0.0;
     double ir2 = ir * ir;
     double ir3 = ir2 * ir;
     double e = exp_cw(-(r * P.inv_rscr));
@@ -131,14 +147,10 @@ __device__ __forceinline__ void pot_gc(const PotParams& P, double x, double y, d
     double tb = (d1 * r) * ir3;
     double tc = ((Z * w1) * ir3) * ir2;
     double vpp = tc - SFHK_FMA(2.0, tb, ta);             // V''
-    if (r2 > 0.0) {
-      g = vp * inv_r;
-      c = (vpp - g) * (inv_r * inv_r);
-    } else {  // r = 0 exactly (measure zero): finite isotropic choice
-
-      g = vpp;
-      c = 0.0;
-    }
+    const double gp = vp * inv_r;
+    const double cp = (vpp - gp) * (inv_r * inv_r);
+    g = pos ? gp : vpp;  // r = 0 exactly (measure zero): finite isotropic choice
+    c = pos ? cp : 0.0;
   } else if constexpr (KIND == POT_HARMONIC) {
     double w2 = P.omega_ho * P.omega_ho;
     V = (0.5 * w2) * r2;
