@@ -249,6 +249,9 @@ __device__ __forceinline__ void flush_ring(double2 (*ring)[kRingStride], int lan
   __syncthreads();
 }
 
+// KIND >= 0: the potential kind is a compile-time constant (its dispatch folds away); -1: read from
+// the job descriptor at run time
+template <int KIND>
 __device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const int max_steps,
                                          double2 (*ring)[kRingStride]) {
   const int lane = threadIdx.x;
@@ -282,7 +285,7 @@ __device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const 
   double2* __restrict__ part = J.part;
   const const_dptr eh = (const_dptr)J.e_half;
   const PotParams P = J.pot;
-  const int kind = J.kind;
+  const int kind = KIND >= 0 ? KIND : J.kind;
   const double gamma = J.gamma, inv4g = J.inv4g, kay2 = J.kay2, cut = J.cut;
   const double h = J.h, h2 = J.h2, h6 = J.h6, t_a = J.t_a;
 
@@ -389,12 +392,13 @@ __device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const 
 #ifndef SFHK_PROPAGATE_WAVES_PER_EU
 #define SFHK_PROPAGATE_WAVES_PER_EU 2
 #endif
+template <int KIND>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_PROPAGATE_WAVES_PER_EU)))
 void k_propagate_fp64(
     const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work, int max_steps) {
   __shared__ double2 ring[kRing][kRingStride];
   const WorkItem wi = work[blockIdx.x];
-  run_tile(jobs[wi.job], wi.tile, max_steps, ring);
+  run_tile<KIND>(jobs[wi.job], wi.tile, max_steps, ring);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -404,6 +408,7 @@ void k_propagate_fp64(
 // result back to FP32. The precision decision is per lane, so a trajectory's result does not
 // depend on the other trajectories of its wave.
 // ------------------------------------------------------------------------------------------------
+template <int KIND>
 __device__ __forceinline__ void run_tile_mixed(const JobDev& J, const int tile, const int max_steps,
                                                double2 (*ring)[kRingStride]) {
   const int lane = threadIdx.x;
@@ -439,7 +444,7 @@ __device__ __forceinline__ void run_tile_mixed(const JobDev& J, const int tile, 
   const PotParams P = J.pot;
   const PotParamsF PF = {(float)P.z_inf, (float)P.z_in, (float)P.soft2, (float)P.omega_ho,
                          (float)P.inv_rscr};
-  const int kind = J.kind;
+  const int kind = KIND >= 0 ? KIND : J.kind;
   const double kay2 = J.kay2, cut = J.cut;
   const double h = J.h, h2 = J.h2, h6 = J.h6, t_a = J.t_a;
   const float hf = (float)h, h2f = (float)h2, h6f = (float)h6;
@@ -575,11 +580,12 @@ __device__ __forceinline__ void run_tile_mixed(const JobDev& J, const int tile, 
 #ifndef SFHK_MIXED_WAVES_PER_EU
 #define SFHK_MIXED_WAVES_PER_EU 2
 #endif
+template <int KIND>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_MIXED_WAVES_PER_EU)))
 void k_propagate_mixed(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work, int max_steps) {
   __shared__ double2 ring[kRing][kRingStride];
   const WorkItem wi = work[blockIdx.x];
-  run_tile_mixed(jobs[wi.job], wi.tile, max_steps, ring);
+  run_tile_mixed<KIND>(jobs[wi.job], wi.tile, max_steps, ring);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -588,75 +594,82 @@ void k_propagate_mixed(const JobDev* __restrict__ jobs, const WorkItem* __restri
 // segment sizes live in device memory so the host can rewrite the job table between graph
 // replays without capturing again.
 // ------------------------------------------------------------------------------------------------
+constexpr int kKinds = 4;              // potential kinds
+constexpr int kSegs = 2 * kKinds;       // work-list segments: precision * kKinds + kind
+
 struct BatchDev {
-  int n_items[2];         // per precision segment (0: FP64, 1: mixed)
-  int offset[2];          // first work item of the segment
-  unsigned int next[2];   // queue heads, zeroed at the start of every replay
+  int n_items[kSegs];        // per segment
+  int offset[kSegs];         // first work item of the segment
+  unsigned int next[kSegs];  // queue heads, zeroed at the start of every replay
 };
 
 __global__ void k_batch_reset(BatchDev* __restrict__ B) {
-  if (threadIdx.x < 2) B->next[threadIdx.x] = 0u;
+  if (threadIdx.x < kSegs) B->next[threadIdx.x] = 0u;
 }
 
 // one tile per call: inlined into the queue loop, the tile loop's register allocation degrades.
 // The LDS ring is declared here, not passed in, so its accesses stay LDS instructions.
-__device__ __noinline__ void tile_call_fp64(const JobDev* J, int tile, int max_steps) {
+template <int PREC, int KIND>
+__device__ __noinline__ void tile_call(const JobDev* J, int tile, int max_steps) {
   __shared__ double2 ring[kRing][kRingStride];
-  run_tile(*J, tile, max_steps, ring);
-}
-__device__ __noinline__ void tile_call_mixed(const JobDev* J, int tile, int max_steps) {
-  __shared__ double2 ring[kRing][kRingStride];
-  run_tile_mixed(*J, tile, max_steps, ring);
+  if (PREC == 0)
+    run_tile<KIND>(*J, tile, max_steps, ring);
+  else
+    run_tile_mixed<KIND>(*J, tile, max_steps, ring);
 }
 
-template <int PREC>
+template <int PREC, int KIND>
 __device__ __forceinline__ void queue_loop(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work,
                                            BatchDev* __restrict__ B, int max_steps) {
-  const int n_items = B->n_items[PREC];
-  const WorkItem* seg = work + B->offset[PREC];
+  constexpr int seg = PREC * kKinds + KIND;
+  const int n_items = B->n_items[seg];
+  const WorkItem* sw = work + B->offset[seg];
   for (;;) {
     unsigned int it = 0;
-    if (threadIdx.x == 0) it = atomicAdd(&B->next[PREC], 1u);
+    if (threadIdx.x == 0) it = atomicAdd(&B->next[seg], 1u);
     it = __shfl(it, 0, 64);
     if (it >= (unsigned int)n_items) break;  // every wave of the grid reaches this exit
-    const WorkItem wi = seg[it];
-    if (PREC == 0)
-      tile_call_fp64(jobs + wi.job, wi.tile, max_steps);
-    else
-      tile_call_mixed(jobs + wi.job, wi.tile, max_steps);
+    const WorkItem wi = sw[it];
+    tile_call<PREC, KIND>(jobs + wi.job, wi.tile, max_steps);
   }
 }
 
+template <int KIND>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_PROPAGATE_WAVES_PER_EU)))
 void k_queue_fp64(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work,
                   BatchDev* __restrict__ B, int max_steps) {
-  queue_loop<0>(jobs, work, B, max_steps);
+  queue_loop<0, KIND>(jobs, work, B, max_steps);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_MIXED_WAVES_PER_EU)))
+void k_queue_mixed(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work,
+                   BatchDev* __restrict__ B, int max_steps) {
+  queue_loop<1, KIND>(jobs, work, B, max_steps);
 }
 
 // hardware-dispatch alternative for graph replays: one workgroup per work item of capacity;
 // workgroups past the segment's current size exit at once
+template <int KIND>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_PROPAGATE_WAVES_PER_EU)))
 void k_grid_fp64(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work,
                  const BatchDev* __restrict__ B, int max_steps) {
   __shared__ double2 ring[kRing][kRingStride];
-  if ((int)blockIdx.x >= B->n_items[0]) return;
-  const WorkItem wi = work[B->offset[0] + blockIdx.x];
-  run_tile(jobs[wi.job], wi.tile, max_steps, ring);
+  constexpr int seg = KIND;
+  if ((int)blockIdx.x >= B->n_items[seg]) return;
+  const WorkItem wi = work[B->offset[seg] + blockIdx.x];
+  run_tile<KIND>(jobs[wi.job], wi.tile, max_steps, ring);
 }
 
+template <int KIND>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_MIXED_WAVES_PER_EU)))
 void k_grid_mixed(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work,
                   const BatchDev* __restrict__ B, int max_steps) {
   __shared__ double2 ring[kRing][kRingStride];
-  if ((int)blockIdx.x >= B->n_items[1]) return;
-  const WorkItem wi = work[B->offset[1] + blockIdx.x];
-  run_tile_mixed(jobs[wi.job], wi.tile, max_steps, ring);
-}
-
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_MIXED_WAVES_PER_EU)))
-void k_queue_mixed(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work,
-                   BatchDev* __restrict__ B, int max_steps) {
-  queue_loop<1>(jobs, work, B, max_steps);
+  constexpr int seg = kKinds + KIND;
+  if ((int)blockIdx.x >= B->n_items[seg]) return;
+  const WorkItem wi = work[B->offset[seg] + blockIdx.x];
+  run_tile_mixed<KIND>(jobs[wi.job], wi.tile, max_steps, ring);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -892,16 +905,28 @@ void job_free(sfhk_job* j) {
 
 int blocks_for(long long n, int t) { return (int)((n + t - 1) / t); }
 
-sfhk_status launch_propagate(int precision, const JobDev* descs, const WorkItem* work, int n_items,
-                             int max_steps, hipStream_t st) {
+// launch the (precision, kind) instance of the propagate kernel
+sfhk_status launch_propagate(int precision, int kind, const JobDev* descs, const WorkItem* work,
+                             int n_items, int max_steps, hipStream_t st) {
   if (n_items <= 0) return SFHK_OK;
-  if (precision == SFHK_FP32_MIXED)
-    hipLaunchKernelGGL(k_propagate_mixed, dim3(n_items), dim3(kTile), 0, st, descs, work, max_steps);
-  else
-    hipLaunchKernelGGL(k_propagate_fp64, dim3(n_items), dim3(kTile), 0, st, descs, work, max_steps);
+  const dim3 g(n_items), b(kTile);
+#define SFHK_LAUNCH(K)                                                                             \
+  if (precision == SFHK_FP32_MIXED)                                                                \
+    hipLaunchKernelGGL(k_propagate_mixed<K>, g, b, 0, st, descs, work, max_steps);                 \
+  else                                                                                             \
+    hipLaunchKernelGGL(k_propagate_fp64<K>, g, b, 0, st, descs, work, max_steps);
+  switch (kind) {
+    case SFHK_POT_SOFTCORE: SFHK_LAUNCH(POT_SOFTCORE) break;
+    case SFHK_POT_SCREENED: SFHK_LAUNCH(POT_SCREENED) break;
+    case SFHK_POT_HARMONIC: SFHK_LAUNCH(POT_HARMONIC) break;
+    default: SFHK_LAUNCH(POT_NONE) break;
+  }
+#undef SFHK_LAUNCH
   HIP_TRY(hipGetLastError());
   return SFHK_OK;
 }
+
+int segment_of(int precision, int kind) { return (precision == SFHK_FP32_MIXED ? kKinds : 0) + kind; }
 
 }  // namespace
 
@@ -1164,7 +1189,7 @@ sfhk_status sfhk_propagate(sfhk_job* job, int64_t max_steps, void* stream) {
   const int nt = unfinished_tiles(job, job->steps_done);
   if (nt > 0) {
     int ms = (max_steps <= 0 || max_steps > NS + 1) ? 0 : (int)max_steps;
-    sfhk_status rc = launch_propagate(job->precision, job->dev, job->work, nt, ms, st);
+    sfhk_status rc = launch_propagate(job->precision, job->kind, job->dev, job->work, nt, ms, st);
     if (rc) return rc;
   }
   job->steps_done += (max_steps <= 0) ? (long long)NS + 1 : max_steps;
@@ -1186,7 +1211,7 @@ sfhk_status sfhk_propagate_many(sfhk_job* const* jobs, int32_t n_jobs, int64_t m
   // one launch over the unfinished tiles of every job, ordered by steps left (longest first)
   struct Item {
     long long left;
-    int job, tile, precision;
+    int job, tile, seg;
   };
   std::vector<Item> items;
   for (int i = 0; i < n_jobs; ++i) {
@@ -1195,11 +1220,12 @@ sfhk_status sfhk_propagate_many(sfhk_job* const* jobs, int32_t n_jobs, int64_t m
     const int NS = j->host.n_steps;
     const int nt = unfinished_tiles(j, j->steps_done);
     for (int t = 0; t < nt; ++t)
-      items.push_back({NS + 1 - (j->tile_n0_host[t] + j->steps_done), i, t, j->precision});
+      items.push_back({NS + 1 - (j->tile_n0_host[t] + j->steps_done), i, t,
+                       segment_of(j->precision, j->kind)});
   }
-  // one launch per precision (each precision has its own kernel), each ordered longest first
+  // one launch per (precision, potential kind) kernel, each ordered longest first
   std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
-    return a.precision != b.precision ? a.precision < b.precision : a.left > b.left;
+    return a.seg != b.seg ? a.seg < b.seg : a.left > b.left;
   });
   if (!items.empty()) {
     HIP_TRY(hipStreamSynchronize(st));  // the staging buffers of the previous call are free
@@ -1231,9 +1257,10 @@ sfhk_status sfhk_propagate_many(sfhk_job* const* jobs, int32_t n_jobs, int64_t m
     size_t a = 0;
     while (a < items.size()) {
       size_t b = a;
-      while (b < items.size() && items[b].precision == items[a].precision) ++b;
-      sfhk_status rc = launch_propagate(items[a].precision, ctx->many_desc, ctx->many_work + a,
-                                        (int)(b - a), ms, st);
+      while (b < items.size() && items[b].seg == items[a].seg) ++b;
+      const int sg = items[a].seg;
+      sfhk_status rc = launch_propagate(sg >= kKinds ? SFHK_FP32_MIXED : SFHK_FP64, sg % kKinds,
+                                        ctx->many_desc, ctx->many_work + a, (int)(b - a), ms, st);
       if (rc) return rc;
       a = b;
     }
@@ -1312,16 +1339,25 @@ sfhk_status sfhk_batch_create(sfhk_ctx* ctx, int32_t max_jobs, int64_t max_tiles
   // capture: reset the queue heads with a kernel (no memset node), then one kernel per precision
   TRY_B(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, b->cap_stream, b->bdev);
-  if (workers_per_cu > 0) {
-    hipLaunchKernelGGL(k_queue_fp64, dim3(b->n_workers), dim3(kTile), 0, b->cap_stream,
-                       (const JobDev*)b->desc, (const WorkItem*)b->work, b->bdev, ms);
-    hipLaunchKernelGGL(k_queue_mixed, dim3(b->n_workers), dim3(kTile), 0, b->cap_stream,
-                       (const JobDev*)b->desc, (const WorkItem*)b->work, b->bdev, ms);
-  } else {
-    hipLaunchKernelGGL(k_grid_fp64, dim3((unsigned)max_tiles), dim3(kTile), 0, b->cap_stream,
-                       (const JobDev*)b->desc, (const WorkItem*)b->work, (const BatchDev*)b->bdev, ms);
-    hipLaunchKernelGGL(k_grid_mixed, dim3((unsigned)max_tiles), dim3(kTile), 0, b->cap_stream,
-                       (const JobDev*)b->desc, (const WorkItem*)b->work, (const BatchDev*)b->bdev, ms);
+  {
+    const JobDev* D = b->desc;
+    const WorkItem* W = b->work;
+    BatchDev* BD = b->bdev;
+    const dim3 gq(b->n_workers), gg((unsigned)max_tiles), bl(kTile);
+    hipStream_t cs = b->cap_stream;
+#define SFHK_CAPTURE(K)                                                                            \
+    if (workers_per_cu > 0) {                                                                      \
+      hipLaunchKernelGGL(k_queue_fp64<K>, gq, bl, 0, cs, D, W, BD, ms);                             \
+      hipLaunchKernelGGL(k_queue_mixed<K>, gq, bl, 0, cs, D, W, BD, ms);                            \
+    } else {                                                                                       \
+      hipLaunchKernelGGL(k_grid_fp64<K>, gg, bl, 0, cs, D, W, (const BatchDev*)BD, ms);            \
+      hipLaunchKernelGGL(k_grid_mixed<K>, gg, bl, 0, cs, D, W, (const BatchDev*)BD, ms);           \
+    }
+    SFHK_CAPTURE(POT_NONE)
+    SFHK_CAPTURE(POT_SOFTCORE)
+    SFHK_CAPTURE(POT_SCREENED)
+    SFHK_CAPTURE(POT_HARMONIC)
+#undef SFHK_CAPTURE
   }
   hipError_t le = hipGetLastError();
   hipGraph_t g = nullptr;
@@ -1344,7 +1380,7 @@ sfhk_status sfhk_batch_set_jobs(sfhk_batch* b, sfhk_job* const* jobs, int32_t n_
   hipStream_t st = (hipStream_t)stream;
   struct Item {
     long long left;
-    int job, tile, precision;
+    int job, tile, seg;
   };
   std::vector<Item> items;
   for (int i = 0; i < n_jobs; ++i) {
@@ -1353,20 +1389,17 @@ sfhk_status sfhk_batch_set_jobs(sfhk_batch* b, sfhk_job* const* jobs, int32_t n_
     const int NS = j->host.n_steps;
     const int nt = unfinished_tiles(j, j->steps_done);
     for (int t = 0; t < nt; ++t)
-      items.push_back({NS + 1 - (j->tile_n0_host[t] + j->steps_done), i, t, j->precision});
+      items.push_back({NS + 1 - (j->tile_n0_host[t] + j->steps_done), i, t,
+                       segment_of(j->precision, j->kind)});
   }
   if ((long long)items.size() > b->max_items) return fail(SFHK_E_INVALID, "more unfinished tiles than the batch was created for");
   std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) {
-    return x.precision != y.precision ? x.precision < y.precision : x.left > y.left;
+    return x.seg != y.seg ? x.seg < y.seg : x.left > y.left;
   });
   HIP_TRY(hipStreamSynchronize(st));  // earlier copies from the staging buffers have completed
   BatchDev bd{};
-  int n64 = 0;
-  for (const Item& it : items) n64 += it.precision == SFHK_FP64;
-  bd.n_items[0] = n64;
-  bd.offset[0] = 0;
-  bd.n_items[1] = (int)items.size() - n64;
-  bd.offset[1] = n64;
+  for (const Item& it : items) bd.n_items[it.seg]++;
+  for (int g = 1; g < kSegs; ++g) bd.offset[g] = bd.offset[g - 1] + bd.n_items[g - 1];
   for (int i = 0; i < n_jobs; ++i) b->desc_host[i] = jobs[i]->host;
   for (size_t k = 0; k < items.size(); ++k) b->work_host[k] = {items[k].job, items[k].tile};
   *b->bdev_host = bd;

@@ -65,6 +65,24 @@ __device__ __forceinline__ double exp_cw(double x) {
   return x != x ? x : y;
 }
 
+// exp_cw on x <= 0 (and NaN), the only arguments the screened potential produces: the same values
+// with one select instead of three (a NaN runs through the sequence and stays NaN)
+__device__ __forceinline__ double exp_cw_nonpos(double x) {
+  constexpr double kInvLn2 = 0x1.71547652b82fep+0;
+  constexpr double kLn2Hi = 0x1.62e42feep-1;
+  constexpr double kLn2Lo = 0x1.a39ef35793c76p-33;
+  const double k = rint(x * kInvLn2);
+  double r = SFHK_FMA(-k, kLn2Hi, x);
+  r = SFHK_FMA(-k, kLn2Lo, r);
+  double p = kInvFact.v[13];
+#pragma unroll
+  for (int n = 12; n >= 3; --n) p = fma3(p, r, kInvFact.v[n]);
+#pragma unroll
+  for (int n = 2; n >= 0; --n) p = SFHK_FMA(p, r, kInvFact.v[n]);
+  const double y = ldexp(p, (int)k);
+  return x < -708.0 ? 0.0 : y;
+}
+
 // ----------------------------------------------------------------------------------------------
 // the reciprocal square root of the rounding contract: the binary64 bit-pattern seed with magic
 // constant 0x5FE6EB50C7B537A9 (Lomont; relative error below 3.5%), three Newton steps
@@ -135,7 +153,7 @@ __device__ __forceinline__ void pot_gc(const PotParams& P, double x, double y, d
     const double r = pos ? r2 * inv_r : 0.0;
     double ir2 = ir * ir;
     double ir3 = ir2 * ir;
-    double e = exp_cw(-(r * P.inv_rscr));
+    double e = exp_cw_nonpos(-(r * P.inv_rscr));
     double ez = P.z_in * e;
     double Z = P.z_inf + ez;
     double d1 = ez * P.inv_rscr;  // -Z'
