@@ -207,15 +207,27 @@ __global__ void k_init(JobDev J, const long long* __restrict__ perm, long long n
 // ------------------------------------------------------------------------------------------------
 // propagation, FP64: one wave per tile, one trajectory per lane
 // ------------------------------------------------------------------------------------------------
-// Per step every lane writes its integrand f_j(t_n) to an LDS ring of kRing steps; when the ring is
-// full (or the launch ends) the wave sums each step's 64 values in a fixed order (four interleaved
-// quarters of 16 lanes, then the quarters pairwise) and one lane per step writes the tile's
-// partial row. The wave is the whole workgroup, so the ring needs no cross-wave synchronisation.
-constexpr int kRing = 16;                // = kTile / 4: four lanes sum each buffered step
-constexpr int kRingStride = kTile + 4;   // double2 per ring row; the padding staggers the banks
+// The dipole integrand is deferred. At a given step few lanes of a wave are near the ground state,
+// and evaluated in place their integrand would cost the whole wave. Instead each such lane appends
+// (q, p, S, w C, n) to a per-wave LDS queue; when the queue cannot take the next step's entries,
+// and at the end of the launch, the wave evaluates up to 64 of them at once. A step's entries are
+// consecutive and in lane order, and the first of them sums the run in that order and stores the
+// tile's partial row for the step; rows of steps without entries keep the zeros they were
+// allocated with. The entries of one step never straddle two evaluations, so the sums do not
+// depend on how the propagation is split into launches or batched. The wave is the whole
+// workgroup, so the queue needs no cross-wave synchronisation.
+constexpr int kQueue = kTile;
 
 struct WorkItem {
   int job, tile;
+};
+
+struct QueueEntry {
+  double2 a, b, c, d, e;  // (qx, qy) (qz, px) (py, pz) (S, Re wC) (Im wC, n)
+};
+struct IntegrandQueue {
+  QueueEntry e[kQueue];
+  double2 f[kQueue];
 };
 
 typedef __attribute__((address_space(4))) const double* const_dptr;  // scalar (uniform) loads
@@ -229,31 +241,62 @@ __device__ __forceinline__ long long uniform_i64(long long v) {
   return (long long)(((unsigned long long)hi << 32) | lo);
 }
 
-__device__ __forceinline__ void flush_ring(double2 (*ring)[kRingStride], int lane, int slot_lo,
-                                           int slot_hi, double2* __restrict__ part,
-                                           long long base) {
+// position of this lane among the set bits of the wave mask m
+__device__ __forceinline__ int lanes_below(unsigned long long m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((unsigned int)(m >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((unsigned int)m, 0u));
+}
+
+__device__ __forceinline__ void queue_push(IntegrandQueue& Q, int idx, double qx, double qy,
+                                           double qz, double px, double py, double pz, double S,
+                                           cplx wC, int n) {
+  QueueEntry& x = Q.e[idx];
+  x.a = make_double2(qx, qy);
+  x.b = make_double2(qz, px);
+  x.c = make_double2(py, pz);
+  x.d = make_double2(S, wC.re);
+  x.e = make_double2(wC.im, (double)n);
+}
+
+// evaluates the qn queued entries (one per lane) and stores their per-step sums; returns this
+// lane's count of evaluated primitives
+__device__ __forceinline__ unsigned int queue_eval(IntegrandQueue& Q, int qn, int lane,
+                                                   const JobDev& J, double2* __restrict__ part,
+                                                   long long roff, int t0) {
   __syncthreads();
-  const int s = lane >> 2, qq = lane & 3;
-  double sr = 0.0, si = 0.0;
-#pragma unroll
-  for (int i = 0; i < kTile / 4; ++i) {
-    double2 v = ring[s][qq + 4 * i];
-    sr += v.x;
-    si += v.y;
+  unsigned int n_eval = 0;
+  if (lane < qn) {
+    const QueueEntry x = Q.e[lane];
+    const double qx = x.a.x, qy = x.a.y, qz = x.b.x, px = x.b.y, py = x.c.x, pz = x.c.y;
+    const double p2 = SFHK_FMA(pz, pz, SFHK_FMA(py, py, px * px));
+    const double q2 = SFHK_FMA(qz, qz, SFHK_FMA(qy, qy, qx * qx));
+    const Contrib cb = contribution(&J.gto, J.cut, qx, qy, qz, px, py, pz, p2, q2, x.d.x,
+                                    J.t_a + x.e.y * J.h, x.d.y, x.e.x);
+    Q.f[lane] = make_double2(cb.re, cb.im);
+    n_eval = cb.n_eval;
   }
-  sr += __shfl_xor(sr, 1, 64);
-  si += __shfl_xor(si, 1, 64);
-  sr += __shfl_xor(sr, 2, 64);
-  si += __shfl_xor(si, 2, 64);
-  if (qq == 0 && s >= slot_lo && s <= slot_hi) part[base + s] = make_double2(sr, si);
   __syncthreads();
+  if (lane < qn) {
+    const double ns = Q.e[lane].e.y;
+    if (lane == 0 || Q.e[lane - 1].e.y != ns) {
+      double2 acc = Q.f[lane];
+      for (int j = lane + 1; j < qn && Q.e[j].e.y == ns; ++j) {
+        const double2 v = Q.f[j];
+        acc.x += v.x;
+        acc.y += v.y;
+      }
+      part[roff + ((long long)ns - t0)] = acc;
+    }
+  }
+  __syncthreads();
+  return n_eval;
 }
 
 // KIND >= 0: the potential kind is a compile-time constant (its dispatch folds away); -1: read from
 // the job descriptor at run time
 template <int KIND>
 __device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const int max_steps,
-                                         double2 (*ring)[kRingStride]) {
+                                         IntegrandQueue& Q) {
   const int lane = threadIdx.x;
   const int n_begin = uniform_i32(J.tile_next[tile]);
   const int N = J.n_steps;
@@ -286,16 +329,14 @@ __device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const 
   const const_dptr eh = (const_dptr)J.e_half;
   const PotParams P = J.pot;
   const int kind = KIND >= 0 ? KIND : J.kind;
-  const double gamma = J.gamma, inv4g = J.inv4g, kay2 = J.kay2, cut = J.cut;
-  const double h = J.h, h2 = J.h2, h6 = J.h6, t_a = J.t_a;
+  const double gamma = J.gamma, inv4g = J.inv4g, kay2 = J.kay2;
+  const double h = J.h, h2 = J.h2, h6 = J.h6;
 
-  int slot_lo = (n_begin - t0) % kRing;
+  int qn = 0;  // queued integrands (wave-uniform)
   unsigned int kay = 0, nonfin = 0, prims = 0;
   int n = n_begin;
   double ea = eh[2 * n];
   for (; n <= n_stop; ++n) {
-    const int slot = (n - t0) % kRing;
-    double fr = 0.0, fi = 0.0;
     bool contrib = false;
     cplx C = {0.0, 0.0};
     if (alive && n >= n0l) {
@@ -325,33 +366,29 @@ __device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const 
     double p2 = SFHK_FMA(T.p[2], T.p[2], SFHK_FMA(T.p[1], T.p[1], T.p[0] * T.p[0]));
     double q2 = SFHK_FMA(T.q[2], T.q[2], SFHK_FMA(T.q[1], T.q[1], T.q[0] * T.q[0]));
     const bool need = contrib && !overlap_all_skipped(J.gto, p2, q2);
-    if (__any(need)) {
-      if (need) {
-        const cplx wC = cmul(w, C);
-        const Contrib cb = contribution(&J.gto, cut, T.q[0], T.q[1], T.q[2], T.p[0], T.p[1],
-                                        T.p[2], p2, q2, T.S, t_a + (double)n * h, wC.re, wC.im);
-        fr = cb.re;
-        fi = cb.im;
-        prims += cb.n_eval;
+    const unsigned long long m = __ballot(need);
+    if (m) {
+      const int k = __popcll(m);
+      if (qn + k > kQueue) {
+        prims += queue_eval(Q, qn, lane, J, part, roff, t0);
+        qn = 0;
       }
-    }
-    ring[slot][lane] = make_double2(fr, fi);
-    const bool last = (n == n_stop);
-    if (slot == kRing - 1 || last) {
-      flush_ring(ring, lane, slot_lo, slot, part, roff + (n - slot - t0));
-      slot_lo = 0;
+      if (need)
+        queue_push(Q, qn + lanes_below(m), T.q[0], T.q[1], T.q[2], T.p[0], T.p[1], T.p[2], T.S,
+                   cmul(w, C), n);
+      qn += k;
     }
     if (n < N) {
       const double eb = eh[2 * n + 1], ec = eh[2 * n + 2];
       if (alive && n >= n0l) rk4_step(kind, P, T, ea, eb, ec, h, h2, h6);
       ea = ec;
     }
-    if (!__any(alive)) {  // every lane removed: the rest of the tile's row stays unwritten
-      if (!(slot == kRing - 1 || last)) flush_ring(ring, lane, slot_lo, slot, part, roff + (n - slot - t0));
+    if (!__any(alive)) {  // every lane removed: the rest of the tile's row stays zero
       ++n;
       break;
     }
   }
+  if (qn > 0) prims += queue_eval(Q, qn, lane, J, part, roff, t0);
   // n is now one past the last step processed
   double* yw = J.y;
 #pragma unroll
@@ -396,9 +433,9 @@ template <int KIND>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_PROPAGATE_WAVES_PER_EU)))
 void k_propagate_fp64(
     const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work, int max_steps) {
-  __shared__ double2 ring[kRing][kRingStride];
+  __shared__ IntegrandQueue Q;
   const WorkItem wi = work[blockIdx.x];
-  run_tile<KIND>(jobs[wi.job], wi.tile, max_steps, ring);
+  run_tile<KIND>(jobs[wi.job], wi.tile, max_steps, Q);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -410,7 +447,7 @@ void k_propagate_fp64(
 // ------------------------------------------------------------------------------------------------
 template <int KIND>
 __device__ __forceinline__ void run_tile_mixed(const JobDev& J, const int tile, const int max_steps,
-                                               double2 (*ring)[kRingStride]) {
+                                               IntegrandQueue& Q) {
   const int lane = threadIdx.x;
   const int n_begin = uniform_i32(J.tile_next[tile]);
   const int N = J.n_steps;
@@ -445,21 +482,19 @@ __device__ __forceinline__ void run_tile_mixed(const JobDev& J, const int tile, 
   const PotParamsF PF = {(float)P.z_inf, (float)P.z_in, (float)P.soft2, (float)P.omega_ho,
                          (float)P.inv_rscr};
   const int kind = KIND >= 0 ? KIND : J.kind;
-  const double kay2 = J.kay2, cut = J.cut;
-  const double h = J.h, h2 = J.h2, h6 = J.h6, t_a = J.t_a;
+  const double kay2 = J.kay2;
+  const double h = J.h, h2 = J.h2, h6 = J.h6;
   const float hf = (float)h, h2f = (float)h2, h6f = (float)h6;
   const float gammaf = (float)J.gamma, inv4gf = (float)J.inv4g;
   const float aminf = (float)J.gto.Amin, bminf = (float)J.gto.Bmin;
   const float cut_lo = (float)(J.cut * (1.0 + 1e-5));  // FP32 bound: margin for FP32 rounding
   const float r64sq = (float)J.r64sq;
 
-  int slot_lo = (n_begin - t0) % kRing;
+  int qn = 0;  // queued integrands (wave-uniform)
   unsigned int kay = 0, nonfin = 0, prims = 0, steps64 = 0;
   int n = n_begin;
   double ea = eh[2 * n];
   for (; n <= n_stop; ++n) {
-    const int slot = (n - t0) % kRing;
-    double fr = 0.0, fi = 0.0;
     bool contrib = false;
     cplx C = {0.0, 0.0};
     if (alive && n >= n0l) {
@@ -488,24 +523,17 @@ __device__ __forceinline__ void run_tile_mixed(const JobDev& J, const int tile, 
     const float p2f = __builtin_fmaf(T.p[2], T.p[2], __builtin_fmaf(T.p[1], T.p[1], T.p[0] * T.p[0]));
     const float q2f = __builtin_fmaf(T.q[2], T.q[2], __builtin_fmaf(T.q[1], T.q[1], T.q[0] * T.q[0]));
     const bool need = contrib && !(__builtin_fmaf(p2f, aminf, q2f * bminf) > cut_lo);
-    if (__any(need)) {
-      if (need) {
-        const double qx = T.q[0], qy = T.q[1], qz = T.q[2], px = T.p[0], py = T.p[1], pz = T.p[2];
-        const double p2 = SFHK_FMA(pz, pz, SFHK_FMA(py, py, px * px));
-        const double q2 = SFHK_FMA(qz, qz, SFHK_FMA(qy, qy, qx * qx));
-        const cplx wC = cmul(w, C);
-        const Contrib cb = contribution(&J.gto, cut, qx, qy, qz, px, py, pz, p2, q2, T.S,
-                                        t_a + (double)n * h, wC.re, wC.im);
-        fr = cb.re;
-        fi = cb.im;
-        prims += cb.n_eval;
+    const unsigned long long m = __ballot(need);
+    if (m) {
+      const int k = __popcll(m);
+      if (qn + k > kQueue) {
+        prims += queue_eval(Q, qn, lane, J, part, roff, t0);
+        qn = 0;
       }
-    }
-    ring[slot][lane] = make_double2(fr, fi);
-    const bool last = (n == n_stop);
-    if (slot == kRing - 1 || last) {
-      flush_ring(ring, lane, slot_lo, slot, part, roff + (n - slot - t0));
-      slot_lo = 0;
+      if (need)
+        queue_push(Q, qn + lanes_below(m), T.q[0], T.q[1], T.q[2], T.p[0], T.p[1], T.p[2], T.S,
+                   cmul(w, C), n);
+      qn += k;
     }
     if (n < N) {
       const double eb = eh[2 * n + 1], ec = eh[2 * n + 2];
@@ -537,11 +565,11 @@ __device__ __forceinline__ void run_tile_mixed(const JobDev& J, const int tile, 
       ea = ec;
     }
     if (!__any(alive)) {
-      if (!(slot == kRing - 1 || last)) flush_ring(ring, lane, slot_lo, slot, part, roff + (n - slot - t0));
       ++n;
       break;
     }
   }
+  if (qn > 0) prims += queue_eval(Q, qn, lane, J, part, roff, t0);
   double* yw = J.y;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -583,9 +611,9 @@ __device__ __forceinline__ void run_tile_mixed(const JobDev& J, const int tile, 
 template <int KIND>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_MIXED_WAVES_PER_EU)))
 void k_propagate_mixed(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work, int max_steps) {
-  __shared__ double2 ring[kRing][kRingStride];
+  __shared__ IntegrandQueue Q;
   const WorkItem wi = work[blockIdx.x];
-  run_tile_mixed<KIND>(jobs[wi.job], wi.tile, max_steps, ring);
+  run_tile_mixed<KIND>(jobs[wi.job], wi.tile, max_steps, Q);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -608,14 +636,14 @@ __global__ void k_batch_reset(BatchDev* __restrict__ B) {
 }
 
 // one tile per call: inlined into the queue loop, the tile loop's register allocation degrades.
-// The LDS ring is declared here, not passed in, so its accesses stay LDS instructions.
+// The LDS queue is declared here, not passed in, so its accesses stay LDS instructions.
 template <int PREC, int KIND>
 __device__ __noinline__ void tile_call(const JobDev* J, int tile, int max_steps) {
-  __shared__ double2 ring[kRing][kRingStride];
+  __shared__ IntegrandQueue Q;
   if (PREC == 0)
-    run_tile<KIND>(*J, tile, max_steps, ring);
+    run_tile<KIND>(*J, tile, max_steps, Q);
   else
-    run_tile_mixed<KIND>(*J, tile, max_steps, ring);
+    run_tile_mixed<KIND>(*J, tile, max_steps, Q);
 }
 
 template <int PREC, int KIND>
@@ -654,22 +682,22 @@ template <int KIND>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_PROPAGATE_WAVES_PER_EU)))
 void k_grid_fp64(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work,
                  const BatchDev* __restrict__ B, int max_steps) {
-  __shared__ double2 ring[kRing][kRingStride];
+  __shared__ IntegrandQueue Q;
   constexpr int seg = KIND;
   if ((int)blockIdx.x >= B->n_items[seg]) return;
   const WorkItem wi = work[B->offset[seg] + blockIdx.x];
-  run_tile<KIND>(jobs[wi.job], wi.tile, max_steps, ring);
+  run_tile<KIND>(jobs[wi.job], wi.tile, max_steps, Q);
 }
 
 template <int KIND>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_MIXED_WAVES_PER_EU)))
 void k_grid_mixed(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work,
                   const BatchDev* __restrict__ B, int max_steps) {
-  __shared__ double2 ring[kRing][kRingStride];
+  __shared__ IntegrandQueue Q;
   constexpr int seg = kKinds + KIND;
   if ((int)blockIdx.x >= B->n_items[seg]) return;
   const WorkItem wi = work[B->offset[seg] + blockIdx.x];
-  run_tile_mixed<KIND>(jobs[wi.job], wi.tile, max_steps, ring);
+  run_tile_mixed<KIND>(jobs[wi.job], wi.tile, max_steps, Q);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1145,6 +1173,7 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   for (int t = 0; t < n_tiles; ++t) work[t] = {0, t};
   TRY_C(hipMemcpyAsync(j->work, work.data(), n_tiles * sizeof(WorkItem), hipMemcpyHostToDevice, st));
   TRY_C(hipMemsetAsync(H.counters, 0, 8 * sizeof(unsigned long long), st));
+  TRY_C(hipMemsetAsync(H.part, 0, (size_t)part_elems * sizeof(double2), st));  // rows without integrands stay 0
   TRY_C(hipMemcpyAsync(j->dev, &H, sizeof(JobDev), hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL(k_init, dim3(blocks_for(n_pad, 256)), dim3(256), 0, st, H, j->perm, N, q0, p0, w);
   TRY_C(hipGetLastError());
