@@ -1097,8 +1097,12 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   j->bytes = bytes;
   j->tile_n0_host = tile_n0;
   JobDev& H = j->host;
+  // fast range of the screened potential: 2^-1000 <= r^2 <= 2^999 and 0 <= a <= 2^999 keep r^2
+  // and r^2 + a within the square root's core range
+  const double r2_fast = (pot->kind == SFHK_POT_SCREENED && pot->soft2 >= 0.0 && pot->soft2 <= 0x1p999)
+                             ? 0x1p999 : -1.0;
   H.pot = {pot->z_inf, pot->z_in, pot->r_scr, pot->soft2, pot->omega_ho,
-           pot->kind == SFHK_POT_SCREENED ? 1.0 / pot->r_scr : 0.0};
+           pot->kind == SFHK_POT_SCREENED ? 1.0 / pot->r_scr : 0.0, r2_fast};
   const double g = params->gamma;
   H.gto.l = ground->l;
   H.gto.n_prim = ground->n_prim;

@@ -46,11 +46,11 @@ __device__ __forceinline__ double fma3(double a, double b, double c) {
   return d;
 }
 
-__device__ __forceinline__ double exp_cw(double x) {
+// the sequence alone: exp_cw for arguments in [-708, 709] (a NaN runs through and stays NaN)
+__device__ __forceinline__ double exp_cw_core(double x) {
   constexpr double kInvLn2 = 0x1.71547652b82fep+0;  // 1/ln2 rounded to binary64
   constexpr double kLn2Hi = 0x1.62e42feep-1;         // ln2 truncated to 32 significant bits
   constexpr double kLn2Lo = 0x1.a39ef35793c76p-33;   // ln2 - kLn2Hi rounded to binary64
-  // the sequence runs for every x; the three out-of-range cases are selected afterwards
   const double k = rint(x * kInvLn2);
   double r = SFHK_FMA(-k, kLn2Hi, x);
   r = SFHK_FMA(-k, kLn2Lo, r);
@@ -59,28 +59,21 @@ __device__ __forceinline__ double exp_cw(double x) {
   for (int n = 12; n >= 3; --n) p = fma3(p, r, kInvFact.v[n]);
 #pragma unroll
   for (int n = 2; n >= 0; --n) p = SFHK_FMA(p, r, kInvFact.v[n]);  // 1/2, 1, 1: inline constants
-  double y = ldexp(p, (int)k);
+  return ldexp(p, (int)k);
+}
+
+// exp_cw on x <= 0 (and NaN)
+__device__ __forceinline__ double exp_cw_nonpos(double x) {
+  const double y = exp_cw_core(x);
+  return x < -708.0 ? 0.0 : y;
+}
+
+// the sequence runs for every x; the three out-of-range cases are selected afterwards
+__device__ __forceinline__ double exp_cw(double x) {
+  double y = exp_cw_core(x);
   y = x < -708.0 ? 0.0 : y;
   y = x > 709.0 ? __builtin_inf() : y;
   return x != x ? x : y;
-}
-
-// exp_cw on x <= 0 (and NaN), the only arguments the screened potential produces: the same values
-// with one select instead of three (a NaN runs through the sequence and stays NaN)
-__device__ __forceinline__ double exp_cw_nonpos(double x) {
-  constexpr double kInvLn2 = 0x1.71547652b82fep+0;
-  constexpr double kLn2Hi = 0x1.62e42feep-1;
-  constexpr double kLn2Lo = 0x1.a39ef35793c76p-33;
-  const double k = rint(x * kInvLn2);
-  double r = SFHK_FMA(-k, kLn2Hi, x);
-  r = SFHK_FMA(-k, kLn2Lo, r);
-  double p = kInvFact.v[13];
-#pragma unroll
-  for (int n = 12; n >= 3; --n) p = fma3(p, r, kInvFact.v[n]);
-#pragma unroll
-  for (int n = 2; n >= 0; --n) p = SFHK_FMA(p, r, kInvFact.v[n]);
-  const double y = ldexp(p, (int)k);
-  return x < -708.0 ? 0.0 : y;
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -107,6 +100,11 @@ __device__ __forceinline__ double rsqrt_rare(double x) {
   return rsqrt_core(x * 0x1p-1000) * 0x1p-500;
 }
 
+// rsqrt_c per lane, for code that already runs only on lanes with special cases
+__device__ __forceinline__ double rsqrt_lane(double x) {
+  return (x >= 0x1p-1000 && x <= 0x1p1000) ? rsqrt_core(x) : rsqrt_rare(x);
+}
+
 // The in-range sequence runs unconditionally; lanes outside [2^-1000, 2^1000] are redone under a
 // wave-uniform test, so the common path has no divergent branch to merge.
 __device__ __forceinline__ double rsqrt_c(double x) {
@@ -126,7 +124,44 @@ enum PotKind : int { POT_NONE = 0, POT_SOFTCORE = 1, POT_SCREENED = 2, POT_HARMO
 struct PotParams {
   double z_inf, z_in, r_scr, soft2, omega_ho;
   double inv_rscr;  // 1 / r_scr (correctly rounded quotient)
+  // screened potential: for 2^-1000 <= r^2 <= r2_fast both square roots are in the core range of
+  // rsqrt_c (set by the host; -1 disables the fast form)
+  double r2_fast;
 };
+
+// The screened potential's terms. FAST: the sequence for lanes with 2^-1000 <= r^2 <= r2_fast,
+// where the square roots' range tests and the r = 0 selects of the careful form are known to
+// pick the ordinary branch, so both forms give the same bits there; the careful form keeps every
+// special case. Both keep the exponential's underflow select: distant trajectories hit it often.
+template <bool FAST>
+__device__ __forceinline__ void screened_terms(const PotParams& P, double r2, double& V, double& g,
+                                               double& c) {
+  // V = -Z(r)/rho, Z = z_inf + z_in exp(-r/r_scr), rho = (r^2 + a)^(1/2)
+  double s = r2 + P.soft2;
+  double ir = FAST ? rsqrt_core(s) : rsqrt_lane(s);  // 1/rho
+  const bool pos = FAST || r2 > 0.0;
+  const double inv_r = FAST ? rsqrt_core(r2) : rsqrt_lane(r2);  // +inf at r = 0, unused there
+  const double r = pos ? r2 * inv_r : 0.0;
+  double ir2 = ir * ir;
+  double ir3 = ir2 * ir;
+  const double xe = -(r * P.inv_rscr);
+  double e = exp_cw_nonpos(xe);
+  double ez = P.z_in * e;
+  double Z = P.z_inf + ez;
+  double d1 = ez * P.inv_rscr;  // -Z'
+  double d2 = d1 * P.inv_rscr;  //  Z''
+  V = -(Z * ir);
+  double vp = SFHK_FMA(Z * r, ir3, d1 * ir);           // V'
+  double w1 = SFHK_FMA(-2.0, r2, P.soft2);             // a - 2 r^2
+  double ta = d2 * ir;
+  double tb = (d1 * r) * ir3;
+  double tc = ((Z * w1) * ir3) * ir2;
+  double vpp = tc - SFHK_FMA(2.0, tb, ta);             // V''
+  const double gp = vp * inv_r;
+  const double cp = (vpp - gp) * (inv_r * inv_r);
+  g = pos ? gp : vpp;  // r = 0 exactly (measure zero): finite isotropic choice
+  c = pos ? cp : 0.0;
+}
 
 template <int KIND>
 __device__ __forceinline__ void pot_gc(const PotParams& P, double x, double y, double z, double& V,
@@ -145,30 +180,12 @@ __device__ __forceinline__ void pot_gc(const PotParams& P, double x, double y, d
     g = P.z_inf * u3;
     c = (-3.0 * P.z_inf) * u5;
   } else if constexpr (KIND == POT_SCREENED) {
-    // V = -Z(r)/rho, Z = z_inf + z_in exp(-r/r_scr), rho = (r^2 + a)^(1/2)
-    double s = r2 + P.soft2;
-    double ir = rsqrt_c(s);  // 1/rho
-    const bool pos = r2 > 0.0;
-    const double inv_r = rsqrt_c(r2);   // +inf at r = 0, unused there
-    const double r = pos ? r2 * inv_r : 0.0;
-    double ir2 = ir * ir;
-    double ir3 = ir2 * ir;
-    double e = exp_cw_nonpos(-(r * P.inv_rscr));
-    double ez = P.z_in * e;
-    double Z = P.z_inf + ez;
-    double d1 = ez * P.inv_rscr;  // -Z'
-    double d2 = d1 * P.inv_rscr;  //  Z''
-    V = -(Z * ir);
-    double vp = SFHK_FMA(Z * r, ir3, d1 * ir);           // V'
-    double w1 = SFHK_FMA(-2.0, r2, P.soft2);             // a - 2 r^2
-    double ta = d2 * ir;
-    double tb = (d1 * r) * ir3;
-    double tc = ((Z * w1) * ir3) * ir2;
-    double vpp = tc - SFHK_FMA(2.0, tb, ta);             // V''
-    const double gp = vp * inv_r;
-    const double cp = (vpp - gp) * (inv_r * inv_r);
-    g = pos ? gp : vpp;  // r = 0 exactly (measure zero): finite isotropic choice
-    c = pos ? cp : 0.0;
+    // lanes outside the fast range are redone in the careful form under a wave-uniform test
+    screened_terms<true>(P, r2, V, g, c);
+    const bool slow = !(r2 >= 0x1p-1000 && r2 <= P.r2_fast);
+    if (__builtin_expect(__any(slow), 0)) {
+      if (slow) screened_terms<false>(P, r2, V, g, c);
+    }
   } else if constexpr (KIND == POT_HARMONIC) {
     double w2 = P.omega_ho * P.omega_ho;
     V = (0.5 * w2) * r2;
