@@ -143,15 +143,15 @@ void sfhk_job_destroy(sfhk_job* job);
  * status is known on the host without waiting for the kernels. */
 sfhk_status sfhk_propagate(sfhk_job* job, int64_t max_steps, void* stream);
 
-/* Propagate several jobs of one context in a single kernel launch (jobs may differ in size,
- * pulse, potential and precision). Same semantics per job as sfhk_propagate; returns
- * SFHK_E_NOT_DONE if any job is unfinished. */
+/* Propagate several jobs of one context with one kernel launch per (precision, potential kind)
+ * present (jobs may differ in size, pulse, potential and precision). Same semantics per job as
+ * sfhk_propagate; returns SFHK_E_NOT_DONE if any job is unfinished. */
 sfhk_status sfhk_propagate_many(sfhk_job* const* jobs, int32_t n_jobs, int64_t max_steps,
                                 void* stream);
 
 /* Batched, graph-captured propagation. A batch owns a job table of fixed capacity (max_jobs
  * jobs, max_tiles unfinished tiles) at fixed device addresses and a HIP graph captured once at
- * creation: a queue reset followed by one kernel per precision (FP64 and mixed). Each replay
+ * creation: a queue reset followed by one kernel per (precision, potential kind). Each replay
  * (sfhk_batch_run) advances every staged unfinished tile by up to max_steps steps (max_steps <= 0:
  * to the end of its grid), longest tiles first. workers_per_cu > 0: that many single-wave workgroups
  * per compute unit stay resident and pop tiles from a device-side atomic queue (persistent

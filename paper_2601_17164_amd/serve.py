@@ -3,8 +3,8 @@
 Requests (one SFHK instance each) arrive at given times. Between graph replays of one batch,
 arrived requests are admitted in arrival order while their device footprint fits the context's
 HBM budget and the batch's capacity; admitted requests keep their trajectory state in HBM and
-every replay advances all of them by `chunk` steps (one launch per precision over all their tiles,
-longest first). A request that has finished gets its dipole and spectrum computed on the device
+every replay advances all of them by `chunk` steps (one launch per precision and potential kind
+over all their tiles, longest first). A request that has finished gets its dipole and spectrum computed on the device
 and copied to pinned host memory; its latency runs from arrival to that copy's completion.
 Results are identical to each request propagated alone (the batch path is bitwise equal to it).
 """
