@@ -116,6 +116,21 @@ def test_mixed_volkov_closed_form(S):
     assert g["stats"].steps_fp64 == 0
 
 
+def test_mixed_oscillator_closed_form(S):
+    """Harmonic oscillator with omega = 2 gamma in the mixed form, every step on the FP32 path:
+    C = exp(-3 i omega tau / 2) to FP32 accumulation accuracy."""
+    pulse = I.Pulse(800.0, 1e14, 2.0)
+    om, n_steps, h = 1.0, 3000, 0.01
+    grid = I.Grid(0.0, h, n_steps)
+    inst = I.Instance("ho", I.Potential(I.POT_HARMONIC, 0, 0, 1, 0, om), I.gto_h1s(), pulse,
+                      grid, np.zeros(2 * n_steps + 1), np.array([0.0]),
+                      np.array([[0.7], [-0.4], [1.1]]), np.array([[0.2], [0.5], [-0.3]]))
+    g = _run(S, inst, r_fp64=0.0)
+    tau = n_steps * h
+    assert abs(g["c"][0] - np.exp(-1.5j * om * tau)) < 1e-3
+    assert g["stats"].steps_fp64 == 0
+
+
 def test_mixed_precision_switch(S):
     """r_fp64 = 0: no FP64 steps; a huge r_fp64: every propagated step is an FP64 step."""
     inst = I.config0(n_birth=4, n_per_birth=16)

@@ -222,6 +222,31 @@ def test_nonfinite_sample_is_removed_and_counted(S):
     assert rel_l2(g["F"], r.F) <= TOL
 
 
+@pytest.mark.parametrize("which", ["screened", "softcore"])
+def test_extreme_radii_take_the_careful_paths(S, which):
+    """Lanes outside the potential's fast range (r = 0 exactly, r^2 below 2^-1000, r^2 just above
+    2^999 and beyond the square root's core range, r^2 overflowing to inf) and one on the range's
+    edge (r^2 = 2^999), in a wave whose other lanes take the fast form: bit for bit with the
+    oracle."""
+    if which == "screened":
+        inst = I.config1_birth_subset(I.config1(), [900], 64)
+    else:
+        base = I.config0()
+        inst = base.subset(np.arange(32 * 32, 33 * 32))
+        inst = inst.subset(np.concatenate([np.arange(32), np.arange(32)]))
+    q0 = inst.q0.copy()
+    q0[:, 0] = 0.0
+    q0[:, 1] = [1e-160, 0.0, 0.0]
+    q0[:, 2] = [2.0 ** 499, 2.0 ** 499, 0.0]
+    q0[:, 3] = [2.0 ** 499, 2.0 ** 499, 2.0 ** 498]
+    q0[:, 4] = [2e150, 2e150, 2e150]
+    q0[:, 5] = [1e200, 0.0, 0.0]
+    inst.q0 = q0
+    r = run_oracle(inst)
+    g = _gpu_run(S, inst)
+    _assert_parity(f"extreme-radii-{which}", g, r)
+
+
 def test_volkov_and_oscillator_closed_forms_through_gpu(S):
     """Laser-only motion: M = [[I, tau I], [0, I]], C = (1 - i gamma tau)^{3/2}; harmonic
     oscillator with omega = 2 gamma: C = exp(-3 i omega tau / 2)."""
