@@ -192,7 +192,7 @@ int64_t sfhk_job_n_out(const sfhk_job* job);
  *   X_k = dt sum_n d_n W_H(t_n) exp(i omega_k t_n),  W_H(t) = (1 + cos(pi t / tau_h)) / 2 for
  *   |t| < tau_h and 0 otherwise,  omega_k = 2 pi k / (n_fft dt),  k = 0..n_fft/2.
  * Writes omega_out[k], power_out[k] = |X_k|^2 and (nullable) x_out[2k], x_out[2k+1] = X_k.
- * Stateless. Errors: SFHK_E_INVALID for n < 1, n_fft < n, dt <= 0 or tau_h <= 0. */
+ * Stateless. Errors: SFHK_E_INVALID for n < 1, n_fft < n, n_fft > 2^31, dt <= 0 or tau_h <= 0. */
 sfhk_status sfhk_spectrum(const double* d, int64_t n, double t_first, double dt, double tau_h,
                           int64_t n_fft, double* omega_out, double* power_out, double* x_out,
                           void* stream);

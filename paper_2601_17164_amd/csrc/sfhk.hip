@@ -17,7 +17,6 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
-#include <numeric>
 #include <string>
 #include <vector>
 
@@ -788,33 +787,55 @@ __global__ void k_window(const double* __restrict__ d, long long n, long long n_
   tw[i] = make_double2(c, s);
 }
 
-__global__ __launch_bounds__(256) void k_dft(const double* __restrict__ xw, const double2* __restrict__ tw,
-                                             long long n, long long n_fft, double t_first, double dt,
-                                             double* __restrict__ omega_out, double* __restrict__ power_out,
-                                             double* __restrict__ x_out) {
-  __shared__ double xs[1024];
-  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+// Direct DFT, Y_k = sum_n x_n e^{2 pi i k n / n_fft} for k = 0..n_fft/2. Blocks along y take
+// consecutive spans of samples; within a span each lane keeps its twiddle by the recurrence
+// t <- t e^{2 pi i k / n_fft}, re-anchored from the exact table (index k m mod n_fft) at every
+// staged chunk of kDftChunk samples, so the recurrence error stays near kDftChunk ulps. Partial
+// sums per span are added in span order by k_dft_final (deterministic).
+constexpr int kDftChunk = 1024;
+constexpr int kDftMaxSpans = 64;
+
+__global__ __launch_bounds__(256) void k_dft_partial(const double* __restrict__ xw,
+                                                     const double2* __restrict__ tw, long long n,
+                                                     long long n_fft, long long span,
+                                                     double2* __restrict__ part) {
+  __shared__ double xs[kDftChunk];
   const long long nk = n_fft / 2 + 1;
-  double sr = 0.0, si = 0.0;
-  long long m = 0;  // k * i mod n_fft
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long kk = k < nk ? k : 0;
-  for (long long base = 0; base < n; base += 1024) {
-    const int cnt = (int)min((long long)1024, n - base);
+  const long long lo = (long long)blockIdx.y * span;
+  const long long hi = min(n, lo + span);
+  const double2 step = tw[kk];
+  double cr = 0.0, ci = 0.0;
+  for (long long base = lo; base < hi; base += kDftChunk) {
+    const int cnt = (int)min((long long)kDftChunk, hi - base);
     __syncthreads();
     for (int i = threadIdx.x; i < cnt; i += blockDim.x) xs[i] = xw[base + i];
     __syncthreads();
-    double cr = 0.0, ci = 0.0;
+    double2 t = tw[(kk * base) % n_fft];
     for (int i = 0; i < cnt; ++i) {
-      double2 t = tw[m];
       cr = SFHK_FMA(xs[i], t.x, cr);
       ci = SFHK_FMA(xs[i], t.y, ci);
-      m += kk;
-      if (m >= n_fft) m -= n_fft;
+      const double tr = SFHK_FMA(t.x, step.x, -(t.y * step.y));
+      t.y = SFHK_FMA(t.x, step.y, t.y * step.x);
+      t.x = tr;
     }
-    sr += cr;
-    si += ci;
   }
+  if (k < nk) part[(long long)blockIdx.y * nk + k] = make_double2(cr, ci);
+}
+
+__global__ void k_dft_final(const double2* __restrict__ part, int n_spans, long long n_fft,
+                            double t_first, double dt, double* __restrict__ omega_out,
+                            double* __restrict__ power_out, double* __restrict__ x_out) {
+  const long long nk = n_fft / 2 + 1;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nk) return;
+  double sr = 0.0, si = 0.0;
+  for (int g = 0; g < n_spans; ++g) {
+    const double2 v = part[(long long)g * nk + k];
+    sr += v.x;
+    si += v.y;
+  }
   const double omega = 2.0 * M_PI * (double)k / ((double)n_fft * dt);
   double s, c;
   sincos(omega * t_first, &s, &c);
@@ -1057,16 +1078,26 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
     if (nn > (double)NS) nn = (double)NS;
     n0h[i] = (int)nn;
   }
-  std::vector<long long> order(N);
-  std::iota(order.begin(), order.end(), 0LL);
-  std::stable_sort(order.begin(), order.end(), [&](long long a, long long b) { return n0h[a] < n0h[b]; });
+  // stable order by birth step: the identity when the samples already come in birth order (the
+  // usual layout), else a counting sort over the grid steps 0..NS
+  bool in_order = true;
+  for (long long i = 1; i < N && in_order; ++i) in_order = n0h[i - 1] <= n0h[i];
+  std::vector<long long> order;
+  if (!in_order) {
+    std::vector<long long> next(NS + 2, 0);
+    for (long long i = 0; i < N; ++i) ++next[n0h[i] + 1];
+    for (int k = 0; k <= NS; ++k) next[k + 1] += next[k];
+    order.resize(N);
+    for (long long i = 0; i < N; ++i) order[next[n0h[i]]++] = i;
+  }
   const long long n_pad = (N + kTile - 1) / kTile * kTile;
   const int n_tiles = (int)(n_pad / kTile);
   std::vector<long long> perm(n_pad, -1);
   std::vector<int> n0s(n_pad, NS + 1);
   for (long long s = 0; s < N; ++s) {
-    perm[s] = order[s];
-    n0s[s] = n0h[order[s]];
+    const long long o = in_order ? s : order[s];
+    perm[s] = o;
+    n0s[s] = n0h[o];
   }
   std::vector<int> tile_n0(n_tiles), tile_next(n_tiles), tile_last(n_tiles);
   std::vector<long long> row_off(n_tiles);
@@ -1493,21 +1524,33 @@ sfhk_status sfhk_spectrum(const double* d, int64_t n, double t_first, double dt,
                           int64_t n_fft, double* omega_out, double* power_out, double* x_out,
                           void* stream) {
   if (n_fft == 0) n_fft = n;
-  if (!d || n < 1 || n_fft < n || !(dt > 0.0) || !(tau_h > 0.0))
-    return fail(SFHK_E_INVALID, "spectrum: need d, n >= 1, n_fft >= n, dt > 0, tau_h > 0");
+  if (!d || n < 1 || n_fft < n || n_fft > (1LL << 31) || !(dt > 0.0) || !(tau_h > 0.0))
+    return fail(SFHK_E_INVALID, "spectrum: need d, 1 <= n <= n_fft <= 2^31, dt > 0, tau_h > 0");
   hipStream_t st = (hipStream_t)stream;
+  const long long nk = n_fft / 2 + 1;
+  // spans of samples per block row: whole chunks, at most kDftMaxSpans rows
+  const long long chunks = (n + kDftChunk - 1) / kDftChunk;
+  const long long per = (chunks + kDftMaxSpans - 1) / kDftMaxSpans;
+  const long long span = per * kDftChunk;
+  const int n_spans = (int)((n + span - 1) / span);
   double* xw = nullptr;
   double2* tw = nullptr;
+  double2* part = nullptr;
   HIP_TRY(hipMallocAsync((void**)&xw, n_fft * sizeof(double), st));
   HIP_TRY(hipMallocAsync((void**)&tw, n_fft * sizeof(double2), st));
+  HIP_TRY(hipMallocAsync((void**)&part, (size_t)n_spans * nk * sizeof(double2), st));
   hipLaunchKernelGGL(k_window, dim3(blocks_for(n_fft, 256)), dim3(256), 0, st, d, (long long)n,
                      (long long)n_fft, t_first, dt, tau_h, xw, tw);
   HIP_TRY(hipGetLastError());
-  const long long nk = n_fft / 2 + 1;
-  hipLaunchKernelGGL(k_dft, dim3(blocks_for(nk, 256)), dim3(256), 0, st, (const double*)xw,
-                     (const double2*)tw, (long long)n_fft, (long long)n_fft, t_first, dt, omega_out,
+  hipLaunchKernelGGL(k_dft_partial, dim3(blocks_for(nk, 256), n_spans), dim3(256), 0, st,
+                     (const double*)xw, (const double2*)tw, (long long)n, (long long)n_fft, span,
+                     part);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_dft_final, dim3(blocks_for(nk, 256)), dim3(256), 0, st,
+                     (const double2*)part, n_spans, (long long)n_fft, t_first, dt, omega_out,
                      power_out, x_out);
   HIP_TRY(hipGetLastError());
+  HIP_TRY(hipFreeAsync(part, st));
   HIP_TRY(hipFreeAsync(xw, st));
   HIP_TRY(hipFreeAsync(tw, st));
   return SFHK_OK;
