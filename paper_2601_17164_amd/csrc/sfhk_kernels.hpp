@@ -1,0 +1,837 @@
+// sfhk_kernels.hpp -- device data structures and HIP kernels of the SFHK hot path (gfx950).
+// Included by sfhk.hip (the host runtime behind include/sfhk.h), in one translation unit.
+//
+// Layout in HBM (per job):
+//   trajectories are ordered by birth step (stable) and padded to tiles of 64 lanes; tile t holds
+//   sorted trajectories 64t..64t+63, so tiles are ordered longest first;
+//   state y[43][n_pad] (SoA, FP64): q(3) p(3) M(6 columns of Q(3) P(3)) S; aux[5][n_pad]:
+//   C_prev (re, im), w (re, im), branch sign; n0[n_pad], death[n_pad] (int32);
+//   one partial row per tile: F_tile(t_n) for n = tile_n0 .. n_steps (complex FP64), zero when
+//   the job is created; the propagate kernel stores a step's entry when some lane of the tile had
+//   a dipole integrand at that step.
+// Reduction order is fixed (tile order inside groups of 64 tiles, then group order), so the dipole
+// is bitwise reproducible for a given input.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "../../include/sfhk.h"
+#include "sfhk_device.hpp"
+#include "sfhk_device_f32.hpp"
+
+using namespace sfhk;
+
+namespace {
+
+constexpr int kTile = 64;           // trajectories per tile = lanes per wave
+constexpr int kReduceGroup = 64;    // tiles per first-level reduction group
+constexpr int kNY = 43;
+
+// ------------------------------------------------------------------------------------------------
+// device-side job description
+// ------------------------------------------------------------------------------------------------
+struct GtoConst {
+  int l, n_prim;
+  double A[SFHK_MAX_PRIM];   // 1 / (4 (gamma + alpha_j))
+  double B[SFHK_MAX_PRIM];   // alpha_j gamma / (gamma + alpha_j)
+  double D[SFHK_MAX_PRIM];   // alpha_j / (gamma + alpha_j)
+  double N[SFHK_MAX_PRIM];   // c_j (gamma + alpha_j)^(-5/2) (l = 0) or ^(-7/2) (l = 1)
+  double G2[SFHK_MAX_PRIM];  // 2 (gamma + alpha_j)
+  double two_gamma, ip;
+  double Amin, Bmin, cut_hi;  // all-primitives-skipped bound (see overlap_all_skipped)
+};
+
+struct JobDev {
+  int kind;
+  PotParams pot;
+  GtoConst gto;
+  double gamma, inv4g, kay2, cut;
+  double r64sq;  // mixed precision: steps that start at r^2 < r64sq run in FP64
+  double t_a, h, h2, h6;
+  int n_steps;
+  int n_tiles;
+  long long n_pad;
+  const double* e_half;
+  double* y;
+  double* aux;
+  int* n0;
+  int* death;
+  int* tile_n0;
+  int* tile_next;
+  int* tile_last;
+  long long* row_off;
+  double2* part;
+  unsigned long long* counters;  // steps_evaluated, kay_removed, nonfinite_removed, steps_fp64,
+                                 // GTO primitives evaluated
+};
+
+// ------------------------------------------------------------------------------------------------
+// wave-level sum (butterfly: every lane ends with the same, order-independent-by-symmetry value)
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// ------------------------------------------------------------------------------------------------
+// dipole element <psi0|z|p,q,gamma> over GTOs (App. C.1, overall constant 1). Tolerance-level
+// arithmetic: it does not feed back into the trajectory.
+// ------------------------------------------------------------------------------------------------
+// Every primitive is skipped when p^2 A_j + q^2 B_j > cut for all j. Since A_j >= A_min and
+// B_j >= B_min, p^2 A_min + q^2 B_min > cut (1 + 1e-12) implies it; the margin covers rounding.
+__device__ __forceinline__ bool overlap_all_skipped(const GtoConst& G, double p2, double q2) {
+  return SFHK_FMA(p2, G.Amin, q2 * G.Bmin) > G.cut_hi;
+}
+
+__device__ __forceinline__ cplx overlap(const GtoConst& G, double cut, const double* q,
+                                        const double* p, double p2, double q2,
+                                        unsigned int& n_eval) {
+  double pq = SFHK_FMA(p[2], q[2], SFHK_FMA(p[1], q[1], p[0] * q[0]));
+  cplx a = {G.two_gamma * q[2], p[2]};
+  cplx sum = {0.0, 0.0};
+  cplx a2 = cmul(a, a);
+  for (int j = 0; j < G.n_prim; ++j) {
+    double re = -SFHK_FMA(p2, G.A[j], q2 * G.B[j]);
+    if (re >= -cut) {
+      ++n_eval;
+      double im = -(pq * G.D[j]);
+      double e = exp(re) * G.N[j];
+      double s, c;
+      sincos(im, &s, &c);
+      cplx E = {e * c, e * s};
+      if (G.l == 0) {
+        sum.re += E.re;
+        sum.im += E.im;
+      } else {
+        cplx b = {a2.re + G.G2[j], a2.im};
+        cplx t = cmul(E, b);
+        sum.re += t.re;
+        sum.im += t.im;
+      }
+    }
+  }
+  return G.l == 0 ? cmul(a, sum) : sum;
+}
+
+// The dipole integrand f = w C O e^{i (S - Ip t_n)} of one lane (0 when every primitive is skipped).
+// Kept out of line: it runs only for lanes near the ground state, and inlined, the constants and
+// temporaries of its exp and sincos would occupy registers for the whole step loop.
+struct Contrib {
+  double re, im;
+  unsigned int n_eval;
+};
+
+__device__ __noinline__ Contrib contribution(const GtoConst* __restrict__ G, double cut, double qx,
+                                             double qy, double qz, double px, double py, double pz,
+                                             double p2, double q2, double S, double tn, double wcr,
+                                             double wci) {
+  const double q[3] = {qx, qy, qz}, p[3] = {px, py, pz};
+  unsigned int n_eval = 0;
+  const cplx O = overlap(*G, cut, q, p, p2, q2, n_eval);
+  Contrib r = {0.0, 0.0, n_eval};
+  if (O.re != 0.0 || O.im != 0.0) {
+    const double ph = S - G->ip * tn;
+    double sp, cp;
+    sincos(ph, &sp, &cp);
+    const cplx f = cmul(cplx{wcr, wci}, cmul(O, cplx{cp, sp}));
+    r.re = f.re;
+    r.im = f.im;
+  }
+  return r;
+}
+
+// ------------------------------------------------------------------------------------------------
+// initialisation: gather the sorted samples into the SoA state
+// ------------------------------------------------------------------------------------------------
+__global__ void k_init(JobDev J, const long long* __restrict__ perm, long long n_traj,
+                       const double* __restrict__ q0, const double* __restrict__ p0,
+                       const double* __restrict__ w) {
+  long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= J.n_pad) return;
+  long long np = J.n_pad;
+  long long o = perm[s];
+  double* y = J.y;
+  double q[3] = {0, 0, 0}, p[3] = {0, 0, 0}, wr = 0.0, wi = 0.0;
+  if (o >= 0) {
+    for (int i = 0; i < 3; ++i) {
+      q[i] = q0[i * n_traj + o];
+      p[i] = p0[i * n_traj + o];
+    }
+    if (w) {
+      wr = w[o];
+      wi = w[n_traj + o];
+    } else {  // exp(i p0.q0) / n
+      double pq = p[0] * q[0] + p[1] * q[1] + p[2] * q[2];
+      double sn, cs;
+      sincos(pq, &sn, &cs);
+      wr = cs / (double)n_traj;
+      wi = sn / (double)n_traj;
+    }
+  }
+  for (int i = 0; i < 3; ++i) {
+    y[i * np + s] = q[i];
+    y[(3 + i) * np + s] = p[i];
+  }
+  for (int c = 0; c < 36; ++c) y[(6 + c) * np + s] = (c % 7 == 0) ? 1.0 : 0.0;  // M = I
+  y[42 * np + s] = 0.0;
+  J.aux[0 * np + s] = 1.0;  // C_prev
+  J.aux[1 * np + s] = 0.0;
+  J.aux[2 * np + s] = wr;
+  J.aux[3 * np + s] = wi;
+  J.aux[4 * np + s] = 1.0;  // branch sign
+  J.death[s] = (o >= 0) ? -1 : -2;
+}
+
+// ------------------------------------------------------------------------------------------------
+// propagation, FP64: one wave per tile, one trajectory per lane
+// ------------------------------------------------------------------------------------------------
+// The dipole integrand is deferred. At a given step few lanes of a wave are near the ground state,
+// and evaluated in place their integrand would cost the whole wave. Instead each such lane appends
+// (q, p, S, w C, n) to a per-wave LDS queue; when the queue cannot take the next step's entries,
+// and at the end of the launch, the wave evaluates up to 64 of them at once. A step's entries are
+// consecutive and in lane order, and the first of them sums the run in that order and stores the
+// tile's partial row for the step; rows of steps without entries keep the zeros they were
+// allocated with. The entries of one step never straddle two evaluations, so the sums do not
+// depend on how the propagation is split into launches or batched. The wave is the whole
+// workgroup, so the queue needs no cross-wave synchronisation.
+constexpr int kQueue = kTile;
+
+struct WorkItem {
+  int job, tile;
+};
+
+struct QueueEntry {
+  double2 a, b, c, d, e;  // (qx, qy) (qz, px) (py, pz) (S, Re wC) (Im wC, n)
+};
+struct IntegrandQueue {
+  QueueEntry e[kQueue];
+  double2 f[kQueue];
+};
+
+typedef __attribute__((address_space(4))) const double* const_dptr;  // scalar (uniform) loads
+
+// values that are the same in every lane of the wave (per-tile bookkeeping): kept in scalar
+// registers so the step loop's control runs on the scalar unit
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long uniform_i64(long long v) {
+  const unsigned int lo = __builtin_amdgcn_readfirstlane((unsigned int)(unsigned long long)v);
+  const unsigned int hi = __builtin_amdgcn_readfirstlane((unsigned int)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// position of this lane among the set bits of the wave mask m
+__device__ __forceinline__ int lanes_below(unsigned long long m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((unsigned int)(m >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((unsigned int)m, 0u));
+}
+
+__device__ __forceinline__ void queue_push(IntegrandQueue& Q, int idx, double qx, double qy,
+                                           double qz, double px, double py, double pz, double S,
+                                           cplx wC, int n) {
+  QueueEntry& x = Q.e[idx];
+  x.a = make_double2(qx, qy);
+  x.b = make_double2(qz, px);
+  x.c = make_double2(py, pz);
+  x.d = make_double2(S, wC.re);
+  x.e = make_double2(wC.im, (double)n);
+}
+
+// evaluates the qn queued entries (one per lane) and stores their per-step sums; returns this
+// lane's count of evaluated primitives
+__device__ __forceinline__ unsigned int queue_eval(IntegrandQueue& Q, int qn, int lane,
+                                                   const JobDev& J, double2* __restrict__ part,
+                                                   long long roff, int t0) {
+  __syncthreads();
+  unsigned int n_eval = 0;
+  if (lane < qn) {
+    const QueueEntry x = Q.e[lane];
+    const double qx = x.a.x, qy = x.a.y, qz = x.b.x, px = x.b.y, py = x.c.x, pz = x.c.y;
+    const double p2 = SFHK_FMA(pz, pz, SFHK_FMA(py, py, px * px));
+    const double q2 = SFHK_FMA(qz, qz, SFHK_FMA(qy, qy, qx * qx));
+    const Contrib cb = contribution(&J.gto, J.cut, qx, qy, qz, px, py, pz, p2, q2, x.d.x,
+                                    J.t_a + x.e.y * J.h, x.d.y, x.e.x);
+    Q.f[lane] = make_double2(cb.re, cb.im);
+    n_eval = cb.n_eval;
+  }
+  __syncthreads();
+  if (lane < qn) {
+    const double ns = Q.e[lane].e.y;
+    if (lane == 0 || Q.e[lane - 1].e.y != ns) {
+      double2 acc = Q.f[lane];
+      for (int j = lane + 1; j < qn && Q.e[j].e.y == ns; ++j) {
+        const double2 v = Q.f[j];
+        acc.x += v.x;
+        acc.y += v.y;
+      }
+      part[roff + ((long long)ns - t0)] = acc;
+    }
+  }
+  __syncthreads();
+  return n_eval;
+}
+
+// KIND >= 0: the potential kind is a compile-time constant (its dispatch folds away); -1: read from
+// the job descriptor at run time
+template <int KIND>
+__device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const int max_steps,
+                                         IntegrandQueue& Q) {
+  const int lane = threadIdx.x;
+  const int n_begin = uniform_i32(J.tile_next[tile]);
+  const int N = J.n_steps;
+  if (n_begin > N) return;
+  const int n_stop = (max_steps > 0) ? min(N, n_begin + max_steps - 1) : N;
+  const long long np = J.n_pad;
+  const long long s = (long long)tile * kTile + lane;
+
+  Traj T;
+  const double* y = J.y;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T.q[i] = y[i * np + s];
+    T.p[i] = y[(3 + i) * np + s];
+  }
+#pragma unroll
+  for (int c = 0; c < 36; ++c) T.M[c] = y[(6 + c) * np + s];
+  T.S = y[42 * np + s];
+  cplx cprev = {J.aux[s], J.aux[np + s]};
+  const cplx w = {J.aux[2 * np + s], J.aux[3 * np + s]};
+  double sgn = J.aux[4 * np + s];
+  const int n0l = J.n0[s];
+  const int death_in = J.death[s];
+  int death = death_in;
+  bool alive = death_in == -1;
+
+  const int t0 = uniform_i32(J.tile_n0[tile]);
+  const long long roff = uniform_i64(J.row_off[tile]);
+  double2* __restrict__ part = J.part;
+  const const_dptr eh = (const_dptr)J.e_half;
+  const PotParams P = J.pot;
+  const int kind = KIND >= 0 ? KIND : J.kind;
+  const double gamma = J.gamma, inv4g = J.inv4g, kay2 = J.kay2;
+  const double h = J.h, h2 = J.h2, h6 = J.h6;
+
+  int qn = 0;  // queued integrands (wave-uniform)
+  unsigned int kay = 0, nonfin = 0, prims = 0;
+  int n = n_begin;
+  double ea = eh[2 * n];
+  for (; n <= n_stop; ++n) {
+    bool contrib = false;
+    cplx C = {0.0, 0.0};
+    if (alive && n >= n0l) {
+      cplx d = hk_det(T.M, gamma, inv4g);
+      double a2 = d.re * d.re;
+      a2 = SFHK_FMA(d.im, d.im, a2);
+      bool finite = isfinite(T.q[0]) && isfinite(T.q[1]) && isfinite(T.q[2]) &&
+                    isfinite(T.p[0]) && isfinite(T.p[1]) && isfinite(T.p[2]) && isfinite(T.S);
+      if (!(a2 <= kay2) || !finite) {  // Kay removal (or a non-finite state) from step n on
+        alive = false;
+        death = n;
+        if (!finite || isnan(a2))
+          ++nonfin;
+        else
+          ++kay;
+      } else {
+        const double mod = a2 > 0.0 ? a2 * rsqrt_c(a2) : 0.0;  // |det G|
+        cplx c = csqrt_principal(d, mod);
+        double dot = SFHK_FMA(c.im, cprev.im, c.re * cprev.re);
+        if (sgn * dot < 0.0) sgn = -sgn;
+        C = {sgn * c.re, sgn * c.im};
+        cprev = C;
+        contrib = true;
+      }
+    }
+    // dipole element: costly only for lanes near the ground state
+    double p2 = SFHK_FMA(T.p[2], T.p[2], SFHK_FMA(T.p[1], T.p[1], T.p[0] * T.p[0]));
+    double q2 = SFHK_FMA(T.q[2], T.q[2], SFHK_FMA(T.q[1], T.q[1], T.q[0] * T.q[0]));
+    const bool need = contrib && !overlap_all_skipped(J.gto, p2, q2);
+    const unsigned long long m = __ballot(need);
+    if (m) {
+      const int k = __popcll(m);
+      if (qn + k > kQueue) {
+        prims += queue_eval(Q, qn, lane, J, part, roff, t0);
+        qn = 0;
+      }
+      if (need)
+        queue_push(Q, qn + lanes_below(m), T.q[0], T.q[1], T.q[2], T.p[0], T.p[1], T.p[2], T.S,
+                   cmul(w, C), n);
+      qn += k;
+    }
+    if (n < N) {
+      const double eb = eh[2 * n + 1], ec = eh[2 * n + 2];
+      if (alive && n >= n0l) rk4_step(kind, P, T, ea, eb, ec, h, h2, h6);
+      ea = ec;
+    }
+    if (!__any(alive)) {  // every lane removed: the rest of the tile's row stays zero
+      ++n;
+      break;
+    }
+  }
+  if (qn > 0) prims += queue_eval(Q, qn, lane, J, part, roff, t0);
+  // n is now one past the last step processed
+  double* yw = J.y;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    yw[i * np + s] = T.q[i];
+    yw[(3 + i) * np + s] = T.p[i];
+  }
+#pragma unroll
+  for (int c = 0; c < 36; ++c) yw[(6 + c) * np + s] = T.M[c];
+  yw[42 * np + s] = T.S;
+  J.aux[s] = cprev.re;
+  J.aux[np + s] = cprev.im;
+  J.aux[4 * np + s] = sgn;
+  J.death[s] = death;
+  const bool finished = !__any(alive) || n > N;
+  if (lane == 0) {
+    J.tile_next[tile] = finished ? N + 1 : n;
+    J.tile_last[tile] = n - 1;
+  }
+  // steps evaluated by this lane in this launch: from max(n_begin, n0) to its removal step or the
+  // last step processed
+  int evals = 0;
+  if (death_in == -1) {
+    const int first = max(n_begin, n0l);
+    const int lastn = death >= 0 ? death : n - 1;
+    evals = max(0, lastn - first + 1);
+  }
+  double ev = wave_sum((double)evals), ka = wave_sum((double)kay), nf = wave_sum((double)nonfin);
+  double pr = wave_sum((double)prims);
+  if (lane == 0) {
+    atomicAdd(&J.counters[0], (unsigned long long)ev);
+    atomicAdd(&J.counters[1], (unsigned long long)ka);
+    atomicAdd(&J.counters[2], (unsigned long long)nf);
+    atomicAdd(&J.counters[4], (unsigned long long)pr);
+  }
+}
+
+#ifndef SFHK_PROPAGATE_WAVES_PER_EU
+#define SFHK_PROPAGATE_WAVES_PER_EU 2
+#endif
+template <int KIND>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_PROPAGATE_WAVES_PER_EU)))
+void k_propagate_fp64(
+    const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work, int max_steps) {
+  __shared__ IntegrandQueue Q;
+  const WorkItem wi = work[blockIdx.x];
+  run_tile<KIND>(jobs[wi.job], wi.tile, max_steps, Q);
+}
+
+// ------------------------------------------------------------------------------------------------
+// propagation, mixed precision: q, p, M carried and integrated in FP32 away from the nucleus; the
+// action, the HK square root and branch, the dipole integrand and the reduction in FP64; a lane
+// whose step starts at r < r_fp64 takes the FP64 step on its exactly promoted state and rounds the
+// result back to FP32. The precision decision is per lane, so a trajectory's result does not
+// depend on the other trajectories of its wave.
+// ------------------------------------------------------------------------------------------------
+template <int KIND>
+__device__ __forceinline__ void run_tile_mixed(const JobDev& J, const int tile, const int max_steps,
+                                               IntegrandQueue& Q) {
+  const int lane = threadIdx.x;
+  const int n_begin = uniform_i32(J.tile_next[tile]);
+  const int N = J.n_steps;
+  if (n_begin > N) return;
+  const int n_stop = (max_steps > 0) ? min(N, n_begin + max_steps - 1) : N;
+  const long long np = J.n_pad;
+  const long long s = (long long)tile * kTile + lane;
+
+  TrajF T;
+  const double* y = J.y;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T.q[i] = (float)y[i * np + s];
+    T.p[i] = (float)y[(3 + i) * np + s];
+  }
+#pragma unroll
+  for (int c = 0; c < 36; ++c) T.M[c] = (float)y[(6 + c) * np + s];
+  T.S = y[42 * np + s];
+  cplx cprev = {J.aux[s], J.aux[np + s]};
+  const cplx w = {J.aux[2 * np + s], J.aux[3 * np + s]};
+  double sgn = J.aux[4 * np + s];
+  const int n0l = J.n0[s];
+  const int death_in = J.death[s];
+  int death = death_in;
+  bool alive = death_in == -1;
+
+  const int t0 = uniform_i32(J.tile_n0[tile]);
+  const long long roff = uniform_i64(J.row_off[tile]);
+  double2* __restrict__ part = J.part;
+  const const_dptr eh = (const_dptr)J.e_half;
+  const PotParams P = J.pot;
+  const PotParamsF PF = {(float)P.z_inf, (float)P.z_in, (float)P.soft2, (float)P.omega_ho,
+                         (float)P.inv_rscr};
+  const int kind = KIND >= 0 ? KIND : J.kind;
+  const double kay2 = J.kay2;
+  const double h = J.h, h2 = J.h2, h6 = J.h6;
+  const float hf = (float)h, h2f = (float)h2, h6f = (float)h6;
+  const float gammaf = (float)J.gamma, inv4gf = (float)J.inv4g;
+  const float aminf = (float)J.gto.Amin, bminf = (float)J.gto.Bmin;
+  const float cut_lo = (float)(J.cut * (1.0 + 1e-5));  // FP32 bound: margin for FP32 rounding
+  const float r64sq = (float)J.r64sq;
+
+  int qn = 0;  // queued integrands (wave-uniform)
+  unsigned int kay = 0, nonfin = 0, prims = 0, steps64 = 0;
+  int n = n_begin;
+  double ea = eh[2 * n];
+  for (; n <= n_stop; ++n) {
+    bool contrib = false;
+    cplx C = {0.0, 0.0};
+    if (alive && n >= n0l) {
+      cplx d = hk_det_f32(T.M, gammaf, inv4gf);
+      double a2 = d.re * d.re;
+      a2 = SFHK_FMA(d.im, d.im, a2);
+      bool finite = isfinite(T.q[0]) && isfinite(T.q[1]) && isfinite(T.q[2]) &&
+                    isfinite(T.p[0]) && isfinite(T.p[1]) && isfinite(T.p[2]) && isfinite(T.S);
+      if (!(a2 <= kay2) || !finite) {
+        alive = false;
+        death = n;
+        if (!finite || isnan(a2))
+          ++nonfin;
+        else
+          ++kay;
+      } else {
+        const double mod = a2 > 0.0 ? a2 * rsqrt_c(a2) : 0.0;
+        cplx c = csqrt_principal(d, mod);
+        double dot = SFHK_FMA(c.im, cprev.im, c.re * cprev.re);
+        if (sgn * dot < 0.0) sgn = -sgn;
+        C = {sgn * c.re, sgn * c.im};
+        cprev = C;
+        contrib = true;
+      }
+    }
+    const float p2f = __builtin_fmaf(T.p[2], T.p[2], __builtin_fmaf(T.p[1], T.p[1], T.p[0] * T.p[0]));
+    const float q2f = __builtin_fmaf(T.q[2], T.q[2], __builtin_fmaf(T.q[1], T.q[1], T.q[0] * T.q[0]));
+    const bool need = contrib && !(__builtin_fmaf(p2f, aminf, q2f * bminf) > cut_lo);
+    const unsigned long long m = __ballot(need);
+    if (m) {
+      const int k = __popcll(m);
+      if (qn + k > kQueue) {
+        prims += queue_eval(Q, qn, lane, J, part, roff, t0);
+        qn = 0;
+      }
+      if (need)
+        queue_push(Q, qn + lanes_below(m), T.q[0], T.q[1], T.q[2], T.p[0], T.p[1], T.p[2], T.S,
+                   cmul(w, C), n);
+      qn += k;
+    }
+    if (n < N) {
+      const double eb = eh[2 * n + 1], ec = eh[2 * n + 2];
+      if (alive && n >= n0l) {
+        if (q2f < r64sq) {  // near the nucleus: the FP64 step on the promoted state
+          Traj D;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            D.q[i] = T.q[i];
+            D.p[i] = T.p[i];
+          }
+#pragma unroll
+          for (int c = 0; c < 36; ++c) D.M[c] = T.M[c];
+          D.S = T.S;
+          rk4_step(kind, P, D, ea, eb, ec, h, h2, h6);
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            T.q[i] = (float)D.q[i];
+            T.p[i] = (float)D.p[i];
+          }
+#pragma unroll
+          for (int c = 0; c < 36; ++c) T.M[c] = (float)D.M[c];
+          T.S = D.S;
+          ++steps64;
+        } else {
+          rk4_step_f32(kind, PF, T, (float)ea, (float)eb, (float)ec, hf, h2f, h6f, h6);
+        }
+      }
+      ea = ec;
+    }
+    if (!__any(alive)) {
+      ++n;
+      break;
+    }
+  }
+  if (qn > 0) prims += queue_eval(Q, qn, lane, J, part, roff, t0);
+  double* yw = J.y;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    yw[i * np + s] = T.q[i];
+    yw[(3 + i) * np + s] = T.p[i];
+  }
+#pragma unroll
+  for (int c = 0; c < 36; ++c) yw[(6 + c) * np + s] = T.M[c];
+  yw[42 * np + s] = T.S;
+  J.aux[s] = cprev.re;
+  J.aux[np + s] = cprev.im;
+  J.aux[4 * np + s] = sgn;
+  J.death[s] = death;
+  const bool finished = !__any(alive) || n > N;
+  if (lane == 0) {
+    J.tile_next[tile] = finished ? N + 1 : n;
+    J.tile_last[tile] = n - 1;
+  }
+  int evals = 0;
+  if (death_in == -1) {
+    const int first = max(n_begin, n0l);
+    const int lastn = death >= 0 ? death : n - 1;
+    evals = max(0, lastn - first + 1);
+  }
+  double ev = wave_sum((double)evals), ka = wave_sum((double)kay), nf = wave_sum((double)nonfin);
+  double pr = wave_sum((double)prims), s64 = wave_sum((double)steps64);
+  if (lane == 0) {
+    atomicAdd(&J.counters[0], (unsigned long long)ev);
+    atomicAdd(&J.counters[1], (unsigned long long)ka);
+    atomicAdd(&J.counters[2], (unsigned long long)nf);
+    atomicAdd(&J.counters[3], (unsigned long long)s64);
+    atomicAdd(&J.counters[4], (unsigned long long)pr);
+  }
+}
+
+#ifndef SFHK_MIXED_WAVES_PER_EU
+#define SFHK_MIXED_WAVES_PER_EU 2
+#endif
+template <int KIND>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_MIXED_WAVES_PER_EU)))
+void k_propagate_mixed(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work, int max_steps) {
+  __shared__ IntegrandQueue Q;
+  const WorkItem wi = work[blockIdx.x];
+  run_tile_mixed<KIND>(jobs[wi.job], wi.tile, max_steps, Q);
+}
+
+// ------------------------------------------------------------------------------------------------
+// persistent form (batched, graph-captured launches): a fixed number of single-wave workgroups pop
+// tiles from a longest-first work list through one atomic counter per precision segment. The
+// segment sizes live in device memory so the host can rewrite the job table between graph
+// replays without capturing again.
+// ------------------------------------------------------------------------------------------------
+constexpr int kKinds = 4;              // potential kinds
+constexpr int kSegs = 2 * kKinds;       // work-list segments: precision * kKinds + kind
+
+struct BatchDev {
+  int n_items[kSegs];        // per segment
+  int offset[kSegs];         // first work item of the segment
+  unsigned int next[kSegs];  // queue heads, zeroed at the start of every replay
+};
+
+__global__ void k_batch_reset(BatchDev* __restrict__ B) {
+  if (threadIdx.x < kSegs) B->next[threadIdx.x] = 0u;
+}
+
+// one tile per call: inlined into the queue loop, the tile loop's register allocation degrades.
+// The LDS queue is declared here, not passed in, so its accesses stay LDS instructions.
+template <int PREC, int KIND>
+__device__ __noinline__ void tile_call(const JobDev* J, int tile, int max_steps) {
+  __shared__ IntegrandQueue Q;
+  if (PREC == 0)
+    run_tile<KIND>(*J, tile, max_steps, Q);
+  else
+    run_tile_mixed<KIND>(*J, tile, max_steps, Q);
+}
+
+template <int PREC, int KIND>
+__device__ __forceinline__ void queue_loop(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work,
+                                           BatchDev* __restrict__ B, int max_steps) {
+  constexpr int seg = PREC * kKinds + KIND;
+  const int n_items = B->n_items[seg];
+  const WorkItem* sw = work + B->offset[seg];
+  for (;;) {
+    unsigned int it = 0;
+    if (threadIdx.x == 0) it = atomicAdd(&B->next[seg], 1u);
+    it = __shfl(it, 0, 64);
+    if (it >= (unsigned int)n_items) break;  // every wave of the grid reaches this exit
+    const WorkItem wi = sw[it];
+    tile_call<PREC, KIND>(jobs + wi.job, wi.tile, max_steps);
+  }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_PROPAGATE_WAVES_PER_EU)))
+void k_queue_fp64(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work,
+                  BatchDev* __restrict__ B, int max_steps) {
+  queue_loop<0, KIND>(jobs, work, B, max_steps);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_MIXED_WAVES_PER_EU)))
+void k_queue_mixed(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work,
+                   BatchDev* __restrict__ B, int max_steps) {
+  queue_loop<1, KIND>(jobs, work, B, max_steps);
+}
+
+// hardware-dispatch alternative for graph replays: one workgroup per work item of capacity;
+// workgroups past the segment's current size exit at once
+template <int KIND>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_PROPAGATE_WAVES_PER_EU)))
+void k_grid_fp64(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work,
+                 const BatchDev* __restrict__ B, int max_steps) {
+  __shared__ IntegrandQueue Q;
+  constexpr int seg = KIND;
+  if ((int)blockIdx.x >= B->n_items[seg]) return;
+  const WorkItem wi = work[B->offset[seg] + blockIdx.x];
+  run_tile<KIND>(jobs[wi.job], wi.tile, max_steps, Q);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_MIXED_WAVES_PER_EU)))
+void k_grid_mixed(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work,
+                  const BatchDev* __restrict__ B, int max_steps) {
+  __shared__ IntegrandQueue Q;
+  constexpr int seg = kKinds + KIND;
+  if ((int)blockIdx.x >= B->n_items[seg]) return;
+  const WorkItem wi = work[B->offset[seg] + blockIdx.x];
+  run_tile_mixed<KIND>(jobs[wi.job], wi.tile, max_steps, Q);
+}
+
+// ------------------------------------------------------------------------------------------------
+// reduction of the partial rows (fixed order) and the dipole
+// ------------------------------------------------------------------------------------------------
+__global__ void k_reduce_groups(JobDev J, double2* __restrict__ gsum) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = blockIdx.y;
+  if (n > J.n_steps) return;
+  const int t_lo = g * kReduceGroup;
+  const int t_hi = min(J.n_tiles, t_lo + kReduceGroup);
+  double sr = 0.0, si = 0.0;
+  for (int t = t_lo; t < t_hi; ++t) {
+    const int a = J.tile_n0[t];
+    if (a > n) break;  // tiles are sorted by birth step
+    if (n <= J.tile_last[t]) {
+      double2 v = J.part[J.row_off[t] + (n - a)];
+      sr += v.x;
+      si += v.y;
+    }
+  }
+  gsum[(long long)g * (J.n_steps + 1) + n] = make_double2(sr, si);
+}
+
+__global__ void k_reduce_final(int n_steps, int n_groups, const double2* __restrict__ gsum,
+                               double* __restrict__ d, double* __restrict__ f_out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n > n_steps) return;
+  double sr = 0.0, si = 0.0;
+  for (int g = 0; g < n_groups; ++g) {
+    double2 v = gsum[(long long)g * (n_steps + 1) + n];
+    sr += v.x;
+    si += v.y;
+  }
+  d[n] = -2.0 * sr;
+  if (f_out) {
+    f_out[n] = sr;
+    f_out[n_steps + 1 + n] = si;
+  }
+}
+
+__global__ void k_resample(const double* __restrict__ d, long long n_steps, long long n_out,
+                           double* __restrict__ out) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_out) return;
+  long long num = k * n_steps;
+  long long i = num / n_out;
+  long long rem = num - i * n_out;
+  double frac = (double)rem / (double)n_out;
+  out[k] = (i >= n_steps) ? d[n_steps] : d[i] + frac * (d[i + 1] - d[i]);
+}
+
+// ------------------------------------------------------------------------------------------------
+// trajectories in the caller's order
+// ------------------------------------------------------------------------------------------------
+__global__ void k_scatter_traj(JobDev J, const long long* __restrict__ perm, long long n_traj,
+                               double* __restrict__ y_out, double* __restrict__ c_out,
+                               long long* __restrict__ death_out) {
+  long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= J.n_pad) return;
+  long long o = perm[s];
+  if (o < 0) return;
+  if (y_out)
+    for (int c = 0; c < kNY; ++c) y_out[c * n_traj + o] = J.y[c * J.n_pad + s];
+  if (c_out) {
+    c_out[o] = J.aux[s];
+    c_out[n_traj + o] = J.aux[J.n_pad + s];
+  }
+  if (death_out) death_out[o] = J.death[s];
+}
+
+// ------------------------------------------------------------------------------------------------
+// spectrum: Hann window and direct Fourier sum with exact index reduction k n mod n_fft
+// ------------------------------------------------------------------------------------------------
+__global__ void k_window(const double* __restrict__ d, long long n, long long n_fft, double t_first,
+                         double dt, double tau_h, double* __restrict__ xw, double2* __restrict__ tw) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_fft) return;
+  double v = 0.0;
+  if (i < n) {
+    double t = t_first + (double)i * dt;
+    double win = fabs(t) >= tau_h ? 0.0 : 0.5 * (1.0 + cos(M_PI * t / tau_h));
+    v = d[i] * win;
+  }
+  xw[i] = v;
+  double s, c;
+  sincospi(2.0 * (double)i / (double)n_fft, &s, &c);
+  tw[i] = make_double2(c, s);
+}
+
+// Direct DFT, Y_k = sum_n x_n e^{2 pi i k n / n_fft} for k = 0..n_fft/2. Blocks along y take
+// consecutive spans of samples; within a span each lane keeps its twiddle by the recurrence
+// t <- t e^{2 pi i k / n_fft}, re-anchored from the exact table (index k m mod n_fft) at every
+// staged chunk of kDftChunk samples, so the recurrence error stays near kDftChunk ulps. Partial
+// sums per span are added in span order by k_dft_final (deterministic).
+constexpr int kDftChunk = 1024;
+constexpr int kDftMaxSpans = 64;
+
+__global__ __launch_bounds__(256) void k_dft_partial(const double* __restrict__ xw,
+                                                     const double2* __restrict__ tw, long long n,
+                                                     long long n_fft, long long span,
+                                                     double2* __restrict__ part) {
+  __shared__ double xs[kDftChunk];
+  const long long nk = n_fft / 2 + 1;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long kk = k < nk ? k : 0;
+  const long long lo = (long long)blockIdx.y * span;
+  const long long hi = min(n, lo + span);
+  const double2 step = tw[kk];
+  double cr = 0.0, ci = 0.0;
+  for (long long base = lo; base < hi; base += kDftChunk) {
+    const int cnt = (int)min((long long)kDftChunk, hi - base);
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) xs[i] = xw[base + i];
+    __syncthreads();
+    double2 t = tw[(kk * base) % n_fft];
+    for (int i = 0; i < cnt; ++i) {
+      cr = SFHK_FMA(xs[i], t.x, cr);
+      ci = SFHK_FMA(xs[i], t.y, ci);
+      const double tr = SFHK_FMA(t.x, step.x, -(t.y * step.y));
+      t.y = SFHK_FMA(t.x, step.y, t.y * step.x);
+      t.x = tr;
+    }
+  }
+  if (k < nk) part[(long long)blockIdx.y * nk + k] = make_double2(cr, ci);
+}
+
+__global__ void k_dft_final(const double2* __restrict__ part, int n_spans, long long n_fft,
+                            double t_first, double dt, double* __restrict__ omega_out,
+                            double* __restrict__ power_out, double* __restrict__ x_out) {
+  const long long nk = n_fft / 2 + 1;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nk) return;
+  double sr = 0.0, si = 0.0;
+  for (int g = 0; g < n_spans; ++g) {
+    const double2 v = part[(long long)g * nk + k];
+    sr += v.x;
+    si += v.y;
+  }
+  const double omega = 2.0 * M_PI * (double)k / ((double)n_fft * dt);
+  double s, c;
+  sincos(omega * t_first, &s, &c);
+  const double xr = dt * (sr * c - si * s);
+  const double xi = dt * (sr * s + si * c);
+  if (omega_out) omega_out[k] = omega;
+  if (power_out) power_out[k] = xr * xr + xi * xi;
+  if (x_out) {
+    x_out[2 * k] = xr;
+    x_out[2 * k + 1] = xi;
+  }
+}
+
+__global__ void k_traj_fn(int which, const double* __restrict__ x, double* __restrict__ y,
+                          long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = which == 0 ? exp_cw(x[i]) : rsqrt_c(x[i]);
+}
+
+}  // namespace
