@@ -407,4 +407,21 @@ __device__ __forceinline__ cplx csqrt_principal(cplx z, double mod) {
   return {(0.5 * fabs(z.im)) * rw, copysign(t, z.im)};
 }
 
+// C = principal square root of d = det G, for a2 = |d|^2 (a lane that passed the Kay test). For
+// 2^-1000 <= a2 <= 2^1000 the careful form's tests always pick the ordinary branch (|d| > 0 and
+// w = (|d| + |Re d|)/2 within the square root's core range), so both give the same bits there;
+// lanes outside are recomputed in the careful form under a wave-uniform test.
+__device__ __forceinline__ cplx hk_sqrt(cplx d, double a2) {
+  const double mod = a2 * rsqrt_core(a2);
+  const double w = 0.5 * (mod + fabs(d.re));
+  const double rw = rsqrt_core(w);
+  const double t = w * rw;
+  cplx c = d.re >= 0.0 ? cplx{t, (0.5 * d.im) * rw} : cplx{(0.5 * fabs(d.im)) * rw, copysign(t, d.im)};
+  const bool slow = !(a2 >= 0x1p-1000 && a2 <= 0x1p1000);
+  if (__builtin_expect(__any(slow), 0)) {
+    if (slow) c = csqrt_principal(d, a2 > 0.0 ? a2 * rsqrt_c(a2) : 0.0);
+  }
+  return c;
+}
+
 }  // namespace sfhk

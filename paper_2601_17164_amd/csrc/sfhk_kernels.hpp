@@ -331,8 +331,7 @@ __device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const 
         else
           ++kay;
       } else {
-        const double mod = a2 > 0.0 ? a2 * rsqrt_c(a2) : 0.0;  // |det G|
-        cplx c = csqrt_principal(d, mod);
+        cplx c = hk_sqrt(d, a2);
         double dot = SFHK_FMA(c.im, cprev.im, c.re * cprev.re);
         if (sgn * dot < 0.0) sgn = -sgn;
         C = {sgn * c.re, sgn * c.im};
@@ -344,7 +343,7 @@ __device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const 
     double p2 = SFHK_FMA(T.p[2], T.p[2], SFHK_FMA(T.p[1], T.p[1], T.p[0] * T.p[0]));
     double q2 = SFHK_FMA(T.q[2], T.q[2], SFHK_FMA(T.q[1], T.q[1], T.q[0] * T.q[0]));
     const bool need = contrib && !overlap_all_skipped(J.gto, p2, q2);
-    const unsigned long long m = __ballot(need);
+    const unsigned long long m = __builtin_amdgcn_ballot_w64(need);
     if (m) {
       const int k = __popcll(m);
       if (qn + k > kQueue) {
@@ -489,8 +488,7 @@ __device__ __forceinline__ void run_tile_mixed(const JobDev& J, const int tile, 
         else
           ++kay;
       } else {
-        const double mod = a2 > 0.0 ? a2 * rsqrt_c(a2) : 0.0;
-        cplx c = csqrt_principal(d, mod);
+        cplx c = hk_sqrt(d, a2);
         double dot = SFHK_FMA(c.im, cprev.im, c.re * cprev.re);
         if (sgn * dot < 0.0) sgn = -sgn;
         C = {sgn * c.re, sgn * c.im};
@@ -501,7 +499,7 @@ __device__ __forceinline__ void run_tile_mixed(const JobDev& J, const int tile, 
     const float p2f = __builtin_fmaf(T.p[2], T.p[2], __builtin_fmaf(T.p[1], T.p[1], T.p[0] * T.p[0]));
     const float q2f = __builtin_fmaf(T.q[2], T.q[2], __builtin_fmaf(T.q[1], T.q[1], T.q[0] * T.q[0]));
     const bool need = contrib && !(__builtin_fmaf(p2f, aminf, q2f * bminf) > cut_lo);
-    const unsigned long long m = __ballot(need);
+    const unsigned long long m = __builtin_amdgcn_ballot_w64(need);
     if (m) {
       const int k = __popcll(m);
       if (qn + k > kQueue) {
