@@ -108,10 +108,15 @@ typedef struct sfhk_ctx sfhk_ctx;
 typedef struct sfhk_job sfhk_job;
 
 /* Create a context on HIP device `device` whose jobs may hold at most hbm_budget_bytes of device
- * memory in total (0: no limit). Synchronous. */
+ * memory in total (0: no limit). Job buffers come from a stream-ordered memory pool owned by the
+ * context, which keeps freed memory cached for later jobs until the context is destroyed (or an
+ * allocation would fail, when the cache is returned). Synchronous. */
 sfhk_status sfhk_ctx_create(int device, size_t hbm_budget_bytes, sfhk_ctx** out);
+/* Waits for all work on the device, then releases the context and its memory pool. Every job of
+ * the context must have been destroyed. */
 void sfhk_ctx_destroy(sfhk_ctx* ctx);
-/* Bytes of device memory currently held by the context's jobs. */
+/* Bytes of device memory held by the context's live jobs (a destroyed job's bytes are counted
+ * out at once, while its memory returns to the pool when its last issued work completes). */
 size_t sfhk_ctx_bytes_in_use(const sfhk_ctx* ctx);
 
 /* Device bytes a job of this shape will hold (the admission test of a serving loop). */
@@ -133,6 +138,9 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
                             const sfhk_grid* grid, const sfhk_params* params, int64_t n_traj,
                             const double* t0, const double* q0, const double* p0, const double* w,
                             void* stream, sfhk_job** out);
+/* Release a job. Does not block: the job's memory is freed in stream order once all work issued
+ * on it so far (on any stream) has completed. The caller must not issue further work on the job,
+ * nor replay a batch whose staged table still lists it. */
 void sfhk_job_destroy(sfhk_job* job);
 
 /* Propagate the job's trajectories (RK4 steps of the 43 ODEs, HK prefactor, Kay removal, dipole
@@ -164,8 +172,10 @@ sfhk_status sfhk_propagate_many(sfhk_job* const* jobs, int32_t n_jobs, int64_t m
 typedef struct sfhk_batch sfhk_batch;
 sfhk_status sfhk_batch_create(sfhk_ctx* ctx, int32_t max_jobs, int64_t max_tiles, int64_t max_steps,
                               int32_t workers_per_cu, sfhk_batch** out);
-/* Stage the unfinished tiles of jobs[0..n_jobs) (synchronises `stream`, then copies the table
- * asynchronously on it). */
+/* Stage the unfinished tiles of jobs[0..n_jobs): the table is written to one of two pinned
+ * staging sets, used in turn, and copied asynchronously on `stream`. The call waits only until
+ * the replay issued after the previous use of that set has completed, so a caller can stage the
+ * next replay while the current one runs (the host stays at most one replay ahead). */
 sfhk_status sfhk_batch_set_jobs(sfhk_batch* batch, sfhk_job* const* jobs, int32_t n_jobs, void* stream);
 /* One graph replay on `stream`. SFHK_OK when every staged job has finished, else SFHK_E_NOT_DONE. */
 sfhk_status sfhk_batch_run(sfhk_batch* batch, void* stream);

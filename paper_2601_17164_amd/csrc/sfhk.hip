@@ -42,6 +42,10 @@ struct sfhk_ctx {
   size_t budget;
   size_t in_use = 0;
   std::mutex mu;
+  // job buffers come from a stream-ordered pool of this context that keeps freed memory for
+  // reuse; sfhk_job_destroy frees them on free_stream once the job's last issued work is done
+  hipMemPool_t pool = nullptr;
+  hipStream_t free_stream = nullptr;
   // staging of sfhk_propagate_many: job descriptors and the combined work list
   JobDev* many_desc = nullptr;
   WorkItem* many_work = nullptr;
@@ -64,6 +68,7 @@ struct sfhk_job {
   double2* gsum = nullptr;     // [n_groups][n_steps+1]
   size_t bytes = 0;
   std::vector<void*> allocs;
+  hipEvent_t last_use = nullptr;  // recorded after every piece of work issued on the job
   std::vector<int> tile_n0_host;
   long long steps_done = 0;    // steps requested so far (uniform across tiles)
   bool done = false;
@@ -82,9 +87,15 @@ struct sfhk_batch {
   JobDev* desc = nullptr;             // device, [max_jobs]
   WorkItem* work = nullptr;           // device, [max_items]
   BatchDev* bdev = nullptr;           // device
-  JobDev* desc_host = nullptr;        // pinned staging
-  WorkItem* work_host = nullptr;
-  BatchDev* bdev_host = nullptr;
+  // two pinned staging sets, used in turn: set s is refilled only after the replay that followed
+  // its last copies has completed (event done[s]), so the host runs at most one replay ahead and
+  // never waits for the replay in flight
+  JobDev* desc_host[2] = {nullptr, nullptr};
+  WorkItem* work_host[2] = {nullptr, nullptr};
+  BatchDev* bdev_host[2] = {nullptr, nullptr};
+  hipEvent_t done[2] = {nullptr, nullptr};
+  bool done_recorded[2] = {false, false};
+  int cur = 0;  // set of the latest staging
   std::vector<sfhk_job*> jobs;
   bool staged = false;
 };
@@ -115,18 +126,39 @@ size_t footprint_parts(long long n_traj, long long n_steps, long long n_out,
 }
 
 template <typename T>
-sfhk_status job_alloc(sfhk_job* j, T** p, size_t count) {
+sfhk_status job_alloc(sfhk_job* j, T** p, size_t count, hipStream_t st) {
   void* q = nullptr;
-  hipError_t e = hipMalloc(&q, count * sizeof(T) + 16);
-  if (e != hipSuccess) return fail(SFHK_E_NOMEM, "hipMalloc failed for a job buffer");
+  const size_t bytes = count * sizeof(T) + 16;
+  hipError_t e = hipMallocFromPoolAsync(&q, bytes, j->ctx->pool, st);
+  if (e == hipErrorOutOfMemory) {
+    // memory freed by destroyed jobs may still wait on the free stream, or sit cached in the
+    // pool in blocks too small: let the frees complete, return the cache, try once more
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(j->ctx->free_stream);
+    (void)hipMemPoolTrimTo(j->ctx->pool, 0);
+    e = hipMallocFromPoolAsync(&q, bytes, j->ctx->pool, st);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SFHK_E_NOMEM, "device allocation failed for a job buffer");
+  }
   j->allocs.push_back(q);
   *p = (T*)q;
   return SFHK_OK;
 }
 
+// frees the job's buffers in stream order after all work issued on it so far; does not block
 void job_free(sfhk_job* j) {
-  for (void* p : j->allocs) (void)hipFree(p);
+  hipStream_t fs = j->ctx->free_stream;
+  if (j->last_use) (void)hipStreamWaitEvent(fs, j->last_use, 0);
+  for (void* p : j->allocs) (void)hipFreeAsync(p, fs);
   j->allocs.clear();
+}
+
+// records that work touching the job has been issued on `st`
+sfhk_status mark_use(sfhk_job* j, hipStream_t st) {
+  HIP_TRY(hipEventRecord(j->last_use, st));
+  return SFHK_OK;
 }
 
 int blocks_for(long long n, int t) { return (int)((n + t - 1) / t); }
@@ -181,6 +213,26 @@ sfhk_status sfhk_ctx_create(int device, size_t hbm_budget_bytes, sfhk_ctx** out)
   sfhk_ctx* c = new sfhk_ctx();
   c->device = device;
   c->budget = hbm_budget_bytes;
+  hipMemPoolProps props = {};
+  props.allocType = hipMemAllocationTypePinned;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = device;
+  hipError_t e = hipMemPoolCreate(&c->pool, &props);
+  if (e == hipSuccess) {
+    uint64_t keep = UINT64_MAX;  // keep freed memory cached for the next jobs
+    e = hipMemPoolSetAttribute(c->pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
+  if (e == hipSuccess) {
+    int no = 0;  // never make an allocating stream wait for another stream's frees
+    e = hipMemPoolSetAttribute(c->pool, hipMemPoolReuseAllowInternalDependencies, &no);
+  }
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->free_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    if (c->free_stream) (void)hipStreamDestroy(c->free_stream);
+    if (c->pool) (void)hipMemPoolDestroy(c->pool);
+    delete c;
+    return fail(SFHK_E_DEVICE, std::string("context set-up: ") + hipGetErrorString(e));
+  }
   *out = c;
   return SFHK_OK;
 }
@@ -193,6 +245,8 @@ void sfhk_ctx_destroy(sfhk_ctx* ctx) {
   (void)hipFree(ctx->many_work);
   (void)hipHostFree(ctx->many_desc_host);
   (void)hipHostFree(ctx->many_work_host);
+  if (ctx->free_stream) (void)hipStreamDestroy(ctx->free_stream);
+  if (ctx->pool) (void)hipMemPoolDestroy(ctx->pool);
   delete ctx;
 }
 
@@ -241,8 +295,8 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   // birth steps on the host: nearest grid step, ties to the lower one (same arithmetic as the
   // definition: u = (t0 - t_a)/h, n0 = ceil(u - 1/2))
   std::vector<double> t0h(N);
+  HIP_TRY(hipMemcpyAsync(t0h.data(), t0, N * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  HIP_TRY(hipMemcpy(t0h.data(), t0, N * sizeof(double), hipMemcpyDeviceToHost));
   std::vector<int> n0h(N);
   const double t_b = grid->t_a + (double)NS * grid->h;
   for (long long i = 0; i < N; ++i) {
@@ -298,6 +352,12 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
 
   sfhk_job* j = new sfhk_job();
   j->ctx = ctx;
+  if (hipEventCreateWithFlags(&j->last_use, hipEventDisableTiming) != hipSuccess) {
+    delete j;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->in_use -= bytes;
+    return fail(SFHK_E_DEVICE, "hipEventCreateWithFlags failed");
+  }
   j->kind = pot->kind;
   j->precision = params->precision;
   j->n_traj = N;
@@ -347,7 +407,9 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   H.n_pad = n_pad;
 
   auto cleanup = [&](sfhk_status s) {
+    (void)hipEventRecord(j->last_use, st);  // copies already issued on st finish before the frees
     job_free(j);
+    (void)hipEventDestroy(j->last_use);
     {
       std::lock_guard<std::mutex> lk(ctx->mu);
       ctx->in_use -= bytes;
@@ -357,16 +419,16 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   };
   sfhk_status rc;
   double* e_half = nullptr;
-  if ((rc = job_alloc(j, &e_half, 2 * (size_t)NS + 1)) || (rc = job_alloc(j, &H.y, (size_t)n_pad * kNY)) ||
-      (rc = job_alloc(j, &H.aux, (size_t)n_pad * 5)) || (rc = job_alloc(j, &H.n0, (size_t)n_pad)) ||
-      (rc = job_alloc(j, &H.death, (size_t)n_pad)) || (rc = job_alloc(j, &H.tile_n0, (size_t)n_tiles)) ||
-      (rc = job_alloc(j, &H.tile_next, (size_t)n_tiles)) || (rc = job_alloc(j, &H.tile_last, (size_t)n_tiles)) ||
-      (rc = job_alloc(j, &H.row_off, (size_t)n_tiles)) || (rc = job_alloc(j, &H.part, (size_t)part_elems)) ||
-      (rc = job_alloc(j, &H.counters, 8)) || (rc = job_alloc(j, &j->perm, (size_t)n_pad)) ||
-      (rc = job_alloc(j, &j->work, (size_t)n_tiles)) ||
-      (rc = job_alloc(j, &j->dbuf, (size_t)NS + 1)) ||
-      (rc = job_alloc(j, &j->gsum, (size_t)((n_tiles + kReduceGroup - 1) / kReduceGroup) * (NS + 1))) ||
-      (rc = job_alloc(j, &j->dev, 1)))
+  if ((rc = job_alloc(j, &e_half, 2 * (size_t)NS + 1, st)) || (rc = job_alloc(j, &H.y, (size_t)n_pad * kNY, st)) ||
+      (rc = job_alloc(j, &H.aux, (size_t)n_pad * 5, st)) || (rc = job_alloc(j, &H.n0, (size_t)n_pad, st)) ||
+      (rc = job_alloc(j, &H.death, (size_t)n_pad, st)) || (rc = job_alloc(j, &H.tile_n0, (size_t)n_tiles, st)) ||
+      (rc = job_alloc(j, &H.tile_next, (size_t)n_tiles, st)) || (rc = job_alloc(j, &H.tile_last, (size_t)n_tiles, st)) ||
+      (rc = job_alloc(j, &H.row_off, (size_t)n_tiles, st)) || (rc = job_alloc(j, &H.part, (size_t)part_elems, st)) ||
+      (rc = job_alloc(j, &H.counters, 8, st)) || (rc = job_alloc(j, &j->perm, (size_t)n_pad, st)) ||
+      (rc = job_alloc(j, &j->work, (size_t)n_tiles, st)) ||
+      (rc = job_alloc(j, &j->dbuf, (size_t)NS + 1, st)) ||
+      (rc = job_alloc(j, &j->gsum, (size_t)((n_tiles + kReduceGroup - 1) / kReduceGroup) * (NS + 1), st)) ||
+      (rc = job_alloc(j, &j->dev, 1, st)))
     return cleanup(rc);
   H.e_half = e_half;
 #define TRY_C(expr)                                                              \
@@ -389,6 +451,7 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   TRY_C(hipMemcpyAsync(j->dev, &H, sizeof(JobDev), hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL(k_init, dim3(blocks_for(n_pad, 256)), dim3(256), 0, st, H, j->perm, N, q0, p0, w);
   TRY_C(hipGetLastError());
+  TRY_C(hipEventRecord(j->last_use, st));
   // the host vectors above are about to go out of scope: finish the copies before returning
   TRY_C(hipStreamSynchronize(st));
 #undef TRY_C
@@ -399,8 +462,8 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
 void sfhk_job_destroy(sfhk_job* job) {
   if (!job) return;
   (void)hipSetDevice(job->ctx->device);
-  (void)hipDeviceSynchronize();
   job_free(job);
+  if (job->last_use) (void)hipEventDestroy(job->last_use);
   {
     std::lock_guard<std::mutex> lk(job->ctx->mu);
     job->ctx->in_use -= job->bytes;
@@ -432,6 +495,7 @@ sfhk_status sfhk_propagate(sfhk_job* job, int64_t max_steps, void* stream) {
     int ms = (max_steps <= 0 || max_steps > NS + 1) ? 0 : (int)max_steps;
     sfhk_status rc = launch_propagate(job->precision, job->kind, job->dev, job->work, nt, ms, st);
     if (rc) return rc;
+    if ((rc = mark_use(job, st))) return rc;
   }
   job->steps_done += (max_steps <= 0) ? (long long)NS + 1 : max_steps;
   if (unfinished_tiles(job, job->steps_done) == 0) {
@@ -505,6 +569,8 @@ sfhk_status sfhk_propagate_many(sfhk_job* const* jobs, int32_t n_jobs, int64_t m
       if (rc) return rc;
       a = b;
     }
+    for (int i = 0; i < n_jobs; ++i)
+      if (!jobs[i]->done) HIP_TRY(hipEventRecord(jobs[i]->last_use, st));
   }
   sfhk_status agg = SFHK_OK;
   for (int i = 0; i < n_jobs; ++i) {
@@ -533,9 +599,12 @@ void sfhk_batch_destroy(sfhk_batch* b) {
   (void)hipFree(b->desc);
   (void)hipFree(b->work);
   (void)hipFree(b->bdev);
-  (void)hipHostFree(b->desc_host);
-  (void)hipHostFree(b->work_host);
-  (void)hipHostFree(b->bdev_host);
+  for (int s = 0; s < 2; ++s) {
+    (void)hipHostFree(b->desc_host[s]);
+    (void)hipHostFree(b->work_host[s]);
+    (void)hipHostFree(b->bdev_host[s]);
+    if (b->done[s]) (void)hipEventDestroy(b->done[s]);
+  }
   delete b;
 }
 
@@ -569,12 +638,15 @@ sfhk_status sfhk_batch_create(sfhk_ctx* ctx, int32_t max_jobs, int64_t max_tiles
   TRY_B(hipMalloc(&b->desc, (size_t)max_jobs * sizeof(JobDev)));
   TRY_B(hipMalloc(&b->work, (size_t)max_tiles * sizeof(WorkItem)));
   TRY_B(hipMalloc(&b->bdev, sizeof(BatchDev)));
-  TRY_B(hipHostMalloc(&b->desc_host, (size_t)max_jobs * sizeof(JobDev), hipHostMallocDefault));
-  TRY_B(hipHostMalloc(&b->work_host, (size_t)max_tiles * sizeof(WorkItem), hipHostMallocDefault));
-  TRY_B(hipHostMalloc(&b->bdev_host, sizeof(BatchDev), hipHostMallocDefault));
+  for (int s = 0; s < 2; ++s) {
+    TRY_B(hipHostMalloc(&b->desc_host[s], (size_t)max_jobs * sizeof(JobDev), hipHostMallocDefault));
+    TRY_B(hipHostMalloc(&b->work_host[s], (size_t)max_tiles * sizeof(WorkItem), hipHostMallocDefault));
+    TRY_B(hipHostMalloc(&b->bdev_host[s], sizeof(BatchDev), hipHostMallocDefault));
+    TRY_B(hipEventCreateWithFlags(&b->done[s], hipEventDisableTiming));
+  }
   TRY_B(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
-  std::memset(b->bdev_host, 0, sizeof(BatchDev));
-  TRY_B(hipMemcpyAsync(b->bdev, b->bdev_host, sizeof(BatchDev), hipMemcpyHostToDevice, b->cap_stream));
+  std::memset(b->bdev_host[0], 0, sizeof(BatchDev));
+  TRY_B(hipMemcpyAsync(b->bdev, b->bdev_host[0], sizeof(BatchDev), hipMemcpyHostToDevice, b->cap_stream));
   TRY_B(hipStreamSynchronize(b->cap_stream));
   const int ms = (max_steps <= 0 || max_steps > INT32_MAX / 2) ? 0 : (int)max_steps;
   // capture: reset the queue heads with a kernel (no memset node), then one kernel per precision
@@ -637,17 +709,23 @@ sfhk_status sfhk_batch_set_jobs(sfhk_batch* b, sfhk_job* const* jobs, int32_t n_
   std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) {
     return x.seg != y.seg ? x.seg < y.seg : x.left > y.left;
   });
-  HIP_TRY(hipStreamSynchronize(st));  // earlier copies from the staging buffers have completed
+  // the other staging set than the latest one; its copies were followed by a replay (or by
+  // nothing) recorded in done[s]
+  const int s = b->cur ^ 1;
+  if (b->done_recorded[s]) HIP_TRY(hipEventSynchronize(b->done[s]));
   BatchDev bd{};
   for (const Item& it : items) bd.n_items[it.seg]++;
   for (int g = 1; g < kSegs; ++g) bd.offset[g] = bd.offset[g - 1] + bd.n_items[g - 1];
-  for (int i = 0; i < n_jobs; ++i) b->desc_host[i] = jobs[i]->host;
-  for (size_t k = 0; k < items.size(); ++k) b->work_host[k] = {items[k].job, items[k].tile};
-  *b->bdev_host = bd;
-  if (n_jobs) HIP_TRY(hipMemcpyAsync(b->desc, b->desc_host, n_jobs * sizeof(JobDev), hipMemcpyHostToDevice, st));
+  for (int i = 0; i < n_jobs; ++i) b->desc_host[s][i] = jobs[i]->host;
+  for (size_t k = 0; k < items.size(); ++k) b->work_host[s][k] = {items[k].job, items[k].tile};
+  *b->bdev_host[s] = bd;
+  if (n_jobs) HIP_TRY(hipMemcpyAsync(b->desc, b->desc_host[s], n_jobs * sizeof(JobDev), hipMemcpyHostToDevice, st));
   if (!items.empty())
-    HIP_TRY(hipMemcpyAsync(b->work, b->work_host, items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(b->bdev, b->bdev_host, sizeof(BatchDev), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(b->work, b->work_host[s], items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(b->bdev, b->bdev_host[s], sizeof(BatchDev), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(b->done[s], st));
+  b->done_recorded[s] = true;
+  b->cur = s;
   b->jobs.assign(jobs, jobs + n_jobs);
   b->staged = true;
   return SFHK_OK;
@@ -658,6 +736,9 @@ sfhk_status sfhk_batch_run(sfhk_batch* b, void* stream) {
   HIP_TRY(hipSetDevice(b->ctx->device));
   if (!b->staged || b->jobs.empty()) return SFHK_OK;
   HIP_TRY(hipGraphLaunch(b->exec, (hipStream_t)stream));
+  for (sfhk_job* j : b->jobs) HIP_TRY(hipEventRecord(j->last_use, (hipStream_t)stream));
+  // the latest staging set is refilled only after this replay: at most one replay ahead
+  HIP_TRY(hipEventRecord(b->done[b->cur], (hipStream_t)stream));
   sfhk_status agg = SFHK_OK;
   for (sfhk_job* j : b->jobs) {
     if (j->done) continue;
@@ -694,7 +775,7 @@ sfhk_status sfhk_dipole(sfhk_job* job, double* d_out, double* f_out, void* strea
                        (const double*)job->dbuf, (long long)H.n_steps, (long long)job->n_out, d_out);
     HIP_TRY(hipGetLastError());
   }
-  return SFHK_OK;
+  return mark_use(job, st);
 }
 
 sfhk_status sfhk_spectrum(const double* d, int64_t n, double t_first, double dt, double tau_h,
@@ -761,7 +842,7 @@ sfhk_status sfhk_job_trajectories(sfhk_job* job, double* y_out, double* c_out, i
                      job->host, (const long long*)job->perm, (long long)job->n_traj, y_out, c_out,
                      (long long*)death_out);
   HIP_TRY(hipGetLastError());
-  return SFHK_OK;
+  return mark_use(job, st);
 }
 
 static sfhk_status traj_fn(int which, const double* x, double* y, int64_t n, void* stream) {

@@ -4,8 +4,14 @@ Requests (one SFHK instance each) arrive at given times. Between graph replays o
 arrived requests are admitted in arrival order while their device footprint fits the context's
 HBM budget and the batch's capacity; admitted requests keep their trajectory state in HBM and
 every replay advances all of them by `chunk` steps (one launch per precision and potential kind
-over all their tiles, longest first). A request that has finished gets its dipole and spectrum computed on the device
-and copied to pinned host memory; its latency runs from arrival to that copy's completion.
+over all their tiles, longest first). A request that has finished gets its dipole and spectrum
+computed on the device and copied to pinned host memory; its latency runs from arrival to the
+moment the loop sees that copy complete.
+
+The loop is pipelined: replays, dipoles and spectra run on one compute stream, uploads and job
+creation on an admission stream, and nothing waits for the replay in flight. Staging the next
+replay's table waits only for the replay before it (the batch keeps two staging sets), finished
+requests are collected by polling events, and destroyed jobs return their memory in stream order.
 Results are identical to each request propagated alone (the batch path is bitwise equal to it).
 """
 from __future__ import annotations
@@ -63,7 +69,6 @@ class _Finishing:
     omega: object
     power: object
     dipole: object
-    steps: int
 
 
 class Server:
@@ -83,7 +88,9 @@ class Server:
     def run(self, requests: List[Request]) -> List[Result]:
         import torch
         sfhk = self.sfhk
-        stream = torch.cuda.current_stream()
+        dev = torch.device(f"cuda:{self.ctx.device}")
+        comp = torch.cuda.Stream(dev)   # replays, dipoles, spectra, copies to the host
+        adm = torch.cuda.Stream(dev)    # uploads and job creation
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         queue: deque = deque()
         active: List[_Active] = []
@@ -92,10 +99,28 @@ class Server:
         tiles_active = 0
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0
+
+        def collect(f: _Finishing):
+            st = f.job.stats(adm)  # the counters were final when the event completed
+            results.append(Result(f.req.req_id, f.req.arrival, f.admitted, now(),
+                                  f.req.inst.n_traj, st.steps_evaluated,
+                                  None if f.omega is None else f.omega.numpy(),
+                                  f.power.numpy() if self.keep else None,
+                                  None if f.dipole is None else f.dipole.numpy()))
+            f.job.close()
+
         while pending or queue or active or finishing:
             t = now()
             while pending and pending[0].arrival <= t:
                 queue.append(pending.popleft())
+            # finished requests whose spectrum has reached host memory
+            still = []
+            for f in finishing:
+                if f.event.query():
+                    collect(f)
+                else:
+                    still.append(f)
+            finishing = still
             # admission, in arrival order, by HBM footprint and batch capacity
             while queue and len(active) < self.max_jobs:
                 req = queue[0]
@@ -105,7 +130,9 @@ class Server:
                 if tiles_active + nt > self.max_tiles:
                     break
                 try:
-                    job = sfhk.make_job(self.ctx, req.inst, precision=self.precision)
+                    with torch.cuda.stream(adm):
+                        job = sfhk.make_job(self.ctx, req.inst, precision=self.precision,
+                                            stream=adm)
                 except sfhk.SfhkError as e:
                     if e.status == sfhk.SFHK_E_BUDGET and (active or finishing):
                         break  # wait for running requests to free HBM
@@ -113,48 +140,42 @@ class Server:
                 queue.popleft()
                 active.append(_Active(req, job, now()))
                 tiles_active += nt
-            # staging the table synchronises the stream: every earlier replay and every finished
-            # request's spectrum copy is complete after it
             if active:
-                self.batch.set_jobs([a.job for a in active])
-            elif finishing:
-                stream.synchronize()
-            t_sync = now()
-            for f in finishing:
-                st = f.job.stats()
-                results.append(Result(f.req.req_id, f.req.arrival, f.admitted, t_sync,
-                                      f.req.inst.n_traj, st.steps_evaluated,
-                                      None if f.omega is None else f.omega.numpy(),
-                                      f.power.numpy() if self.keep else None,
-                                      None if f.dipole is None else f.dipole.numpy()))
-                f.job.close()
-            finishing = []
-            if active:
-                self.batch.run()
+                # waits only for the replay before the one in flight
+                self.batch.set_jobs([a.job for a in active], stream=comp)
+                self.batch.run(stream=comp)
                 still = []
-                for a in active:
-                    if not a.job.done:
-                        still.append(a)
-                        continue
-                    d = a.job.dipole()
-                    inst = a.req.inst
-                    T = inst.grid.h * inst.grid.n_steps
-                    dt = T / inst.n_out if inst.n_out else inst.grid.h
-                    om, pw, _ = sfhk.spectrum(d, inst.grid.t_a, dt, T / 2)
-                    host_pw = torch.empty(pw.shape, dtype=pw.dtype, pin_memory=True)
-                    host_pw.copy_(pw, non_blocking=True)
-                    host_om = host_d = None
-                    if self.keep:
-                        host_om = torch.empty(om.shape, dtype=om.dtype, pin_memory=True)
-                        host_om.copy_(om, non_blocking=True)
-                        host_d = torch.empty(d.shape, dtype=d.dtype, pin_memory=True)
-                        host_d.copy_(d, non_blocking=True)
-                    finishing.append(_Finishing(a.req, a.job, a.admitted, None, host_om, host_pw,
-                                                host_d, 0))
-                    tiles_active -= sfhk.tiles_of(inst)
+                with torch.cuda.stream(comp):
+                    for a in active:
+                        if not a.job.done:
+                            still.append(a)
+                            continue
+                        d = a.job.dipole(stream=comp)
+                        inst = a.req.inst
+                        T = inst.grid.h * inst.grid.n_steps
+                        dt = T / inst.n_out if inst.n_out else inst.grid.h
+                        om, pw, _ = sfhk.spectrum(d, inst.grid.t_a, dt, T / 2, stream=comp)
+                        host_pw = torch.empty(pw.shape, dtype=pw.dtype, pin_memory=True)
+                        host_pw.copy_(pw, non_blocking=True)
+                        host_om = host_d = None
+                        if self.keep:
+                            host_om = torch.empty(om.shape, dtype=om.dtype, pin_memory=True)
+                            host_om.copy_(om, non_blocking=True)
+                            host_d = torch.empty(d.shape, dtype=d.dtype, pin_memory=True)
+                            host_d.copy_(d, non_blocking=True)
+                        ev = torch.cuda.Event()
+                        ev.record(comp)
+                        finishing.append(_Finishing(a.req, a.job, a.admitted, ev, host_om,
+                                                    host_pw, host_d))
+                        tiles_active -= sfhk.tiles_of(inst)
                 active = still
-            elif not queue and pending and not finishing:
+            elif finishing:
+                finishing[0].event.synchronize()
+            elif queue:
+                comp.synchronize()  # admission waits for memory held by finished requests
+            elif pending:
                 time.sleep(max(0.0, min(0.05, pending[0].arrival - now())))
+        comp.synchronize()
         return sorted(results, key=lambda r: r.req_id)
 
 

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as ct
 import os
+import weakref
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -141,12 +142,15 @@ class Context:
                "sfhk_ctx_create")
         self.handle = h
         self.device = int(device)
+        self._jobs = weakref.WeakSet()  # live jobs: closed before the context
 
     def bytes_in_use(self) -> int:
         return int(lib().sfhk_ctx_bytes_in_use(self.handle))
 
     def close(self):
         if self.handle:
+            for job in list(self._jobs):
+                job.close()
             lib().sfhk_ctx_destroy(self.handle)
             self.handle = _VP()
 
@@ -205,6 +209,7 @@ class Job:
                                      _stream_ptr(stream), ct.byref(h)), "sfhk_job_create")
         self.handle = h
         self.ctx = ctx
+        ctx._jobs.add(self)
         self.n_traj = n
         self.n_steps = int(n_steps)
         self.t_a = float(grid_t_a)

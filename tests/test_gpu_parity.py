@@ -316,3 +316,20 @@ def test_budget_and_invalid_arguments(S):
         sfhk.make_job(ctx, bad2)
     assert ei.value.status == sfhk.SFHK_E_INVALID
     assert sfhk.job_footprint(inst.n_traj, inst.grid.n_steps) > 43 * 8 * inst.n_traj
+
+
+def test_cancel_mid_job_releases_its_memory(S):
+    """A job destroyed between chunks (cancellation) returns its bytes to the context, and a job
+    created afterwards from the same inputs still matches the oracle."""
+    sfhk, ctx, torch = S
+    inst = I.config0(n_birth=8, n_per_birth=16)
+    before = ctx.bytes_in_use()
+    job = sfhk.make_job(ctx, inst)
+    assert ctx.bytes_in_use() > before
+    assert not job.propagate(300)
+    job.close()
+    torch.cuda.synchronize()
+    assert ctx.bytes_in_use() == before
+    r = run_oracle(inst)
+    g = _gpu_run(S, inst)
+    _assert_parity("after-cancel", g, r)
