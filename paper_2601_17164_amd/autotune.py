@@ -1,8 +1,9 @@
 """Autotuner of the batched propagation: chooses the launch form (persistent queue with a given
 number of resident workgroups per compute unit, or hardware dispatch of one workgroup per tile)
 and the step chunk for a precision, by timing short trials of each candidate through the C ABI on
-a scaled-down batch drawn from the uneven-batch distribution. Results are cached per device name
-and precision in a JSON file.
+a scaled-down batch drawn from the uneven-batch distribution (16 instances with a quarter of their
+trajectories: 1/16 of the 64-instance batch's work, large enough for its tail effects to show).
+Results are cached per device name and precision in a JSON file.
 """
 from __future__ import annotations
 
@@ -52,7 +53,7 @@ def choose(rates: dict) -> str:
     return best
 
 
-def tune(ctx, precision: int = 0, n_instances: int = 16, traj_scale: float = 1.0 / 16,
+def tune(ctx, precision: int = 0, n_instances: int = 16, traj_scale: float = 1.0 / 4,
          seed: int = 77, use_cache: bool = True, verbose: bool = False) -> dict:
     """Returns {"workers_per_cu": w, "chunk": k, "rates": {...}} for this device and precision."""
     import torch
