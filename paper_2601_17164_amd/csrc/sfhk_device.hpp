@@ -145,7 +145,8 @@ __device__ __forceinline__ void screened_terms(const PotParams& P, double r2, do
   double ir2 = ir * ir;
   double ir3 = ir2 * ir;
   const double xe = -(r * P.inv_rscr);
-  double e = exp_cw_nonpos(xe);
+  double e = 0.0;  // exp_cw_nonpos gives exactly 0 below -708: a wave with every lane there skips it
+  if (!FAST || __any(!(xe < -708.0))) e = exp_cw_nonpos(xe);
   double ez = P.z_in * e;
   double Z = P.z_inf + ez;
   double d1 = ez * P.inv_rscr;  // -Z'
