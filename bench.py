@@ -79,6 +79,8 @@ def _args():
     ap.add_argument("--serve-chunk", type=int, default=1024)
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the short serving run of the default benchmark")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the uneven-batch pass of the default benchmark")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (calibrates the "
                          "HBM traffic counters) and exit")
@@ -189,14 +191,13 @@ def run_serve(a):
     print(json.dumps(out), flush=True)
 
 
-def run_batch(a):
-    """The uneven batch: 64 instances (wavelength 800-2000 nm, 0.8-3e14 W/cm^2, 2-10 cycles,
-    potential of either workload, 2^14-2^20 trajectories each), all tiles of all instances in one
-    graph replay, in FP64 and then in the FP32-mixed form."""
+def batch_results(ctx, batch_size):
+    """The uneven batch: `batch_size` instances (wavelength 800-2000 nm, 0.8-3e14 W/cm^2, 2-10
+    cycles, potential of either workload, 2^14-2^20 trajectories each), all tiles of all instances
+    in one graph replay with the autotuned launch form, in FP64 and then in the FP32-mixed form."""
     import torch
     from paper_2601_17164_amd import autotune, inputs as I, sfhk
-    insts = I.batch_instances(a.batch_size, seed=3)
-    ctx = sfhk.Context(0)
+    insts = I.batch_instances(batch_size, seed=3)
     arrays = [sfhk.to_device(x, "cuda:0") for x in insts]
     n_tiles = sum(sfhk.tiles_of(x) for x in insts)
     out = {"metric": "HK trajectory-steps/s, uneven batch in one graph-captured launch",
@@ -224,7 +225,14 @@ def run_batch(a):
         for j in jobs:
             j.close()
         b.close()
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def run_batch(a):
+    from paper_2601_17164_amd import sfhk
+    ctx = sfhk.Context(0)
+    print(json.dumps(batch_results(ctx, a.batch_size)), flush=True)
+    ctx.close()
 
 
 def main():
@@ -324,6 +332,8 @@ def main():
     if not a.no_serving:
         out["serving"] = {name: serving_run(ctx, 5.0, 30, 2, prec, a.serve_chunk)
                           for prec, name in ((0, "fp64"), (1, "fp32_mixed"))}
+    if not a.no_batch:
+        out["batch"] = batch_results(ctx, a.batch_size)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, a.cpu_births, a.cpu_per_birth)
     print(json.dumps(out), flush=True)
