@@ -105,3 +105,49 @@ def test_batch_capacity_errors(S):
     b.close()
     for j in jobs:
         j.close()
+
+
+def _kind_instances():
+    """One instance of each potential kind (none, soft-core, screened, harmonic): each runs in its
+    own kernel instance."""
+    pulse = I.Pulse(800.0, 1e14, 2.0)
+    grid = I.time_grid(pulse, 0.1)
+    e = I.field_table(pulse, grid)
+    rng = np.random.default_rng(5)
+    n = 96
+    t0 = np.sort(grid.t_a + rng.integers(0, grid.n_steps, n) * grid.h)
+    q0 = rng.normal(0.0, 1.0, (3, n))
+    p0 = rng.normal(0.0, 0.5, (3, n))
+    none = I.Instance("none", I.Potential(I.POT_NONE, 0, 0, 1, 0, 0), I.gto_h1s(), pulse, grid, e,
+                      t0, q0, p0)
+    ho = I.Instance("ho", I.Potential(I.POT_HARMONIC, 0, 0, 1, 0, 0.3), I.gto_h1s(), pulse, grid,
+                    e, t0, q0, p0)
+    soft = I.config0(n_birth=4, n_per_birth=24, seed=3)
+    scr = I.config1_birth_subset(I.config1(), [700, 900], 40)
+    return [none, soft, scr, ho]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_all_potential_kinds_in_one_batch_and_one_call(S, precision):
+    """Jobs of all four potential kinds together (one kernel instance per kind and precision) in
+    a batch replay, hardware dispatch and persistent form, and in one sfhk_propagate_many call:
+    each equals the job alone."""
+    sfhk, ctx, torch = S
+    insts = _kind_instances()
+    alone = [_alone(S, x, precision) for x in insts]
+    n_tiles = sum(sfhk.tiles_of(x) for x in insts)
+    for workers in (0, 8):
+        jobs = [sfhk.make_job(ctx, x, precision=precision) for x in insts]
+        b = sfhk.Batch(ctx, len(jobs), n_tiles, 0, workers)
+        b.set_jobs(jobs)
+        assert b.run()
+        for job, ref in zip(jobs, alone):
+            np.testing.assert_array_equal(job.dipole().cpu().numpy(), ref)
+            job.close()
+        b.close()
+    jobs = [sfhk.make_job(ctx, x, precision=precision) for x in insts]
+    while not sfhk.propagate_many(jobs, 300):
+        pass
+    for job, ref in zip(jobs, alone):
+        np.testing.assert_array_equal(job.dipole().cpu().numpy(), ref)
+        job.close()
