@@ -164,12 +164,17 @@ __device__ __forceinline__ void screened_terms(const PotParams& P, double r2, do
   c = pos ? cp : 0.0;
 }
 
-template <int KIND>
-__device__ __forceinline__ void pot_gc(const PotParams& P, double x, double y, double z, double& V,
-                                       double& g, double& c) {
+// r^2 = x^2 + y^2 + z^2 in the contract's order
+__device__ __forceinline__ double norm2(double x, double y, double z) {
   double r2 = x * x;
   r2 = SFHK_FMA(y, y, r2);
-  r2 = SFHK_FMA(z, z, r2);
+  return SFHK_FMA(z, z, r2);
+}
+
+// V, g, c at (x, y, z) with r2 = norm2(x, y, z)
+template <int KIND>
+__device__ __forceinline__ void pot_gc(const PotParams& P, double x, double y, double z, double r2,
+                                       double& V, double& g, double& c) {
   if constexpr (KIND == POT_SOFTCORE) {
     // V = -Z u, u = (r^2 + a)^(-1/2); dV/dr / r = Z u^3; (V'' - V'/r)/r^2 = -3 Z u^5
     double s = r2 + P.soft2;
@@ -201,15 +206,15 @@ __device__ __forceinline__ void pot_gc(const PotParams& P, double x, double y, d
 
 // kind known only at run time (uniform across the wave): a scalar branch per evaluation
 __device__ __forceinline__ void pot_gc_rt(int kind, const PotParams& P, double x, double y, double z,
-                                          double& V, double& g, double& c) {
+                                          double r2, double& V, double& g, double& c) {
   if (kind == POT_SCREENED)
-    pot_gc<POT_SCREENED>(P, x, y, z, V, g, c);
+    pot_gc<POT_SCREENED>(P, x, y, z, r2, V, g, c);
   else if (kind == POT_SOFTCORE)
-    pot_gc<POT_SOFTCORE>(P, x, y, z, V, g, c);
+    pot_gc<POT_SOFTCORE>(P, x, y, z, r2, V, g, c);
   else if (kind == POT_HARMONIC)
-    pot_gc<POT_HARMONIC>(P, x, y, z, V, g, c);
+    pot_gc<POT_HARMONIC>(P, x, y, z, r2, V, g, c);
   else
-    pot_gc<POT_NONE>(P, x, y, z, V, g, c);
+    pot_gc<POT_NONE>(P, x, y, z, r2, V, g, c);
 }
 
 struct Hess3 {
@@ -254,28 +259,34 @@ struct Traj {
   double M[36];  // 6 columns (Q(3), P(3)): column j = d(q_t, p_t)/d z_j, z = (q0, p0)
 };
 
+// the (q, p, S) right-hand side; q2 = norm2(q), p2 = norm2(p)
 __device__ __forceinline__ void qps_rhs(int kind, const PotParams& P, const double* q, const double* p,
-                                        double E, double* kp, double& kS, Hess3& H) {
+                                        double q2, double p2, double E, double* kp, double& kS,
+                                        Hess3& H) {
   double V, g, c;
-  pot_gc_rt(kind, P, q[0], q[1], q[2], V, g, c);
+  pot_gc_rt(kind, P, q[0], q[1], q[2], q2, V, g, c);
   H = hess_from(g, c, q[0], q[1], q[2]);
   kp[0] = -(g * q[0]);
   kp[1] = -(g * q[1]);
   kp[2] = -SFHK_FMA(g, q[2], E);
-  double p2 = p[0] * p[0];
-  p2 = SFHK_FMA(p[1], p[1], p2);
-  p2 = SFHK_FMA(p[2], p[2], p2);
   double L = SFHK_FMA(0.5, p2, -V);
   kS = SFHK_FMA(-q[2], E, L);
 }
 
-__device__ __forceinline__ void rk4_step(int kind, const PotParams& P, Traj& T, double ea, double eb,
-                                         double ec, double h, double h2, double h6) {
+__device__ __forceinline__ void qps_rhs(int kind, const PotParams& P, const double* q, const double* p,
+                                        double E, double* kp, double& kS, Hess3& H) {
+  qps_rhs(kind, P, q, p, norm2(q[0], q[1], q[2]), norm2(p[0], p[1], p[2]), E, kp, kS, H);
+}
+
+// q2 = norm2(T.q) and p2 = norm2(T.p) of the state the step starts from (the caller has them)
+__device__ __forceinline__ void rk4_step(int kind, const PotParams& P, Traj& T, double q2, double p2,
+                                         double ea, double eb, double ec, double h, double h2,
+                                         double h6) {
   Hess3 H1, H2, H3, H4;
   {
     double accq[3], accp[3], accS, ysq[3], ysp[3], ysS, kp[3], kS;
     // stage 1
-    qps_rhs(kind, P, T.q, T.p, ea, kp, kS, H1);
+    qps_rhs(kind, P, T.q, T.p, q2, p2, ea, kp, kS, H1);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       accq[i] = T.p[i];
@@ -364,6 +375,12 @@ __device__ __forceinline__ void rk4_step(int kind, const PotParams& P, Traj& T, 
       Pc[i] = SFHK_FMA(h6, aP[i], Pc[i]);
     }
   }
+}
+
+__device__ __forceinline__ void rk4_step(int kind, const PotParams& P, Traj& T, double ea, double eb,
+                                         double ec, double h, double h2, double h6) {
+  rk4_step(kind, P, T, norm2(T.q[0], T.q[1], T.q[2]), norm2(T.p[0], T.p[1], T.p[2]), ea, eb, ec, h,
+           h2, h6);
 }
 
 // ----------------------------------------------------------------------------------------------

@@ -340,8 +340,9 @@ __device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const 
       }
     }
     // dipole element: costly only for lanes near the ground state
-    double p2 = SFHK_FMA(T.p[2], T.p[2], SFHK_FMA(T.p[1], T.p[1], T.p[0] * T.p[0]));
-    double q2 = SFHK_FMA(T.q[2], T.q[2], SFHK_FMA(T.q[1], T.q[1], T.q[0] * T.q[0]));
+    // |p|^2 and |q|^2 of the state at t_n: the skip bound below and the RK4's first stage use them
+    const double p2 = norm2(T.p[0], T.p[1], T.p[2]);
+    const double q2 = norm2(T.q[0], T.q[1], T.q[2]);
     const bool need = contrib && !overlap_all_skipped(J.gto, p2, q2);
     const unsigned long long m = __builtin_amdgcn_ballot_w64(need);
     if (m) {
@@ -357,7 +358,7 @@ __device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const 
     }
     if (n < N) {
       const double eb = eh[2 * n + 1], ec = eh[2 * n + 2];
-      if (alive && n >= n0l) rk4_step(kind, P, T, ea, eb, ec, h, h2, h6);
+      if (alive && n >= n0l) rk4_step(kind, P, T, q2, p2, ea, eb, ec, h, h2, h6);
       ea = ec;
     }
     if (!__any(alive)) {  // every lane removed: the rest of the tile's row stays zero
