@@ -292,79 +292,106 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   const long long N = n_traj;
   const int NS = (int)grid->n_steps;
 
-  // birth steps on the host: nearest grid step, ties to the lower one (same arithmetic as the
-  // definition: u = (t0 - t_a)/h, n0 = ceil(u - 1/2))
-  std::vector<double> t0h(N);
-  HIP_TRY(hipMemcpyAsync(t0h.data(), t0, N * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  std::vector<int> n0h(N);
+  const long long n_pad = (N + kTile - 1) / kTile * kTile;
+  const int n_tiles = (int)(n_pad / kTile);
   const double t_b = grid->t_a + (double)NS * grid->h;
-  for (long long i = 0; i < N; ++i) {
-    double t = t0h[i];
-    if (!(t >= grid->t_a - 0.5 * grid->h && t <= t_b + 0.5 * grid->h))
-      return fail(SFHK_E_INVALID, "t0[" + std::to_string(i) + "] outside the time grid");
-    double u = (t - grid->t_a) / grid->h;
-    double nn = std::ceil(u - 0.5);
-    if (!(nn >= 0.0)) nn = 0.0;
-    if (nn > (double)NS) nn = (double)NS;
-    n0h[i] = (int)nn;
+
+  sfhk_job* j = new sfhk_job();
+  j->ctx = ctx;
+  if (hipEventCreateWithFlags(&j->last_use, hipEventDisableTiming) != hipSuccess) {
+    delete j;
+    return fail(SFHK_E_DEVICE, "hipEventCreateWithFlags failed");
   }
+  size_t bytes = 0;  // counted against the budget once known
+  auto cleanup = [&](sfhk_status s) {
+    (void)hipEventRecord(j->last_use, st);  // work already issued on st finishes before the frees
+    job_free(j);
+    (void)hipEventDestroy(j->last_use);
+    if (bytes) {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      ctx->in_use -= bytes;
+    }
+    delete j;
+    return s;
+  };
+#define TRY_C(expr)                                                              \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess) return cleanup(fail(SFHK_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_))); \
+  } while (0)
+  JobDev& H = j->host;
+  sfhk_status rc;
+
+  // birth steps on the device (k_birth); the host reads back only each tile's first birth step and
+  // two flags unless the samples are not in birth order
+  unsigned long long* flags = nullptr;
+  if ((rc = job_alloc(j, &H.n0, (size_t)n_pad, st)) || (rc = job_alloc(j, &H.tile_n0, (size_t)n_tiles, st)) ||
+      (rc = job_alloc(j, &flags, 2, st)))
+    return cleanup(rc);
+  TRY_C(hipMemsetAsync(flags, 0xFF, sizeof(unsigned long long), st));
+  TRY_C(hipMemsetAsync(flags + 1, 0, sizeof(unsigned long long), st));
+  hipLaunchKernelGGL(k_birth, dim3(blocks_for(n_pad, 256)), dim3(256), 0, st, t0, N, n_pad,
+                     grid->t_a, grid->h, grid->t_a - 0.5 * grid->h, t_b + 0.5 * grid->h, NS, H.n0,
+                     H.tile_n0, flags);
+  TRY_C(hipGetLastError());
+  unsigned long long fl[2] = {0, 0};
+  std::vector<int> tile_n0(n_tiles);
+  TRY_C(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, st));
+  TRY_C(hipMemcpyAsync(tile_n0.data(), H.tile_n0, n_tiles * sizeof(int), hipMemcpyDeviceToHost, st));
+  TRY_C(hipStreamSynchronize(st));
+  if (fl[0] != ~0ull)
+    return cleanup(fail(SFHK_E_INVALID, "t0[" + std::to_string(fl[0]) + "] outside the time grid"));
   // stable order by birth step: the identity when the samples already come in birth order (the
-  // usual layout), else a counting sort over the grid steps 0..NS
-  bool in_order = true;
-  for (long long i = 1; i < N && in_order; ++i) in_order = n0h[i - 1] <= n0h[i];
-  std::vector<long long> order;
+  // usual layout), else a counting sort over the grid steps 0..NS on the host
+  const bool in_order = fl[1] == 0;
+  std::vector<long long> perm;
+  std::vector<int> n0s;
   if (!in_order) {
+    std::vector<int> n0h(N);
+    TRY_C(hipMemcpyAsync(n0h.data(), H.n0, N * sizeof(int), hipMemcpyDeviceToHost, st));
+    TRY_C(hipStreamSynchronize(st));
     std::vector<long long> next(NS + 2, 0);
     for (long long i = 0; i < N; ++i) ++next[n0h[i] + 1];
     for (int k = 0; k <= NS; ++k) next[k + 1] += next[k];
-    order.resize(N);
-    for (long long i = 0; i < N; ++i) order[next[n0h[i]]++] = i;
+    perm.assign(n_pad, -1);
+    for (long long i = 0; i < N; ++i) perm[next[n0h[i]]++] = i;
+    n0s.assign(n_pad, NS + 1);
+    for (long long s = 0; s < N; ++s) n0s[s] = n0h[perm[s]];
+    for (int t = 0; t < n_tiles; ++t) tile_n0[t] = n0s[(long long)t * kTile];
   }
-  const long long n_pad = (N + kTile - 1) / kTile * kTile;
-  const int n_tiles = (int)(n_pad / kTile);
-  std::vector<long long> perm(n_pad, -1);
-  std::vector<int> n0s(n_pad, NS + 1);
-  for (long long s = 0; s < N; ++s) {
-    const long long o = in_order ? s : order[s];
-    perm[s] = o;
-    n0s[s] = n0h[o];
-  }
-  std::vector<int> tile_n0(n_tiles), tile_next(n_tiles), tile_last(n_tiles);
+  std::vector<int> tile_next(n_tiles), tile_last(n_tiles);
   std::vector<long long> row_off(n_tiles);
   long long off = 0;
   for (int t = 0; t < n_tiles; ++t) {
-    tile_n0[t] = n0s[(long long)t * kTile];
     tile_next[t] = tile_n0[t];
     tile_last[t] = tile_n0[t] - 1;
     row_off[t] = off;
     off += NS - tile_n0[t] + 1;
   }
   long long part_elems = 0;
-  size_t bytes = footprint_parts(N, NS, params->n_out, &tile_n0, &part_elems);
+  const size_t need = footprint_parts(N, NS, params->n_out, &tile_n0, &part_elems);
+  bool over = false;
+  size_t left = 0;
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
-    if (ctx->budget && ctx->in_use + bytes > ctx->budget)
-      return fail(SFHK_E_BUDGET, "job needs " + std::to_string(bytes) + " bytes; budget left " +
-                                     std::to_string(ctx->budget - ctx->in_use));
-    ctx->in_use += bytes;
+    if (ctx->budget && ctx->in_use + need > ctx->budget) {
+      over = true;
+      left = ctx->budget - ctx->in_use;
+    } else {
+      ctx->in_use += need;
+    }
   }
+  if (over)
+    return cleanup(fail(SFHK_E_BUDGET, "job needs " + std::to_string(need) + " bytes; budget left " +
+                                           std::to_string(left)));
+  bytes = need;
 
-  sfhk_job* j = new sfhk_job();
-  j->ctx = ctx;
-  if (hipEventCreateWithFlags(&j->last_use, hipEventDisableTiming) != hipSuccess) {
-    delete j;
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    ctx->in_use -= bytes;
-    return fail(SFHK_E_DEVICE, "hipEventCreateWithFlags failed");
-  }
   j->kind = pot->kind;
   j->precision = params->precision;
   j->n_traj = N;
   j->n_out = params->n_out;
   j->bytes = bytes;
   j->tile_n0_host = tile_n0;
-  JobDev& H = j->host;
   // fast range of the screened potential: 2^-1000 <= r^2 <= 2^999 and 0 <= a <= 2^999 keep r^2
   // and r^2 + a within the square root's core range
   const double r2_fast = (pot->kind == SFHK_POT_SCREENED && pot->soft2 >= 0.0 && pot->soft2 <= 0x1p999)
@@ -406,40 +433,24 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   H.n_tiles = n_tiles;
   H.n_pad = n_pad;
 
-  auto cleanup = [&](sfhk_status s) {
-    (void)hipEventRecord(j->last_use, st);  // copies already issued on st finish before the frees
-    job_free(j);
-    (void)hipEventDestroy(j->last_use);
-    {
-      std::lock_guard<std::mutex> lk(ctx->mu);
-      ctx->in_use -= bytes;
-    }
-    delete j;
-    return s;
-  };
-  sfhk_status rc;
   double* e_half = nullptr;
   if ((rc = job_alloc(j, &e_half, 2 * (size_t)NS + 1, st)) || (rc = job_alloc(j, &H.y, (size_t)n_pad * kNY, st)) ||
-      (rc = job_alloc(j, &H.aux, (size_t)n_pad * 5, st)) || (rc = job_alloc(j, &H.n0, (size_t)n_pad, st)) ||
-      (rc = job_alloc(j, &H.death, (size_t)n_pad, st)) || (rc = job_alloc(j, &H.tile_n0, (size_t)n_tiles, st)) ||
+      (rc = job_alloc(j, &H.aux, (size_t)n_pad * 5, st)) || (rc = job_alloc(j, &H.death, (size_t)n_pad, st)) ||
       (rc = job_alloc(j, &H.tile_next, (size_t)n_tiles, st)) || (rc = job_alloc(j, &H.tile_last, (size_t)n_tiles, st)) ||
       (rc = job_alloc(j, &H.row_off, (size_t)n_tiles, st)) || (rc = job_alloc(j, &H.part, (size_t)part_elems, st)) ||
-      (rc = job_alloc(j, &H.counters, 8, st)) || (rc = job_alloc(j, &j->perm, (size_t)n_pad, st)) ||
-      (rc = job_alloc(j, &j->work, (size_t)n_tiles, st)) ||
+      (rc = job_alloc(j, &H.counters, 8, st)) || (rc = job_alloc(j, &j->work, (size_t)n_tiles, st)) ||
       (rc = job_alloc(j, &j->dbuf, (size_t)NS + 1, st)) ||
       (rc = job_alloc(j, &j->gsum, (size_t)((n_tiles + kReduceGroup - 1) / kReduceGroup) * (NS + 1), st)) ||
       (rc = job_alloc(j, &j->dev, 1, st)))
     return cleanup(rc);
+  if (!in_order && (rc = job_alloc(j, &j->perm, (size_t)n_pad, st))) return cleanup(rc);
   H.e_half = e_half;
-#define TRY_C(expr)                                                              \
-  do {                                                                           \
-    hipError_t e_ = (expr);                                                      \
-    if (e_ != hipSuccess) return cleanup(fail(SFHK_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_))); \
-  } while (0)
   TRY_C(hipMemcpyAsync(e_half, grid->e_half, (2 * (size_t)NS + 1) * sizeof(double), hipMemcpyDeviceToDevice, st));
-  TRY_C(hipMemcpyAsync(j->perm, perm.data(), n_pad * sizeof(long long), hipMemcpyHostToDevice, st));
-  TRY_C(hipMemcpyAsync(H.n0, n0s.data(), n_pad * sizeof(int), hipMemcpyHostToDevice, st));
-  TRY_C(hipMemcpyAsync(H.tile_n0, tile_n0.data(), n_tiles * sizeof(int), hipMemcpyHostToDevice, st));
+  if (!in_order) {  // the sorted order replaces the caller order k_birth wrote
+    TRY_C(hipMemcpyAsync(j->perm, perm.data(), n_pad * sizeof(long long), hipMemcpyHostToDevice, st));
+    TRY_C(hipMemcpyAsync(H.n0, n0s.data(), n_pad * sizeof(int), hipMemcpyHostToDevice, st));
+    TRY_C(hipMemcpyAsync(H.tile_n0, tile_n0.data(), n_tiles * sizeof(int), hipMemcpyHostToDevice, st));
+  }
   TRY_C(hipMemcpyAsync(H.tile_next, tile_next.data(), n_tiles * sizeof(int), hipMemcpyHostToDevice, st));
   TRY_C(hipMemcpyAsync(H.tile_last, tile_last.data(), n_tiles * sizeof(int), hipMemcpyHostToDevice, st));
   TRY_C(hipMemcpyAsync(H.row_off, row_off.data(), n_tiles * sizeof(long long), hipMemcpyHostToDevice, st));

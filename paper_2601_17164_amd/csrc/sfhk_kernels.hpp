@@ -143,13 +143,43 @@ __device__ __noinline__ Contrib contribution(const GtoConst* __restrict__ G, dou
 // ------------------------------------------------------------------------------------------------
 // initialisation: gather the sorted samples into the SoA state
 // ------------------------------------------------------------------------------------------------
+// birth step of sample i: the nearest grid step to t0, ties to the lower one (u = (t0 - t_a)/h,
+// n0 = ceil(u - 1/2), clamped to 0..n_steps)
+__device__ __forceinline__ int birth_step(double t, double t_a, double h, int n_steps) {
+  double nn = ceil((t - t_a) / h - 0.5);
+  if (!(nn >= 0.0)) nn = 0.0;
+  if (nn > (double)n_steps) nn = (double)n_steps;
+  return (int)nn;
+}
+
+// Birth steps of the samples in caller order (n_steps + 1 on padding slots), each tile's first
+// birth step, and two flags for the host: flags[0] = smallest index whose t0 lies outside
+// [t_lo, t_hi] (all ones if none), flags[1] != 0 if the birth steps are not non-decreasing.
+__global__ void k_birth(const double* __restrict__ t0, long long n_traj, long long n_pad,
+                        double t_a, double h, double t_lo, double t_hi, int n_steps,
+                        int* __restrict__ n0, int* __restrict__ tile_n0,
+                        unsigned long long* __restrict__ flags) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pad) return;
+  int b = n_steps + 1;
+  if (i < n_traj) {
+    const double t = t0[i];
+    if (!(t >= t_lo && t <= t_hi)) atomicMin(&flags[0], (unsigned long long)i);
+    b = birth_step(t, t_a, h, n_steps);
+    if (i > 0 && birth_step(t0[i - 1], t_a, h, n_steps) > b) atomicOr(&flags[1], 1ull);
+  }
+  n0[i] = b;
+  if ((i % kTile) == 0) tile_n0[i / kTile] = b;
+}
+
+// perm == nullptr: slot s holds sample s (samples already in birth order), padding beyond n_traj
 __global__ void k_init(JobDev J, const long long* __restrict__ perm, long long n_traj,
                        const double* __restrict__ q0, const double* __restrict__ p0,
                        const double* __restrict__ w) {
   long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= J.n_pad) return;
   long long np = J.n_pad;
-  long long o = perm[s];
+  long long o = perm ? perm[s] : (s < n_traj ? s : -1);
   double* y = J.y;
   double q[3] = {0, 0, 0}, p[3] = {0, 0, 0}, wr = 0.0, wi = 0.0;
   if (o >= 0) {
@@ -735,7 +765,7 @@ __global__ void k_scatter_traj(JobDev J, const long long* __restrict__ perm, lon
                                long long* __restrict__ death_out) {
   long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= J.n_pad) return;
-  long long o = perm[s];
+  long long o = perm ? perm[s] : (s < n_traj ? s : -1);
   if (o < 0) return;
   if (y_out)
     for (int c = 0; c < kNY; ++c) y_out[c * n_traj + o] = J.y[c * J.n_pad + s];
