@@ -1,6 +1,6 @@
 // sfhk.hip -- host runtime of the SFHK hot path (gfx950) behind include/sfhk.h: contexts, jobs,
-// launches, batches (graph capture), dipole and spectrum calls. The kernels and the device data
-// layout are in sfhk_kernels.hpp.
+// launches, batches (graph capture), dipole and spectrum calls. The propagation kernels and the
+// device data layout are in sfhk_kernels.hpp, the kernels around them in sfhk_io_kernels.hpp.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -14,6 +14,7 @@
 
 #include "../../include/sfhk.h"
 #include "sfhk_kernels.hpp"
+#include "sfhk_io_kernels.hpp"
 
 namespace {
 
