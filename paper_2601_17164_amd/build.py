@@ -14,7 +14,9 @@ ARCH = os.environ.get("SFHK_OFFLOAD_ARCH", "gfx950")
 HIPCC_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
                "-ffp-contract=off", "-fno-fast-math", "-munsafe-fp-atomics",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-               "-Wno-unused-command-line-argument"]
+               "-Wno-unused-command-line-argument",
+               # roctx ranges around the host API calls
+               "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
 
 
 def build(verbose: bool = False, out: str = LIB, defines=()) -> str:

@@ -12,6 +12,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/sfhk.h"
 #include "sfhk_kernels.hpp"
 #include "sfhk_io_kernels.hpp"
@@ -32,6 +34,15 @@ sfhk_status fail(sfhk_status s, const std::string& msg) {
       return fail(e_ == hipErrorOutOfMemory ? SFHK_E_NOMEM : SFHK_E_DEVICE,            \
                   std::string(#expr) + ": " + hipGetErrorString(e_));                  \
   } while (0)
+
+// a roctx range around a host API call (visible with rocprofv3 --marker-trace; a few nanoseconds
+// when no profiler is attached)
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 }  // namespace
 
@@ -268,6 +279,7 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
                             const sfhk_grid* grid, const sfhk_params* params, int64_t n_traj,
                             const double* t0, const double* q0, const double* p0, const double* w,
                             void* stream, sfhk_job** out) {
+  TraceRange trace_("sfhk_job_create");
   if (!ctx || !pot || !ground || !grid || !params || !t0 || !q0 || !p0 || !out)
     return fail(SFHK_E_INVALID, "NULL argument");
   if (!(params->gamma > 0.0)) return fail(SFHK_E_INVALID, "gamma must be > 0");
@@ -497,6 +509,7 @@ static int unfinished_tiles(const sfhk_job* j, long long done) {
 }
 
 sfhk_status sfhk_propagate(sfhk_job* job, int64_t max_steps, void* stream) {
+  TraceRange trace_("sfhk_propagate");
   if (!job) return fail(SFHK_E_INVALID, "job is NULL");
   if (job->done) return SFHK_OK;
   HIP_TRY(hipSetDevice(job->ctx->device));
@@ -518,6 +531,7 @@ sfhk_status sfhk_propagate(sfhk_job* job, int64_t max_steps, void* stream) {
 }
 
 sfhk_status sfhk_propagate_many(sfhk_job* const* jobs, int32_t n_jobs, int64_t max_steps, void* stream) {
+  TraceRange trace_("sfhk_propagate_many");
   if (!jobs || n_jobs < 0) return fail(SFHK_E_INVALID, "bad job list");
   if (n_jobs == 0) return SFHK_OK;
   sfhk_ctx* ctx = jobs[0] ? jobs[0]->ctx : nullptr;
@@ -697,6 +711,7 @@ sfhk_status sfhk_batch_create(sfhk_ctx* ctx, int32_t max_jobs, int64_t max_tiles
 }
 
 sfhk_status sfhk_batch_set_jobs(sfhk_batch* b, sfhk_job* const* jobs, int32_t n_jobs, void* stream) {
+  TraceRange trace_("sfhk_batch_set_jobs");
   if (!b || (!jobs && n_jobs > 0) || n_jobs < 0) return fail(SFHK_E_INVALID, "bad batch or job list");
   if (n_jobs > b->max_jobs) return fail(SFHK_E_INVALID, "more jobs than the batch was created for");
   for (int i = 0; i < n_jobs; ++i)
@@ -744,6 +759,7 @@ sfhk_status sfhk_batch_set_jobs(sfhk_batch* b, sfhk_job* const* jobs, int32_t n_
 }
 
 sfhk_status sfhk_batch_run(sfhk_batch* b, void* stream) {
+  TraceRange trace_("sfhk_batch_run");
   if (!b) return fail(SFHK_E_INVALID, "batch is NULL");
   HIP_TRY(hipSetDevice(b->ctx->device));
   if (!b->staged || b->jobs.empty()) return SFHK_OK;
@@ -769,6 +785,7 @@ int32_t sfhk_batch_workers(const sfhk_batch* b) { return b ? b->n_workers : 0; }
 int32_t sfhk_job_is_done(const sfhk_job* job) { return job && job->done ? 1 : 0; }
 
 sfhk_status sfhk_dipole(sfhk_job* job, double* d_out, double* f_out, void* stream) {
+  TraceRange trace_("sfhk_dipole");
   if (!job || !d_out) return fail(SFHK_E_INVALID, "NULL argument");
   if (!job->done) return fail(SFHK_E_NOT_DONE, "job is not finished");
   HIP_TRY(hipSetDevice(job->ctx->device));
@@ -793,6 +810,7 @@ sfhk_status sfhk_dipole(sfhk_job* job, double* d_out, double* f_out, void* strea
 sfhk_status sfhk_spectrum(const double* d, int64_t n, double t_first, double dt, double tau_h,
                           int64_t n_fft, double* omega_out, double* power_out, double* x_out,
                           void* stream) {
+  TraceRange trace_("sfhk_spectrum");
   if (n_fft == 0) n_fft = n;
   if (!d || n < 1 || n_fft < n || n_fft > (1LL << 31) || !(dt > 0.0) || !(tau_h > 0.0))
     return fail(SFHK_E_INVALID, "spectrum: need d, 1 <= n <= n_fft <= 2^31, dt > 0, tau_h > 0");
