@@ -197,6 +197,21 @@ int32_t sfhk_job_is_done(const sfhk_job* job);
 /* Number of points sfhk_dipole writes to d_out. */
 int64_t sfhk_job_n_out(const sfhk_job* job);
 
+/* Checkpoint and restore of a job's propagation state, for suspending a job (for instance to free
+ * its HBM) and resuming it later: the trajectory state, removal steps, per-tile progress, partial
+ * rows, counters and the number of steps requested so far.
+ * sfhk_job_checkpoint_bytes: size of a checkpoint of this job.
+ * sfhk_job_checkpoint: writes it to dst (DEVICE, checkpoint_bytes, caller-owned) on `stream` and
+ *   returns once the copies have completed. Errors: SFHK_E_INVALID (NULL), SFHK_E_DEVICE.
+ * sfhk_job_restore: loads a checkpoint into `job`, which must have been created from the same
+ *   inputs (same shape, potential kind and precision) and not propagated; propagation then
+ *   continues exactly as the checkpointed job would have (bit for bit). Reads the header
+ *   synchronously, copies the state asynchronously on `stream`. Errors: SFHK_E_INVALID (NULL,
+ *   not a checkpoint, another job's shape, a job already propagated), SFHK_E_DEVICE. */
+int64_t sfhk_job_checkpoint_bytes(const sfhk_job* job);
+sfhk_status sfhk_job_checkpoint(sfhk_job* job, void* dst, void* stream);
+sfhk_status sfhk_job_restore(sfhk_job* job, const void* src, void* stream);
+
 /* Hann-windowed Fourier transform (App. D): with t_n = t_first + n dt and d zero-padded to
  * n_fft samples (n_fft = 0: n),
  *   X_k = dt sum_n d_n W_H(t_n) exp(i omega_k t_n),  W_H(t) = (1 + cos(pi t / tau_h)) / 2 for

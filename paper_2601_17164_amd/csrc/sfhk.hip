@@ -83,6 +83,7 @@ struct sfhk_job {
   hipEvent_t last_use = nullptr;  // recorded after every piece of work issued on the job
   std::vector<int> tile_n0_host;
   long long steps_done = 0;    // steps requested so far (uniform across tiles)
+  long long part_elems = 0;    // complex entries of the partial rows
   bool done = false;
 };
 
@@ -197,6 +198,41 @@ sfhk_status launch_propagate(int precision, int kind, const JobDev* descs, const
 }
 
 int segment_of(int precision, int kind) { return (precision == SFHK_FP32_MIXED ? kKinds : 0) + kind; }
+
+}  // namespace
+
+namespace {
+
+constexpr uint64_t kCkptMagic = 0x54504b434b484653ull;  // "SFHKCKPT"
+constexpr size_t kCkptAlign = 256;
+
+struct CkptHeader {
+  uint64_t magic;
+  int64_t n_traj, n_pad, n_tiles, n_steps, part_elems, steps_done;
+  int32_t kind, precision, done, reserved;
+};
+static_assert(sizeof(CkptHeader) <= kCkptAlign, "checkpoint header");
+
+size_t ckpt_round(size_t b) { return (b + kCkptAlign - 1) / kCkptAlign * kCkptAlign; }
+
+// (device pointer of the job, bytes) of every section after the header, in checkpoint order
+std::vector<std::pair<void*, size_t>> ckpt_sections(sfhk_job* j) {
+  const JobDev& H = j->host;
+  const size_t np = (size_t)H.n_pad, nt = (size_t)H.n_tiles;
+  return {{H.y, np * kNY * sizeof(double)},
+          {H.aux, np * 5 * sizeof(double)},
+          {H.death, np * sizeof(int)},
+          {H.tile_next, nt * sizeof(int)},
+          {H.tile_last, nt * sizeof(int)},
+          {H.counters, 8 * sizeof(unsigned long long)},
+          {H.part, (size_t)j->part_elems * sizeof(double2)}};
+}
+
+size_t ckpt_bytes(sfhk_job* j) {
+  size_t b = kCkptAlign;
+  for (const auto& sec : ckpt_sections(j)) b += ckpt_round(sec.second);
+  return b;
+}
 
 }  // namespace
 
@@ -405,6 +441,7 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   j->n_out = params->n_out;
   j->bytes = bytes;
   j->tile_n0_host = tile_n0;
+  j->part_elems = part_elems;
   // fast range of the screened potential: 2^-1000 <= r^2 <= 2^999 and 0 <= a <= 2^999 keep r^2
   // and r^2 + a within the square root's core range
   const double r2_fast = (pot->kind == SFHK_POT_SCREENED && pot->soft2 >= 0.0 && pot->soft2 <= 0x1p999)
@@ -873,6 +910,68 @@ sfhk_status sfhk_job_trajectories(sfhk_job* job, double* y_out, double* c_out, i
                      (long long*)death_out);
   HIP_TRY(hipGetLastError());
   return mark_use(job, st);
+}
+
+// ------------------------------------------------------------------------------------------------
+// checkpoint / restore of a job's propagation state
+// ------------------------------------------------------------------------------------------------
+
+int64_t sfhk_job_checkpoint_bytes(const sfhk_job* job) {
+  return job ? (int64_t)ckpt_bytes(const_cast<sfhk_job*>(job)) : 0;
+}
+
+sfhk_status sfhk_job_checkpoint(sfhk_job* job, void* dst, void* stream) {
+  if (!job || !dst) return fail(SFHK_E_INVALID, "NULL argument");
+  HIP_TRY(hipSetDevice(job->ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  CkptHeader h{};
+  h.magic = kCkptMagic;
+  h.n_traj = job->n_traj;
+  h.n_pad = job->host.n_pad;
+  h.n_tiles = job->host.n_tiles;
+  h.n_steps = job->host.n_steps;
+  h.part_elems = job->part_elems;
+  h.steps_done = job->steps_done;
+  h.kind = job->kind;
+  h.precision = job->precision;
+  h.done = job->done ? 1 : 0;
+  char* out = (char*)dst;
+  HIP_TRY(hipMemcpyAsync(out, &h, sizeof(h), hipMemcpyHostToDevice, st));
+  size_t off = kCkptAlign;
+  for (const auto& sec : ckpt_sections(job)) {
+    HIP_TRY(hipMemcpyAsync(out + off, sec.first, sec.second, hipMemcpyDeviceToDevice, st));
+    off += ckpt_round(sec.second);
+  }
+  sfhk_status rc = mark_use(job, st);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(st));  // the header above lives on this call's stack
+  return SFHK_OK;
+}
+
+sfhk_status sfhk_job_restore(sfhk_job* job, const void* src, void* stream) {
+  if (!job || !src) return fail(SFHK_E_INVALID, "NULL argument");
+  if (job->steps_done != 0) return fail(SFHK_E_INVALID, "restore needs a job that has not been propagated");
+  HIP_TRY(hipSetDevice(job->ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  CkptHeader h{};
+  const char* in = (const char*)src;
+  HIP_TRY(hipMemcpyAsync(&h, in, sizeof(h), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (h.magic != kCkptMagic || h.n_traj != job->n_traj || h.n_pad != job->host.n_pad ||
+      h.n_tiles != job->host.n_tiles || h.n_steps != job->host.n_steps ||
+      h.part_elems != job->part_elems || h.kind != job->kind || h.precision != job->precision ||
+      h.steps_done < 0)
+    return fail(SFHK_E_INVALID, "checkpoint does not match this job (other inputs or not a checkpoint)");
+  size_t off = kCkptAlign;
+  for (const auto& sec : ckpt_sections(job)) {
+    HIP_TRY(hipMemcpyAsync(sec.first, in + off, sec.second, hipMemcpyDeviceToDevice, st));
+    off += ckpt_round(sec.second);
+  }
+  sfhk_status rc = mark_use(job, st);
+  if (rc) return rc;
+  job->steps_done = h.steps_done;
+  job->done = h.done != 0;
+  return SFHK_OK;
 }
 
 static sfhk_status traj_fn(int which, const double* x, double* y, int64_t n, void* stream) {

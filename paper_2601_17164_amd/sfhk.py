@@ -77,6 +77,9 @@ _SIGS = {
     "sfhk_dipole": (ct.c_int, [_VP, _VP, _VP, _VP]),
     "sfhk_job_n_out": (ct.c_int64, [_VP]),
     "sfhk_job_is_done": (ct.c_int32, [_VP]),
+    "sfhk_job_checkpoint_bytes": (ct.c_int64, [_VP]),
+    "sfhk_job_checkpoint": (ct.c_int, [_VP, _VP, _VP]),
+    "sfhk_job_restore": (ct.c_int, [_VP, _VP, _VP]),
     "sfhk_spectrum": (ct.c_int, [_VP, ct.c_int64, ct.c_double, ct.c_double, ct.c_double,
                                  ct.c_int64, _VP, _VP, _VP, _VP]),
     "sfhk_job_stats": (ct.c_int, [_VP, ct.POINTER(_Stats), _VP]),
@@ -245,6 +248,21 @@ class Job:
         return Stats(s.n_traj, s.n_steps, s.steps_evaluated, s.steps_fp64, s.kay_removed,
                      s.nonfinite_removed, s.tiles_total, s.tiles_done,
                      s.prims_evaluated)
+
+    def checkpoint(self, stream=None) -> torch.Tensor:
+        """The job's propagation state as a device byte tensor (sfhk_job_checkpoint)."""
+        n = int(lib().sfhk_job_checkpoint_bytes(self.handle))
+        buf = torch.empty(n, dtype=torch.uint8, device=f"cuda:{self.ctx.device}")
+        _check(lib().sfhk_job_checkpoint(self.handle, _dptr(buf), _stream_ptr(stream)),
+               "sfhk_job_checkpoint")
+        return buf
+
+    def restore(self, checkpoint: torch.Tensor, stream=None):
+        """Load a checkpoint taken from a job of the same inputs (sfhk_job_restore)."""
+        if checkpoint.dtype != torch.uint8 or not checkpoint.is_cuda:
+            raise ValueError("checkpoint must be a device uint8 tensor")
+        _check(lib().sfhk_job_restore(self.handle, _dptr(checkpoint), _stream_ptr(stream)),
+               "sfhk_job_restore")
 
     def trajectories(self, stream=None):
         dev = torch.device("cuda", self.ctx.device)

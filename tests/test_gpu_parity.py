@@ -333,3 +333,40 @@ def test_cancel_mid_job_releases_its_memory(S):
     r = run_oracle(inst)
     g = _gpu_run(S, inst)
     _assert_parity("after-cancel", g, r)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_checkpoint_restore_resumes_bitwise(S, precision):
+    """Suspend a job mid-pulse (checkpoint, destroy), restore the checkpoint into a new job made
+    from the same inputs and finish it: final states and the dipole equal an uninterrupted run bit
+    for bit. A checkpoint of another shape, or a job already propagated, is refused."""
+    sfhk, ctx, torch = S
+    inst = I.config0(n_birth=16, n_per_birth=32)
+    ref = _gpu_run(S, inst, precision=precision)
+    a = sfhk.make_job(ctx, inst, precision=precision)
+    assert not a.propagate(700)
+    ck = a.checkpoint()
+    a.close()
+    b = sfhk.make_job(ctx, inst, precision=precision)
+    b.restore(ck)
+    while not b.propagate(500):
+        pass
+    d, f = b.dipole(want_f=True)
+    y, c, death = b.trajectories()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(d.cpu().numpy(), ref["d"])
+    np.testing.assert_array_equal(y.cpu().numpy(), ref["y"])
+    np.testing.assert_array_equal(death.cpu().numpy(), ref["death"])
+    assert b.stats().steps_evaluated == ref["stats"].steps_evaluated
+    b.close()
+    other = sfhk.make_job(ctx, I.config0(n_birth=8, n_per_birth=32), precision=precision)
+    with pytest.raises(sfhk.SfhkError) as ei:
+        other.restore(ck)
+    assert ei.value.status == sfhk.SFHK_E_INVALID
+    other.close()
+    used = sfhk.make_job(ctx, inst, precision=precision)
+    used.propagate(10)
+    with pytest.raises(sfhk.SfhkError) as ei:
+        used.restore(ck)
+    assert ei.value.status == sfhk.SFHK_E_INVALID
+    used.close()
