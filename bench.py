@@ -170,6 +170,7 @@ def serving_run(ctx, rate, n_req, warmup, precision, chunk, reqs=None, verbose=F
     summ = serve.summarize(kept)
     summ.update({"offered_rate": rate, "served_rate": len(kept) / summ["span_s"],
                  "precision": "fp32_mixed" if precision else "fp64", "chunk": chunk})
+    summ.update(srv.stats)
     if verbose:
         print(json.dumps(summ), flush=True)
     return summ

@@ -81,6 +81,9 @@ class Server:
         self.keep = keep_results
         self.max_jobs, self.max_tiles = max_jobs, max_tiles
         self.batch = sfhk.Batch(ctx, max_jobs, max_tiles, chunk, workers_per_cu)
+        # occupancy of the last run: replays issued, requests in the batch and waiting for
+        # admission (sampled at each replay)
+        self.stats = {}
 
     def close(self):
         self.batch.close()
@@ -97,6 +100,7 @@ class Server:
         finishing: List[_Finishing] = []
         results: List[Result] = []
         tiles_active = 0
+        replays, active_sum, active_max, queued_max = 0, 0, 0, 0
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0
 
@@ -144,6 +148,10 @@ class Server:
                 # waits only for the replay before the one in flight
                 self.batch.set_jobs([a.job for a in active], stream=comp)
                 self.batch.run(stream=comp)
+                replays += 1
+                active_sum += len(active)
+                active_max = max(active_max, len(active))
+                queued_max = max(queued_max, len(queue))
                 still = []
                 with torch.cuda.stream(comp):
                     for a in active:
@@ -176,6 +184,8 @@ class Server:
             elif pending:
                 time.sleep(max(0.0, min(0.05, pending[0].arrival - now())))
         comp.synchronize()
+        self.stats = {"replays": replays, "mean_active": active_sum / max(1, replays),
+                      "max_active": active_max, "max_queued": queued_max}
         return sorted(results, key=lambda r: r.req_id)
 
 
