@@ -84,6 +84,52 @@ __device__ __forceinline__ bool overlap_all_skipped(const GtoConst& G, double p2
   return SFHK_FMA(p2, G.Amin, q2 * G.Bmin) > G.cut_hi;
 }
 
+// sin and cos of x for the dipole integrand (held to the oracle at a relative tolerance, not bit
+// for bit). Reduction x = n pi/2 + r with the two-part constant pi/2 = C1 + C2 and fused
+// multiply-adds (|r| <= pi/4, error ~|n| 1e-33), Taylor polynomials in r^2 to degree 15 (sin) and
+// 16 (cos), truncation below 5e-17, then the quadrant. Arguments beyond 1e9 go to the library.
+struct InvFactorials17 {
+  double v[18];
+  constexpr InvFactorials17() : v() {
+    double f = 1.0;
+    for (int n = 0; n < 18; ++n) {
+      if (n > 0) f *= (double)n;  // n! is exact in binary64 for n <= 18
+      v[n] = 1.0 / f;
+    }
+  }
+};
+constexpr InvFactorials17 kInvFact17{};
+
+__device__ __forceinline__ void sincos_integrand(double x, double* sp, double* cp) {
+  constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
+  constexpr double kC1 = 0x1.921fb54442d18p+0;   // pi/2 rounded to binary64
+  constexpr double kC2 = 0x1.1a62633145c07p-54;  // pi/2 - kC1 rounded
+  const double n = rint(x * kTwoOverPi);
+  double r = SFHK_FMA(-n, kC1, x);
+  r = SFHK_FMA(-n, kC2, r);
+  const double r2 = r * r;
+  // sin r = r (1 - r^2/3! + r^4/5! - ...), cos r = 1 - r^2/2! + r^4/4! - ...
+  double ps = -kInvFact17.v[15];
+#pragma unroll
+  for (int k = 13; k >= 3; k -= 2) ps = SFHK_FMA(ps, r2, (k % 4 == 1) ? kInvFact17.v[k] : -kInvFact17.v[k]);
+  const double sr = SFHK_FMA(ps * r2, r, r);
+  double pc = kInvFact17.v[16];
+#pragma unroll
+  for (int k = 14; k >= 2; k -= 2) pc = SFHK_FMA(pc, r2, (k % 4 == 0) ? kInvFact17.v[k] : -kInvFact17.v[k]);
+  const double cr = SFHK_FMA(pc, r2, 1.0);
+  const int q = (int)n & 3;
+  double s = (q & 1) ? cr : sr;
+  double c = (q & 1) ? sr : cr;
+  s = (q & 2) ? -s : s;
+  c = ((q + 1) & 2) ? -c : c;
+  const bool big = !(fabs(x) <= 1e9);
+  if (__builtin_expect(__any(big), 0)) {
+    if (big) sincos(x, &s, &c);
+  }
+  *sp = s;
+  *cp = c;
+}
+
 __device__ __forceinline__ cplx overlap(const GtoConst& G, double cut, const double* q,
                                         const double* p, double p2, double q2,
                                         unsigned int& n_eval) {
@@ -96,9 +142,9 @@ __device__ __forceinline__ cplx overlap(const GtoConst& G, double cut, const dou
     if (re >= -cut) {
       ++n_eval;
       double im = -(pq * G.D[j]);
-      double e = exp(re) * G.N[j];
+      double e = exp_cw_nonpos(re) * G.N[j];  // re <= 0
       double s, c;
-      sincos(im, &s, &c);
+      sincos_integrand(im, &s, &c);
       cplx E = {e * c, e * s};
       if (G.l == 0) {
         sum.re += E.re;
@@ -133,7 +179,7 @@ __device__ __noinline__ Contrib contribution(const GtoConst* __restrict__ G, dou
   if (O.re != 0.0 || O.im != 0.0) {
     const double ph = S - G->ip * tn;
     double sp, cp;
-    sincos(ph, &sp, &cp);
+    sincos_integrand(ph, &sp, &cp);
     const cplx f = cmul(cplx{wcr, wci}, cmul(O, cplx{cp, sp}));
     r.re = f.re;
     r.im = f.im;
