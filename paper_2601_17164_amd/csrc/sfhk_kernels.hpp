@@ -86,19 +86,22 @@ __device__ __forceinline__ bool overlap_all_skipped(const GtoConst& G, double p2
 
 // sin and cos of x for the dipole integrand (held to the oracle at a relative tolerance, not bit
 // for bit). Reduction x = n pi/2 + r with the two-part constant pi/2 = C1 + C2 and fused
-// multiply-adds (|r| <= pi/4, error ~|n| 1e-33), Taylor polynomials in r^2 to degree 15 (sin) and
-// 16 (cos), truncation below 5e-17, then the quadrant. Arguments beyond 1e9 go to the library.
-struct InvFactorials17 {
-  double v[18];
-  constexpr InvFactorials17() : v() {
+// multiply-adds (|r| <= pi/4, error about |n| 2e-33), Taylor polynomials in r^2 to degree 13 (sin)
+// and 14 (cos), truncation below 3e-14, then the quadrant. Accurate for |x| < 2^52; beyond that,
+// and for a NaN or an infinity, both are NaN. The integrand's arguments stay far below: an evaluated primitive has
+// p^2 A_j + q^2 B_j <= overlap_cut, so |p.q| <= overlap_cut / sqrt(A_min B_min), and the phase
+// S - Ip t is an action of order 10^4 at most.
+struct InvFactorials14 {
+  double v[15];
+  constexpr InvFactorials14() : v() {
     double f = 1.0;
-    for (int n = 0; n < 18; ++n) {
+    for (int n = 0; n < 15; ++n) {
       if (n > 0) f *= (double)n;  // n! is exact in binary64 for n <= 18
       v[n] = 1.0 / f;
     }
   }
 };
-constexpr InvFactorials17 kInvFact17{};
+constexpr InvFactorials14 kInvFact14{};
 
 __device__ __forceinline__ void sincos_integrand(double x, double* sp, double* cp) {
   constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
@@ -109,25 +112,22 @@ __device__ __forceinline__ void sincos_integrand(double x, double* sp, double* c
   r = SFHK_FMA(-n, kC2, r);
   const double r2 = r * r;
   // sin r = r (1 - r^2/3! + r^4/5! - ...), cos r = 1 - r^2/2! + r^4/4! - ...
-  double ps = -kInvFact17.v[15];
+  double ps = kInvFact14.v[13];
 #pragma unroll
-  for (int k = 13; k >= 3; k -= 2) ps = SFHK_FMA(ps, r2, (k % 4 == 1) ? kInvFact17.v[k] : -kInvFact17.v[k]);
+  for (int k = 11; k >= 3; k -= 2) ps = SFHK_FMA(ps, r2, (k % 4 == 1) ? kInvFact14.v[k] : -kInvFact14.v[k]);
   const double sr = SFHK_FMA(ps * r2, r, r);
-  double pc = kInvFact17.v[16];
+  double pc = -kInvFact14.v[14];
 #pragma unroll
-  for (int k = 14; k >= 2; k -= 2) pc = SFHK_FMA(pc, r2, (k % 4 == 0) ? kInvFact17.v[k] : -kInvFact17.v[k]);
+  for (int k = 12; k >= 2; k -= 2) pc = SFHK_FMA(pc, r2, (k % 4 == 0) ? kInvFact14.v[k] : -kInvFact14.v[k]);
   const double cr = SFHK_FMA(pc, r2, 1.0);
-  const int q = (int)n & 3;
+  const int q = (int)(n - 4.0 * floor(0.25 * n));  // n mod 4, exact for |n| < 2^53
   double s = (q & 1) ? cr : sr;
   double c = (q & 1) ? sr : cr;
   s = (q & 2) ? -s : s;
   c = ((q + 1) & 2) ? -c : c;
-  const bool big = !(fabs(x) <= 1e9);
-  if (__builtin_expect(__any(big), 0)) {
-    if (big) sincos(x, &s, &c);
-  }
-  *sp = s;
-  *cp = c;
+  const bool ok = fabs(x) < 0x1p52;  // beyond, and for NaN or infinity: NaN
+  *sp = ok ? s : __builtin_nan("");
+  *cp = ok ? c : __builtin_nan("");
 }
 
 __device__ __forceinline__ cplx overlap(const GtoConst& G, double cut, const double* q,
@@ -142,7 +142,7 @@ __device__ __forceinline__ cplx overlap(const GtoConst& G, double cut, const dou
     if (re >= -cut) {
       ++n_eval;
       double im = -(pq * G.D[j]);
-      double e = exp_cw_nonpos(re) * G.N[j];  // re <= 0
+      double e = exp(re) * G.N[j];
       double s, c;
       sincos_integrand(im, &s, &c);
       cplx E = {e * c, e * s};
