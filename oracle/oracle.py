@@ -60,6 +60,11 @@ class _Grid(ct.Structure):
                 ("e_half", ct.POINTER(ct.c_double))]
 
 
+class _Pulse(ct.Structure):
+    _fields_ = [("e0", ct.c_double), ("omega", ct.c_double), ("n_cycles", ct.c_double),
+                ("cep", ct.c_double)]
+
+
 class _Diag(ct.Structure):
     _fields_ = [("n0", ct.POINTER(ct.c_int64)), ("death", ct.POINTER(ct.c_int64)),
                 ("y_final", ct.POINTER(ct.c_double)), ("c_final", ct.POINTER(ct.c_double))]
@@ -83,6 +88,13 @@ def lib():
         L.or_exp_cw.argtypes = [D]
         L.or_rsqrt_c.restype = D
         L.or_rsqrt_c.argtypes = [D]
+        for nm in ("or_sin_cr", "or_cos_cr"):
+            getattr(L, nm).restype = D
+            getattr(L, nm).argtypes = [D]
+        L.or_sincos_c.argtypes = [D, P, P]
+        L.or_sfa_birth.restype = ct.c_int
+        L.or_sfa_birth.argtypes = [ct.POINTER(_Pulse), ct.POINTER(_Ground), ct.c_int32,
+                                   ct.c_int64, P, P, P, ct.c_int, P, P, P, P]
         for nm in ("or_field_A", "or_field_E", "or_field_intA"):
             getattr(L, nm).restype = D
             getattr(L, nm).argtypes = [D, D, D, D, D]
@@ -159,6 +171,49 @@ def exp_cw(x: float) -> float:
 def rsqrt_c(x: float) -> float:
     """The reciprocal square root of the trajectory arithmetic."""
     return lib().or_rsqrt_c(float(x))
+
+
+def sin_cr(x: float) -> float:
+    return lib().or_sin_cr(float(x))
+
+
+def cos_cr(x: float) -> float:
+    return lib().or_cos_cr(float(x))
+
+
+def sincos_c(x: float):
+    """The sine and cosine of the SFA saddle-point solve (Cody-Waite + Taylor, degree 17/18)."""
+    s, c = ct.c_double(), ct.c_double()
+    lib().or_sincos_c(float(x), ct.byref(s), ct.byref(c))
+    return s.value, c.value
+
+
+@dataclass
+class SfaBirth:
+    q0: np.ndarray   # [3, n]
+    p0: np.ndarray   # [3, n]
+    w: np.ndarray    # complex [n]
+    tt: np.ndarray   # [n] imaginary part of the saddle-point time
+
+
+def sfa_birth(e0, omega, n_cycles, cep, ground: "Ground", t0, kperp, u=None, mode=0,
+              n_threads=0) -> SfaBirth:
+    """SFA birth step (App. A saddle point and tunnel exit, App. B tunnelling element):
+    (t0, k_perp) -> (q0, p0, w, t_t); see ``or_sfa_birth`` in ``sfhk_oracle.h``."""
+    t0 = _f64(t0)
+    kperp = _f64(kperp).reshape(2, -1)
+    n = t0.shape[0]
+    assert kperp.shape[1] == n
+    uu = None if u is None else _f64(u)
+    q0, p0, w2, tt = np.zeros((3, n)), np.zeros((3, n)), np.zeros((2, n)), np.zeros(n)
+    g = ground.c()
+    pl = _Pulse(float(e0), float(omega), float(n_cycles), float(cep))
+    rc = lib().or_sfa_birth(ct.byref(pl), ct.byref(g), int(mode), n, _p(t0), _p(kperp),
+                            None if uu is None else _p(uu), int(n_threads), _p(q0), _p(p0),
+                            _p(w2), _p(tt))
+    if rc != 0:
+        raise ValueError(f"or_sfa_birth failed ({rc})")
+    return SfaBirth(q0, p0, w2[0] + 1j * w2[1], tt)
 
 
 def field_A(t, e0, omega, T, cep=0.0):

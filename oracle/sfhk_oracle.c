@@ -99,6 +99,59 @@ double or_rsqrt_c(double x) {
 }
 
 /* ------------------------------------------------------------------------------------------ */
+/* correctly rounded sine and cosine (binary128 evaluation rounded once; the reference the       */
+/* contract's sine and cosine below are checked against)                                        */
+/* ------------------------------------------------------------------------------------------ */
+double or_sin_cr(double x) { return (double)sinq((__float128)x); }
+double or_cos_cr(double x) { return (double)cosq((__float128)x); }
+
+/* ------------------------------------------------------------------------------------------ */
+/* sine and cosine of the rounding contract (saddle-point solve of the SFA birth step):        */
+/* Cody-Waite reduction x = k pi/2 + r, k = rint(x 2/pi), with pi/2 split as P1 + P2 + P3      */
+/* (P1, P2 truncated to 33 significant bits, so k P1 and k P2 are exact for |k| < 2^20; P3 the */
+/* rounded remainder), then sin r = r + r z Ps(z) and cos r = 1 + z Pc(z), z = r^2, with the    */
+/* Taylor coefficients (-1)^j / (2j+1)! (j = 1..8, degree 17) and (-1)^j / (2j)! (j = 1..9,      */
+/* degree 18) in Horner form with fused multiply-adds, and the quadrant k mod 4 selecting       */
+/* (+-sin r, +-cos r). |x| >= 2^20 and non-finite x give NaN.                                   */
+/* ------------------------------------------------------------------------------------------ */
+#define SINC_2_OVER_PI 0x1.45f306dc9c883p-1 /* 2/pi rounded to binary64 */
+#define SINC_PIO2_1 0x1.921fb544p+0         /* pi/2 truncated to 33 significant bits */
+#define SINC_PIO2_2 0x1.0b4611a6p-34        /* next 33 significant bits of pi/2 */
+#define SINC_PIO2_3 0x1.3198a2e037073p-69   /* pi/2 - P1 - P2 rounded to binary64 */
+
+void or_sincos_c(double x, double* s, double* c) {
+  if (!(fabs(x) < 0x1p20)) {
+    *s = NAN;
+    *c = NAN;
+    return;
+  }
+  /* 1/n!, n = 0..18, each the correctly rounded quotient (n! is exact in binary64) */
+  double inv_fact[19];
+  double f = 1.0;
+  for (int n = 0; n < 19; ++n) {
+    if (n > 0) f *= (double)n;
+    inv_fact[n] = 1.0 / f;
+  }
+  double k = rint(x * SINC_2_OVER_PI);
+  double r = fma(-k, SINC_PIO2_1, x);
+  r = fma(-k, SINC_PIO2_2, r);
+  r = fma(-k, SINC_PIO2_3, r);
+  double z = r * r;
+  double ps = inv_fact[17];
+  for (int j = 7; j >= 1; --j) ps = fma(ps, z, (j & 1) ? -inv_fact[2 * j + 1] : inv_fact[2 * j + 1]);
+  double pc = -inv_fact[18];
+  for (int j = 8; j >= 1; --j) pc = fma(pc, z, (j & 1) ? -inv_fact[2 * j] : inv_fact[2 * j]);
+  double sr = fma(r * z, ps, r);
+  double cr = fma(z, pc, 1.0);
+  switch ((int)((int64_t)k & 3)) {
+    case 0: *s = sr; *c = cr; break;
+    case 1: *s = cr; *c = -sr; break;
+    case 2: *s = -sr; *c = -cr; break;
+    default: *s = -cr; *c = sr; break;
+  }
+}
+
+/* ------------------------------------------------------------------------------------------ */
 /* laser field (Sec. II.B field equation with the sin^2 envelope; E = -dA/dt, App. A)          */
 /* ------------------------------------------------------------------------------------------ */
 double or_field_A(double t, double e0, double omega, double T, double cep) {
@@ -688,5 +741,243 @@ int or_spectrum(const double* d, int64_t n, double t_first, double dt, double ta
   free(xw);
   free(tc);
   free(ts);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* SFA birth step (App. A, saddle-point equation and tunnel exit; App. B tunnelling elements)   */
+/*                                                                                              */
+/* For a birth time t0 and a transverse momentum k_perp = (kx, ky), the saddle point            */
+/* t_s = t0 + i t_t of [k + A(t_s) - A(t0)]^2 / 2 + Ip = 0 fixes the longitudinal momentum k_z  */
+/* (App. A). With A along z the equation splits into Im A(t0 + i t_t) = +-kappa,                 */
+/* kappa = sqrt(2 Ip + k_perp^2), and k_z = A(t0) - Re A(t0 + i t_t). The pulse in              */
+/* product-to-sum form, A(t) = -K sum_m c_m sin(w_m t + cep), K = e0/(2 omega),                 */
+/* (w_m, c_m) = (omega, 1), (omega + W, 1/2), (omega - W, 1/2), W = omega / n_cycles, gives      */
+/*   Im A(t0 + i tau) = -K sum_m c_m cos(th_m) sinh(w_m tau),  th_m = w_m t0 + cep,              */
+/*   k_z  =  K sum_m c_m sin(th_m) (cosh(w_m t_t) - 1),                                         */
+/*   q0_z = Re int_{t_s}^{t0} A = -K sum_m (c_m / w_m) cos(th_m) (cosh(w_m t_t) - 1)            */
+/* (the tunnel exit of App. A; q0_x = q0_y = 0). Of the roots t_t > 0 the one nearest the real  */
+/* axis is taken: a march in steps of 1/(4 w_max) up to 512 steps finds the first point where   */
+/* |Im A| >= kappa, then 64 bisection steps on the sign of that crossing. No crossing: NaN.     */
+/* These numbers decide the trajectory's initial state, so they follow the rounding contract:   */
+/* exp_cw for sinh and cosh, sincos_c, rsqrt_c, one operation per step as written.              */
+/* ------------------------------------------------------------------------------------------ */
+static double sinh_c(double x) {
+  double e = or_exp_cw(x);
+  return 0.5 * (e - 1.0 / e);
+}
+
+/* cosh(x) - 1 = 2 sinh(x/2)^2 */
+static double coshm1_c(double x) {
+  double s = sinh_c(0.5 * x);
+  return 2.0 * (s * s);
+}
+
+typedef struct {
+  double om[3], S[3], C[3], K;
+} sfa_terms;
+
+static void sfa_setup(const or_pulse* pl, double t0, sfa_terms* a) {
+  double W = pl->omega / pl->n_cycles;
+  a->om[0] = pl->omega;
+  a->om[1] = pl->omega + W;
+  a->om[2] = pl->omega - W;
+  a->K = pl->e0 / (2.0 * pl->omega);
+  for (int m = 0; m < 3; ++m) or_sincos_c(a->om[m] * t0 + pl->cep, &a->S[m], &a->C[m]);
+}
+
+static double sfa_im_a(const sfa_terms* a, double tau) {
+  double s0 = sinh_c(a->om[0] * tau);
+  double s1 = sinh_c(a->om[1] * tau);
+  double s2 = sinh_c(a->om[2] * tau);
+  return -(a->K * (a->C[0] * s0 + 0.5 * (a->C[1] * s1 + a->C[2] * s2)));
+}
+
+#define SFA_MARCH 512
+#define SFA_BISECT 64
+
+/* returns 0 and (t_t, k_z, q0_z), or -1 when no crossing lies within the march */
+static int sfa_saddle(const or_pulse* pl, double ip, double t0, double kx, double ky, double* tt,
+                      double* kz, double* qz) {
+  sfa_terms a;
+  sfa_setup(pl, t0, &a);
+  double kap2 = 2.0 * ip + (kx * kx + ky * ky);
+  double kap = kap2 * or_rsqrt_c(kap2);
+  double dtau = 0.25 / a.om[1];
+  double lo = 0.0, hi = 0.0, ahi = 0.0;
+  int found = 0;
+  for (int k = 1; k <= SFA_MARCH; ++k) {
+    double tau = (double)k * dtau;
+    double v = sfa_im_a(&a, tau);
+    if (fabs(v) >= kap) {
+      hi = tau;
+      ahi = v;
+      found = 1;
+      break;
+    }
+    lo = tau;
+  }
+  if (!found) return -1;
+  int up = ahi >= 0.0; /* the crossing is at Im A = +kappa */
+  for (int it = 0; it < SFA_BISECT; ++it) {
+    double mid = lo + 0.5 * (hi - lo);
+    double v = sfa_im_a(&a, mid);
+    if ((up ? v : -v) < kap)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  double t = lo + 0.5 * (hi - lo);
+  double c0 = coshm1_c(a.om[0] * t);
+  double c1 = coshm1_c(a.om[1] * t);
+  double c2 = coshm1_c(a.om[2] * t);
+  *tt = t;
+  *kz = a.K * (a.S[0] * c0 + 0.5 * (a.S[1] * c1 + a.S[2] * c2));
+  *qz = -(a.K * (a.C[0] * c0 / a.om[0] + 0.5 * (a.C[1] * c1 / a.om[1] + a.C[2] * c2 / a.om[2])));
+  return 0;
+}
+
+/* the pulse at complex time, straight from its definition (weights only) */
+static double complex pulse_A(const or_pulse* pl, double complex t) {
+  double T = 2.0 * M_PI * pl->n_cycles / pl->omega;
+  double complex c = ccos(M_PI * t / T);
+  return -(pl->e0 / pl->omega) * c * c * csin(pl->omega * t + pl->cep);
+}
+
+static double complex pulse_E(const or_pulse* pl, double complex t) {
+  double T = 2.0 * M_PI * pl->n_cycles / pl->omega;
+  double complex c = ccos(M_PI * t / T);
+  return pl->e0 * c * c * ccos(pl->omega * t + pl->cep) -
+         (pl->e0 * M_PI / (pl->omega * T)) * csin(2.0 * M_PI * t / T) * csin(pl->omega * t + pl->cep);
+}
+
+/* Gauss-Legendre nodes and weights on [-1, 1] (Newton on P_n from the three-term recurrence) */
+#define SFA_GL 64
+static void gauss_legendre(int n, double* x, double* wt) {
+  for (int i = 0; i < n; ++i) {
+    double z = cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int j = 2; j <= n; ++j) {
+        double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-17) break;
+    }
+    x[i] = z;
+    wt[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+typedef struct {
+  const or_pulse* pl;
+  const or_ground* gs;
+  int mode;
+  int64_t lo, hi, n;
+  const double *t0, *kperp, *u;
+  double *q0, *p0, *w, *tt;
+  const double *glx, *glw;
+} sfa_job;
+
+static void sfa_one(const sfa_job* jb, int64_t j) {
+  const or_pulse* pl = jb->pl;
+  const or_ground* gs = jb->gs;
+  int64_t n = jb->n;
+  double t0 = jb->t0[j], kx = jb->kperp[j], ky = jb->kperp[n + j];
+  double u = jb->u ? jb->u[j] : 1.0 / (double)n;
+  double t = NAN, kz = NAN, qz = NAN;
+  double complex wj = NAN;
+  if (sfa_saddle(pl, gs->ip, t0, kx, ky, &t, &kz, &qz) == 0) {
+    double complex ts = t0 + I * t;
+    double complex a0 = pulse_A(pl, t0);
+    /* S_down = Ip t_s - int_{t_s}^{t0} v^2/2 dt'' along t'' = t0 + i tau: the integral is
+     * -i int_0^{t_t} v^2/2 dtau, v = (kx, ky, kz + A(t0 + i tau) - A(t0)) */
+    double complex integ = 0.0;
+    for (int i = 0; i < SFA_GL; ++i) {
+      double tau = 0.5 * t * (1.0 + jb->glx[i]);
+      double complex vz = kz + pulse_A(pl, t0 + I * tau) - a0;
+      integ += (0.5 * t * jb->glw[i]) * (0.5 * (kx * kx + ky * ky + vz * vz));
+    }
+    double complex S = gs->ip * ts + I * integ;
+    double complex kzs = kz + pulse_A(pl, ts) - a0; /* z component of k + A(t_s) - A(t0) */
+    double complex ez = pulse_E(pl, ts);
+    double complex ek = ez * kzs;                  /* E(t_s) . [k + A(t_s) - A(t0)] */
+    double complex amp;
+    if (jb->mode == 0) {
+      /* <k|z|psi0> with <k|r> = exp(-i k.r), the GTO integrals written out (App. B.1):
+       * s-wave -i (pi^{3/2}/2) k_z sum_j c_j a_j^{-5/2} e^{-k^2/(4 a_j)},
+       * p-wave (pi^{3/2}/4) sum_j c_j a_j^{-7/2} (2 a_j - k_z^2) e^{-k^2/(4 a_j)} */
+      double complex k2 = kx * kx + ky * ky + kzs * kzs;
+      double complex sum = 0.0;
+      for (int i = 0; i < gs->n_prim; ++i) {
+        double al = gs->alpha[i];
+        double complex e = cexp(-k2 / (4.0 * al));
+        if (gs->l == 0)
+          sum += gs->coef[i] * pow(al, -2.5) * e;
+        else
+          sum += gs->coef[i] * pow(al, -3.5) * (2.0 * al - kzs * kzs) * e;
+      }
+      double complex me = gs->l == 0 ? -I * (0.5 * pow(M_PI, 1.5)) * kzs * sum
+                                     : (0.25 * pow(M_PI, 1.5)) * sum;
+      /* Eq. A.2: -i sqrt(2 pi i / (E.k)) <k + A(t_s) - A(t0)| r.E(t_s) |psi0> e^{i S_down} */
+      amp = -I * csqrt(2.0 * M_PI * I / ek) * (ez * me) * cexp(I * S);
+    } else {
+      /* modified saddle-point form (App. B.2): e^{i S_down} / (E.k) */
+      amp = cexp(I * S) / ek;
+    }
+    /* birth weight of Eq. A.9: e^{i p0.q0} times the amplitude, p0.q0 = k_z q0_z */
+    wj = u * cexp(I * (kz * qz)) * amp;
+  }
+  jb->q0[j] = 0.0;
+  jb->q0[n + j] = 0.0;
+  jb->q0[2 * n + j] = qz;
+  jb->p0[j] = kx;
+  jb->p0[n + j] = ky;
+  jb->p0[2 * n + j] = kz;
+  jb->w[j] = creal(wj);
+  jb->w[n + j] = cimag(wj);
+  if (jb->tt) jb->tt[j] = t;
+}
+
+static void* sfa_worker(void* arg) {
+  sfa_job* jb = (sfa_job*)arg;
+  for (int64_t j = jb->lo; j < jb->hi; ++j) sfa_one(jb, j);
+  return NULL;
+}
+
+int or_sfa_birth(const or_pulse* pl, const or_ground* gs, int32_t mode, int64_t n,
+                 const double* t0, const double* kperp, const double* u, int n_threads,
+                 double* q0, double* p0, double* w, double* tt) {
+  if (n < 0 || !(pl->e0 > 0.0) || !(pl->omega > 0.0) || !(pl->n_cycles > 1.0) ||
+      !(gs->ip > 0.0) || (mode != 0 && mode != 1) || (gs->l != 0 && gs->l != 1))
+    return -1;
+  if (n == 0) return 0;
+  double glx[SFA_GL], glw[SFA_GL];
+  gauss_legendre(SFA_GL, glx, glw);
+  if (n_threads <= 0) n_threads = (int)sysconf(_SC_NPROCESSORS_ONLN);
+  if (n_threads < 1) n_threads = 1;
+  if (n < n_threads) n_threads = (int)n;
+  sfa_job* jobs = (sfa_job*)calloc((size_t)n_threads, sizeof(sfa_job));
+  pthread_t* th = (pthread_t*)calloc((size_t)n_threads, sizeof(pthread_t));
+  if (!jobs || !th) {
+    free(jobs);
+    free(th);
+    return -2;
+  }
+  for (int t = 0; t < n_threads; ++t) {
+    sfa_job jb = {pl, gs, mode, n * t / n_threads, n * (t + 1) / n_threads, n, t0, kperp, u,
+                  q0, p0, w, tt, glx, glw};
+    jobs[t] = jb;
+  }
+  for (int t = 1; t < n_threads; ++t) pthread_create(&th[t], NULL, sfa_worker, &jobs[t]);
+  sfa_worker(&jobs[0]);
+  for (int t = 1; t < n_threads; ++t) pthread_join(th[t], NULL);
+  free(jobs);
+  free(th);
   return 0;
 }

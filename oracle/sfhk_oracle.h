@@ -79,6 +79,14 @@ double or_exp_cw(double x);
  * and a refined final step; within one ulp of 1/sqrt(x). */
 double or_rsqrt_c(double x);
 
+/* Correctly rounded sine and cosine (binary128 evaluation rounded once). */
+double or_sin_cr(double x);
+double or_cos_cr(double x);
+/* Sine and cosine of the SFA birth step's saddle-point solve: Cody-Waite reduction by pi/2 in
+ * three parts, Taylor polynomials of degree 17 / 18, quadrant select; within about one ulp.
+ * |x| >= 2^20 or non-finite x gives NaN. */
+void or_sincos_c(double x, double* s, double* c);
+
 /* Laser field of a linearly polarised sin^2 pulse of total duration T centred at t = 0
  * (Sec. II.B, field equation; E = -dA/dt as in App. A):
  *   A(t) = -(E0/omega) cos^2(pi t/T) sin(omega t + cep) for |t| <= T/2, else 0. */
@@ -114,6 +122,27 @@ int or_trajectory(const or_potential* pot, const or_ground* gs, const or_hk* hk,
                   const or_grid* grid, double t0, const double q0[3], const double p0[3],
                   const double w[2], double* y_rec, double* c_rec, double* f_rec, double* o_rec,
                   double* det_rec, int8_t* alive_rec);
+
+/* Linearly polarised (z) sin^2 pulse, A(t) = -(e0/omega) cos^2(pi t/T) sin(omega t + cep) with
+ * T = 2 pi n_cycles / omega (Sec. II.B field; E = -dA/dt). */
+typedef struct {
+  double e0, omega, n_cycles, cep;
+} or_pulse;
+
+/* SFA birth step (App. A: saddle-point equation, tunnel exit, action under the barrier; App. B:
+ * tunnelling matrix elements). For each sample j with birth time t0[j] and transverse momentum
+ * kperp = [2][n] (kx, ky): the saddle point t_s = t0 + i t_t of [k + A(t_s) - A(t0)]^2/2 + Ip = 0
+ * nearest the real axis, with k = p0 = (kx, ky, k_z); the tunnel exit q0 = (0, 0,
+ * Re int_{t_s}^{t0} A); S_down = Ip t_s - int_{t_s}^{t0} [k + A - A(t0)]^2/2; and the weight
+ *   w = u e^{i p0.q0} (-i) sqrt(2 pi i / (E(t_s).k_s)) <k_s| r.E(t_s) |psi0> e^{i S_down}
+ * (mode 0, Eq. A.2 with the GTO element of App. B.1 and its constant written out), or
+ *   w = u e^{i p0.q0} e^{i S_down} / (E(t_s).k_s)   (mode 1, modified saddle point, App. B.2),
+ * k_s = k + A(t_s) - A(t0). u = [n] Monte-Carlo weights or NULL for 1/n. Outputs q0, p0 [3][n],
+ * w [2][n] (re, im), tt [n] (t_t; may be NULL). A sample whose saddle is not found gets NaN.
+ * Requires n_cycles > 1. Returns 0 or a negative error code. */
+int or_sfa_birth(const or_pulse* pulse, const or_ground* gs, int32_t mode, int64_t n,
+                 const double* t0, const double* kperp, const double* u, int n_threads,
+                 double* q0, double* p0, double* w, double* tt);
 
 /* d = -2 Re F on the step grid (Eq. 2 and App. C.1: "+ c.c." with a leading minus). */
 void or_dipole(const double* f, int64_t n_steps, double* d_out);

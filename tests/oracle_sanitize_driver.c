@@ -108,5 +108,27 @@ int main(void) {
   const double q[3] = {0.0, 0.0, 0.0};
   or_potential_eval(&scr, q, &V, g, H);
   printf("pieces %.17g det=(%.17g, %.17g) V0=%.17g\n", acc, det[0], det[1], V);
+  /* contract sine/cosine and the SFA birth step (a NaN, a sample without saddle, both modes) */
+  double sc = 0.0;
+  for (int i = 0; i < 8; ++i) {
+    double s, c;
+    or_sincos_c(xs[i] * 1e-300 + (double)i, &s, &c);
+    sc += (isfinite(s) ? s : 1.0) + (isfinite(c) ? c : 1.0) + or_sin_cr((double)i) + or_cos_cr((double)i);
+  }
+  const double e0 = sqrt(1e14 / 3.50944758e16), om = 45.5633525 / 800.0;
+  or_pulse pl = {e0, om, 2.0, 0.3};
+  enum { NB = 7 };
+  double bt0[NB] = {0.0, 10.0, -60.0, 25.0, NAN, 0.0, -100.0};
+  double kp[2 * NB] = {0.0, 0.1, 0.3, 0.0, 0.0, 1e80, 0.2, 0.0, -0.2, 0.0, 0.05, 0.0, 0.0, 0.1};
+  double bq[3 * NB], bp[3 * NB], bw[2 * NB], btt[NB];
+  for (int mode = 0; mode < 2 && !rc; ++mode) {
+    const or_ground* gsb = mode ? &p_wave : &s_wave;
+    rc = or_sfa_birth(&pl, gsb, mode, NB, bt0, kp, NULL, 3, bq, bp, bw, btt);
+    double sb = 0.0;
+    for (int j = 0; j < NB; ++j)
+      if (isfinite(btt[j])) sb += btt[j] + bp[2 * NB + j] + bq[2 * NB + j] + bw[j] + bw[NB + j];
+    printf("sfa mode %d: %.17g\n", mode, sb);
+  }
+  printf("sincos %.17g\n", sc);
   return rc ? 1 : 0;
 }

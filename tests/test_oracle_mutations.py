@@ -15,7 +15,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "sfhk_oracle.c")
 HDR = os.path.join(ROOT, "oracle", "sfhk_oracle.h")
-PINS = os.path.join(ROOT, "tests", "test_oracle_pins.py")
+PINS = [os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+        os.path.join(ROOT, "tests", "test_oracle_sfa.py")]
 
 MUTANTS = {
     "G imaginary part sign": ("G[i][k].im = fma(M_PQ(m, i, k), inv4g, -(gamma * M_QP(m, i, k)));",
@@ -56,6 +57,24 @@ MUTANTS = {
                                        "return rsqrt_core(x);"),
     "principal sqrt: imaginary part halved twice": ("r.im = (0.5 * z.im) * rw;",
                                                     "r.im = (0.25 * z.im) * rw;"),
+    "SFA: crossing sign ignored in the bisection": ("if ((up ? v : -v) < kap)", "if (v < kap)"),
+    "SFA: tunnel exit sign": ("*qz = -(a.K * (a.C[0]", "*qz = (a.K * (a.C[0]"),
+    "SFA: k_z from sinh instead of cosh - 1": ("double c0 = coshm1_c(a.om[0] * t);",
+                                              "double c0 = sinh_c(a.om[0] * t);"),
+    "SFA: sinh as cosh": ("return 0.5 * (e - 1.0 / e);", "return 0.5 * (e + 1.0 / e);"),
+    "SFA: envelope sideband frequency": ("a->om[1] = pl->omega + W;", "a->om[1] = pl->omega + 2.0 * W;"),
+    "SFA: action under the barrier sign": ("double complex S = gs->ip * ts + I * integ;",
+                                           "double complex S = gs->ip * ts - I * integ;"),
+    "SFA: modified weight without 1/(E.k)": ("amp = cexp(I * S) / ek;", "amp = cexp(I * S);"),
+    "SFA: s-wave tunnelling element phase": ("-I * (0.5 * pow(M_PI, 1.5)) * kzs * sum",
+                                             "(0.5 * pow(M_PI, 1.5)) * kzs * sum"),
+    "SFA: p-wave tunnelling bracket": ("(2.0 * al - kzs * kzs) * e;", "(al - kzs * kzs) * e;"),
+    "SFA: weight without e^{i p0.q0}": ("wj = u * cexp(I * (kz * qz)) * amp;", "wj = u * amp;"),
+    "sincos: quadrant 1 cosine sign": ("case 1: *s = cr; *c = -sr; break;",
+                                       "case 1: *s = cr; *c = sr; break;"),
+    "sincos: reduction drops the pi/2 tail": ("r = fma(-k, SINC_PIO2_3, r);", "r = r;"),
+    "sincos: sine series two terms short": ("double ps = inv_fact[17];\n  for (int j = 7;",
+                                            "double ps = inv_fact[13];\n  for (int j = 5;"),
 }
 
 
@@ -71,7 +90,7 @@ def _run_mutant(name, old, new, tmp):
                     "-std=gnu11", "-w", "-o", lib, os.path.join(d, "sfhk_oracle.c"),
                     "-lquadmath", "-lm", "-lpthread"], check=True)
     env = dict(os.environ, SFHK_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
-    r = subprocess.run([sys.executable, "-m", "pytest", PINS, "-x", "-q", "-p", "no:cacheprovider",
+    r = subprocess.run([sys.executable, "-m", "pytest", *PINS, "-x", "-q", "-p", "no:cacheprovider",
                         "-W", "ignore"], cwd=ROOT, env=env, capture_output=True, text=True,
                        timeout=600)
     return name, r.returncode
