@@ -79,6 +79,9 @@ def _args():
     ap.add_argument("--serve-chunk", type=int, default=1024)
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the short serving run of the default benchmark")
+    ap.add_argument("--no-sfa", action="store_true",
+                    help="skip the SFA birth step leg (birth kernel timing, SFA-born propagation)")
+    ap.add_argument("--sfa-reps", type=int, default=5)
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the uneven-batch pass of the default benchmark")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -236,6 +239,45 @@ def run_batch(a):
     ctx.close()
 
 
+def sfa_results(ctx, stream, reps):
+    """The SFA birth step (sfhk_sfa_birth) on the 2^20 samples of the screened 1600 nm workload:
+    mean duration of the birth kernel over `reps` launches (HIP events on the launch stream), then
+    one propagation of the trajectories it bore."""
+    import torch
+    from paper_2601_17164_amd import flops, inputs as I, sfhk
+    inst = I.sfa_config1()
+    dev = sfhk.to_device(inst, "cuda:0")
+    kp = torch.from_numpy(inst.meta["kperp"]).to("cuda:0")
+    u = torch.from_numpy(inst.meta["u"]).to("cuda:0")
+    b = sfhk.sfa_birth(inst.pulse, inst.ground, dev["t0"], kp, u, sfhk.SFHK_BIRTH_GTO, stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for _ in range(reps):
+        b = sfhk.sfa_birth(inst.pulse, inst.ground, dev["t0"], kp, u, sfhk.SFHK_BIRTH_GTO, stream)
+    ev[1].record(stream)
+    dev.update(q0=b["q0"], p0=b["p0"], w=b["w"])
+    job = sfhk.make_job(ctx, inst, dev)
+    ev[2].record(stream)
+    assert job.propagate(0)
+    ev[3].record(stream)
+    st = job.stats(stream)
+    no_saddle = int(torch.isnan(b["tt"]).sum())
+    job.close()
+    torch.cuda.synchronize()
+    birth_ms = ev[0].elapsed_time(ev[1]) / reps
+    prop_ms = ev[2].elapsed_time(ev[3])
+    fl = flops.flops(inst.potential.kind, inst.ground.l, st.steps_evaluated, st.prims_evaluated)
+    return {"workload": "screened-SAE 1600nm 1.5e14 W/cm2 8-cycle, 1024x1024 SFA births "
+                        "(GTO tunnelling element), dt 0.05",
+            "n": inst.n_traj, "birth_kernel_ms": birth_ms, "births_per_s": inst.n_traj / birth_ms * 1e3,
+            "no_saddle": no_saddle, "propagate_kernel_ms": prop_ms,
+            "trajectory_steps": st.steps_evaluated,
+            "trajectory_steps_per_s": st.steps_evaluated / prop_ms * 1e3,
+            "propagate_fp64_frac": fl / (prop_ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+            "kay_removed": st.kay_removed, "prims_per_step": st.prims_evaluated / max(1, st.steps_evaluated)}
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -335,6 +377,8 @@ def main():
                           for prec, name in ((0, "fp64"), (1, "fp32_mixed"))}
     if not a.no_batch:
         out["batch"] = batch_results(ctx, a.batch_size)
+    if not a.no_sfa:
+        out["sfa_birth"] = sfa_results(ctx, stream, a.sfa_reps)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, a.cpu_births, a.cpu_per_birth)
     print(json.dumps(out), flush=True)

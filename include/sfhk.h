@@ -253,6 +253,58 @@ const char* sfhk_status_string(sfhk_status s);
 sfhk_status sfhk_traj_exp(const double* x, double* y, int64_t n, void* stream);
 sfhk_status sfhk_traj_rsqrt(const double* x, double* y, int64_t n, void* stream);
 
+/* sfhk_traj_sincos: s[i], c[i] = sin(x[i]), cos(x[i]) as evaluated in the SFA birth step's
+ * saddle-point solve. Cody-Waite reduction x = k pi/2 + r, k = rint(x 2/pi), with pi/2 split into
+ * two 33-significant-bit heads and a rounded tail (applied with fused multiply-adds), Taylor
+ * polynomials in r^2 of degree 17 (sine) and 18 (cosine) in Horner form with fused multiply-adds,
+ * and the quadrant k mod 4. NaN for |x| >= 2^20 or non-finite x. Within one ulp for |x| <= 64.
+ * n must be below 2^31. */
+sfhk_status sfhk_traj_sincos(const double* x, double* s, double* c, int64_t n, void* stream);
+
+/* ------------------------------------------------------------------------------------------------
+ * SFA birth step (App. A: the continuum wave packet right after tunnelling, the saddle-point
+ * equation, the tunnel exit and the action under the barrier; App. B: tunnelling elements).
+ *
+ * The pulse: linear polarisation along z, A(t) = -(e0/omega) cos^2(pi t/T) sin(omega t + cep),
+ * T = 2 pi n_cycles / omega, E = -dA/dt (Sec. II.B field; the same pulse the field table of
+ * sfhk_grid tabulates). n_cycles must exceed 1.
+ */
+typedef struct {
+  double e0, omega, n_cycles, cep;
+} sfhk_pulse;
+
+typedef enum {
+  SFHK_BIRTH_GTO = 0,      /* Eq. A.2 with the GTO tunnelling element of App. B.1 */
+  SFHK_BIRTH_MODIFIED = 1  /* the modified saddle-point form of App. B.2 */
+} sfhk_birth_mode;
+
+/* For every sample j < n, with birth time t0[j] and transverse momentum (kx, ky) =
+ * (kperp[j], kperp[n + j]):
+ *  - the saddle point t_s = t0 + i t_t of [k + A(t_s) - A(t0)]^2 / 2 + Ip = 0 (Ip = gs->ip) with
+ *    k = p0 = (kx, ky, k_z): Im A(t_s) = +-kappa, kappa^2 = 2 Ip + kx^2 + ky^2, fixes t_t > 0 (the
+ *    root nearest the real axis) and k_z = A(t0) - Re A(t_s);
+ *  - the tunnel exit q0 = (0, 0, Re int_{t_s}^{t0} A(t) dt);
+ *  - S_down = Ip t_s - int_{t_s}^{t0} [k + A(t) - A(t0)]^2 / 2 dt and the birth weight
+ *      SFHK_BIRTH_GTO:      w = u_j e^{i p0.q0} (-i) sqrt(2 pi i / (E(t_s).k_s)) <k_s| r.E(t_s) |psi0>
+ *                               e^{i S_down},  k_s = k + A(t_s) - A(t0),
+ *                           <k|z|psi0> = int e^{-i k.r} z psi0(r) d^3r over the GTOs of gs (s-wave:
+ *                           -i (pi^{3/2}/2) k_z sum_i c_i a_i^{-5/2} e^{-k^2/(4 a_i)}; p-wave:
+ *                           (pi^{3/2}/4) sum_i c_i a_i^{-7/2} (2 a_i - k_z^2) e^{-k^2/(4 a_i)});
+ *      SFHK_BIRTH_MODIFIED: w = u_j e^{i p0.q0} e^{i S_down} / (E(t_s).k_s).
+ * u[n] are Monte-Carlo weights (NULL: 1/n). Outputs: q0[3][n], p0[3][n], w[2][n] (re block, im
+ * block) -- the layout sfhk_job_create takes -- and t_tun[n] = t_t (may be NULL).
+ * t_t, k_z and q0 are computed with the trajectory arithmetic (sfhk_traj_sincos, sfhk_traj_exp,
+ * sfhk_traj_rsqrt; a march of at most 512 steps of 1/(4 (omega + omega/n_cycles)) to the first
+ * |Im A| >= kappa, then 64 bisection steps), so they are reproducible bit for bit; the weight uses
+ * library functions. A sample with no crossing within the march, or with non-finite inputs, gets
+ * NaN outputs (sfhk_job_create then counts it as a removed trajectory).
+ * All arrays are DEVICE pointers owned by the caller; asynchronous on `stream`. SFHK_E_INVALID for a
+ * bad pulse, Ip <= 0, l not 0/1, an unknown mode, no or too many GTO primitives (mode GTO), a NULL
+ * array, or n outside [0, 2^31). */
+sfhk_status sfhk_sfa_birth(const sfhk_pulse* pulse, const sfhk_ground* gs, int32_t mode, int64_t n,
+                           const double* t0, const double* kperp, const double* u, double* q0,
+                           double* p0, double* w, double* t_tun, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,6 +17,7 @@
 #include "../../include/sfhk.h"
 #include "sfhk_kernels.hpp"
 #include "sfhk_io_kernels.hpp"
+#include "sfhk_sfa_kernels.hpp"
 
 namespace {
 
@@ -989,6 +990,52 @@ sfhk_status sfhk_traj_exp(const double* x, double* y, int64_t n, void* stream) {
 
 sfhk_status sfhk_traj_rsqrt(const double* x, double* y, int64_t n, void* stream) {
   return traj_fn(1, x, y, n, stream);
+}
+
+sfhk_status sfhk_traj_sincos(const double* x, double* s, double* c, int64_t n, void* stream) {
+  if (!x || !s || !c || n < 0 || n > INT32_MAX) return fail(SFHK_E_INVALID, "NULL pointer or bad count");
+  if (n == 0) return SFHK_OK;
+  hipLaunchKernelGGL(k_traj_sincos, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, x, s,
+                     c, (long long)n);
+  HIP_TRY(hipGetLastError());
+  return SFHK_OK;
+}
+
+sfhk_status sfhk_sfa_birth(const sfhk_pulse* pulse, const sfhk_ground* gs, int32_t mode, int64_t n,
+                           const double* t0, const double* kperp, const double* u, double* q0,
+                           double* p0, double* w, double* t_tun, void* stream) {
+  TraceRange trace_("sfhk_sfa_birth");
+  if (!pulse || !gs) return fail(SFHK_E_INVALID, "NULL pulse or ground state");
+  if (!(pulse->e0 > 0.0) || !(pulse->omega > 0.0) || !(pulse->n_cycles > 1.0) ||
+      !std::isfinite(pulse->e0) || !std::isfinite(pulse->omega) || !std::isfinite(pulse->n_cycles) ||
+      !std::isfinite(pulse->cep))
+    return fail(SFHK_E_INVALID, "pulse needs finite e0 > 0, omega > 0, n_cycles > 1 and cep");
+  if (!(gs->ip > 0.0) || !std::isfinite(gs->ip)) return fail(SFHK_E_INVALID, "ip must be finite and > 0");
+  if (gs->l != 0 && gs->l != 1) return fail(SFHK_E_INVALID, "ground state l must be 0 or 1");
+  if (mode != SFHK_BIRTH_GTO && mode != SFHK_BIRTH_MODIFIED) return fail(SFHK_E_INVALID, "unknown birth mode");
+  if (mode == SFHK_BIRTH_GTO && (gs->n_prim < 1 || gs->n_prim > SFHK_MAX_PRIM || !gs->alpha || !gs->coef))
+    return fail(SFHK_E_INVALID, "ground state needs 1..SFHK_MAX_PRIM primitives");
+  if (n < 0 || n > INT32_MAX) return fail(SFHK_E_INVALID, "n must be in [0, 2^31)");
+  if (n == 0) return SFHK_OK;
+  if (!t0 || !kperp || !q0 || !p0 || !w) return fail(SFHK_E_INVALID, "NULL sample or output array");
+  SfaParams P{};
+  P.e0 = pulse->e0;
+  P.omega = pulse->omega;
+  P.n_cycles = pulse->n_cycles;
+  P.cep = pulse->cep;
+  P.ip = gs->ip;
+  P.mode = mode;
+  P.l = gs->l;
+  P.n_prim = mode == SFHK_BIRTH_GTO ? gs->n_prim : 0;
+  for (int i = 0; i < P.n_prim; ++i) {
+    if (!(gs->alpha[i] > 0.0)) return fail(SFHK_E_INVALID, "GTO exponents must be > 0");
+    P.alpha[i] = gs->alpha[i];
+    P.coef[i] = gs->coef[i];
+  }
+  hipLaunchKernelGGL(k_sfa_birth, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, P,
+                     (long long)n, t0, kperp, u, q0, p0, w, t_tun);
+  HIP_TRY(hipGetLastError());
+  return SFHK_OK;
 }
 
 }  // extern "C"

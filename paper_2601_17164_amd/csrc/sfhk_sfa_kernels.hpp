@@ -1,0 +1,307 @@
+// sfhk_sfa_kernels.hpp -- the SFA birth step on the device (App. A: saddle-point equation,
+// tunnel exit, action under the barrier; App. B: tunnelling matrix elements).
+//
+// One lane per sample (t0, kx, ky). The pulse A(t) = -(e0/omega) cos^2(pi t/T) sin(omega t + cep)
+// in product-to-sum form is A(t) = -K sum_m c_m sin(w_m t + cep), K = e0/(2 omega), with
+// (w_m, c_m) = (omega, 1), (omega + W, 1/2), (omega - W, 1/2), W = omega / n_cycles, so at complex
+// time t0 + i tau every quantity is a short sum of sin/cos of th_m = w_m t0 + cep times
+// cosh/sinh of w_m tau:
+//   Im A(t0 + i tau) = -K sum_m c_m cos(th_m) sinh(w_m tau)
+//   k_z  = A(t0) - Re A(t_s)   =  K sum_m c_m sin(th_m) (cosh(w_m t_t) - 1)
+//   q0_z = Re int_{t_s}^{t0} A = -K sum_m (c_m/w_m) cos(th_m) (cosh(w_m t_t) - 1)
+// The saddle point t_s = t0 + i t_t solves Im A(t_s) = +-kappa, kappa^2 = 2 Ip + kx^2 + ky^2, and is
+// the root nearest the real axis: a march in steps of 1/(4 w_max) (at most kSfaMarch steps) to the
+// first |Im A| >= kappa, then kSfaBisect bisection steps. These values decide the trajectory's
+// initial state and follow the rounding contract (sincos_c, exp_cw, rsqrt_c, one IEEE operation per
+// step as written), so they agree bit for bit with a CPU implementation of the same sequence.
+//
+// The weight does not feed back into any trajectory and uses library functions: the action
+//   S_down = Ip t_s - (1/2) int_{t_s}^{t0} v^2,  v = (kx, ky, k_z + A(t) - A(t0)),
+// from the antiderivatives of A and A^2 (A^2 = (K^2/2) sum_{m,n} c_m c_n [cos((w_m - w_n) t)
+// - cos((w_m + w_n) t + 2 cep)]), E(t_s) = -A'(t_s), k_s = k + A(t_s) - A(t0), and
+//   mode 0: w = u e^{i p0.q0} (-i) sqrt(2 pi i / (E.k_s)) E(t_s) <k_s|z|psi0> e^{i S_down}
+//           (Eq. A.2; <k|z|psi0> = int e^{-i k.r} z psi0 written out for the GTOs, App. B.1)
+//   mode 1: w = u e^{i p0.q0} e^{i S_down} / (E.k_s)       (modified saddle point, App. B.2)
+#pragma once
+#include "sfhk_device.hpp"
+
+namespace sfhk {
+
+// ----------------------------------------------------------------------------------------------
+// the sine and cosine of the rounding contract (the SFA birth step's saddle-point solve).
+// Cody-Waite reduction x = k pi/2 + r, k = rint(x 2/pi), with pi/2 = kPio2_1 + kPio2_2 + kPio2_3,
+// the first two truncated to 33 significant bits (k kPio2_1 and k kPio2_2 are exact for
+// |k| < 2^20) and the third the rounded remainder; sin r = r + r z Ps(z), cos r = 1 + z Pc(z),
+// z = r^2, with the Taylor coefficients (-1)^j/(2j+1)! (j = 1..8) and (-1)^j/(2j)! (j = 1..9) in
+// Horner form with fused multiply-adds; the quadrant k mod 4 selects (+-sin r, +-cos r).
+// |x| >= 2^20 and non-finite x give NaN. Within one ulp for |x| <= 64.
+// ----------------------------------------------------------------------------------------------
+struct InvFactorials19 {
+  double v[19];
+  constexpr InvFactorials19() : v() {
+    double f = 1.0;
+    for (int n = 0; n < 19; ++n) {
+      if (n > 0) f *= (double)n;  // exact for n <= 18
+      v[n] = 1.0 / f;
+    }
+  }
+};
+constexpr InvFactorials19 kInvFact19{};
+
+__device__ inline void sincos_c(double x, double* s, double* c) {
+  if (!(fabs(x) < 0x1p20)) {
+    *s = __builtin_nan("");
+    *c = __builtin_nan("");
+    return;
+  }
+  constexpr double k2OverPi = 0x1.45f306dc9c883p-1;  // 2/pi rounded to binary64
+  constexpr double kPio2_1 = 0x1.921fb544p+0;        // pi/2 truncated to 33 significant bits
+  constexpr double kPio2_2 = 0x1.0b4611a6p-34;       // its next 33 significant bits
+  constexpr double kPio2_3 = 0x1.3198a2e037073p-69;  // the rest, rounded
+  const double k = rint(x * k2OverPi);
+  double r = SFHK_FMA(-k, kPio2_1, x);
+  r = SFHK_FMA(-k, kPio2_2, r);
+  r = SFHK_FMA(-k, kPio2_3, r);
+  const double z = r * r;
+  double ps = kInvFact19.v[17];
+#pragma unroll
+  for (int j = 7; j >= 1; --j)
+    ps = SFHK_FMA(ps, z, (j & 1) ? -kInvFact19.v[2 * j + 1] : kInvFact19.v[2 * j + 1]);
+  double pc = -kInvFact19.v[18];
+#pragma unroll
+  for (int j = 8; j >= 1; --j) pc = SFHK_FMA(pc, z, (j & 1) ? -kInvFact19.v[2 * j] : kInvFact19.v[2 * j]);
+  const double sr = SFHK_FMA(r * z, ps, r);
+  const double cr = SFHK_FMA(z, pc, 1.0);
+  const int q = (int)((long long)k & 3);
+  *s = (q == 0) ? sr : (q == 1) ? cr : (q == 2) ? -sr : -cr;
+  *c = (q == 0) ? cr : (q == 1) ? -sr : (q == 2) ? -cr : sr;
+}
+
+constexpr int kSfaMarch = 512;
+constexpr int kSfaBisect = 64;
+constexpr int kSfaMaxPrim = 8;
+
+struct SfaParams {
+  double e0, omega, n_cycles, cep, ip;
+  int mode, l, n_prim;
+  double alpha[kSfaMaxPrim], coef[kSfaMaxPrim];
+};
+
+struct SfaTerms {
+  double om[3], S[3], C[3], K;
+};
+
+__device__ inline double sinh_c(double x) {
+  const double e = exp_cw(x);
+  return 0.5 * (e - 1.0 / e);
+}
+
+// cosh(x) - 1 = 2 sinh(x/2)^2
+__device__ inline double coshm1_c(double x) {
+  const double s = sinh_c(0.5 * x);
+  return 2.0 * (s * s);
+}
+
+__device__ inline double sfa_im_a(const SfaTerms& a, double tau) {
+  const double s0 = sinh_c(a.om[0] * tau);
+  const double s1 = sinh_c(a.om[1] * tau);
+  const double s2 = sinh_c(a.om[2] * tau);
+  return -(a.K * (a.C[0] * s0 + 0.5 * (a.C[1] * s1 + a.C[2] * s2)));
+}
+
+// small complex helpers for the weight (library arithmetic, no contract)
+struct zd {
+  double re, im;
+};
+__device__ inline zd zadd(zd a, zd b) { return {a.re + b.re, a.im + b.im}; }
+__device__ inline zd zscale(zd a, double s) { return {a.re * s, a.im * s}; }
+__device__ inline zd zmul(zd a, zd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline zd zdiv(zd a, zd b) {
+  const double d = b.re * b.re + b.im * b.im;
+  return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+__device__ inline zd zexp(zd a) {
+  double s, c;
+  ::sincos(a.im, &s, &c);
+  const double m = ::exp(a.re);
+  return {m * c, m * s};
+}
+// principal square root (branch cut on the negative real axis, sign of a zero imaginary part kept)
+__device__ inline zd zsqrt(zd a) {
+  const double r = ::hypot(a.re, a.im);
+  if (r == 0.0) return {0.0, a.im};
+  if (a.re >= 0.0) {
+    const double t = ::sqrt(0.5 * (r + a.re));
+    return {t, a.im / (2.0 * t)};
+  }
+  const double t = ::sqrt(0.5 * (r - a.re));
+  return {::fabs(a.im) / (2.0 * t), ::copysign(t, a.im)};
+}
+
+// sin(a) (1 - cosh b) - i cos(a) sinh(b) = sin(a + i 0) - sin(a + i b)
+__device__ inline zd sin_drop(double a, double b) {
+  double sa, ca;
+  ::sincos(a, &sa, &ca);
+  const double sh = ::sinh(0.5 * b);
+  return {-sa * (2.0 * sh * sh), -ca * ::sinh(b)};
+}
+
+__global__ __launch_bounds__(256) void k_sfa_birth(SfaParams P, long long n, const double* __restrict__ t0v,
+                                                   const double* __restrict__ kperp,
+                                                   const double* __restrict__ uv, double* __restrict__ q0,
+                                                   double* __restrict__ p0, double* __restrict__ w,
+                                                   double* __restrict__ ttv) {
+  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double t0 = t0v[j], kx = kperp[j], ky = kperp[n + j];
+  const double nan = __builtin_nan("");
+
+  // ---- contract part: saddle point, k_z, tunnel exit ----------------------------------------
+  SfaTerms a;
+  const double W = P.omega / P.n_cycles;
+  a.om[0] = P.omega;
+  a.om[1] = P.omega + W;
+  a.om[2] = P.omega - W;
+  a.K = P.e0 / (2.0 * P.omega);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) sincos_c(a.om[m] * t0 + P.cep, &a.S[m], &a.C[m]);
+  const double kap2 = 2.0 * P.ip + (kx * kx + ky * ky);
+  const double kap = kap2 * rsqrt_lane(kap2);
+  const double dtau = 0.25 / a.om[1];
+  double lo = 0.0, hi = 0.0, ahi = 0.0;
+  bool found = false;
+  for (int k = 1; k <= kSfaMarch; ++k) {
+    const double tau = (double)k * dtau;
+    const double v = sfa_im_a(a, tau);
+    if (fabs(v) >= kap) {
+      hi = tau;
+      ahi = v;
+      found = true;
+      break;
+    }
+    lo = tau;
+  }
+  double tt = nan, kz = nan, qz = nan, wr = nan, wi = nan;
+  if (found) {
+    const bool up = ahi >= 0.0;
+    for (int it = 0; it < kSfaBisect; ++it) {
+      const double mid = lo + 0.5 * (hi - lo);
+      const double v = sfa_im_a(a, mid);
+      if ((up ? v : -v) < kap)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    tt = lo + 0.5 * (hi - lo);
+    const double c0 = coshm1_c(a.om[0] * tt);
+    const double c1 = coshm1_c(a.om[1] * tt);
+    const double c2 = coshm1_c(a.om[2] * tt);
+    kz = a.K * (a.S[0] * c0 + 0.5 * (a.S[1] * c1 + a.S[2] * c2));
+    qz = -(a.K * (a.C[0] * c0 / a.om[0] + 0.5 * (a.C[1] * c1 / a.om[1] + a.C[2] * c2 / a.om[2])));
+
+    // ---- weight (library arithmetic) ----------------------------------------------------------
+    const double cw[3] = {1.0, 0.5, 0.5};
+    double sh[3], ch[3], cm1[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const double b = a.om[m] * tt;
+      sh[m] = ::sinh(b);
+      ch[m] = ::cosh(b);
+      const double hb = ::sinh(0.5 * b);
+      cm1[m] = 2.0 * hb * hb;
+    }
+    double a0 = 0.0;
+    zd dA = {0.0, 0.0}, ez = {0.0, 0.0}, dP = {0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      a0 -= a.K * cw[m] * a.S[m];
+      dA = zadd(dA, zd{-a.K * cw[m] * a.S[m] * cm1[m], -a.K * cw[m] * a.C[m] * sh[m]});
+      ez = zadd(ez, zd{a.K * cw[m] * a.om[m] * a.C[m] * ch[m], -a.K * cw[m] * a.om[m] * a.S[m] * sh[m]});
+      dP = zadd(dP, zd{-a.K * cw[m] / a.om[m] * a.C[m] * cm1[m], a.K * cw[m] / a.om[m] * a.S[m] * sh[m]});
+    }
+    // int_{t_s}^{t0} A^2 dt from the antiderivative of each product term
+    zd dQ = {0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const double f = 0.5 * a.K * a.K * cw[m] * cw[q];
+        zd g;
+        if (m == q) {
+          g = zd{0.0, -tt};  // cos(0 t) integrates to t0 - t_s = -i t_t
+        } else {
+          const double om = a.om[m] - a.om[q];
+          g = zscale(sin_drop(om * t0, om * tt), 1.0 / om);
+        }
+        const double os = a.om[m] + a.om[q];
+        g = zadd(g, zscale(sin_drop(os * t0 + 2.0 * P.cep, os * tt), -1.0 / os));
+        dQ = zadd(dQ, zscale(g, f));
+      }
+    }
+    const double c = kz - a0;
+    zd I = zd{0.0, -(kx * kx + ky * ky + c * c) * tt};
+    I = zadd(I, zscale(dP, 2.0 * c));
+    I = zadd(I, dQ);
+    const zd S = {P.ip * t0 - 0.5 * I.re, P.ip * tt - 0.5 * I.im};
+    const zd kzs = {kz + dA.re, dA.im};
+    const zd ek = zmul(ez, kzs);
+    const zd eS = zexp(zd{-S.im, S.re});  // e^{i S}
+    zd amp;
+    if (P.mode == 0) {
+      const zd kz2 = zmul(kzs, kzs);
+      const zd k2 = {kx * kx + ky * ky + kz2.re, kz2.im};
+      zd sum = {0.0, 0.0};
+      for (int i = 0; i < P.n_prim; ++i) {
+        const double al = P.alpha[i];
+        const zd e = zexp(zscale(k2, -1.0 / (4.0 * al)));
+        if (P.l == 0) {
+          sum = zadd(sum, zscale(e, P.coef[i] * ::pow(al, -2.5)));
+        } else {
+          sum = zadd(sum, zscale(zmul(zd{2.0 * al - kz2.re, -kz2.im}, e), P.coef[i] * ::pow(al, -3.5)));
+        }
+      }
+      const double pi32 = 5.568327996831707845284817982118835702;  // pi^{3/2}
+      zd me;
+      if (P.l == 0) {
+        const zd t = zscale(zmul(kzs, sum), 0.5 * pi32);
+        me = zd{t.im, -t.re};  // -i t
+      } else {
+        me = zscale(sum, 0.25 * pi32);
+      }
+      const double two_pi = 6.283185307179586476925286766559005768;
+      const zd root = zsqrt(zdiv(zd{0.0, two_pi}, ek));
+      const zd t = zmul(zmul(root, zmul(ez, me)), eS);
+      amp = zd{t.im, -t.re};  // -i t
+    } else {
+      amp = zdiv(eS, ek);
+    }
+    const double u = uv ? uv[j] : 1.0 / (double)n;
+    double sp, cp;
+    ::sincos(kz * qz, &sp, &cp);
+    const zd wj = zscale(zmul(zd{cp, sp}, amp), u);
+    wr = wj.re;
+    wi = wj.im;
+  }
+  q0[j] = 0.0;
+  q0[n + j] = 0.0;
+  q0[2 * n + j] = qz;
+  p0[j] = kx;
+  p0[n + j] = ky;
+  p0[2 * n + j] = kz;
+  w[j] = wr;
+  w[n + j] = wi;
+  if (ttv) ttv[j] = tt;
+}
+
+// the contract sine and cosine, exported for bitwise checks
+__global__ __launch_bounds__(256) void k_traj_sincos(const double* __restrict__ x, double* __restrict__ s,
+                                                     double* __restrict__ c, long long n) {
+  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double sv, cv;
+  sincos_c(x[j], &sv, &cv);
+  s[j] = sv;
+  c[j] = cv;
+}
+
+}  // namespace sfhk

@@ -177,10 +177,14 @@ class Instance:
 
     def subset(self, idx) -> "Instance":
         idx = np.asarray(idx)
+        meta = dict(self.meta)
+        if "kperp" in meta:
+            meta["kperp"] = np.ascontiguousarray(meta["kperp"][:, idx])
+            meta["u"] = meta["u"][idx].copy()
         return replace(self, name=self.name + "[subset]", t0=self.t0[idx].copy(),
                        q0=np.ascontiguousarray(self.q0[:, idx]),
                        p0=np.ascontiguousarray(self.p0[:, idx]),
-                       w=None if self.w is None else self.w[idx].copy())
+                       w=None if self.w is None else self.w[idx].copy(), meta=meta)
 
     def nominal_steps(self) -> int:
         """Sum over trajectories of (n_steps - birth step + 1) for births snapped to the grid."""
@@ -249,6 +253,53 @@ def serving_request(req_id: int, traj_scale=1.0) -> Instance:
     s = 4000 + int(req_id)
     rng = np.random.Generator(np.random.PCG64(s))
     return random_instance(rng, s, f"req{req_id}", traj_scale)
+
+
+def sfa_samples(seed: int, pulse: Pulse, grid: Grid, n_birth: int, n_per_birth: int, ip: float):
+    """Samples of the SFA birth step: birth times are the n_birth bin midpoints snapped to the
+    nearest grid step (ties to the lower), so each trajectory is born exactly at a step; transverse
+    momenta k_perp ~ N(0, s^2) per axis with s^2 = E0 / (2 sqrt(2 Ip)) (the width of the
+    quasi-static transverse momentum distribution at the field peak), drawn birth-major, then
+    sample, then (kx, ky); Monte-Carlo weights u = dt0 / (n_per_birth pdf(k_perp)), dt0 = T/n_birth,
+    so sum_j u_j f_j estimates int dt0 d^2k_perp f. Returns t0 [n], kperp [2, n], u [n]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    z = rng.standard_normal((n_birth, n_per_birth, 2)).reshape(-1, 2)
+    s2 = pulse.e0 / (2.0 * math.sqrt(2.0 * ip))
+    kperp = np.ascontiguousarray((z * math.sqrt(s2)).T)
+    tb = birth_times(grid, n_birth)
+    n0 = np.clip(np.ceil((tb - grid.t_a) / grid.h - 0.5), 0, grid.n_steps)
+    t0 = np.repeat(grid.t_a + n0 * grid.h, n_per_birth)
+    T = grid.h * grid.n_steps
+    r2 = np.sum(kperp * kperp, axis=0)
+    u = (T / n_birth) * (2.0 * math.pi * s2) * np.exp(r2 / (2.0 * s2)) / n_per_birth
+    return t0, kperp, u
+
+
+def sfa_instance(name, potential, ground, pulse, dt, n_birth, n_per_birth, seed, mode=0,
+                 gamma=0.5, kay_max=1e30, n_out=0, overlap_cut=60.0) -> Instance:
+    """An instance whose initial conditions come from the SFA birth step: t0, k_perp and u are
+    here (``meta``); q0, p0 and w are zero until the birth step fills them."""
+    grid = time_grid(pulse, dt)
+    e_half = field_table(pulse, grid)
+    t0, kperp, u = sfa_samples(seed, pulse, grid, n_birth, n_per_birth, ground.ip)
+    n = t0.shape[0]
+    return Instance(name, potential, ground, pulse, grid, e_half, t0, np.zeros((3, n)),
+                    np.zeros((3, n)), np.zeros(n, dtype=np.complex128), gamma, kay_max,
+                    overlap_cut, n_out, n_birth, n_per_birth, seed,
+                    meta=dict(kperp=kperp, u=u, mode=mode))
+
+
+def sfa_config0(n_birth=64, n_per_birth=32, seed=10, mode=0) -> Instance:
+    """Config 0 (soft-core H, 800 nm, 1e14 W/cm^2, 2 cycles, dt 0.1) born by the SFA step."""
+    return sfa_instance("softcore-H 800nm 1e14 2cyc sfa", SOFTCORE_H, gto_h1s(),
+                        Pulse(800.0, 1e14, 2.0), 0.1, n_birth, n_per_birth, seed, mode)
+
+
+def sfa_config1(n_birth=1024, n_per_birth=1024, seed=11, mode=0, n_out=1 << 15) -> Instance:
+    """Config 1 (screened SAE, 1600 nm, 1.5e14 W/cm^2, 8 cycles, dt 0.05) born by the SFA step."""
+    return sfa_instance("screened-SAE 1600nm 1.5e14 8cyc sfa", SCREENED_SAE, gto_p058(),
+                        Pulse(1600.0, 1.5e14, 8.0), 0.05, n_birth, n_per_birth, seed, mode,
+                        n_out=n_out)
 
 
 def harmonic_instance(omega_ho, pulse, dt, n_birth, n_per_birth, seed, gamma=0.5) -> Instance:

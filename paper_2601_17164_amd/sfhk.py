@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(HERE, "libsfhk.so")
 SFHK_OK, SFHK_E_INVALID, SFHK_E_NOMEM, SFHK_E_DEVICE, SFHK_E_NOT_DONE, SFHK_E_BUDGET = (
     0, -1, -2, -3, -4, -5)
 SFHK_FP64, SFHK_FP32_MIXED = 0, 1
+SFHK_BIRTH_GTO, SFHK_BIRTH_MODIFIED = 0, 1
 SFHK_MAX_PRIM = 8
 
 
@@ -50,6 +51,11 @@ class _Grid(ct.Structure):
 class _Params(ct.Structure):
     _fields_ = [("gamma", ct.c_double), ("kay_max", ct.c_double), ("overlap_cut", ct.c_double),
                 ("r_fp64", ct.c_double), ("precision", ct.c_int32), ("n_out", ct.c_int64)]
+
+
+class _Pulse(ct.Structure):
+    _fields_ = [("e0", ct.c_double), ("omega", ct.c_double), ("n_cycles", ct.c_double),
+                ("cep", ct.c_double)]
 
 
 class _Stats(ct.Structure):
@@ -94,6 +100,9 @@ _SIGS = {
     "sfhk_status_string": (ct.c_char_p, [ct.c_int]),
     "sfhk_traj_exp": (ct.c_int, [_VP, _VP, ct.c_int64, _VP]),
     "sfhk_traj_rsqrt": (ct.c_int, [_VP, _VP, ct.c_int64, _VP]),
+    "sfhk_traj_sincos": (ct.c_int, [_VP, _VP, _VP, ct.c_int64, _VP]),
+    "sfhk_sfa_birth": (ct.c_int, [ct.POINTER(_Pulse), ct.POINTER(_Ground), ct.c_int32, ct.c_int64,
+                                  _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
 }
 
 
@@ -365,6 +374,40 @@ def traj_rsqrt(x: torch.Tensor, stream=None) -> torch.Tensor:
     _check(lib().sfhk_traj_rsqrt(_dptr(x), _dptr(y), int(x.numel()), _stream_ptr(stream)),
            "sfhk_traj_rsqrt")
     return y
+
+
+def traj_sincos(x: torch.Tensor, stream=None):
+    """sin, cos as evaluated in the SFA birth step's saddle-point solve (device)."""
+    s, c = torch.empty_like(x), torch.empty_like(x)
+    _check(lib().sfhk_traj_sincos(_dptr(x), _dptr(s), _dptr(c), int(x.numel()),
+                                  _stream_ptr(stream)), "sfhk_traj_sincos")
+    return s, c
+
+
+def sfa_birth(pulse, ground, t0: torch.Tensor, kperp: torch.Tensor,
+              u: Optional[torch.Tensor] = None, mode: int = SFHK_BIRTH_GTO, stream=None) -> dict:
+    """sfhk_sfa_birth: SFA birth step on the device. ``pulse`` has e0, omega, n_cycles, cep;
+    ``ground`` has l, alpha, coef, ip; t0 [n], kperp [2, n], u [n] or None (float64 tensors).
+    Returns device tensors q0 [3, n], p0 [3, n], w [2, n] (re, im) and tt [n]."""
+    n = int(t0.shape[0])
+    if tuple(kperp.shape) != (2, n) or kperp.dtype != torch.float64 or t0.dtype != torch.float64:
+        raise ValueError("t0 must be float64 [n] and kperp float64 [2, n]")
+    if u is not None and (tuple(u.shape) != (n,) or u.dtype != torch.float64):
+        raise ValueError("u must be float64 [n]")
+    alpha = np.ascontiguousarray(ground.alpha, dtype=np.float64)
+    coef = np.ascontiguousarray(ground.coef, dtype=np.float64)
+    gs = _Ground(int(ground.l), len(alpha), alpha.ctypes.data_as(ct.POINTER(ct.c_double)),
+                 coef.ctypes.data_as(ct.POINTER(ct.c_double)), float(ground.ip))
+    pl = _Pulse(float(pulse.e0), float(pulse.omega), float(pulse.n_cycles), float(pulse.cep))
+    dev = t0.device
+    out = dict(q0=torch.empty(3, n, dtype=torch.float64, device=dev),
+               p0=torch.empty(3, n, dtype=torch.float64, device=dev),
+               w=torch.empty(2, n, dtype=torch.float64, device=dev),
+               tt=torch.empty(n, dtype=torch.float64, device=dev))
+    _check(lib().sfhk_sfa_birth(ct.byref(pl), ct.byref(gs), int(mode), n, _dptr(t0), _dptr(kperp),
+                                _dptr(u), _dptr(out["q0"]), _dptr(out["p0"]), _dptr(out["w"]),
+                                _dptr(out["tt"]), _stream_ptr(stream)), "sfhk_sfa_birth")
+    return out
 
 
 # ------------------------------------------------------------------------------------------------

@@ -28,6 +28,17 @@ def run_oracle(inst: I.Instance, n_threads: int = 0, kay_max=None) -> O.Propagat
                        inst.overlap_cut, n_threads)
 
 
+def oracle_sfa_births(inst: I.Instance, mode=None, n_threads: int = 0) -> I.Instance:
+    """The instance with q0, p0 and w from the oracle's SFA birth step (``inst.meta`` holds the
+    birth samples k_perp and Monte-Carlo weights u)."""
+    from dataclasses import replace
+    pl = inst.pulse
+    m = inst.meta["mode"] if mode is None else mode
+    b = O.sfa_birth(pl.e0, pl.omega, pl.n_cycles, pl.cep, oracle_ground(inst.ground), inst.t0,
+                    inst.meta["kperp"], inst.meta["u"], m, n_threads)
+    return replace(inst, q0=b.q0, p0=b.p0, w=b.w, meta=dict(inst.meta, tt=b.tt, mode=m))
+
+
 def rel_l2(a, b) -> float:
     a, b = np.asarray(a), np.asarray(b)
     den = np.linalg.norm(b)
