@@ -82,6 +82,8 @@ def _args():
     ap.add_argument("--no-sfa", action="store_true",
                     help="skip the SFA birth step leg (birth kernel timing, SFA-born propagation)")
     ap.add_argument("--sfa-reps", type=int, default=5)
+    ap.add_argument("--sfa-only", action="store_true",
+                    help="time only the SFA birth step (2^20 samples) and print its JSON line")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the uneven-batch pass of the default benchmark")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -239,6 +241,43 @@ def run_batch(a):
     ctx.close()
 
 
+def sfa_saddle_work(inst, tt):
+    """March steps and algorithmic FP64 operations of the saddle-point kernel for the t_t it
+    returned (the march stops at k = ceil(t_t / dtau), dtau = 1 / (4 (omega + omega/n_cycles)))."""
+    from paper_2601_17164_amd import flops
+    om = inst.pulse.omega
+    dtau = 0.25 / (om + om / inst.pulse.n_cycles)
+    ok = np.isfinite(tt)
+    k = np.ceil(tt[ok] / dtau)
+    fl = flops.sfa_saddle_flops(int(k.sum()), int(ok.sum()))
+    return {"march_steps_mean": float(k.mean()) if ok.any() else 0.0, "saddle_flop": fl}
+
+
+def sfa_only(a):
+    """Only the SFA birth step on the 2^20 samples of the screened 1600 nm workload."""
+    import torch
+    from paper_2601_17164_amd import inputs as I, sfhk
+    inst = I.sfa_config1()
+    stream = torch.cuda.current_stream()
+    t0 = torch.from_numpy(inst.t0).to("cuda:0")
+    kp = torch.from_numpy(inst.meta["kperp"]).to("cuda:0")
+    u = torch.from_numpy(inst.meta["u"]).to("cuda:0")
+    for _ in range(a.warmup):
+        sfhk.sfa_birth(inst.pulse, inst.ground, t0, kp, u, sfhk.SFHK_BIRTH_GTO, stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for _ in range(a.sfa_reps):
+        b = sfhk.sfa_birth(inst.pulse, inst.ground, t0, kp, u, sfhk.SFHK_BIRTH_GTO, stream)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / a.sfa_reps
+    w = sfa_saddle_work(inst, b["tt"].cpu().numpy())
+    print(json.dumps({"workload": "SFA births, screened-SAE 1600nm 1.5e14 W/cm2 8-cycle, "
+                                  "1024x1024 samples", "n": inst.n_traj, "reps": a.sfa_reps,
+                      "birth_ms": ms, "births_per_s": inst.n_traj / ms * 1e3, **w}), flush=True)
+
+
 def sfa_results(ctx, stream, reps):
     """The SFA birth step (sfhk_sfa_birth) on the 2^20 samples of the screened 1600 nm workload:
     mean duration of the birth kernel over `reps` launches (HIP events on the launch stream), then
@@ -267,11 +306,13 @@ def sfa_results(ctx, stream, reps):
     torch.cuda.synchronize()
     birth_ms = ev[0].elapsed_time(ev[1]) / reps
     prop_ms = ev[2].elapsed_time(ev[3])
+    tt = b["tt"].cpu().numpy()
     fl = flops.flops(inst.potential.kind, inst.ground.l, st.steps_evaluated, st.prims_evaluated)
     return {"workload": "screened-SAE 1600nm 1.5e14 W/cm2 8-cycle, 1024x1024 SFA births "
                         "(GTO tunnelling element), dt 0.05",
             "n": inst.n_traj, "birth_kernel_ms": birth_ms, "births_per_s": inst.n_traj / birth_ms * 1e3,
-            "no_saddle": no_saddle, "propagate_kernel_ms": prop_ms,
+            "no_saddle": no_saddle, **sfa_saddle_work(inst, tt),
+            "propagate_kernel_ms": prop_ms,
             "trajectory_steps": st.steps_evaluated,
             "trajectory_steps_per_s": st.steps_evaluated / prop_ms * 1e3,
             "propagate_fp64_frac": fl / (prop_ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
@@ -293,6 +334,9 @@ def main():
         return
     if a.serve:
         run_serve(a)
+        return
+    if a.sfa_only:
+        sfa_only(a)
         return
     import torch
     from paper_2601_17164_amd import flops, inputs as I, sfhk

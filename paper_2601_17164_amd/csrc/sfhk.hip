@@ -1032,8 +1032,12 @@ sfhk_status sfhk_sfa_birth(const sfhk_pulse* pulse, const sfhk_ground* gs, int32
     P.alpha[i] = gs->alpha[i];
     P.coef[i] = gs->coef[i];
   }
-  hipLaunchKernelGGL(k_sfa_birth, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, P,
-                     (long long)n, t0, kperp, u, q0, p0, w, t_tun);
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_sfa_saddle, dim3(blocks_for(n, 256)), dim3(256), 0, st, P, (long long)n, t0, kperp,
+                     q0, p0, w, t_tun);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_sfa_weight, dim3(blocks_for(n, 256)), dim3(256), 0, st, P, (long long)n, t0, kperp, u,
+                     q0, p0, w, t_tun);
   HIP_TRY(hipGetLastError());
   return SFHK_OK;
 }

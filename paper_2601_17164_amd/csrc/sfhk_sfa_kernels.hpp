@@ -146,17 +146,7 @@ __device__ inline zd sin_drop(double a, double b) {
   return {-sa * (2.0 * sh * sh), -ca * ::sinh(b)};
 }
 
-__global__ __launch_bounds__(256) void k_sfa_birth(SfaParams P, long long n, const double* __restrict__ t0v,
-                                                   const double* __restrict__ kperp,
-                                                   const double* __restrict__ uv, double* __restrict__ q0,
-                                                   double* __restrict__ p0, double* __restrict__ w,
-                                                   double* __restrict__ ttv) {
-  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const double t0 = t0v[j], kx = kperp[j], ky = kperp[n + j];
-  const double nan = __builtin_nan("");
-
-  // ---- contract part: saddle point, k_z, tunnel exit ----------------------------------------
+__device__ inline SfaTerms sfa_terms(const SfaParams& P, double t0) {
   SfaTerms a;
   const double W = P.omega / P.n_cycles;
   a.om[0] = P.omega;
@@ -165,6 +155,21 @@ __global__ __launch_bounds__(256) void k_sfa_birth(SfaParams P, long long n, con
   a.K = P.e0 / (2.0 * P.omega);
 #pragma unroll
   for (int m = 0; m < 3; ++m) sincos_c(a.om[m] * t0 + P.cep, &a.S[m], &a.C[m]);
+  return a;
+}
+
+// Saddle point, k_z and tunnel exit (the contract part). Writes q0, p0 and t_t, the latter to
+// ttv or, when the caller wants no t_t, to the imaginary-part slot of w, which k_sfa_weight reads
+// back before it writes the weight there.
+__global__ __launch_bounds__(256) void k_sfa_saddle(SfaParams P, long long n, const double* __restrict__ t0v,
+                                                    const double* __restrict__ kperp, double* __restrict__ q0,
+                                                    double* __restrict__ p0, double* __restrict__ w,
+                                                    double* __restrict__ ttv) {
+  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double t0 = t0v[j], kx = kperp[j], ky = kperp[n + j];
+  const double nan = __builtin_nan("");
+  const SfaTerms a = sfa_terms(P, t0);
   const double kap2 = 2.0 * P.ip + (kx * kx + ky * ky);
   const double kap = kap2 * rsqrt_lane(kap2);
   const double dtau = 0.25 / a.om[1];
@@ -181,7 +186,7 @@ __global__ __launch_bounds__(256) void k_sfa_birth(SfaParams P, long long n, con
     }
     lo = tau;
   }
-  double tt = nan, kz = nan, qz = nan, wr = nan, wi = nan;
+  double tt = nan, kz = nan, qz = nan;
   if (found) {
     const bool up = ahi >= 0.0;
     for (int it = 0; it < kSfaBisect; ++it) {
@@ -198,8 +203,33 @@ __global__ __launch_bounds__(256) void k_sfa_birth(SfaParams P, long long n, con
     const double c2 = coshm1_c(a.om[2] * tt);
     kz = a.K * (a.S[0] * c0 + 0.5 * (a.S[1] * c1 + a.S[2] * c2));
     qz = -(a.K * (a.C[0] * c0 / a.om[0] + 0.5 * (a.C[1] * c1 / a.om[1] + a.C[2] * c2 / a.om[2])));
+  }
+  q0[j] = 0.0;
+  q0[n + j] = 0.0;
+  q0[2 * n + j] = qz;
+  p0[j] = kx;
+  p0[n + j] = ky;
+  p0[2 * n + j] = kz;
+  if (ttv)
+    ttv[j] = tt;
+  else
+    w[n + j] = tt;
+}
 
-    // ---- weight (library arithmetic) ----------------------------------------------------------
+// The birth weight (library arithmetic) from t0, k_perp, u and the saddle kernel's t_t, k_z, q0_z.
+__global__ __launch_bounds__(256) void k_sfa_weight(SfaParams P, long long n, const double* __restrict__ t0v,
+                                                    const double* __restrict__ kperp,
+                                                    const double* __restrict__ uv, const double* __restrict__ q0,
+                                                    const double* __restrict__ p0, double* __restrict__ w,
+                                                    const double* __restrict__ ttv) {
+  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double tt = ttv ? ttv[j] : w[n + j];
+  double wr = __builtin_nan(""), wi = __builtin_nan("");
+  if (tt == tt) {
+    const double t0 = t0v[j], kx = kperp[j], ky = kperp[n + j];
+    const double kz = p0[2 * n + j], qz = q0[2 * n + j];
+    const SfaTerms a = sfa_terms(P, t0);
     const double cw[3] = {1.0, 0.5, 0.5};
     double sh[3], ch[3], cm1[3];
 #pragma unroll
@@ -219,13 +249,14 @@ __global__ __launch_bounds__(256) void k_sfa_birth(SfaParams P, long long n, con
       ez = zadd(ez, zd{a.K * cw[m] * a.om[m] * a.C[m] * ch[m], -a.K * cw[m] * a.om[m] * a.S[m] * sh[m]});
       dP = zadd(dP, zd{-a.K * cw[m] / a.om[m] * a.C[m] * cm1[m], a.K * cw[m] / a.om[m] * a.S[m] * sh[m]});
     }
-    // int_{t_s}^{t0} A^2 dt from the antiderivative of each product term
+    // int_{t_s}^{t0} A^2 dt from the antiderivative of each product term; the (m, q) and (q, m)
+    // terms are equal, so the pairs m < q count twice
     zd dQ = {0.0, 0.0};
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        const double f = 0.5 * a.K * a.K * cw[m] * cw[q];
+      for (int q = m; q < 3; ++q) {
+        const double f = (m == q ? 0.5 : 1.0) * a.K * a.K * cw[m] * cw[q];
         zd g;
         if (m == q) {
           g = zd{0.0, -tt};  // cos(0 t) integrates to t0 - t_s = -i t_t
@@ -282,15 +313,8 @@ __global__ __launch_bounds__(256) void k_sfa_birth(SfaParams P, long long n, con
     wr = wj.re;
     wi = wj.im;
   }
-  q0[j] = 0.0;
-  q0[n + j] = 0.0;
-  q0[2 * n + j] = qz;
-  p0[j] = kx;
-  p0[n + j] = ky;
-  p0[2 * n + j] = kz;
   w[j] = wr;
   w[n + j] = wi;
-  if (ttv) ttv[j] = tt;
 }
 
 // the contract sine and cosine, exported for bitwise checks
