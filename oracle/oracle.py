@@ -14,6 +14,7 @@ import ctypes as ct
 import os
 import subprocess
 from dataclasses import dataclass, field
+from typing import Optional
 
 import numpy as np
 
@@ -103,8 +104,9 @@ def lib():
         L.or_overlap.argtypes = [ct.POINTER(_Ground), D, D, P, P, P]
         L.or_propagate.restype = ct.c_int
         L.or_propagate.argtypes = [ct.POINTER(_Potential), ct.POINTER(_Ground), ct.POINTER(_HK),
-                                   ct.POINTER(_Grid), ct.c_int64, P, P, P, P, ct.c_int, P,
+                                   ct.POINTER(_Grid), ct.c_int64, P, P, P, P, ct.c_int, P, P,
                                    ct.POINTER(_Diag), ct.POINTER(_Stats)]
+        L.or_overlap_v.argtypes = [ct.POINTER(_Ground), D, D, P, P, P]
         L.or_trajectory.restype = ct.c_int
         L.or_trajectory.argtypes = [ct.POINTER(_Potential), ct.POINTER(_Ground), ct.POINTER(_HK),
                                     ct.POINTER(_Grid), D, P, P, P, P, P, P, P, P,
@@ -246,6 +248,15 @@ def hk_det(m36, gamma):
     return complex(out[0], out[1])
 
 
+def overlap_v(ground: Ground, gamma, q, p, cut=60.0):
+    """<psi0|k_z|p,q,gamma> (App. C.2) in the scale of ``overlap``."""
+    q, p = _f64(q), _f64(p)
+    out = np.zeros(2)
+    g = ground.c()
+    lib().or_overlap_v(ct.byref(g), float(gamma), float(cut), _p(q), _p(p), _p(out))
+    return complex(out[0], out[1])
+
+
 def overlap(ground: Ground, gamma, q, p, cut=60.0):
     q, p = _f64(q), _f64(p)
     out = np.zeros(2)
@@ -264,11 +275,14 @@ class PropagateResult:
     steps_evaluated: int
     kay_removed: int
     nonfinite_removed: int
+    V: Optional[np.ndarray] = None  # complex, n_steps+1: the dipole velocity (velocity=True)
 
 
 def propagate(pot: Potential, ground: Ground, e_half, t_a, h, n_steps, t0, q0, p0, w=None,
-              gamma=0.5, kay_max=1e30, overlap_cut=60.0, n_threads=0) -> PropagateResult:
-    """Run the oracle over all trajectories; q0, p0 are [3, n] arrays, w is complex [n] or None."""
+              gamma=0.5, kay_max=1e30, overlap_cut=60.0, n_threads=0,
+              velocity=False) -> PropagateResult:
+    """Run the oracle over all trajectories; q0, p0 are [3, n] arrays, w is complex [n] or None.
+    velocity=True also accumulates the dipole velocity V(t_n) (App. C.2)."""
     L = lib()
     e_half = _f64(e_half)
     if len(e_half) != 2 * n_steps + 1:
@@ -281,6 +295,7 @@ def propagate(pot: Potential, ground: Ground, e_half, t_a, h, n_steps, t0, q0, p
         wa = np.ascontiguousarray(np.stack([np.real(w), np.imag(w)]).astype(np.float64))
         wp = _p(wa)
     f = np.zeros(2 * (n_steps + 1))
+    v = np.zeros(2 * (n_steps + 1)) if velocity else None
     n0 = np.zeros(n, dtype=np.int64)
     death = np.zeros(n, dtype=np.int64)
     yf = np.zeros((43, n))
@@ -292,13 +307,14 @@ def propagate(pot: Potential, ground: Ground, e_half, t_a, h, n_steps, t0, q0, p
     hk = _HK(float(gamma), float(kay_max), float(overlap_cut))
     g = ground.c()
     rc = L.or_propagate(ct.byref(pot.c()), ct.byref(g), ct.byref(hk), ct.byref(grid), n,
-                        _p(t0), _p(q0), _p(p0), wp, int(n_threads), _p(f), ct.byref(diag),
-                        ct.byref(st))
+                        _p(t0), _p(q0), _p(p0), wp, int(n_threads), _p(f),
+                        None if v is None else _p(v), ct.byref(diag), ct.byref(st))
     if rc != 0:
         raise RuntimeError(f"or_propagate failed: {rc}")
     F = f[: n_steps + 1] + 1j * f[n_steps + 1:]
+    V = None if v is None else v[: n_steps + 1] + 1j * v[n_steps + 1:]
     return PropagateResult(F, n0, death, yf, cf[0] + 1j * cf[1], st.steps_evaluated,
-                           st.kay_removed, st.nonfinite_removed)
+                           st.kay_removed, st.nonfinite_removed, V)
 
 
 @dataclass

@@ -423,6 +423,40 @@ static double complex overlap_c(const or_ground* gs, double gamma, double cut, c
   return gs->l == 0 ? a * sum : sum;
 }
 
+/* <psi0|k_z|p,q,gamma> over GTOs (App. C.2), in the scale of overlap_c above. The printed forms
+ * are s: (p_z - 2i g q_z) sum_j c_j a_j (g+a_j)^{-5/2} E_j and
+ * p: sum_j c_j a_j (g+a_j)^{-7/2} E_j [(p_z - 2i g q_z)^2/(2g) + (g+a_j)/a_j], with E_j the
+ * exponential of the dipole element. Written out, the integrals carry pi^{3/2} (s) and
+ * i pi^{3/2} g (p) where the dipole element's carry pi^{3/2}/2 (s) and pi^{3/2}/4 (p), so in the
+ * dipole element's scale the printed forms are multiplied by 2 (s) and 4 i g (p): the ratio keeps
+ * the relative phase of the velocity and length forms, which "+ c.c." turns into the real part. */
+static double complex overlap_v(const or_ground* gs, double gamma, double cut, const double* q,
+                                const double* p) {
+  double p2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+  double q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+  double pq = p[0] * q[0] + p[1] * q[1] + p[2] * q[2];
+  double complex b = p[2] - 2.0 * I * gamma * q[2];
+  double complex sum = 0.0;
+  for (int j = 0; j < gs->n_prim; ++j) {
+    double al = gs->alpha[j];
+    double ga = gamma + al;
+    double complex ex = (-p2 - 4.0 * al * (gamma * q2 + I * pq)) / (4.0 * ga);
+    if (creal(ex) < -cut) continue; /* the dipole element's skip rule */
+    if (gs->l == 0)
+      sum += gs->coef[j] * al * pow(ga, -2.5) * cexp(ex);
+    else
+      sum += gs->coef[j] * al * pow(ga, -3.5) * cexp(ex) * (b * b / (2.0 * gamma) + ga / al);
+  }
+  return gs->l == 0 ? 2.0 * b * sum : 4.0 * I * gamma * sum;
+}
+
+void or_overlap_v(const or_ground* gs, double gamma, double cut, const double q[3],
+                  const double p[3], double out[2]) {
+  double complex o = overlap_v(gs, gamma, cut, q, p);
+  out[0] = creal(o);
+  out[1] = cimag(o);
+}
+
 void or_overlap(const or_ground* gs, double gamma, double cut, const double q[3],
                 const double p[3], double out[2]) {
   double complex o = overlap_c(gs, gamma, cut, q, p);
@@ -454,6 +488,8 @@ typedef struct {
 typedef struct {
   long double* acc_re;
   long double* acc_im;
+  long double* accv_re; /* dipole velocity (App. C.2); NULL: not accumulated */
+  long double* accv_im;
   double* y_rec;
   double* c_rec;
   double* f_rec;
@@ -517,6 +553,12 @@ static void run_traj(const or_potential* pot, const or_ground* gs, const or_hk* 
       sk->acc_re[n] += creall(f);
       sk->acc_im[n] += cimagl(f);
     }
+    if (sk->accv_re) {
+      double complex ov = overlap_v(gs, hk->gamma, hk->overlap_cut, y, y + 3);
+      double complex fv = w * (C.re + I * C.im) * ov * cexp(I * (y[IY_S] - gs->ip * tn));
+      sk->accv_re[n] += creall(fv);
+      sk->accv_im[n] += cimagl(fv);
+    }
     if (sk->y_rec) {
       memcpy(sk->y_rec + (size_t)n * NY, y, sizeof(y));
       sk->c_rec[2 * n] = C.re;
@@ -548,7 +590,7 @@ typedef struct {
   const or_grid* g;
   int64_t n_traj, lo, hi;
   const double *t0, *q0, *p0, *w;
-  long double *acc_re, *acc_im;
+  long double *acc_re, *acc_im, *accv_re, *accv_im;
   or_diag* diag;
   or_stats st;
 } job_t;
@@ -559,6 +601,8 @@ static void* worker(void* arg) {
   memset(&sk, 0, sizeof(sk));
   sk.acc_re = jb->acc_re;
   sk.acc_im = jb->acc_im;
+  sk.accv_re = jb->accv_re;
+  sk.accv_im = jb->accv_im;
   int64_t N = jb->n_traj;
   for (int64_t j = jb->lo; j < jb->hi; ++j) {
     double q0[3] = {jb->q0[j], jb->q0[N + j], jb->q0[2 * N + j]};
@@ -591,7 +635,7 @@ static void* worker(void* arg) {
 int or_propagate(const or_potential* pot, const or_ground* gs, const or_hk* hk,
                  const or_grid* grid, int64_t n_traj, const double* t0, const double* q0,
                  const double* p0, const double* w, int n_threads, double* f_out,
-                 or_diag* diag, or_stats* stats) {
+                 double* v_out, or_diag* diag, or_stats* stats) {
   if (n_traj < 0 || grid->n_steps < 0 || !(grid->h > 0.0) || !(hk->gamma > 0.0)) return -1;
   if (gs->l != 0 && gs->l != 1) return -1;
   int64_t nb = grid->n_steps + 1;
@@ -600,7 +644,8 @@ int or_propagate(const or_potential* pot, const or_ground* gs, const or_hk* hk,
   if (n_traj < n_threads) n_threads = n_traj > 0 ? (int)n_traj : 1;
   job_t* jobs = (job_t*)calloc((size_t)n_threads, sizeof(job_t));
   pthread_t* th = (pthread_t*)calloc((size_t)n_threads, sizeof(pthread_t));
-  long double* acc = (long double*)calloc((size_t)n_threads * 2 * nb, sizeof(long double));
+  int vel = v_out != NULL;
+  long double* acc = (long double*)calloc((size_t)n_threads * (vel ? 4 : 2) * nb, sizeof(long double));
   if (!jobs || !th || !acc) {
     free(jobs);
     free(th);
@@ -620,8 +665,10 @@ int or_propagate(const or_potential* pot, const or_ground* gs, const or_hk* hk,
     jb->q0 = q0;
     jb->p0 = p0;
     jb->w = w;
-    jb->acc_re = acc + (size_t)t * 2 * nb;
+    jb->acc_re = acc + (size_t)t * (vel ? 4 : 2) * nb;
     jb->acc_im = jb->acc_re + nb;
+    jb->accv_re = vel ? jb->acc_re + 2 * nb : NULL;
+    jb->accv_im = vel ? jb->acc_re + 3 * nb : NULL;
     jb->diag = diag;
   }
   for (int t = 1; t < n_threads; ++t) pthread_create(&th[t], NULL, worker, &jobs[t]);
@@ -636,6 +683,15 @@ int or_propagate(const or_potential* pot, const or_ground* gs, const or_hk* hk,
     }
     f_out[n] = (double)sr;
     f_out[nb + n] = (double)si;
+    if (vel) {
+      long double vr = 0.0L, vi = 0.0L;
+      for (int t = 0; t < n_threads; ++t) {
+        vr += jobs[t].accv_re[n];
+        vi += jobs[t].accv_im[n];
+      }
+      v_out[n] = (double)vr;
+      v_out[nb + n] = (double)vi;
+    }
   }
   for (int t = 0; t < n_threads; ++t) {
     st.steps_evaluated += jobs[t].st.steps_evaluated;

@@ -107,14 +107,22 @@ void or_hk_det(const double* m36, double gamma, double det[2]);
 void or_overlap(const or_ground* gs, double gamma, double cut, const double q[3],
                 const double p[3], double out[2]);
 
+/* <psi0|k_z|p, q, gamma> for the GTO ground state (App. C.2), in the scale of or_overlap (the
+ * ratio of the two elements' written-out constants kept: printed forms times 2 for s, 4 i gamma
+ * for p). */
+void or_overlap_v(const or_ground* gs, double gamma, double cut, const double q[3],
+                  const double p[3], double out[2]);
+
 /* Propagate n_traj trajectories and accumulate F(t_n) = sum_j f_j(t_n) (complex) into
- * f_out[2][n_steps+1] (re block then im block). q0, p0 are [3][n_traj] (SoA). w is
+ * f_out[2][n_steps+1] (re block then im block) and, when v_out is not NULL, the dipole velocity
+ * V(t_n) = sum_j w_j C <psi0|k_z|p_t,q_t,gamma> e^{i(S - Ip t_n)} (App. C.2, or_overlap_v) into
+ * v_out[2][n_steps+1]. q0, p0 are [3][n_traj] (SoA). w is
  * [2][n_traj] complex birth weights or NULL for exp(i p0.q0)/n_traj.
  * n_threads <= 0 uses every online CPU. Returns 0 or a negative error code. */
 int or_propagate(const or_potential* pot, const or_ground* gs, const or_hk* hk,
                  const or_grid* grid, int64_t n_traj, const double* t0, const double* q0,
                  const double* p0, const double* w, int n_threads, double* f_out,
-                 or_diag* diag, or_stats* stats);
+                 double* v_out, or_diag* diag, or_stats* stats);
 
 /* Record one trajectory at every step n = 0..n_steps (entries before its birth step are 0):
  * y_rec[(n_steps+1)][43], c_rec/f_rec/o_rec/det_rec[(n_steps+1)][2], alive_rec[n_steps+1]. */

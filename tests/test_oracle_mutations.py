@@ -29,8 +29,11 @@ MUTANTS = {
     "field force sign": ("k[5] = -fma(g, q[2], E);", "k[5] = -fma(g, q[2], -E);"),
     "RK4 weight of k3": ("acc = fma(2.0, k3[i], acc);", "acc = acc + k3[i];"),
     "RK4 stage-3 time": ("rhs(pot, eb, ys, k3);", "rhs(pot, ea, ys, k3);"),
-    "overlap phase conjugated": ("(gamma * q2 + I * pq)", "(gamma * q2 - I * pq)"),
-    "overlap s-wave power": ("pow(ga, -2.5)", "pow(ga, -1.5)"),
+    "overlap phase conjugated": ("(gamma * q2 + I * pq)) / (4.0 * ga);\n    if (creal(ex) < -cut) continue; /* primitive",
+                                 "(gamma * q2 - I * pq)) / (4.0 * ga);\n    if (creal(ex) < -cut) continue; /* primitive"),
+    "velocity: exponent phase conjugated": ("(gamma * q2 + I * pq)) / (4.0 * ga);\n    if (creal(ex) < -cut) continue; /* the dipole",
+                                            "(gamma * q2 - I * pq)) / (4.0 * ga);\n    if (creal(ex) < -cut) continue; /* the dipole"),
+    "overlap s-wave power": ("coef[j] * pow(ga, -2.5)", "coef[j] * pow(ga, -1.5)"),
     "overlap p-wave bracket": ("(a * a + 2.0 * ga)", "(a * a + ga)"),
     "no branch tracking": ("if (sgn * dot < 0.0) sgn = -sgn;", ""),
     "screened V' drops Z'": ("double vp = fma(Z * r, ir3, d1 * ir);", "double vp = Z * r * ir3;"),
@@ -41,7 +44,7 @@ MUTANTS = {
     "dipole sign": ("d_out[n] = -2.0 * f[n];", "d_out[n] = 2.0 * f[n];"),
     "Hann window sign": ("0.5 * (1.0 + cos(M_PI * t / tau_h))", "0.5 * (1.0 - cos(M_PI * t / tau_h))"),
     "resample neighbour": ("d[i] + frac * (d[i + 1] - d[i])", "d[i] + frac * (d[i] - d[i])"),
-    "Ip phase sign": ("cexp(I * (y[IY_S] - gs->ip * tn))", "cexp(I * (y[IY_S] + gs->ip * tn))"),
+    "Ip phase sign": ("* o * cexp(I * (y[IY_S] - gs->ip * tn))", "* o * cexp(I * (y[IY_S] + gs->ip * tn))"),
     "default weight sign": ("return cexp(I * pq) / (double)n;", "return cexp(-I * pq) / (double)n;"),
     "exp reference not correctly rounded": ("return (double)expq((__float128)x);",
                                             "return (double)(float)expq((__float128)x);"),
@@ -70,6 +73,17 @@ MUTANTS = {
                                              "(0.5 * pow(M_PI, 1.5)) * kzs * sum"),
     "SFA: p-wave tunnelling bracket": ("(2.0 * al - kzs * kzs) * e;", "(al - kzs * kzs) * e;"),
     "SFA: weight without e^{i p0.q0}": ("wj = u * cexp(I * (kz * qz)) * amp;", "wj = u * amp;"),
+    "velocity: s-wave constant": ("return gs->l == 0 ? 2.0 * b * sum : 4.0 * I * gamma * sum;",
+                                  "return gs->l == 0 ? b * sum : 4.0 * I * gamma * sum;"),
+    "velocity: p-wave phase": ("return gs->l == 0 ? 2.0 * b * sum : 4.0 * I * gamma * sum;",
+                               "return gs->l == 0 ? 2.0 * b * sum : 4.0 * gamma * sum;"),
+    "velocity: q_z term sign": ("double complex b = p[2] - 2.0 * I * gamma * q[2];",
+                                "double complex b = p[2] + 2.0 * I * gamma * q[2];"),
+    "velocity: p-wave bracket": ("(b * b / (2.0 * gamma) + ga / al)", "(b * b / (2.0 * gamma) + 1.0)"),
+    "velocity: Ip phase sign": ("ov * cexp(I * (y[IY_S] - gs->ip * tn));",
+                                "ov * cexp(I * (y[IY_S] + gs->ip * tn));"),
+    "velocity: alpha factor dropped (s)": ("sum += gs->coef[j] * al * pow(ga, -2.5) * cexp(ex);",
+                                           "sum += gs->coef[j] * pow(ga, -2.5) * cexp(ex);"),
     "sincos: quadrant 1 cosine sign": ("case 1: *s = cr; *c = -sr; break;",
                                        "case 1: *s = cr; *c = sr; break;"),
     "sincos: reduction drops the pi/2 tail": ("r = fma(-k, SINC_PIO2_3, r);", "r = r;"),

@@ -182,6 +182,37 @@ def test_overlap_vs_quadrature(gname):
         assert abs(got - ref) < 1e-11 * max(abs(ref), 1e-300) + 1e-16
 
 
+def _dgauss1d(a, q, p, power, gamma):
+    """int x^power exp(-a x^2) (-i d/dx) [exp(-gamma (x-q)^2 + i p (x-q))] dx on the same grid:
+    the derivative of the coherent-state factor is (p + 2 i gamma (x - q)) times the factor."""
+    x = np.linspace(min(-40.0, q - 40.0), max(40.0, q + 40.0), 80001)
+    f = x ** power * np.exp(-a * x * x - gamma * (x - q) ** 2 + 1j * p * (x - q))
+    return np.sum(f * (p + 2j * gamma * (x - q))) * (x[1] - x[0])
+
+
+@pytest.mark.parametrize("gname", ["s", "p"])
+def test_velocity_element_vs_quadrature(gname):
+    """<psi0|k_z|p,q,gamma> (App. C.2) = int psi0 (-i d/dz) <r|p,q,gamma> d^3r by quadrature,
+    expressed in the dipole element's scale (the oracle's dipole element times the dipole
+    constant is the written-out integral; the velocity element times the same constant must be
+    the written-out velocity integral). This fixes the velocity element's constant and phase
+    relative to the length form."""
+    g = I.gto_h1s() if gname == "s" else I.gto_p058()
+    G = _ground(g)
+    rng = np.random.default_rng(6)
+    const = math.pi ** 1.5 / 2 if g.l == 0 else math.pi ** 1.5 / 4
+    zpow = 0 if g.l == 0 else 1
+    for _ in range(6):
+        q = rng.normal(0, 1.5, 3)
+        p = rng.normal(0, 0.8, 3)
+        ref = 0j
+        for a, c in zip(g.alpha, g.coef):
+            ref += c * (_gauss1d(a, q[0], p[0], 0, GAMMA) * _gauss1d(a, q[1], p[1], 0, GAMMA) *
+                        _dgauss1d(a, q[2], p[2], zpow, GAMMA))
+        got = O.overlap_v(G, GAMMA, q, p, cut=1e9) * const
+        assert abs(got - ref) < 1e-11 * max(abs(ref), 1e-300) + 1e-16, (got, ref)
+
+
 # ------------------------------------------------------------------------------------------
 # trajectories: closed forms
 # ------------------------------------------------------------------------------------------
@@ -398,6 +429,17 @@ def _hk_quadrature(qi, pi_, nh):
     return q0, p0, (2 * math.pi) ** -3 * ov / env * W * (sq * sp) ** 3
 
 
+def _gaussian_velocity(alpha, coef, q, p, a):
+    """<psi0|k_z|exp(-a|r-q|^2 + i p.(r-q))> for an s-wave GTO set: -i d/dz brings down
+    p_z + 2 i a (z - q_z), which integrates to pi^{3/2} alpha (a+alpha)^{-5/2} (p_z - 2 i a q_z)
+    times the Gaussian factor of the overlap."""
+    out = 0j
+    for al, c in zip(alpha, coef):
+        out += c * al * (a + al) ** -2.5 * np.exp((-(p @ p) - 4 * al * (a * (q @ q) + 1j * (p @ q)))
+                                                  / (4 * (a + al)))
+    return math.pi ** 1.5 * (p[2] - 2j * a * q[2]) * out
+
+
 def _gaussian_dipole(alpha, coef, q, p, a):
     """<psi0|z|exp(-a|r-q|^2 + i p.(r-q))> for an s-wave GTO set (complex width a)."""
     bz = 2 * a * q[2] + 1j * p[2]
@@ -458,13 +500,19 @@ def test_hk_exact_for_quadratic_hamiltonians(case):
         Dr = 1 + 2j * GAMMA * tau
         a = GAMMA / Dr
     res = O.propagate(pot, G0, e, 0.0, h, n_steps, np.zeros(q0.shape[1]), q0, p0,
-                      w=w * cs * math.pi ** 1.5 / 2, gamma=GAMMA, overlap_cut=1e9)
+                      w=w * cs * math.pi ** 1.5 / 2, gamma=GAMMA, overlap_cut=1e9, velocity=True)
     Drp = np.abs(Dr) ** -1.5 * np.exp(-1.5j * np.unwrap(np.angle(Dr)))
     ref = np.array([cs * Drp[k] * np.exp(1j * Sc[k]) * _gaussian_dipole(alpha, coef, qc[k], pc[k], a[k])
                     for k in range(n_steps + 1)])
     err = np.abs(res.F - ref) / np.max(np.abs(ref))
     assert err[0] < 1e-3
     assert err.max() < 1e-2, err
+    # the dipole velocity (App. C.2) of the same exact wave packet, with the same weights
+    refv = np.array([cs * Drp[k] * np.exp(1j * Sc[k]) * _gaussian_velocity(alpha, coef, qc[k], pc[k], a[k])
+                     for k in range(n_steps + 1)])
+    errv = np.abs(res.V - refv) / np.max(np.abs(refv))
+    assert errv[0] < 1e-3
+    assert errv.max() < 1e-2, errv
 
 
 def test_dipole_oscillates_at_the_transition_frequency():
@@ -481,12 +529,17 @@ def test_dipole_oscillates_at_the_transition_frequency():
     n_steps, h = 60, 0.05
     e = np.zeros(2 * n_steps + 1)
     res = O.propagate(O.Potential("harmonic", omega_ho=om), G0, e, 0.0, h, n_steps,
-                      np.zeros(q0.shape[1]), q0, p0, w=w, gamma=GAMMA, overlap_cut=1e9)
+                      np.zeros(q0.shape[1]), q0, p0, w=w, gamma=GAMMA, overlap_cut=1e9,
+                      velocity=True)
     tau = np.arange(n_steps + 1) * h
     ph = np.unwrap(np.angle(res.F))
     slope = np.polyfit(tau, ph, 1)[0]
     assert abs(slope + om) < 1e-3 * om
     assert np.max(np.abs(np.abs(res.F) / np.abs(res.F[0]) - 1)) < 1e-3
+    # Without a field, bra and ket evolve under the same Hamiltonian, so the cross term obeys
+    # Ehrenfest's relation: <psi0 e^{i Ip t}|k_z|psi_c> = d/dt <psi0 e^{i Ip t}|z|psi_c>, i.e. the
+    # dipole velocity (App. C.2) is V = dF/dt = -i w F here.
+    assert np.max(np.abs(res.V - (-1j * om) * res.F)) < 1e-3 * np.max(np.abs(res.V))
 
 
 # ------------------------------------------------------------------------------------------
