@@ -82,6 +82,8 @@ def _args():
     ap.add_argument("--no-sfa", action="store_true",
                     help="skip the SFA birth step leg (birth kernel timing, SFA-born propagation)")
     ap.add_argument("--sfa-reps", type=int, default=5)
+    ap.add_argument("--no-velocity", action="store_true",
+                    help="skip the dipole-velocity leg (one propagation with both accumulators)")
     ap.add_argument("--sfa-only", action="store_true",
                     help="time only the SFA birth step (2^20 samples) and print its JSON line")
     ap.add_argument("--no-batch", action="store_true",
@@ -278,6 +280,27 @@ def sfa_only(a):
                       "birth_ms": ms, "births_per_s": inst.n_traj / ms * 1e3, **w}), flush=True)
 
 
+def velocity_results(ctx, stream, inst, arrays, plain_ms):
+    """One propagation of the benchmark workload with the dipole velocity (App. C.2) accumulated
+    beside the dipole: kernel time against the dipole-only launch of the timed steps."""
+    import torch
+    from paper_2601_17164_amd import sfhk
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    job = sfhk.make_job(ctx, inst, arrays, velocity=True)
+    ev[0].record(stream)
+    assert job.propagate(0)
+    ev[1].record(stream)
+    v = job.velocity()
+    st = job.stats(stream)
+    ok = bool(torch.isfinite(v).all())
+    job.close()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1])
+    return {"propagate_kernel_ms": ms, "dipole_only_kernel_ms": plain_ms,
+            "overhead": ms / plain_ms - 1.0,
+            "trajectory_steps_per_s": st.steps_evaluated / ms * 1e3, "finite": ok}
+
+
 def sfa_results(ctx, stream, reps):
     """The SFA birth step (sfhk_sfa_birth) on the 2^20 samples of the screened 1600 nm workload:
     mean duration of the birth kernel over `reps` launches (HIP events on the launch stream), then
@@ -421,6 +444,8 @@ def main():
                           for prec, name in ((0, "fp64"), (1, "fp32_mixed"))}
     if not a.no_batch:
         out["batch"] = batch_results(ctx, a.batch_size)
+    if not a.no_velocity:
+        out["velocity"] = velocity_results(ctx, stream, inst, arrays, float(kern_ms.mean()))
     if not a.no_sfa:
         out["sfa_birth"] = sfa_results(ctx, stream, a.sfa_reps)
     if not a.no_cpu_baseline:

@@ -81,7 +81,9 @@ typedef struct {
  *   r_fp64       SFHK_FP32_MIXED only: steps that start at r < r_fp64 run in FP64
  *   precision    sfhk_precision
  *   n_out        0: dipole on the step grid (n_steps + 1 points); > 0: linearly resampled onto
- *                t_k = t_a + k (n_steps h) / n_out, k = 0..n_out-1 */
+ *                t_k = t_a + k (n_steps h) / n_out, k = 0..n_out-1
+ *   velocity     1: also accumulate the dipole velocity (App. C.2; read with sfhk_velocity); its
+ *                partial rows double the job's partial-row memory. 0: dipole only */
 typedef struct {
   double gamma;
   double kay_max;
@@ -89,6 +91,7 @@ typedef struct {
   double r_fp64;
   int32_t precision;
   int64_t n_out;
+  int32_t velocity;
 } sfhk_params;
 
 typedef struct {
@@ -119,8 +122,10 @@ void sfhk_ctx_destroy(sfhk_ctx* ctx);
  * out at once, while its memory returns to the pool when its last issued work completes). */
 size_t sfhk_ctx_bytes_in_use(const sfhk_ctx* ctx);
 
-/* Device bytes a job of this shape will hold (the admission test of a serving loop). */
-size_t sfhk_job_footprint(int64_t n_traj, int64_t n_steps, int64_t n_out, int32_t precision);
+/* Device bytes a job of this shape will hold (the admission test of a serving loop); velocity as
+ * in sfhk_params. */
+size_t sfhk_job_footprint(int64_t n_traj, int64_t n_steps, int64_t n_out, int32_t precision,
+                          int32_t velocity);
 
 /* Create a job: n_traj trajectories born at times t0[n_traj] with initial phase-space samples
  * q0[3][n_traj], p0[3][n_traj] (SoA, DEVICE) and complex Monte-Carlo/birth weights
@@ -188,6 +193,18 @@ void sfhk_batch_destroy(sfhk_batch* batch);
  * or n_steps + 1 when n_out = 0). f_out (nullable) receives F on the step grid as
  * [2][n_steps+1] (re block then im block). Requires a finished job (else SFHK_E_NOT_DONE). */
 sfhk_status sfhk_dipole(sfhk_job* job, double* d_out, double* f_out, void* stream);
+
+/* The dipole velocity of a job created with velocity = 1 (App. C.2): the fixed-order sum
+ * V(t_n) = sum_j w_j C_j(t_n) <psi0|k_z|p_t,q_t,gamma> e^{i(S_j - Ip t_n)} over the same
+ * trajectories, steps and removal rule as F, and v_out = -2 Re V on the job's output grid
+ * (as d_out of sfhk_dipole); vf_out (nullable) receives V as [2][n_steps+1]. The velocity element
+ * is the printed s-/p-wave form in the scale of the dipole element: for an s-wave ground state
+ * -2 i a sum_j alpha_j N_j E_j, for a p-wave one 2 i sum_j N_j E_j (2 gamma (gamma + alpha_j)
+ * - alpha_j a^2), with a = 2 gamma q_z + i p_z and N_j E_j the dipole element's primitive terms;
+ * that is, the printed forms times 2 (s) and 4 i gamma (p), the ratio of the two elements'
+ * written-out constants, so that both forms keep their relative phase. Requires a finished job
+ * (SFHK_E_NOT_DONE) created with velocity = 1 (else SFHK_E_INVALID). DEVICE pointers. */
+sfhk_status sfhk_velocity(sfhk_job* job, double* v_out, double* vf_out, void* stream);
 
 /* 1 once every trajectory of the job has been propagated to the end of the grid by the calls
  * issued so far (host-side bookkeeping: no synchronisation; the device work completes in stream

@@ -116,7 +116,7 @@ struct sfhk_batch {
 
 namespace {
 
-size_t footprint_parts(long long n_traj, long long n_steps, long long n_out,
+size_t footprint_parts(long long n_traj, long long n_steps, long long n_out, int velocity,
                        const std::vector<int>* tile_n0, long long* part_elems) {
   long long n_pad = (n_traj + kTile - 1) / kTile * kTile;
   long long n_tiles = n_pad / kTile;
@@ -126,6 +126,7 @@ size_t footprint_parts(long long n_traj, long long n_steps, long long n_out,
   } else {
     pe = n_tiles * (n_steps + 1);  // upper bound
   }
+  if (velocity) pe *= 2;  // the dipole velocity's rows follow the dipole's
   if (part_elems) *part_elems = pe;
   long long n_groups = (n_tiles + kReduceGroup - 1) / kReduceGroup;
   size_t b = 0;
@@ -301,10 +302,11 @@ void sfhk_ctx_destroy(sfhk_ctx* ctx) {
 
 size_t sfhk_ctx_bytes_in_use(const sfhk_ctx* ctx) { return ctx ? ctx->in_use : 0; }
 
-size_t sfhk_job_footprint(int64_t n_traj, int64_t n_steps, int64_t n_out, int32_t precision) {
+size_t sfhk_job_footprint(int64_t n_traj, int64_t n_steps, int64_t n_out, int32_t precision,
+                          int32_t velocity) {
   (void)precision;
   if (n_traj < 1 || n_steps < 1) return 0;
-  return footprint_parts(n_traj, n_steps, n_out, nullptr, nullptr);
+  return footprint_parts(n_traj, n_steps, n_out, velocity != 0, nullptr, nullptr);
 }
 
 int64_t sfhk_job_n_out(const sfhk_job* job) {
@@ -334,6 +336,7 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   if (params->precision != SFHK_FP64 && params->precision != SFHK_FP32_MIXED)
     return fail(SFHK_E_INVALID, "unknown precision");
   if (params->n_out < 0) return fail(SFHK_E_INVALID, "n_out must be >= 0");
+  if (params->velocity != 0 && params->velocity != 1) return fail(SFHK_E_INVALID, "velocity must be 0 or 1");
   for (int j = 0; j < ground->n_prim; ++j)
     if (!(ground->alpha[j] > 0.0)) return fail(SFHK_E_INVALID, "GTO exponents must be > 0");
 
@@ -419,7 +422,7 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
     off += NS - tile_n0[t] + 1;
   }
   long long part_elems = 0;
-  const size_t need = footprint_parts(N, NS, params->n_out, &tile_n0, &part_elems);
+  const size_t need = footprint_parts(N, NS, params->n_out, params->velocity != 0, &tile_n0, &part_elems);
   bool over = false;
   size_t left = 0;
   {
@@ -460,7 +463,11 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
     H.gto.D[k] = a / ga;
     H.gto.N[k] = ground->coef[k] * std::pow(ga, ground->l == 0 ? -2.5 : -3.5);
     H.gto.G2[k] = 2.0 * ga;
+    H.gto.Va[k] = a;
+    H.gto.Vg[k] = 2.0 * g * ga;
   }
+  H.gto.vel = params->velocity;
+  H.vel_off = params->velocity ? part_elems / 2 : 0;
   H.gto.two_gamma = 2.0 * g;
   H.gto.ip = ground->ip;
   H.gto.Amin = H.gto.A[0];
@@ -822,13 +829,15 @@ int32_t sfhk_batch_workers(const sfhk_batch* b) { return b ? b->n_workers : 0; }
 
 int32_t sfhk_job_is_done(const sfhk_job* job) { return job && job->done ? 1 : 0; }
 
-sfhk_status sfhk_dipole(sfhk_job* job, double* d_out, double* f_out, void* stream) {
-  TraceRange trace_("sfhk_dipole");
+// fixed-order sum of one set of partial rows (the dipole's, or the velocity's at part + vel_off)
+static sfhk_status reduce_rows(sfhk_job* job, bool velocity, double* d_out, double* f_out, void* stream) {
   if (!job || !d_out) return fail(SFHK_E_INVALID, "NULL argument");
   if (!job->done) return fail(SFHK_E_NOT_DONE, "job is not finished");
+  if (velocity && !job->host.vel_off) return fail(SFHK_E_INVALID, "job was created without velocity");
   HIP_TRY(hipSetDevice(job->ctx->device));
   hipStream_t st = (hipStream_t)stream;
-  const JobDev& H = job->host;
+  JobDev H = job->host;
+  if (velocity) H.part = job->host.part + job->host.vel_off;
   const int n_groups = (H.n_tiles + kReduceGroup - 1) / kReduceGroup;
   dim3 g1(blocks_for(H.n_steps + 1, 256), n_groups);
   hipLaunchKernelGGL(k_reduce_groups, g1, dim3(256), 0, st, H, job->gsum);
@@ -843,6 +852,16 @@ sfhk_status sfhk_dipole(sfhk_job* job, double* d_out, double* f_out, void* strea
     HIP_TRY(hipGetLastError());
   }
   return mark_use(job, st);
+}
+
+sfhk_status sfhk_dipole(sfhk_job* job, double* d_out, double* f_out, void* stream) {
+  TraceRange trace_("sfhk_dipole");
+  return reduce_rows(job, false, d_out, f_out, stream);
+}
+
+sfhk_status sfhk_velocity(sfhk_job* job, double* v_out, double* vf_out, void* stream) {
+  TraceRange trace_("sfhk_velocity");
+  return reduce_rows(job, true, v_out, vf_out, stream);
 }
 
 sfhk_status sfhk_spectrum(const double* d, int64_t n, double t_first, double dt, double tau_h,

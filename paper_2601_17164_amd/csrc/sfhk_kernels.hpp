@@ -37,8 +37,11 @@ struct GtoConst {
   double D[SFHK_MAX_PRIM];   // alpha_j / (gamma + alpha_j)
   double N[SFHK_MAX_PRIM];   // c_j (gamma + alpha_j)^(-5/2) (l = 0) or ^(-7/2) (l = 1)
   double G2[SFHK_MAX_PRIM];  // 2 (gamma + alpha_j)
+  double Va[SFHK_MAX_PRIM];  // dipole velocity: alpha_j
+  double Vg[SFHK_MAX_PRIM];  // dipole velocity: 2 gamma (gamma + alpha_j)
   double two_gamma, ip;
   double Amin, Bmin, cut_hi;  // all-primitives-skipped bound (see overlap_all_skipped)
+  int vel;                    // also evaluate the dipole-velocity element (App. C.2)
 };
 
 struct JobDev {
@@ -61,6 +64,7 @@ struct JobDev {
   int* tile_last;
   long long* row_off;
   double2* part;
+  long long vel_off;  // dipole velocity: its partial rows start at part + vel_off (0: none)
   unsigned long long* counters;  // steps_evaluated, kay_removed, nonfinite_removed, steps_fp64,
                                  // GTO primitives evaluated
 };
@@ -130,12 +134,23 @@ __device__ __forceinline__ void sincos_integrand(double x, double* sp, double* c
   *cp = ok ? c : __builtin_nan("");
 }
 
-__device__ __forceinline__ cplx overlap(const GtoConst& G, double cut, const double* q,
-                                        const double* p, double p2, double q2,
-                                        unsigned int& n_eval) {
+// The dipole element O = <psi0|z|p,q,gamma> (App. C.1) and, when G.vel is set, the
+// dipole-velocity element Ov = <psi0|k_z|p,q,gamma> (App. C.2) in the same scale. With
+// a = 2 gamma q_z + i p_z (so p_z - 2 i gamma q_z = -i a) and E_j the primitive's exponential:
+//   s-wave: O = a sum_j N_j E_j,                   Ov = -2 i a sum_j alpha_j N_j E_j
+//   p-wave: O = sum_j N_j E_j (a^2 + 2 (g + a_j)),  Ov = 2 i sum_j N_j E_j (2 g (g + a_j) - a_j a^2)
+// (the printed velocity forms times 2 and 4 i gamma, the ratio of the two elements' written-out
+// constants, so that the real part taken by "+ c.c." is the same for both forms).
+struct Elements {
+  cplx o, ov;
+};
+
+__device__ __forceinline__ Elements overlap(const GtoConst& G, double cut, const double* q,
+                                            const double* p, double p2, double q2,
+                                            unsigned int& n_eval) {
   double pq = SFHK_FMA(p[2], q[2], SFHK_FMA(p[1], q[1], p[0] * q[0]));
   cplx a = {G.two_gamma * q[2], p[2]};
-  cplx sum = {0.0, 0.0};
+  cplx sum = {0.0, 0.0}, sumv = {0.0, 0.0};
   cplx a2 = cmul(a, a);
   for (int j = 0; j < G.n_prim; ++j) {
     double re = -SFHK_FMA(p2, G.A[j], q2 * G.B[j]);
@@ -149,22 +164,42 @@ __device__ __forceinline__ cplx overlap(const GtoConst& G, double cut, const dou
       if (G.l == 0) {
         sum.re += E.re;
         sum.im += E.im;
+        if (G.vel) {
+          sumv.re += G.Va[j] * E.re;
+          sumv.im += G.Va[j] * E.im;
+        }
       } else {
         cplx b = {a2.re + G.G2[j], a2.im};
         cplx t = cmul(E, b);
         sum.re += t.re;
         sum.im += t.im;
+        if (G.vel) {
+          cplx bv = {G.Vg[j] - G.Va[j] * a2.re, -(G.Va[j] * a2.im)};
+          cplx tv = cmul(E, bv);
+          sumv.re += tv.re;
+          sumv.im += tv.im;
+        }
       }
     }
   }
-  return G.l == 0 ? cmul(a, sum) : sum;
+  Elements r;
+  if (G.l == 0) {
+    r.o = cmul(a, sum);
+    const cplx t = cmul(a, sumv);
+    r.ov = {2.0 * t.im, -2.0 * t.re};  // -2 i t
+  } else {
+    r.o = sum;
+    r.ov = {-2.0 * sumv.im, 2.0 * sumv.re};  // 2 i sumv
+  }
+  return r;
 }
 
-// The dipole integrand f = w C O e^{i (S - Ip t_n)} of one lane (0 when every primitive is skipped).
-// Kept out of line: it runs only for lanes near the ground state, and inlined, the constants and
-// temporaries of its exp and sincos would occupy registers for the whole step loop.
+// The integrands f = w C O e^{i (S - Ip t_n)} and fv = w C Ov e^{i (S - Ip t_n)} of one lane
+// (0 when every primitive is skipped). Kept out of line: it runs only for lanes near the ground
+// state, and inlined, the constants and temporaries of its exp and sincos would occupy registers
+// for the whole step loop.
 struct Contrib {
-  double re, im;
+  double re, im, vre, vim;
   unsigned int n_eval;
 };
 
@@ -174,15 +209,20 @@ __device__ __noinline__ Contrib contribution(const GtoConst* __restrict__ G, dou
                                              double wci) {
   const double q[3] = {qx, qy, qz}, p[3] = {px, py, pz};
   unsigned int n_eval = 0;
-  const cplx O = overlap(*G, cut, q, p, p2, q2, n_eval);
-  Contrib r = {0.0, 0.0, n_eval};
-  if (O.re != 0.0 || O.im != 0.0) {
+  const Elements el = overlap(*G, cut, q, p, p2, q2, n_eval);
+  Contrib r = {0.0, 0.0, 0.0, 0.0, n_eval};
+  if (el.o.re != 0.0 || el.o.im != 0.0 || el.ov.re != 0.0 || el.ov.im != 0.0) {
     const double ph = S - G->ip * tn;
     double sp, cp;
     sincos_integrand(ph, &sp, &cp);
-    const cplx f = cmul(cplx{wcr, wci}, cmul(O, cplx{cp, sp}));
+    const cplx f = cmul(cplx{wcr, wci}, cmul(el.o, cplx{cp, sp}));
     r.re = f.re;
     r.im = f.im;
+    if (G->vel) {
+      const cplx fv = cmul(cplx{wcr, wci}, cmul(el.ov, cplx{cp, sp}));
+      r.vre = fv.re;
+      r.vim = fv.im;
+    }
   }
   return r;
 }
@@ -211,6 +251,7 @@ struct QueueEntry {
 struct IntegrandQueue {
   QueueEntry e[kQueue];
   double2 f[kQueue];
+  double2 fv[kQueue];  // dipole velocity (jobs that ask for it)
 };
 
 typedef __attribute__((address_space(4))) const double* const_dptr;  // scalar (uniform) loads
@@ -256,6 +297,7 @@ __device__ __forceinline__ unsigned int queue_eval(IntegrandQueue& Q, int qn, in
     const Contrib cb = contribution(&J.gto, J.cut, qx, qy, qz, px, py, pz, p2, q2, x.d.x,
                                     J.t_a + x.e.y * J.h, x.d.y, x.e.x);
     Q.f[lane] = make_double2(cb.re, cb.im);
+    Q.fv[lane] = make_double2(cb.vre, cb.vim);
     n_eval = cb.n_eval;
   }
   __syncthreads();
@@ -269,6 +311,15 @@ __device__ __forceinline__ unsigned int queue_eval(IntegrandQueue& Q, int qn, in
         acc.y += v.y;
       }
       part[roff + ((long long)ns - t0)] = acc;
+      if (J.vel_off) {
+        double2 accv = Q.fv[lane];
+        for (int j = lane + 1; j < qn && Q.e[j].e.y == ns; ++j) {
+          const double2 v = Q.fv[j];
+          accv.x += v.x;
+          accv.y += v.y;
+        }
+        part[J.vel_off + roff + ((long long)ns - t0)] = accv;
+      }
     }
   }
   __syncthreads();

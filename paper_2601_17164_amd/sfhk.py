@@ -50,7 +50,8 @@ class _Grid(ct.Structure):
 
 class _Params(ct.Structure):
     _fields_ = [("gamma", ct.c_double), ("kay_max", ct.c_double), ("overlap_cut", ct.c_double),
-                ("r_fp64", ct.c_double), ("precision", ct.c_int32), ("n_out", ct.c_int64)]
+                ("r_fp64", ct.c_double), ("precision", ct.c_int32), ("n_out", ct.c_int64),
+                ("velocity", ct.c_int32)]
 
 
 class _Pulse(ct.Structure):
@@ -73,7 +74,8 @@ _SIGS = {
     "sfhk_ctx_create": (ct.c_int, [ct.c_int, ct.c_size_t, ct.POINTER(_VP)]),
     "sfhk_ctx_destroy": (None, [_VP]),
     "sfhk_ctx_bytes_in_use": (ct.c_size_t, [_VP]),
-    "sfhk_job_footprint": (ct.c_size_t, [ct.c_int64, ct.c_int64, ct.c_int64, ct.c_int32]),
+    "sfhk_job_footprint": (ct.c_size_t, [ct.c_int64, ct.c_int64, ct.c_int64, ct.c_int32,
+                                         ct.c_int32]),
     "sfhk_job_create": (ct.c_int, [_VP, ct.POINTER(_Potential), ct.POINTER(_Ground),
                                    ct.POINTER(_Grid), ct.POINTER(_Params), ct.c_int64, _VP, _VP,
                                    _VP, _VP, _VP, ct.POINTER(_VP)]),
@@ -81,6 +83,7 @@ _SIGS = {
     "sfhk_propagate": (ct.c_int, [_VP, ct.c_int64, _VP]),
     "sfhk_propagate_many": (ct.c_int, [ct.POINTER(_VP), ct.c_int32, ct.c_int64, _VP]),
     "sfhk_dipole": (ct.c_int, [_VP, _VP, _VP, _VP]),
+    "sfhk_velocity": (ct.c_int, [_VP, _VP, _VP, _VP]),
     "sfhk_job_n_out": (ct.c_int64, [_VP]),
     "sfhk_job_is_done": (ct.c_int32, [_VP]),
     "sfhk_job_checkpoint_bytes": (ct.c_int64, [_VP]),
@@ -126,8 +129,10 @@ def lib():
     return _lib
 
 
-def _check(status: int, where: str):
-    if status not in (SFHK_OK, SFHK_E_NOT_DONE):
+def _check(status: int, where: str, not_done_ok: bool = False):
+    """Raise SfhkError for a failed call. SFHK_E_NOT_DONE is a normal outcome only of the
+    propagation calls (more steps remain); everywhere else it is an error."""
+    if status != SFHK_OK and not (not_done_ok and status == SFHK_E_NOT_DONE):
         msg = lib().sfhk_last_error().decode(errors="replace")
         raise SfhkError(status, where, msg)
     return status
@@ -173,8 +178,10 @@ class Context:
             pass
 
 
-def job_footprint(n_traj: int, n_steps: int, n_out: int = 0, precision: int = SFHK_FP64) -> int:
-    return int(lib().sfhk_job_footprint(int(n_traj), int(n_steps), int(n_out), int(precision)))
+def job_footprint(n_traj: int, n_steps: int, n_out: int = 0, precision: int = SFHK_FP64,
+                  velocity: bool = False) -> int:
+    return int(lib().sfhk_job_footprint(int(n_traj), int(n_steps), int(n_out), int(precision),
+                                        int(bool(velocity))))
 
 
 @dataclass
@@ -199,7 +206,7 @@ class Job:
                  p0: torch.Tensor, w: Optional[torch.Tensor] = None, gamma: float = 0.5,
                  kay_max: float = 1e30, overlap_cut: float = 60.0, r_fp64: float = 2.0,
                  precision: int = SFHK_FP64, n_out: int = 0,
-                 stream: Optional[torch.cuda.Stream] = None):
+                 stream: Optional[torch.cuda.Stream] = None, velocity: bool = False):
         alpha = np.ascontiguousarray(ground.alpha, dtype=np.float64)
         coef = np.ascontiguousarray(ground.coef, dtype=np.float64)
         pot = _Potential(int(potential.kind), float(potential.z_inf), float(potential.z_in),
@@ -208,7 +215,7 @@ class Job:
                      coef.ctypes.data_as(ct.POINTER(ct.c_double)), float(ground.ip))
         grid = _Grid(float(grid_t_a), float(grid_h), int(n_steps), _dptr(e_half))
         prm = _Params(float(gamma), float(kay_max), float(overlap_cut), float(r_fp64),
-                      int(precision), int(n_out))
+                      int(precision), int(n_out), int(bool(velocity)))
         n = int(t0.shape[0])
         for name, t, shp in (("t0", t0, (n,)), ("q0", q0, (3, n)), ("p0", p0, (3, n))):
             if tuple(t.shape) != shp or t.dtype != torch.float64:
@@ -239,7 +246,7 @@ class Job:
     def propagate(self, max_steps: int = 0, stream=None) -> bool:
         """Returns True when every trajectory reached the end of the grid."""
         rc = _check(lib().sfhk_propagate(self.handle, int(max_steps), _stream_ptr(stream)),
-                    "sfhk_propagate")
+                    "sfhk_propagate", not_done_ok=True)
         return rc == SFHK_OK
 
     def dipole(self, want_f: bool = False, stream=None):
@@ -249,6 +256,15 @@ class Job:
         _check(lib().sfhk_dipole(self.handle, _dptr(d), _dptr(f), _stream_ptr(stream)),
                "sfhk_dipole")
         return (d, f) if want_f else d
+
+    def velocity(self, want_v: bool = False, stream=None):
+        """The dipole velocity -2 Re V on the output grid (and V on the step grid, [2, n+1])."""
+        dev = torch.device("cuda", self.ctx.device)
+        v = torch.empty(self.n_out, dtype=torch.float64, device=dev)
+        vf = torch.empty(2, self.n_steps + 1, dtype=torch.float64, device=dev) if want_v else None
+        _check(lib().sfhk_velocity(self.handle, _dptr(v), _dptr(vf), _stream_ptr(stream)),
+               "sfhk_velocity")
+        return (v, vf) if want_v else v
 
     def stats(self, stream=None) -> Stats:
         s = _Stats()
@@ -297,7 +313,7 @@ class Job:
 def propagate_many(jobs: Sequence[Job], max_steps: int = 0, stream=None) -> bool:
     arr = (_VP * len(jobs))(*[j.handle for j in jobs])
     rc = _check(lib().sfhk_propagate_many(arr, len(jobs), int(max_steps), _stream_ptr(stream)),
-                "sfhk_propagate_many")
+                "sfhk_propagate_many", not_done_ok=True)
     return rc == SFHK_OK
 
 
@@ -326,7 +342,8 @@ class Batch:
 
     def run(self, stream=None) -> bool:
         """One graph replay; True when every staged job has finished."""
-        rc = _check(lib().sfhk_batch_run(self.handle, _stream_ptr(stream)), "sfhk_batch_run")
+        rc = _check(lib().sfhk_batch_run(self.handle, _stream_ptr(stream)), "sfhk_batch_run",
+                    not_done_ok=True)
         return rc == SFHK_OK
 
     def close(self):
@@ -424,9 +441,9 @@ def to_device(inst, device="cuda:0"):
 
 
 def make_job(ctx: Context, inst, dev_arrays=None, precision=SFHK_FP64, n_out=None, stream=None,
-             r_fp64=2.0) -> Job:
+             r_fp64=2.0, velocity=False) -> Job:
     a = dev_arrays if dev_arrays is not None else to_device(inst, f"cuda:{ctx.device}")
     return Job(ctx, inst.potential, inst.ground, inst.grid.t_a, inst.grid.h, inst.grid.n_steps,
                a["e_half"], a["t0"], a["q0"], a["p0"], a["w"], inst.gamma, inst.kay_max,
                inst.overlap_cut, r_fp64, precision, inst.n_out if n_out is None else n_out,
-               stream)
+               stream, velocity)

@@ -1,0 +1,170 @@
+"""The dipole-velocity form (App. C.2) on the GPU: jobs created with velocity = 1 accumulate
+V(t_n) = sum_j w C <psi0|k_z|p_t,q_t,gamma> e^{i(S - Ip t_n)} beside F, read with sfhk_velocity.
+Parity with the oracle's velocity accumulation to the FP64 bar (relative L2 1e-9), with the
+trajectories bit for bit and F unchanged by the extra accumulator; Ehrenfest's relation for the
+field-free oscillator through the GPU; batch, chunking, checkpoint and error behaviour."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2601_17164_amd import inputs as I
+from tests.common import oracle_ground, oracle_potential, rel_l2, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def S():
+    require_gpu()
+    import torch
+    from paper_2601_17164_amd import sfhk
+    ctx = sfhk.Context(0)
+    yield sfhk, ctx, torch
+    ctx.close()
+
+
+def _oracle(inst, velocity=True):
+    return O.propagate(oracle_potential(inst.potential), oracle_ground(inst.ground), inst.e_half,
+                       inst.grid.t_a, inst.grid.h, inst.grid.n_steps, inst.t0, inst.q0, inst.p0,
+                       inst.w, inst.gamma, inst.kay_max, inst.overlap_cut, 0, velocity=velocity)
+
+
+def _run(S, inst, velocity=True, chunk=0, precision=0, dev_arrays=None):
+    sfhk, ctx, torch = S
+    job = sfhk.make_job(ctx, inst, dev_arrays=dev_arrays, precision=precision, velocity=velocity)
+    if chunk:
+        while not job.propagate(chunk):
+            pass
+    else:
+        assert job.propagate(0)
+    d, f = job.dipole(want_f=True)
+    out = dict(d=d.cpu().numpy(), F=(f[0] + 1j * f[1]).cpu().numpy())
+    if velocity:
+        v, vf = job.velocity(want_v=True)
+        out.update(v=v.cpu().numpy(), V=(vf[0] + 1j * vf[1]).cpu().numpy())
+    y, c, death = job.trajectories()
+    torch.cuda.synchronize()
+    out.update(y=y.cpu().numpy(), death=death.cpu().numpy())
+    job.close()
+    return out
+
+
+@pytest.mark.parametrize("which", ["softcore-s", "screened-p"])
+def test_velocity_matches_oracle(S, which):
+    if which == "softcore-s":
+        inst = I.config0()
+    else:
+        full = I.config1(n_out=0)
+        inst = I.config1_birth_subset(full, [100, 400, 511, 700], n_per_birth=64)
+    ref = _oracle(inst)
+    g = _run(S, inst)
+    np.testing.assert_array_equal(g["y"], ref.y_final)
+    np.testing.assert_array_equal(g["death"], ref.death)
+    ef, ev = rel_l2(g["F"], ref.F), rel_l2(g["V"], ref.V)
+    print(f"[{which}] rel-L2 F {ef:.3e}  V {ev:.3e}", flush=True)
+    assert ef <= TOL and ev <= TOL
+    assert rel_l2(g["v"], -2.0 * ref.V.real) <= TOL
+
+
+def test_velocity_leaves_the_dipole_unchanged(S):
+    inst = I.config0(n_birth=16, n_per_birth=32)
+    a = _run(S, inst, velocity=True)
+    b = _run(S, inst, velocity=False)
+    np.testing.assert_array_equal(a["d"], b["d"])
+    np.testing.assert_array_equal(a["F"], b["F"])
+
+
+def test_velocity_resampled_output_and_chunking(S):
+    full = I.config1()
+    inst = I.config1_birth_subset(full, [300, 600], n_per_birth=64)
+    one = _run(S, inst)
+    chunked = _run(S, inst, chunk=4000)
+    np.testing.assert_array_equal(one["V"], chunked["V"])
+    np.testing.assert_array_equal(one["v"], chunked["v"])
+    # resampled onto 2^15 points: linear interpolation of -2 Re V on the step grid
+    assert one["v"].shape == (inst.n_out,)
+    assert rel_l2(one["v"], O.resample(-2.0 * one["V"].real, inst.n_out)) <= 1e-14
+
+
+def test_velocity_is_the_derivative_for_the_field_free_oscillator(S):
+    """Oscillator w = 2 gamma with psi0 its ground state (Ip = -3w/2), no field: bra and ket evolve
+    under one Hamiltonian, so V = dF/dt = -i w F (Ehrenfest), through the GPU's accumulators."""
+    from tests.test_oracle_pins import GAMMA, _hk_quadrature
+    sfhk, ctx, torch = S
+    om = 2 * GAMMA
+    qi, pi_ = np.array([0.2, -0.1, 0.5]), np.array([0.1, 0.0, 0.2])
+    q0, p0, w = _hk_quadrature(qi, pi_, 5)
+    n = q0.shape[1]
+    n_steps, h = 60, 0.05
+    grid = I.Grid(0.0, h, n_steps)
+    inst = I.Instance("oscillator", I.Potential(I.POT_HARMONIC, 0, 0, 1, 0, om),
+                      I.Ground(0, np.array([om / 2]), np.array([1.0]), -1.5 * om),
+                      I.Pulse(800.0, 1e14, 2.0), grid, np.zeros(2 * n_steps + 1), np.zeros(n),
+                      q0, p0, w, GAMMA, 1e30, 1e9)
+    g = _run(S, inst)
+    ref = _oracle(inst)
+    assert rel_l2(g["V"], ref.V) <= TOL and rel_l2(g["F"], ref.F) <= TOL
+    assert np.max(np.abs(g["V"] - (-1j * om) * g["F"])) < 1e-3 * np.max(np.abs(g["V"]))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_velocity_in_a_batch_equals_alone(S, precision):
+    sfhk, ctx, torch = S
+    rng = np.random.default_rng(31)
+    insts = [I.random_instance(rng, 900 + k, f"v{k}", traj_scale=1.0 / 512) for k in range(3)]
+    alone = [_run(S, x, precision=precision) for x in insts]
+    jobs = [sfhk.make_job(ctx, x, precision=precision, velocity=(k != 1)) for k, x in enumerate(insts)]
+    b = sfhk.Batch(ctx, len(jobs), sum(sfhk.tiles_of(x) for x in insts), 900, 0)
+    b.set_jobs(jobs)
+    while not b.run():
+        pass
+    for k, (job, ref) in enumerate(zip(jobs, alone)):
+        np.testing.assert_array_equal(job.dipole().cpu().numpy(), ref["d"])
+        if k != 1:
+            np.testing.assert_array_equal(job.velocity().cpu().numpy(), ref["v"])
+        job.close()
+    b.close()
+
+
+def test_velocity_checkpoint_restore(S):
+    sfhk, ctx, torch = S
+    inst = I.config0(n_birth=16, n_per_birth=32)
+    ref = _run(S, inst)
+    a = sfhk.make_job(ctx, inst, velocity=True)
+    assert not a.propagate(800)
+    ck = a.checkpoint()
+    a.close()
+    b = sfhk.make_job(ctx, inst, velocity=True)
+    b.restore(ck)
+    while not b.propagate(600):
+        pass
+    np.testing.assert_array_equal(b.velocity().cpu().numpy(), ref["v"])
+    b.close()
+    plain = sfhk.make_job(ctx, inst, velocity=False)
+    with pytest.raises(sfhk.SfhkError) as ei:
+        plain.restore(ck)
+    assert ei.value.status == sfhk.SFHK_E_INVALID
+    plain.close()
+
+
+def test_velocity_errors_and_footprint(S):
+    sfhk, ctx, torch = S
+    inst = I.config0(n_birth=4, n_per_birth=16)
+    plain = sfhk.make_job(ctx, inst, velocity=False)
+    assert plain.propagate(0)
+    with pytest.raises(sfhk.SfhkError) as ei:
+        plain.velocity()
+    assert ei.value.status == sfhk.SFHK_E_INVALID
+    plain.close()
+    vj = sfhk.make_job(ctx, inst, velocity=True)
+    for read in (vj.velocity, vj.dipole):  # an unfinished job has no dipole or velocity yet
+        with pytest.raises(sfhk.SfhkError) as ei:
+            read()
+        assert ei.value.status == sfhk.SFHK_E_NOT_DONE
+    vj.close()
+    n, ns = inst.n_traj, inst.grid.n_steps
+    f0, f1 = sfhk.job_footprint(n, ns), sfhk.job_footprint(n, ns, velocity=True)
+    tiles = (n + 63) // 64
+    assert f1 - f0 == tiles * (ns + 1) * 16
