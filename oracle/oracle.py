@@ -53,7 +53,8 @@ class _Ground(ct.Structure):
 
 
 class _HK(ct.Structure):
-    _fields_ = [("gamma", ct.c_double), ("kay_max", ct.c_double), ("overlap_cut", ct.c_double)]
+    _fields_ = [("gamma", ct.c_double), ("kay_max", ct.c_double), ("overlap_cut", ct.c_double),
+                ("pw_mask", ct.c_int32), ("pw_radius", ct.c_double)]
 
 
 class _Grid(ct.Structure):
@@ -280,9 +281,10 @@ class PropagateResult:
 
 def propagate(pot: Potential, ground: Ground, e_half, t_a, h, n_steps, t0, q0, p0, w=None,
               gamma=0.5, kay_max=1e30, overlap_cut=60.0, n_threads=0,
-              velocity=False) -> PropagateResult:
+              velocity=False, pw_mask=0, pw_radius=3.0) -> PropagateResult:
     """Run the oracle over all trajectories; q0, p0 are [3, n] arrays, w is complex [n] or None.
-    velocity=True also accumulates the dipole velocity V(t_n) (App. C.2)."""
+    velocity=True also accumulates the dipole velocity V(t_n) (App. C.2). pw_mask != 0 keeps
+    only the steps of the selected partial waves near the core (``or_hk`` in sfhk_oracle.h)."""
     L = lib()
     e_half = _f64(e_half)
     if len(e_half) != 2 * n_steps + 1:
@@ -304,7 +306,7 @@ def propagate(pot: Potential, ground: Ground, e_half, t_a, h, n_steps, t0, q0, p
                  death.ctypes.data_as(ct.POINTER(ct.c_int64)), _p(yf), _p(cf))
     st = _Stats()
     grid = _Grid(float(t_a), float(h), int(n_steps), _p(e_half))
-    hk = _HK(float(gamma), float(kay_max), float(overlap_cut))
+    hk = _HK(float(gamma), float(kay_max), float(overlap_cut), int(pw_mask), float(pw_radius))
     g = ground.c()
     rc = L.or_propagate(ct.byref(pot.c()), ct.byref(g), ct.byref(hk), ct.byref(grid), n,
                         _p(t0), _p(q0), _p(p0), wp, int(n_threads), _p(f),
@@ -328,7 +330,8 @@ class TrajectoryRecord:
 
 
 def trajectory(pot: Potential, ground: Ground, e_half, t_a, h, n_steps, t0, q0, p0, w=1.0,
-               gamma=0.5, kay_max=1e30, overlap_cut=60.0) -> TrajectoryRecord:
+               gamma=0.5, kay_max=1e30, overlap_cut=60.0, pw_mask=0,
+               pw_radius=3.0) -> TrajectoryRecord:
     L = lib()
     e_half = _f64(e_half)
     nb = n_steps + 1
@@ -341,7 +344,7 @@ def trajectory(pot: Potential, ground: Ground, e_half, t_a, h, n_steps, t0, q0, 
     q0, p0 = _f64(q0), _f64(p0)
     wa = np.array([np.real(w), np.imag(w)], dtype=np.float64)
     grid = _Grid(float(t_a), float(h), int(n_steps), _p(e_half))
-    hk = _HK(float(gamma), float(kay_max), float(overlap_cut))
+    hk = _HK(float(gamma), float(kay_max), float(overlap_cut), int(pw_mask), float(pw_radius))
     g = ground.c()
     rc = L.or_trajectory(ct.byref(pot.c()), ct.byref(g), ct.byref(hk), ct.byref(grid),
                          float(t0), _p(q0), _p(p0), _p(wa), _p(y), _p(c), _p(f), _p(o), _p(d),

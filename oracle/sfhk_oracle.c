@@ -498,6 +498,26 @@ typedef struct {
   int8_t* alive_rec;
 } sink;
 
+/* ------------------------------------------------------------------------------------------ */
+/* partial-wave filter (Sec. III.A): near the core the Coulomb force dominates and the angular  */
+/* momentum l = |q x p| is nearly conserved, so each step near the core is labelled by the band */
+/* [k - 1/2, k + 1/2) that holds l (s, p, d, ... for k = 0, 1, 2, ...). The decision compares   */
+/* r^2 and l^2 with the squared radius and band edges, with r^2 and l^2 formed by the sequence  */
+/* below (a decision taken from floating point, so it is fixed like the trajectory arithmetic). */
+/* ------------------------------------------------------------------------------------------ */
+static int pw_keep(const or_hk* hk, const double* q, const double* p) {
+  if (!hk->pw_mask) return 1;
+  double r2 = fma(q[2], q[2], fma(q[1], q[1], q[0] * q[0]));
+  if (!(r2 < hk->pw_radius * hk->pw_radius)) return (hk->pw_mask >> 8) & 1;
+  double cx = fma(q[1], p[2], -(q[2] * p[1]));
+  double cy = fma(q[2], p[0], -(q[0] * p[2]));
+  double cz = fma(q[0], p[1], -(q[1] * p[0]));
+  double l2 = fma(cz, cz, fma(cy, cy, cx * cx));
+  int k = 0;
+  while (k < 7 && !(l2 < (k + 0.5) * (k + 0.5))) ++k;
+  return (hk->pw_mask >> k) & 1;
+}
+
 static void run_traj(const or_potential* pot, const or_ground* gs, const or_hk* hk,
                      const or_grid* g, double t0, const double* q0, const double* p0,
                      double complex w, sink* sk, traj_out* out) {
@@ -545,7 +565,8 @@ static void run_traj(const or_potential* pot, const or_ground* gs, const or_hk* 
     cprev = C;
     out->c = C;
 
-    double complex o = overlap_c(gs, hk->gamma, hk->overlap_cut, y, y + 3);
+    int keep = pw_keep(hk, y, y + 3);
+    double complex o = keep ? overlap_c(gs, hk->gamma, hk->overlap_cut, y, y + 3) : 0.0;
     double tn = g->t_a + (double)n * g->h;
     /* the ground state psi0 e^{i Ip t} sits in the bra of <Psi|z|Psi>, so it enters as e^{-i Ip t} */
     double complex f = w * (C.re + I * C.im) * o * cexp(I * (y[IY_S] - gs->ip * tn));
@@ -554,7 +575,7 @@ static void run_traj(const or_potential* pot, const or_ground* gs, const or_hk* 
       sk->acc_im[n] += cimagl(f);
     }
     if (sk->accv_re) {
-      double complex ov = overlap_v(gs, hk->gamma, hk->overlap_cut, y, y + 3);
+      double complex ov = keep ? overlap_v(gs, hk->gamma, hk->overlap_cut, y, y + 3) : 0.0;
       double complex fv = w * (C.re + I * C.im) * ov * cexp(I * (y[IY_S] - gs->ip * tn));
       sk->accv_re[n] += creall(fv);
       sk->accv_im[n] += cimagl(fv);
@@ -579,6 +600,7 @@ static double complex default_weight(const double* q0, const double* p0, int64_t
   double pq = p0[0] * q0[0] + p0[1] * q0[1] + p0[2] * q0[2];
   return cexp(I * pq) / (double)n;
 }
+
 
 /* ------------------------------------------------------------------------------------------ */
 /* many trajectories, threaded over contiguous blocks, long double accumulation               */

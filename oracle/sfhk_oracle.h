@@ -38,11 +38,17 @@ typedef struct {
 } or_ground;
 
 /* HK / reduction parameters: coherent-state width gamma (App. A), Kay limit D_t on |C|^2
- * (Sec. III.A), overlap skip threshold on -Re(exponent) of each GTO primitive. */
+ * (Sec. III.A), overlap skip threshold on -Re(exponent) of each GTO primitive, and the
+ * partial-wave filter of the returning trajectories (Sec. III.A): pw_mask = 0 keeps every step;
+ * otherwise a step's term counts when r < pw_radius and l = |q x p| lies in a selected band,
+ * bit k (k = 0..6) for l in [k - 1/2, k + 1/2) (s, p, d, ... waves; k = 0 is [0, 1/2)), bit 7
+ * for l >= 13/2, or, with bit 8, when r >= pw_radius. */
 typedef struct {
   double gamma;
   double kay_max;
   double overlap_cut;
+  int32_t pw_mask;
+  double pw_radius;
 } or_hk;
 
 /* Time grid: t_n = t_a + n h, n = 0..n_steps. The field table holds E_z(t_a + m h / 2),

@@ -84,6 +84,13 @@ MUTANTS = {
                                 "ov * cexp(I * (y[IY_S] + gs->ip * tn));"),
     "velocity: alpha factor dropped (s)": ("sum += gs->coef[j] * al * pow(ga, -2.5) * cexp(ex);",
                                            "sum += gs->coef[j] * pow(ga, -2.5) * cexp(ex);"),
+    "partial waves: band edges shifted": ("while (k < 7 && !(l2 < (k + 0.5) * (k + 0.5))) ++k;",
+                                          "while (k < 7 && !(l2 < (k + 1.0) * (k + 1.0))) ++k;"),
+    "partial waves: radius not squared": ("if (!(r2 < hk->pw_radius * hk->pw_radius))",
+                                          "if (!(r2 < hk->pw_radius))"),
+    "partial waves: cross product component": ("double cy = fma(q[2], p[0], -(q[0] * p[2]));",
+                                               "double cy = fma(q[2], p[0], q[0] * p[2]);"),
+    "partial waves: far bit ignored": ("return (hk->pw_mask >> 8) & 1;", "return 0;"),
     "sincos: quadrant 1 cosine sign": ("case 1: *s = cr; *c = -sr; break;",
                                        "case 1: *s = cr; *c = sr; break;"),
     "sincos: reduction drops the pi/2 tail": ("r = fma(-k, SINC_PIO2_3, r);", "r = r;"),

@@ -676,3 +676,77 @@ def test_spectrum_pure_tone_lands_in_its_bin():
     assert int(np.argmax(pw)) == k0
     # Hann window: the two neighbours carry a quarter of the peak amplitude
     assert abs(np.sqrt(pw[k0 + 1] / pw[k0]) - 0.5) < 1e-6
+
+
+# ------------------------------------------------------------------------------------------
+# partial-wave filter of the returning trajectories (Sec. III.A)
+# ------------------------------------------------------------------------------------------
+PW_S, PW_P, PW_D, PW_FAR = 1, 2, 4, 256
+
+
+def test_partial_wave_bands_of_free_motion():
+    """Without potential and field, L = q x p is conserved exactly along q = q0 + p0 t when q0 and
+    p0 lie on the axes: |L| = 0.3, 0.5, 1.0, 1.5 and 2.0 fall in the s, p (lower edge), p, d
+    (lower edge) and d bands. Inside a radius that holds the whole path, the band's mask keeps
+    every step (F equal to the unfiltered run) and the other masks keep none."""
+    G = _ground(I.gto_h1s())
+    n_steps, h = 40, 0.05
+    e = np.zeros(2 * n_steps + 1)
+    pot = O.Potential("none")
+    for lval, band in ((0.3, PW_S), (0.5, PW_P), (1.0, PW_P), (1.5, PW_D), (2.0, PW_D)):
+        q0 = np.array([[0.0], [0.0], [1.0]])  # x-z plane: the s-wave element needs q_z != 0
+        p0 = np.array([[lval], [0.0], [0.0]])
+        args = (pot, G, e, 0.0, h, n_steps, np.zeros(1), q0, p0)
+        full = O.propagate(*args, w=np.ones(1), overlap_cut=1e9).F
+        assert np.all(full != 0)
+        for mask in (PW_S, PW_P, PW_D, PW_S | PW_D, PW_FAR):
+            got = O.propagate(*args, w=np.ones(1), overlap_cut=1e9, pw_mask=mask, pw_radius=50.0).F
+            if mask & band:
+                np.testing.assert_array_equal(got, full)
+            else:
+                assert np.all(got == 0), (lval, mask)
+
+
+def test_partial_wave_masks_partition_the_dipole():
+    """Every step falls in exactly one of the bits 0..8 (bands inside the radius, or the far
+    region), so the nine single-bit runs add up to the unfiltered dipole, and the full mask
+    reproduces it bit for bit."""
+    inst = I.config0(n_birth=16, n_per_birth=8)
+    base = dict(pot=_pot(inst.potential), G=_ground(inst.ground))
+
+    def run(mask):
+        return O.propagate(base["pot"], base["G"], inst.e_half, inst.grid.t_a, inst.grid.h,
+                           inst.grid.n_steps, inst.t0, inst.q0, inst.p0, pw_mask=mask,
+                           pw_radius=3.0, n_threads=1).F
+    full = run(0)
+    np.testing.assert_array_equal(run(0x1FF), full)
+    parts = [run(1 << k) for k in range(9)]
+    total = np.sum(parts, axis=0)
+    assert np.max(np.abs(total - full)) <= 1e-12 * np.max(np.abs(full))
+    assert np.max(np.abs(parts[1])) > 0 and np.max(np.abs(parts[8])) > 0
+
+
+def test_partial_wave_decisions_from_the_recorded_path():
+    """Brute force: from a recorded soft-core trajectory, a step is kept by the p-wave mask
+    exactly when |q| < 3 and |q x p| lies in [1/2, 3/2) (steps whose r or l is within 1e-9 of a
+    band edge are not judged)."""
+    inst = I.config0(n_birth=8, n_per_birth=4)
+    G, pot = _ground(inst.ground), _pot(inst.potential)
+    checked = 0
+    for j in range(inst.n_traj):
+        args = (pot, G, inst.e_half, inst.grid.t_a, inst.grid.h, inst.grid.n_steps, inst.t0[j],
+                inst.q0[:, j], inst.p0[:, j])
+        rec = O.trajectory(*args, overlap_cut=1e9)
+        filt = O.trajectory(*args, overlap_cut=1e9, pw_mask=PW_P, pw_radius=3.0)
+        q, p = rec.y[:, 0:3], rec.y[:, 3:6]
+        r = np.linalg.norm(q, axis=1)
+        l = np.linalg.norm(np.cross(q, p), axis=1)
+        want = (r < 3.0) & (l >= 0.5) & (l < 1.5)
+        clear = (np.abs(r - 3.0) > 1e-9) & (np.abs(l - 0.5) > 1e-9) & (np.abs(l - 1.5) > 1e-9)
+        alive = rec.alive & (rec.f != 0)
+        m = alive & clear
+        kept = filt.f != 0
+        np.testing.assert_array_equal(kept[m], want[m])
+        np.testing.assert_array_equal(filt.f[m & want], rec.f[m & want])
+        checked += int(m.sum())
+    assert checked > 1000
