@@ -83,7 +83,16 @@ typedef struct {
  *   n_out        0: dipole on the step grid (n_steps + 1 points); > 0: linearly resampled onto
  *                t_k = t_a + k (n_steps h) / n_out, k = 0..n_out-1
  *   velocity     1: also accumulate the dipole velocity (App. C.2; read with sfhk_velocity); its
- *                partial rows double the job's partial-row memory. 0: dipole only */
+ *                partial rows double the job's partial-row memory. 0: dipole only
+ *   pw_mask      partial-wave filter of the returning trajectories (Sec. III.A). 0: every step
+ *                counts. Otherwise a step's dipole (and velocity) term counts only when
+ *                r < pw_radius and l = |q x p| lies in a selected band: bit k (k = 0..6) for
+ *                l in [k - 1/2, k + 1/2) (k = 0: [0, 1/2); s, p, d, ... waves), bit 7 for
+ *                l >= 13/2; bit 8 keeps the steps at r >= pw_radius. 0x1FF equals no filter. The
+ *                comparison is of r^2 = fma(q_z, q_z, fma(q_y, q_y, q_x q_x)) and
+ *                l^2 = fma(L_z, L_z, fma(L_y, L_y, L_x L_x)), L_x = fma(q_y, p_z, -(q_z p_y)) and
+ *                cyclic, with pw_radius^2 and the squared band edges.
+ *   pw_radius    radius of the filter's near-core region (> 0 when pw_mask != 0) */
 typedef struct {
   double gamma;
   double kay_max;
@@ -92,6 +101,8 @@ typedef struct {
   int32_t precision;
   int64_t n_out;
   int32_t velocity;
+  int32_t pw_mask;
+  double pw_radius;
 } sfhk_params;
 
 typedef struct {

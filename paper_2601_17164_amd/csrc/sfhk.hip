@@ -337,6 +337,9 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
     return fail(SFHK_E_INVALID, "unknown precision");
   if (params->n_out < 0) return fail(SFHK_E_INVALID, "n_out must be >= 0");
   if (params->velocity != 0 && params->velocity != 1) return fail(SFHK_E_INVALID, "velocity must be 0 or 1");
+  if (params->pw_mask < 0 || params->pw_mask > 0x1FF) return fail(SFHK_E_INVALID, "pw_mask must be in [0, 0x1FF]");
+  if (params->pw_mask && !(params->pw_radius > 0.0 && std::isfinite(params->pw_radius)))
+    return fail(SFHK_E_INVALID, "pw_radius must be finite and > 0");
   for (int j = 0; j < ground->n_prim; ++j)
     if (!(ground->alpha[j] > 0.0)) return fail(SFHK_E_INVALID, "GTO exponents must be > 0");
 
@@ -467,6 +470,8 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
     H.gto.Vg[k] = 2.0 * g * ga;
   }
   H.gto.vel = params->velocity;
+  H.pw_mask = params->pw_mask;
+  H.pw_r2 = params->pw_mask ? params->pw_radius * params->pw_radius : 0.0;
   H.vel_off = params->velocity ? part_elems / 2 : 0;
   H.gto.two_gamma = 2.0 * g;
   H.gto.ip = ground->ip;

@@ -65,6 +65,8 @@ struct JobDev {
   long long* row_off;
   double2* part;
   long long vel_off;  // dipole velocity: its partial rows start at part + vel_off (0: none)
+  int pw_mask;        // partial-wave filter (0: every step counts), see pw_keep
+  double pw_r2;       // its radius, squared
   unsigned long long* counters;  // steps_evaluated, kay_removed, nonfinite_removed, steps_fp64,
                                  // GTO primitives evaluated
 };
@@ -282,6 +284,24 @@ __device__ __forceinline__ void queue_push(IntegrandQueue& Q, int idx, double qx
   x.e = make_double2(wC.im, (double)n);
 }
 
+// Partial-wave filter (Sec. III.A): near the core the angular momentum l = |q x p| is nearly
+// conserved, and each step there is labelled by the band [k - 1/2, k + 1/2) that holds l (s, p,
+// d, ... for k = 0, 1, 2, ...; bit 7 for l >= 13/2). A step's terms count when r^2 < pw_r2 and the
+// band's bit is set, or, beyond the radius, when bit 8 is set. r^2 and l^2 are formed by one fixed
+// sequence and compared with the squared edges, so the decision is reproducible bit for bit.
+__device__ __forceinline__ bool pw_keep(const JobDev& J, double qx, double qy, double qz, double px,
+                                        double py, double pz) {
+  const double r2 = SFHK_FMA(qz, qz, SFHK_FMA(qy, qy, qx * qx));
+  if (!(r2 < J.pw_r2)) return (J.pw_mask >> 8) & 1;
+  const double cx = SFHK_FMA(qy, pz, -(qz * py));
+  const double cy = SFHK_FMA(qz, px, -(qx * pz));
+  const double cz = SFHK_FMA(qx, py, -(qy * px));
+  const double l2 = SFHK_FMA(cz, cz, SFHK_FMA(cy, cy, cx * cx));
+  int k = 0;
+  while (k < 7 && !(l2 < (k + 0.5) * (k + 0.5))) ++k;
+  return (J.pw_mask >> k) & 1;
+}
+
 // evaluates the qn queued entries (one per lane) and stores their per-step sums; returns this
 // lane's count of evaluated primitives
 __device__ __forceinline__ unsigned int queue_eval(IntegrandQueue& Q, int qn, int lane,
@@ -294,8 +314,10 @@ __device__ __forceinline__ unsigned int queue_eval(IntegrandQueue& Q, int qn, in
     const double qx = x.a.x, qy = x.a.y, qz = x.b.x, px = x.b.y, py = x.c.x, pz = x.c.y;
     const double p2 = SFHK_FMA(pz, pz, SFHK_FMA(py, py, px * px));
     const double q2 = SFHK_FMA(qz, qz, SFHK_FMA(qy, qy, qx * qx));
-    const Contrib cb = contribution(&J.gto, J.cut, qx, qy, qz, px, py, pz, p2, q2, x.d.x,
-                                    J.t_a + x.e.y * J.h, x.d.y, x.e.x);
+    Contrib cb = {0.0, 0.0, 0.0, 0.0, 0u};
+    if (!J.pw_mask || pw_keep(J, qx, qy, qz, px, py, pz))
+      cb = contribution(&J.gto, J.cut, qx, qy, qz, px, py, pz, p2, q2, x.d.x, J.t_a + x.e.y * J.h,
+                        x.d.y, x.e.x);
     Q.f[lane] = make_double2(cb.re, cb.im);
     Q.fv[lane] = make_double2(cb.vre, cb.vim);
     n_eval = cb.n_eval;

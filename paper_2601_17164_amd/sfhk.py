@@ -24,6 +24,8 @@ SFHK_OK, SFHK_E_INVALID, SFHK_E_NOMEM, SFHK_E_DEVICE, SFHK_E_NOT_DONE, SFHK_E_BU
     0, -1, -2, -3, -4, -5)
 SFHK_FP64, SFHK_FP32_MIXED = 0, 1
 SFHK_BIRTH_GTO, SFHK_BIRTH_MODIFIED = 0, 1
+# partial-wave filter bits (sfhk_params.pw_mask): bands l in [k - 1/2, k + 1/2), far region
+PW_S, PW_P, PW_D, PW_FAR, PW_ALL = 1 << 0, 1 << 1, 1 << 2, 1 << 8, 0x1FF
 SFHK_MAX_PRIM = 8
 
 
@@ -51,7 +53,7 @@ class _Grid(ct.Structure):
 class _Params(ct.Structure):
     _fields_ = [("gamma", ct.c_double), ("kay_max", ct.c_double), ("overlap_cut", ct.c_double),
                 ("r_fp64", ct.c_double), ("precision", ct.c_int32), ("n_out", ct.c_int64),
-                ("velocity", ct.c_int32)]
+                ("velocity", ct.c_int32), ("pw_mask", ct.c_int32), ("pw_radius", ct.c_double)]
 
 
 class _Pulse(ct.Structure):
@@ -206,7 +208,8 @@ class Job:
                  p0: torch.Tensor, w: Optional[torch.Tensor] = None, gamma: float = 0.5,
                  kay_max: float = 1e30, overlap_cut: float = 60.0, r_fp64: float = 2.0,
                  precision: int = SFHK_FP64, n_out: int = 0,
-                 stream: Optional[torch.cuda.Stream] = None, velocity: bool = False):
+                 stream: Optional[torch.cuda.Stream] = None, velocity: bool = False,
+                 pw_mask: int = 0, pw_radius: float = 3.0):
         alpha = np.ascontiguousarray(ground.alpha, dtype=np.float64)
         coef = np.ascontiguousarray(ground.coef, dtype=np.float64)
         pot = _Potential(int(potential.kind), float(potential.z_inf), float(potential.z_in),
@@ -215,7 +218,8 @@ class Job:
                      coef.ctypes.data_as(ct.POINTER(ct.c_double)), float(ground.ip))
         grid = _Grid(float(grid_t_a), float(grid_h), int(n_steps), _dptr(e_half))
         prm = _Params(float(gamma), float(kay_max), float(overlap_cut), float(r_fp64),
-                      int(precision), int(n_out), int(bool(velocity)))
+                      int(precision), int(n_out), int(bool(velocity)), int(pw_mask),
+                      float(pw_radius))
         n = int(t0.shape[0])
         for name, t, shp in (("t0", t0, (n,)), ("q0", q0, (3, n)), ("p0", p0, (3, n))):
             if tuple(t.shape) != shp or t.dtype != torch.float64:
@@ -441,9 +445,9 @@ def to_device(inst, device="cuda:0"):
 
 
 def make_job(ctx: Context, inst, dev_arrays=None, precision=SFHK_FP64, n_out=None, stream=None,
-             r_fp64=2.0, velocity=False) -> Job:
+             r_fp64=2.0, velocity=False, pw_mask=0, pw_radius=3.0) -> Job:
     a = dev_arrays if dev_arrays is not None else to_device(inst, f"cuda:{ctx.device}")
     return Job(ctx, inst.potential, inst.ground, inst.grid.t_a, inst.grid.h, inst.grid.n_steps,
                a["e_half"], a["t0"], a["q0"], a["p0"], a["w"], inst.gamma, inst.kay_max,
                inst.overlap_cut, r_fp64, precision, inst.n_out if n_out is None else n_out,
-               stream, velocity)
+               stream, velocity, pw_mask, pw_radius)
