@@ -108,6 +108,8 @@ def lib():
                                    ct.POINTER(_Grid), ct.c_int64, P, P, P, P, ct.c_int, P, P,
                                    ct.POINTER(_Diag), ct.POINTER(_Stats)]
         L.or_overlap_v.argtypes = [ct.POINTER(_Ground), D, D, P, P, P]
+        L.or_gabor.restype = ct.c_int
+        L.or_gabor.argtypes = [P, ct.c_int64, D, D, D, D, D, ct.c_int64, D, ct.c_int64, P, P]
         L.or_trajectory.restype = ct.c_int
         L.or_trajectory.argtypes = [ct.POINTER(_Potential), ct.POINTER(_Ground), ct.POINTER(_HK),
                                     ct.POINTER(_Grid), D, P, P, P, P, P, P, P, P,
@@ -381,3 +383,16 @@ def spectrum(d, t_first, dt, tau_h, n_fft=0):
     if rc != 0:
         raise RuntimeError("or_spectrum failed")
     return om, pw, xx[0::2] + 1j * xx[1::2]
+
+
+def gabor(d, t_first, dt, sigma, tc_first, tc_step, n_c, w_step, n_w):
+    """Gabor transform (see ``or_gabor``): returns (power [n_c, n_w], G complex [n_c, n_w])."""
+    d = _f64(d)
+    pw = np.zeros((n_c, n_w))
+    g = np.zeros((n_c, n_w, 2))
+    rc = lib().or_gabor(_p(d), d.shape[0], float(t_first), float(dt), float(sigma),
+                        float(tc_first), float(tc_step), int(n_c), float(w_step), int(n_w),
+                        _p(pw), _p(g))
+    if rc != 0:
+        raise ValueError(f"or_gabor failed ({rc})")
+    return pw, g[..., 0] + 1j * g[..., 1]

@@ -1059,3 +1059,38 @@ int or_sfa_birth(const or_pulse* pl, const or_ground* gs, int32_t mode, int64_t 
   free(th);
   return 0;
 }
+
+/* ------------------------------------------------------------------------------------------ */
+/* Gabor time-frequency transform (the emission-time analysis of Sec. III.A):                  */
+/*   G(t_c, w_k) = dt sum_n d_n exp(-(t_n - t_c)^2 / (2 sigma^2)) exp(i w_k t_n),               */
+/* t_n = t_first + n dt, t_c = tc_first + c tc_step, w_k = k w_step; the plain sum over every   */
+/* sample, in sample order.                                                                    */
+/* ------------------------------------------------------------------------------------------ */
+int or_gabor(const double* d, int64_t n, double t_first, double dt, double sigma, double tc_first,
+             double tc_step, int64_t n_c, double w_step, int64_t n_w, double* power_out,
+             double* g_out) {
+  if (n < 0 || n_c < 0 || n_w < 0 || !(sigma > 0.0) || !(dt > 0.0)) return -1;
+  double* win = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  if (!win) return -2;
+  for (int64_t c = 0; c < n_c; ++c) {
+    double tc = tc_first + (double)c * tc_step;
+    for (int64_t i = 0; i < n; ++i) {
+      double u = (t_first + (double)i * dt - tc) / sigma;
+      win[i] = exp(-0.5 * u * u);
+    }
+    for (int64_t k = 0; k < n_w; ++k) {
+      double w = (double)k * w_step;
+      double complex acc = 0.0;
+      for (int64_t i = 0; i < n; ++i) acc += d[i] * win[i] * cexp(I * (w * (t_first + (double)i * dt)));
+      acc *= dt;
+      size_t o = (size_t)c * (size_t)n_w + (size_t)k;
+      power_out[o] = creal(acc) * creal(acc) + cimag(acc) * cimag(acc);
+      if (g_out) {
+        g_out[2 * o] = creal(acc);
+        g_out[2 * o + 1] = cimag(acc);
+      }
+    }
+  }
+  free(win);
+  return 0;
+}

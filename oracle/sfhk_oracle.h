@@ -172,6 +172,15 @@ void or_resample(const double* d, int64_t n_steps, int64_t n_out, double* out);
 int or_spectrum(const double* d, int64_t n, double t_first, double dt, double tau_h,
                 int64_t n_fft, double* omega_out, double* power_out, double* x_out);
 
+/* Gabor time-frequency transform (the emission-time analysis of Sec. III.A):
+ *   G(t_c, w_k) = dt sum_n d_n exp(-(t_n - t_c)^2 / (2 sigma^2)) exp(i w_k t_n),
+ * t_n = t_first + n dt (n samples), t_c = tc_first + c tc_step (c < n_c), w_k = k w_step (k < n_w).
+ * power_out[n_c][n_w] = |G|^2; g_out (nullable) [n_c][n_w][2] = (Re G, Im G). Direct sum over
+ * every sample. Returns 0 or a negative error code (sigma <= 0, dt <= 0, negative counts). */
+int or_gabor(const double* d, int64_t n, double t_first, double dt, double sigma, double tc_first,
+             double tc_step, int64_t n_c, double w_step, int64_t n_w, double* power_out,
+             double* g_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -69,6 +69,12 @@ static int run_case(const char* name, const or_potential* pot, const or_ground* 
          *x = malloc(sizeof(double) * 2 * (size_t)nk);
   rc = or_spectrum(dr, n_out, t_a, T / (double)n_out, 0.5 * T, n_out, om, pw, x);
   if (rc) return rc;
+  double *gp = malloc(sizeof(double) * 8 * 16), *gg = malloc(sizeof(double) * 2 * 8 * 16);
+  rc = or_gabor(dr, n_out, t_a, T / (double)n_out, 0.1 * T, t_a, T / 8.0, 8, 0.2, 16, gp, gg);
+  if (rc) return rc;
+  printf("%s gabor %.17g\n", name, checksum(gp, 8 * 16));
+  free(gp);
+  free(gg);
   /* one recorded trajectory */
   double *yr = calloc((size_t)(43 * (ns + 1)), sizeof(double)), *cr = calloc((size_t)(2 * (ns + 1)), sizeof(double));
   double *fr = calloc((size_t)(2 * (ns + 1)), sizeof(double)), *orr = calloc((size_t)(2 * (ns + 1)), sizeof(double));

@@ -91,6 +91,12 @@ MUTANTS = {
     "partial waves: cross product component": ("double cy = fma(q[2], p[0], -(q[0] * p[2]));",
                                                "double cy = fma(q[2], p[0], q[0] * p[2]);"),
     "partial waves: far bit ignored": ("return (hk->pw_mask >> 8) & 1;", "return 0;"),
+    "gabor: window width": ("win[i] = exp(-0.5 * u * u);", "win[i] = exp(-u * u);"),
+    "gabor: phase sign": ("cexp(I * (w * (t_first + (double)i * dt)))",
+                          "cexp(-I * (w * (t_first + (double)i * dt)))"),
+    "gabor: centre grid": ("double tc = tc_first + (double)c * tc_step;",
+                           "double tc = tc_first + (double)(c + 1) * tc_step;"),
+    "gabor: missing dt": ("    acc *= dt;\n", "\n"),
     "sincos: quadrant 1 cosine sign": ("case 1: *s = cr; *c = -sr; break;",
                                        "case 1: *s = cr; *c = sr; break;"),
     "sincos: reduction drops the pi/2 tail": ("r = fma(-k, SINC_PIO2_3, r);", "r = r;"),

@@ -750,3 +750,47 @@ def test_partial_wave_decisions_from_the_recorded_path():
         np.testing.assert_array_equal(filt.f[m & want], rec.f[m & want])
         checked += int(m.sum())
     assert checked > 1000
+
+
+# ------------------------------------------------------------------------------------------
+# Gabor time-frequency transform (emission-time analysis, Sec. III.A)
+# ------------------------------------------------------------------------------------------
+def _gabor_packet(t1, tau, w0, tc, sigma, w):
+    """int exp(-(t-t1)^2/(2 tau^2)) cos(w0 t) exp(-(t-tc)^2/(2 sigma^2)) exp(i w t) dt in closed
+    form: each of cos's two exponentials makes a Gaussian integral sqrt(pi/a) e^{b^2/(4a) - c}."""
+    a = 1 / (2 * tau ** 2) + 1 / (2 * sigma ** 2)
+    c = t1 ** 2 / (2 * tau ** 2) + tc ** 2 / (2 * sigma ** 2)
+    out = 0j
+    for sgn in (1, -1):
+        b = t1 / tau ** 2 + tc / sigma ** 2 + 1j * (w + sgn * w0)
+        out += 0.5 * np.sqrt(np.pi / a) * np.exp(b * b / (4 * a) - c)
+    return out
+
+
+def test_gabor_of_a_wave_packet_is_its_closed_form():
+    """A Gaussian wave packet sampled finely on a grid that holds it and every window: the sum
+    equals the integral to rounding (the integrand is band-limited far below the grid's Nyquist
+    frequency), so G matches the closed form, peaks at the packet's time and carrier, and its
+    phase follows e^{i w t_c}."""
+    dt, n = 0.05, 6001
+    t = -150.0 + dt * np.arange(n)
+    t1, tau, w0, sigma = 12.0, 9.0, 1.3, 6.0
+    d = np.exp(-(t - t1) ** 2 / (2 * tau ** 2)) * np.cos(w0 * t)
+    n_c, n_w, tc0, tcs, ws = 21, 40, -40.0, 5.0, 0.07
+    pw, G = O.gabor(d, t[0], dt, sigma, tc0, tcs, n_c, ws, n_w)
+    ref = np.array([[_gabor_packet(t1, tau, w0, tc0 + c * tcs, sigma, k * ws) for k in range(n_w)]
+                    for c in range(n_c)])
+    assert np.max(np.abs(G - ref)) <= 1e-12 * np.max(np.abs(ref))
+    np.testing.assert_allclose(pw, np.abs(G) ** 2, rtol=1e-14, atol=0)
+    c, k = np.unravel_index(np.argmax(pw), pw.shape)
+    assert abs(tc0 + c * tcs - t1) <= tcs / 2 and abs(k * ws - w0) <= ws / 2
+
+
+def test_gabor_edges_and_errors():
+    pw, G = O.gabor(np.zeros(100), 0.0, 0.1, 2.0, 0.0, 1.0, 3, 0.5, 4)
+    assert np.all(pw == 0) and np.all(G == 0)
+    pw, G = O.gabor(np.ones(10), 0.0, 0.1, 2.0, 0.0, 1.0, 0, 0.5, 0)
+    assert pw.shape == (0, 0)
+    for bad in ((0.0, 0.1), (-1.0, 0.1), (2.0, 0.0)):
+        with pytest.raises(ValueError):
+            O.gabor(np.ones(10), 0.0, bad[1], bad[0], 0.0, 1.0, 2, 0.5, 2)
