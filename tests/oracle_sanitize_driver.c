@@ -72,7 +72,7 @@ static int run_case(const char* name, const or_potential* pot, const or_ground* 
   double *gp = malloc(sizeof(double) * 8 * 16), *gg = malloc(sizeof(double) * 2 * 8 * 16);
   rc = or_gabor(dr, n_out, t_a, T / (double)n_out, 0.1 * T, t_a, T / 8.0, 8, 0.2, 16, gp, gg);
   if (rc) return rc;
-  printf("%s gabor %.17g\n", name, checksum(gp, 8 * 16));
+  const double gsum = checksum(gp, 8 * 16);
   free(gp);
   free(gg);
   /* one recorded trajectory */
@@ -83,10 +83,10 @@ static int run_case(const char* name, const or_potential* pot, const or_ground* 
   const double q1[3] = {q0[0], q0[n], q0[2 * n]}, p1[3] = {p0[0], p0[n], p0[2 * n]}, w1[2] = {1.0, 0.0};
   rc = or_trajectory(pot, gs, &hk, &grid, t0[0], q1, p1, w1, yr, cr, fr, orr, dr2, al);
   if (rc) return rc;
-  printf("%s steps=%lld kay=%lld nonfinite=%lld |F|=%.17g |V|=%.17g |d|=%.17g |P|=%.17g |y|=%.17g |traj|=%.17g\n",
+  printf("%s steps=%lld kay=%lld nonfinite=%lld |F|=%.17g |V|=%.17g |d|=%.17g |P|=%.17g |G|=%.17g |y|=%.17g |traj|=%.17g\n",
          name, (long long)st.steps_evaluated, (long long)st.kay_removed,
          (long long)st.nonfinite_removed, checksum(f, 2 * (ns + 1)), checksum(v, 2 * (ns + 1)),
-         checksum(dr, n_out), checksum(pw, nk), checksum(y, 43 * n), checksum(yr, 43 * (ns + 1)));
+         checksum(dr, n_out), checksum(pw, nk), gsum, checksum(y, 43 * n), checksum(yr, 43 * (ns + 1)));
   free(v);
   free(e_half); free(t0); free(q0); free(p0); free(f); free(n0); free(death); free(y); free(c);
   free(d); free(dr); free(om); free(pw); free(x); free(yr); free(cr); free(fr); free(orr); free(dr2);
