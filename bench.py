@@ -298,7 +298,44 @@ def velocity_results(ctx, stream, inst, arrays, plain_ms):
     ms = ev[0].elapsed_time(ev[1])
     return {"propagate_kernel_ms": ms, "dipole_only_kernel_ms": plain_ms,
             "overhead": ms / plain_ms - 1.0,
-            "trajectory_steps_per_s": st.steps_evaluated / ms * 1e3, "finite": ok}
+            "trajectory_steps_per_s": st.steps_evaluated / ms * 1e3, "finite": ok,
+            "gabor": gabor_results(stream, inst, v)}
+
+
+GABOR_CUT = 9.2  # the kernel sums the samples within this many sigma of each centre
+
+
+def gabor_results(stream, inst, v, reps=5):
+    """Gabor map (sfhk_gabor) of the dipole velocity on the 2^15-point output grid: 512 centres
+    over the pulse, 2048 frequencies in steps of omega/10 (beyond the cutoff), sigma = 1/(3 omega).
+    Mean kernel time over `reps` launches (HIP events on the launch stream) and the algorithmic
+    rate at 10 FP64 operations per (centre, frequency, sample) update."""
+    import torch
+    from paper_2601_17164_amd import sfhk
+    T = inst.grid.h * inst.grid.n_steps
+    n = int(v.shape[0])
+    dt = T / n
+    w0 = inst.pulse.omega
+    sigma, n_c, n_w, ws = 1.0 / (3.0 * w0), 512, 2048, w0 / 10
+    tc0, tcs = inst.grid.t_a + T / 1024, T / 512
+    args = (inst.grid.t_a, dt, sigma, tc0, tcs, n_c, ws, n_w)
+    sfhk.gabor(v, *args, stream=stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for _ in range(reps):
+        pw, G = sfhk.gabor(v, *args, stream=stream)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    tc = tc0 + tcs * np.arange(n_c)
+    lo = np.ceil(np.clip((tc - GABOR_CUT * sigma - inst.grid.t_a) / dt, 0, n))
+    hi = np.floor(np.clip((tc + GABOR_CUT * sigma - inst.grid.t_a) / dt, -1, n - 1))
+    updates = float(np.sum(np.maximum(hi - lo + 1, 0))) * n_w
+    fl = 10.0 * updates
+    return {"n": n, "n_centres": n_c, "n_freq": n_w, "sigma": sigma, "kernel_ms": ms,
+            "updates": updates, "achieved_tflops": fl / (ms * 1e-3) / 1e12,
+            "frac_of_fp64_vector_peak": fl / (ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+            "finite": bool(torch.isfinite(pw).all())}
 
 
 def sfa_results(ctx, stream, reps):

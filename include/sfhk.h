@@ -281,6 +281,18 @@ const char* sfhk_status_string(sfhk_status s);
 sfhk_status sfhk_traj_exp(const double* x, double* y, int64_t n, void* stream);
 sfhk_status sfhk_traj_rsqrt(const double* x, double* y, int64_t n, void* stream);
 
+/* Gabor time-frequency transform (the emission-time analysis of Sec. III.A) of a real signal d
+ * (the dipole or the dipole velocity), n samples at t_n = t_first + n dt:
+ *   G(t_c, w_k) = dt sum_n d_n exp(-(t_n - t_c)^2 / (2 sigma^2)) exp(i w_k t_n),
+ * t_c = tc_first + c tc_step (c < n_c <= 65535), w_k = k w_step (k < n_w).
+ * power_out[n_c][n_w] = |G|^2; g_out (nullable) [n_c][n_w][2] = (Re G, Im G). Samples farther than
+ * 9.2 sigma from t_c (window below 4e-19 of its peak) are not summed. DEVICE pointers;
+ * asynchronous on `stream`. SFHK_E_INVALID for negative counts, dt or sigma not finite and > 0,
+ * non-finite grids, more than 65535 centres or 2^31 outputs, or a NULL array. */
+sfhk_status sfhk_gabor(const double* d, int64_t n, double t_first, double dt, double sigma,
+                       double tc_first, double tc_step, int64_t n_c, double w_step, int64_t n_w,
+                       double* power_out, double* g_out, void* stream);
+
 /* sfhk_traj_sincos: s[i], c[i] = sin(x[i]), cos(x[i]) as evaluated in the SFA birth step's
  * saddle-point solve. Cody-Waite reduction x = k pi/2 + r, k = rint(x 2/pi), with pi/2 split into
  * two 33-significant-bit heads and a rounded tail (applied with fused multiply-adds), Taylor

@@ -18,6 +18,7 @@
 #include "sfhk_kernels.hpp"
 #include "sfhk_io_kernels.hpp"
 #include "sfhk_sfa_kernels.hpp"
+#include "sfhk_gabor_kernels.hpp"
 
 namespace {
 
@@ -1014,6 +1015,26 @@ sfhk_status sfhk_traj_exp(const double* x, double* y, int64_t n, void* stream) {
 
 sfhk_status sfhk_traj_rsqrt(const double* x, double* y, int64_t n, void* stream) {
   return traj_fn(1, x, y, n, stream);
+}
+
+sfhk_status sfhk_gabor(const double* d, int64_t n, double t_first, double dt, double sigma,
+                       double tc_first, double tc_step, int64_t n_c, double w_step, int64_t n_w,
+                       double* power_out, double* g_out, void* stream) {
+  TraceRange trace_("sfhk_gabor");
+  if (n < 0 || n_c < 0 || n_w < 0) return fail(SFHK_E_INVALID, "negative count");
+  if (!(dt > 0.0) || !(sigma > 0.0) || !std::isfinite(dt) || !std::isfinite(sigma) ||
+      !std::isfinite(t_first) || !std::isfinite(tc_first) || !std::isfinite(tc_step) ||
+      !std::isfinite(w_step))
+    return fail(SFHK_E_INVALID, "dt and sigma must be finite and > 0, the grids finite");
+  if (n_c > 65535) return fail(SFHK_E_INVALID, "at most 65535 centre times per call");
+  if (n_w > INT32_MAX || n_c * n_w > INT32_MAX) return fail(SFHK_E_INVALID, "output grid too large");
+  if (n_c == 0 || n_w == 0) return SFHK_OK;
+  if (!power_out || (n > 0 && !d)) return fail(SFHK_E_INVALID, "NULL array");
+  dim3 grid((unsigned)((n_w + kGaborThreads - 1) / kGaborThreads), (unsigned)n_c);
+  hipLaunchKernelGGL(k_gabor, grid, dim3(kGaborThreads), 0, (hipStream_t)stream, d, (long long)n, t_first,
+                     dt, sigma, tc_first, tc_step, w_step, (long long)n_w, power_out, (double2*)g_out);
+  HIP_TRY(hipGetLastError());
+  return SFHK_OK;
 }
 
 sfhk_status sfhk_traj_sincos(const double* x, double* s, double* c, int64_t n, void* stream) {

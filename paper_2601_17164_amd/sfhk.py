@@ -106,6 +106,9 @@ _SIGS = {
     "sfhk_traj_exp": (ct.c_int, [_VP, _VP, ct.c_int64, _VP]),
     "sfhk_traj_rsqrt": (ct.c_int, [_VP, _VP, ct.c_int64, _VP]),
     "sfhk_traj_sincos": (ct.c_int, [_VP, _VP, _VP, ct.c_int64, _VP]),
+    "sfhk_gabor": (ct.c_int, [_VP, ct.c_int64, ct.c_double, ct.c_double, ct.c_double,
+                              ct.c_double, ct.c_double, ct.c_int64, ct.c_double, ct.c_int64,
+                              _VP, _VP, _VP]),
     "sfhk_sfa_birth": (ct.c_int, [ct.POINTER(_Pulse), ct.POINTER(_Ground), ct.c_int32, ct.c_int64,
                                   _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
 }
@@ -379,6 +382,17 @@ def spectrum(d: torch.Tensor, t_first: float, dt: float, tau_h: float, n_fft: in
                                _dptr(om), _dptr(pw), _dptr(x), _stream_ptr(stream)),
            "sfhk_spectrum")
     return om, pw, torch.view_as_complex(x)
+
+
+def gabor(d: torch.Tensor, t_first: float, dt: float, sigma: float, tc_first: float,
+          tc_step: float, n_c: int, w_step: float, n_w: int, stream=None):
+    """sfhk_gabor on the device: returns (|G|^2 [n_c, n_w], G complex [n_c, n_w])."""
+    pw = torch.empty(n_c, n_w, dtype=torch.float64, device=d.device)
+    g = torch.empty(n_c, n_w, 2, dtype=torch.float64, device=d.device)
+    _check(lib().sfhk_gabor(_dptr(d), int(d.shape[0]), float(t_first), float(dt), float(sigma),
+                            float(tc_first), float(tc_step), int(n_c), float(w_step), int(n_w),
+                            _dptr(pw), _dptr(g), _stream_ptr(stream)), "sfhk_gabor")
+    return pw, torch.view_as_complex(g)
 
 
 def traj_exp(x: torch.Tensor, stream=None) -> torch.Tensor:
