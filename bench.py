@@ -82,6 +82,8 @@ def _args():
     ap.add_argument("--no-sfa", action="store_true",
                     help="skip the SFA birth step leg (birth kernel timing, SFA-born propagation)")
     ap.add_argument("--sfa-reps", type=int, default=5)
+    ap.add_argument("--gabor-only", action="store_true",
+                    help="time only the Gabor map (512 x 2048) of a seeded 2^15-sample signal")
     ap.add_argument("--no-velocity", action="store_true",
                     help="skip the dipole-velocity leg (one propagation with both accumulators)")
     ap.add_argument("--sfa-only", action="store_true",
@@ -243,6 +245,26 @@ def run_batch(a):
     ctx.close()
 
 
+def gabor_only(a):
+    """The Gabor map of the screened workload's shape (2^15 samples over the 8-cycle 1600 nm
+    pulse) on a seeded signal of harmonic bursts; the kernel's work does not depend on the values."""
+    import torch
+    from paper_2601_17164_amd import inputs as I
+    inst = I.config1(n_birth=1, n_per_birth=1)
+    T = inst.grid.h * inst.grid.n_steps
+    n = inst.n_out
+    t = inst.grid.t_a + (T / n) * np.arange(n)
+    rng = np.random.default_rng(5)
+    d = np.zeros(n)
+    for _ in range(16):
+        tb, wb = rng.uniform(-0.4 * T, 0.4 * T), inst.pulse.omega * rng.uniform(5, 160)
+        d += np.exp(-(t - tb) ** 2 / 50.0) * np.cos(wb * t)
+    v = torch.from_numpy(d).to("cuda:0")
+    out = gabor_results(torch.cuda.current_stream(), inst, v, reps=a.sfa_reps)
+    print(json.dumps({"workload": "Gabor map, 2^15 samples over the screened workload's pulse, "
+                                  "512 centres x 2048 frequencies", **out}), flush=True)
+
+
 def sfa_saddle_work(inst, tt):
     """March steps and algorithmic FP64 operations of the saddle-point kernel for the t_t it
     returned (the march stops at k = ceil(t_t / dtau), dtau = 1 / (4 (omega + omega/n_cycles)))."""
@@ -397,6 +419,9 @@ def main():
         return
     if a.sfa_only:
         sfa_only(a)
+        return
+    if a.gabor_only:
+        gabor_only(a)
         return
     import torch
     from paper_2601_17164_amd import flops, inputs as I, sfhk
