@@ -140,6 +140,7 @@ def mixed_form(step, stream, inst, arrays, ref_spectrum, flops):
     job, (om, pw, x) = step(ev, precision=1)
     st = job.stats(stream)
     wall = time.perf_counter() - t
+    drift = _det_drift(job)
     job.close()
     kms = ev[0].elapsed_time(ev[1])
     fl = flops.flops(inst.potential.kind, inst.ground.l, st.steps_evaluated, st.prims_evaluated)
@@ -151,6 +152,7 @@ def mixed_form(step, stream, inst, arrays, ref_spectrum, flops):
     arrays["q0"] = torch.nextafter(q0, torch.full_like(q0, float("inf")))
     job, (_, _, x_p) = step([torch.cuda.Event(enable_timing=True) for _ in range(2)])
     torch.cuda.synchronize()
+    drift64 = _det_drift(job)
     job.close()
     arrays["q0"] = q0
     return {"value": st.steps_evaluated / wall, "unit": "trajectory-steps/s",
@@ -158,7 +160,17 @@ def mixed_form(step, stream, inst, arrays, ref_spectrum, flops):
             "frac_of_fp64_vector_peak": fl / (kms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
             "fp64_step_fraction": st.steps_fp64 / max(1, st.steps_evaluated),
             "spectral_error_vs_fp64": band(x), "fp64_one_ulp_floor": band(x_p),
-            "kay_max": inst.kay_max}
+            "det_M_drift": drift, "fp64_det_M_drift": drift64, "kay_max": inst.kay_max}
+
+
+def _det_drift(job):
+    """|det M - 1| at each trajectory's last evaluated step (the removal step for removed ones):
+    median and max over the job."""
+    from paper_2601_17164_amd import metrics
+    y, _, _ = job.trajectories()
+    dr = metrics.det_monodromy_drift(y.cpu().numpy())
+    dr = dr[np.isfinite(dr)]
+    return {"median": float(np.median(dr)), "max": float(np.max(dr))} if dr.size else None
 
 
 def serving_run(ctx, rate, n_req, warmup, precision, chunk, reqs=None, verbose=False):
@@ -331,7 +343,8 @@ def gabor_results(stream, inst, v, reps=5):
     """Gabor map (sfhk_gabor) of the dipole velocity on the 2^15-point output grid: 512 centres
     over the pulse, 2048 frequencies in steps of omega/10 (beyond the cutoff), sigma = 1/(3 omega).
     Mean kernel time over `reps` launches (HIP events on the launch stream) and the algorithmic
-    rate at 10 FP64 operations per (centre, frequency, sample) update."""
+    rate at 7 FP64 operations per (centre, frequency, sample) update (one Horner step: a complex
+    multiplication by e^{i w dt} and the sample's addition)."""
     import torch
     from paper_2601_17164_amd import sfhk
     T = inst.grid.h * inst.grid.n_steps
@@ -353,7 +366,7 @@ def gabor_results(stream, inst, v, reps=5):
     lo = np.ceil(np.clip((tc - GABOR_CUT * sigma - inst.grid.t_a) / dt, 0, n))
     hi = np.floor(np.clip((tc + GABOR_CUT * sigma - inst.grid.t_a) / dt, -1, n - 1))
     updates = float(np.sum(np.maximum(hi - lo + 1, 0))) * n_w
-    fl = 10.0 * updates
+    fl = 7.0 * updates
     return {"n": n, "n_centres": n_c, "n_freq": n_w, "sigma": sigma, "kernel_ms": ms,
             "updates": updates, "achieved_tflops": fl / (ms * 1e-3) / 1e12,
             "frac_of_fp64_vector_peak": fl / (ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,

@@ -1,7 +1,7 @@
 """The Gabor time-frequency transform (sfhk_gabor; the emission-time analysis of Sec. III.A) on the
 GPU against the oracle's plain sum over every sample, to the FP64 bar: max |G_gpu - G_ref| within
 1e-9 of max |G_ref| (the GPU drops samples beyond 9.2 sigma, where the window is below 4e-19, and
-builds the twiddles by rotation re-anchored every 256 samples)."""
+sums each chunk of 1024 samples by Horner's rule in e^{i w dt}, anchored with a sincos per chunk)."""
 import math
 
 import numpy as np
