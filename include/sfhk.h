@@ -337,7 +337,9 @@ typedef enum {
  * sfhk_traj_rsqrt; a march of at most 512 steps of 1/(4 (omega + omega/n_cycles)) to the first
  * |Im A| >= kappa, then 64 bisection steps), so they are reproducible bit for bit; the weight uses
  * library functions. A sample with no crossing within the march, or with non-finite inputs, gets
- * NaN outputs (sfhk_job_create then counts it as a removed trajectory).
+ * NaN outputs (sfhk_job_create then counts it as a removed trajectory). Birth times outside the
+ * pulse [-T/2, T/2] are not rejected here (the product-to-sum form of A is continued past the
+ * envelope's support); sfhk_job_create rejects them.
  * All arrays are DEVICE pointers owned by the caller; asynchronous on `stream`. SFHK_E_INVALID for a
  * bad pulse, Ip <= 0, l not 0/1, an unknown mode, no or too many GTO primitives (mode GTO), a NULL
  * array, or n outside [0, 2^31). */
