@@ -232,10 +232,12 @@ int64_t sfhk_job_n_out(const sfhk_job* job);
  * sfhk_job_checkpoint: writes it to dst (DEVICE, checkpoint_bytes, caller-owned) on `stream` and
  *   returns once the copies have completed. Errors: SFHK_E_INVALID (NULL), SFHK_E_DEVICE.
  * sfhk_job_restore: loads a checkpoint into `job`, which must have been created from the same
- *   inputs (same shape, potential kind and precision) and not propagated; propagation then
- *   continues exactly as the checkpointed job would have (bit for bit). Reads the header
- *   synchronously, copies the state asynchronously on `stream`. Errors: SFHK_E_INVALID (NULL,
- *   not a checkpoint, another job's shape, a job already propagated), SFHK_E_DEVICE. */
+ *   inputs and not propagated; propagation then continues exactly as the checkpointed job would
+ *   have (bit for bit). The checkpoint records the job's shape and a fingerprint of its potential,
+ *   ground state, grid (t_a, h) and sfhk_params, and a job that differs in any of them is refused
+ *   (the field table's values are not compared). Reads the header synchronously, copies the state
+ *   asynchronously on `stream`. Errors: SFHK_E_INVALID (NULL, not a checkpoint, another job's
+ *   shape or parameters, a job already propagated), SFHK_E_DEVICE. */
 int64_t sfhk_job_checkpoint_bytes(const sfhk_job* job);
 sfhk_status sfhk_job_checkpoint(sfhk_job* job, void* dst, void* stream);
 sfhk_status sfhk_job_restore(sfhk_job* job, const void* src, void* stream);

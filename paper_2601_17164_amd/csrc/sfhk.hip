@@ -86,6 +86,7 @@ struct sfhk_job {
   std::vector<int> tile_n0_host;
   long long steps_done = 0;    // steps requested so far (uniform across tiles)
   long long part_elems = 0;    // complex entries of the partial rows
+  uint64_t fingerprint = 0;    // of the inputs that define the propagation (checkpoint matching)
   bool done = false;
 };
 
@@ -213,6 +214,7 @@ struct CkptHeader {
   uint64_t magic;
   int64_t n_traj, n_pad, n_tiles, n_steps, part_elems, steps_done;
   int32_t kind, precision, done, reserved;
+  uint64_t fingerprint;  // of the job's potential, ground state, grid and method parameters
 };
 static_assert(sizeof(CkptHeader) <= kCkptAlign, "checkpoint header");
 
@@ -496,6 +498,27 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   H.n_steps = NS;
   H.n_tiles = n_tiles;
   H.n_pad = n_pad;
+  {
+    // FNV-1a over the parameters that define the propagation (not the field table's values)
+    uint64_t fp = 1469598103934665603ULL;
+    auto mix = [&fp](const void* p, size_t n) {
+      const unsigned char* b = (const unsigned char*)p;
+      for (size_t i = 0; i < n; ++i) fp = (fp ^ b[i]) * 1099511628211ULL;
+    };
+    mix(pot, sizeof(*pot));
+    mix(&ground->l, sizeof(ground->l));
+    mix(&ground->ip, sizeof(ground->ip));
+    mix(ground->alpha, sizeof(double) * (size_t)ground->n_prim);
+    mix(ground->coef, sizeof(double) * (size_t)ground->n_prim);
+    mix(&grid->t_a, sizeof(grid->t_a));
+    mix(&grid->h, sizeof(grid->h));
+    const double pv[5] = {params->gamma, params->kay_max, params->overlap_cut, params->r_fp64,
+                          params->pw_mask ? params->pw_radius : 0.0};
+    const int64_t iv[4] = {params->precision, params->n_out, params->velocity, params->pw_mask};
+    mix(pv, sizeof(pv));
+    mix(iv, sizeof(iv));
+    j->fingerprint = fp;
+  }
 
   double* e_half = nullptr;
   if ((rc = job_alloc(j, &e_half, 2 * (size_t)NS + 1, st)) || (rc = job_alloc(j, &H.y, (size_t)n_pad * kNY, st)) ||
@@ -961,6 +984,7 @@ sfhk_status sfhk_job_checkpoint(sfhk_job* job, void* dst, void* stream) {
   h.kind = job->kind;
   h.precision = job->precision;
   h.done = job->done ? 1 : 0;
+  h.fingerprint = job->fingerprint;
   char* out = (char*)dst;
   HIP_TRY(hipMemcpyAsync(out, &h, sizeof(h), hipMemcpyHostToDevice, st));
   size_t off = kCkptAlign;
@@ -986,7 +1010,7 @@ sfhk_status sfhk_job_restore(sfhk_job* job, const void* src, void* stream) {
   if (h.magic != kCkptMagic || h.n_traj != job->n_traj || h.n_pad != job->host.n_pad ||
       h.n_tiles != job->host.n_tiles || h.n_steps != job->host.n_steps ||
       h.part_elems != job->part_elems || h.kind != job->kind || h.precision != job->precision ||
-      h.steps_done < 0)
+      h.fingerprint != job->fingerprint || h.steps_done < 0)
     return fail(SFHK_E_INVALID, "checkpoint does not match this job (other inputs or not a checkpoint)");
   size_t off = kCkptAlign;
   for (const auto& sec : ckpt_sections(job)) {

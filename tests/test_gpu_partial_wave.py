@@ -96,3 +96,32 @@ def test_filter_argument_errors(S):
         with pytest.raises(sfhk.SfhkError) as ei:
             sfhk.make_job(ctx, inst, pw_mask=mask, pw_radius=radius)
         assert ei.value.status == sfhk.SFHK_E_INVALID
+
+
+def test_checkpoint_refused_by_a_job_with_other_parameters(S):
+    """A checkpoint carries a fingerprint of the job's parameters: restoring it into a job of the
+    same shape but another filter, Kay limit or coherent-state width is refused."""
+    sfhk, ctx, torch = S
+    inst = I.config0(n_birth=8, n_per_birth=32)
+    a = sfhk.make_job(ctx, inst, pw_mask=P_, pw_radius=3.0)
+    assert not a.propagate(500)
+    ck = a.checkpoint()
+    a.close()
+    from dataclasses import replace
+    for other in (dict(pw_mask=P_ | FAR, pw_radius=3.0), dict(pw_mask=P_, pw_radius=2.5),
+                  dict(pw_mask=P_, pw_radius=3.0, inst=replace(inst, kay_max=1e20)),
+                  dict(pw_mask=P_, pw_radius=3.0, inst=replace(inst, gamma=0.6))):
+        x = other.pop("inst", inst)
+        b = sfhk.make_job(ctx, x, **other)
+        with pytest.raises(sfhk.SfhkError) as ei:
+            b.restore(ck)
+        assert ei.value.status == sfhk.SFHK_E_INVALID
+        b.close()
+    same = sfhk.make_job(ctx, inst, pw_mask=P_, pw_radius=3.0)
+    same.restore(ck)
+    while not same.propagate(700):
+        pass
+    ref, _ = _gpu(S, inst, P_)
+    _, f = same.dipole(want_f=True)
+    np.testing.assert_array_equal((f[0] + 1j * f[1]).cpu().numpy(), ref)
+    same.close()
