@@ -836,7 +836,9 @@ int or_spectrum(const double* d, int64_t n, double t_first, double dt, double ta
 /*   q0_z = Re int_{t_s}^{t0} A = -K sum_m (c_m / w_m) cos(th_m) (cosh(w_m t_t) - 1)            */
 /* (the tunnel exit of App. A; q0_x = q0_y = 0). Of the roots t_t > 0 the one nearest the real  */
 /* axis is taken: a march in steps of 1/(4 w_max) up to 512 steps finds the first point where   */
-/* |Im A| >= kappa, then 64 bisection steps on the sign of that crossing. No crossing: NaN.     */
+/* |Im A| >= kappa, then 16 bisection steps on the sign of that crossing and 4 Newton steps     */
+/* (with d Im A / d tau from cosh), each kept inside the bracket (a step that would leave it is  */
+/* replaced by the bracket's midpoint). No crossing: NaN.                                      */
 /* These numbers decide the trajectory's initial state, so they follow the rounding contract:   */
 /* exp_cw for sinh and cosh, sincos_c, rsqrt_c, one operation per step as written.              */
 /* ------------------------------------------------------------------------------------------ */
@@ -871,8 +873,23 @@ static double sfa_im_a(const sfa_terms* a, double tau) {
   return -(a->K * (a->C[0] * s0 + 0.5 * (a->C[1] * s1 + a->C[2] * s2)));
 }
 
+/* Im A and its derivative -K sum_m c_m cos(th_m) w_m cosh(w_m tau) from the same exponentials */
+static void sfa_im_a_d(const sfa_terms* a, double tau, double* v, double* dv) {
+  double sh[3], ch[3];
+  for (int m = 0; m < 3; ++m) {
+    double e = or_exp_cw(a->om[m] * tau);
+    double ie = 1.0 / e;
+    sh[m] = 0.5 * (e - ie);
+    ch[m] = 0.5 * (e + ie);
+  }
+  *v = -(a->K * (a->C[0] * sh[0] + 0.5 * (a->C[1] * sh[1] + a->C[2] * sh[2])));
+  *dv = -(a->K * (a->C[0] * a->om[0] * ch[0] +
+                  0.5 * (a->C[1] * a->om[1] * ch[1] + a->C[2] * a->om[2] * ch[2])));
+}
+
 #define SFA_MARCH 512
-#define SFA_BISECT 64
+#define SFA_BISECT 16
+#define SFA_NEWTON 4
 
 /* returns 0 and (t_t, k_z, q0_z), or -1 when no crossing lies within the march */
 static int sfa_saddle(const or_pulse* pl, double ip, double t0, double kx, double ky, double* tt,
@@ -906,6 +923,18 @@ static int sfa_saddle(const or_pulse* pl, double ip, double t0, double kx, doubl
       hi = mid;
   }
   double t = lo + 0.5 * (hi - lo);
+  for (int it = 0; it < SFA_NEWTON; ++it) {
+    double v, dv;
+    sfa_im_a_d(&a, t, &v, &dv);
+    double f = (up ? v : -v) - kap;
+    double fp = up ? dv : -dv;
+    if (f < 0.0)
+      lo = t;
+    else
+      hi = t;
+    double tn = t - f / fp;
+    t = (tn >= lo && tn <= hi) ? tn : lo + 0.5 * (hi - lo);
+  }
   double c0 = coshm1_c(a.om[0] * t);
   double c1 = coshm1_c(a.om[1] * t);
   double c2 = coshm1_c(a.om[2] * t);

@@ -61,6 +61,9 @@ MUTANTS = {
     "principal sqrt: imaginary part halved twice": ("r.im = (0.5 * z.im) * rw;",
                                                     "r.im = (0.25 * z.im) * rw;"),
     "SFA: crossing sign ignored in the bisection": ("if ((up ? v : -v) < kap)", "if (v < kap)"),
+    "SFA: Newton derivative without w_m": ("*dv = -(a->K * (a->C[0] * a->om[0] * ch[0] +",
+                                           "*dv = -(a->K * (a->C[0] * ch[0] +"),
+    "SFA: Newton step sign": ("double tn = t - f / fp;", "double tn = t + f / fp;"),
     "SFA: tunnel exit sign": ("*qz = -(a.K * (a.C[0]", "*qz = (a.K * (a.C[0]"),
     "SFA: k_z from sinh instead of cosh - 1": ("double c0 = coshm1_c(a.om[0] * t);",
                                               "double c0 = sinh_c(a.om[0] * t);"),
