@@ -337,7 +337,8 @@ typedef enum {
  * block) -- the layout sfhk_job_create takes -- and t_tun[n] = t_t (may be NULL).
  * t_t, k_z and q0 are computed with the trajectory arithmetic (sfhk_traj_sincos, sfhk_traj_exp,
  * sfhk_traj_rsqrt; a march of at most 512 steps of 1/(4 (omega + omega/n_cycles)) to the first
- * |Im A| >= kappa, then 64 bisection steps), so they are reproducible bit for bit; the weight uses
+ * |Im A| >= kappa, then 16 bisection steps and 4 Newton steps kept inside the bracket), so they
+ * are reproducible bit for bit; the weight uses
  * library functions. A sample with no crossing within the march, or with non-finite inputs, gets
  * NaN outputs (sfhk_job_create then counts it as a removed trajectory). Birth times outside the
  * pulse [-T/2, T/2] are not rejected here (the product-to-sum form of A is continued past the

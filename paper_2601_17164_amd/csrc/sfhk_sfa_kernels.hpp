@@ -11,7 +11,9 @@
 //   q0_z = Re int_{t_s}^{t0} A = -K sum_m (c_m/w_m) cos(th_m) (cosh(w_m t_t) - 1)
 // The saddle point t_s = t0 + i t_t solves Im A(t_s) = +-kappa, kappa^2 = 2 Ip + kx^2 + ky^2, and is
 // the root nearest the real axis: a march in steps of 1/(4 w_max) (at most kSfaMarch steps) to the
-// first |Im A| >= kappa, then kSfaBisect bisection steps. These values decide the trajectory's
+// first |Im A| >= kappa, then kSfaBisect bisection steps and kSfaNewton Newton steps (the
+// derivative from cosh, each step kept inside the bracket or replaced by its midpoint). These
+// values decide the trajectory's
 // initial state and follow the rounding contract (sincos_c, exp_cw, rsqrt_c, one IEEE operation per
 // step as written), so they agree bit for bit with a CPU implementation of the same sequence.
 //
@@ -78,7 +80,8 @@ __device__ inline void sincos_c(double x, double* s, double* c) {
 }
 
 constexpr int kSfaMarch = 512;
-constexpr int kSfaBisect = 64;
+constexpr int kSfaBisect = 16;
+constexpr int kSfaNewton = 4;
 constexpr int kSfaMaxPrim = 8;
 
 struct SfaParams {
@@ -107,6 +110,20 @@ __device__ inline double sfa_im_a(const SfaTerms& a, double tau) {
   const double s1 = sinh_c(a.om[1] * tau);
   const double s2 = sinh_c(a.om[2] * tau);
   return -(a.K * (a.C[0] * s0 + 0.5 * (a.C[1] * s1 + a.C[2] * s2)));
+}
+
+// Im A and its derivative -K sum_m c_m cos(th_m) w_m cosh(w_m tau) from the same exponentials
+__device__ inline void sfa_im_a_d(const SfaTerms& a, double tau, double* v, double* dv) {
+  double sh[3], ch[3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const double e = exp_cw(a.om[m] * tau);
+    const double ie = 1.0 / e;
+    sh[m] = 0.5 * (e - ie);
+    ch[m] = 0.5 * (e + ie);
+  }
+  *v = -(a.K * (a.C[0] * sh[0] + 0.5 * (a.C[1] * sh[1] + a.C[2] * sh[2])));
+  *dv = -(a.K * (a.C[0] * a.om[0] * ch[0] + 0.5 * (a.C[1] * a.om[1] * ch[1] + a.C[2] * a.om[2] * ch[2])));
 }
 
 // small complex helpers for the weight (library arithmetic, no contract)
@@ -198,6 +215,18 @@ __global__ __launch_bounds__(256) void k_sfa_saddle(SfaParams P, long long n, co
         hi = mid;
     }
     tt = lo + 0.5 * (hi - lo);
+    for (int it = 0; it < kSfaNewton; ++it) {
+      double v, dv;
+      sfa_im_a_d(a, tt, &v, &dv);
+      const double f = (up ? v : -v) - kap;
+      const double fp = up ? dv : -dv;
+      if (f < 0.0)
+        lo = tt;
+      else
+        hi = tt;
+      const double tn = tt - f / fp;
+      tt = (tn >= lo && tn <= hi) ? tn : lo + 0.5 * (hi - lo);
+    }
     const double c0 = coshm1_c(a.om[0] * tt);
     const double c1 = coshm1_c(a.om[1] * tt);
     const double c2 = coshm1_c(a.om[2] * tt);

@@ -44,12 +44,16 @@ def flops(pot_kind: int, l: int, steps_evaluated: int, prims_evaluated: int) -> 
 
 # SFA birth step, saddle-point kernel (same convention; exp, sin, cos, 1/sqrt count 1):
 #   Im A(t0 + i tau): three sinh = (w_m tau, exp, 1/e, difference, half) 5 each, combination 7 = 22
-#   march step: tau = k dtau (1) + 22 = 23;  bisection step: midpoint (3) + 22 = 25 (64 steps)
+#   march step: tau = k dtau (1) + 22 = 23;  bisection step: midpoint (3) + 22 = 25 (16 steps)
+#   Newton step: Im A and its derivative from the same exponentials (w_m tau, exp, 1/e, sinh 2,
+#   cosh 2: 7 each = 21; combinations 7 + 10), f (1), the step (2) = 41 (4 steps)
 #   per sample: three (sin, cos) of w_m t0 + cep (4 each), the frequencies and K (5), kappa^2 (5),
 #   kappa (2), dtau (1), t_t (3), three cosh - 1 (8 each), k_z (7), q0_z (10)             = 69
 SFA_MARCH_STEP = 23
 SFA_BISECT_STEP = 25
-SFA_BISECT_STEPS = 64
+SFA_BISECT_STEPS = 16
+SFA_NEWTON_STEP = 41
+SFA_NEWTON_STEPS = 4
 SFA_FIXED = 69
 
 
@@ -57,4 +61,5 @@ def sfa_saddle_flops(march_steps: int, n_found: int) -> int:
     """Algorithmic FP64 operations of the saddle-point kernel: march_steps is the sum over
     samples of the march index at which the crossing was found (ceil(t_t / dtau))."""
     return (SFA_MARCH_STEP * int(march_steps)
-            + (SFA_BISECT_STEP * SFA_BISECT_STEPS + SFA_FIXED) * int(n_found))
+            + (SFA_BISECT_STEP * SFA_BISECT_STEPS + SFA_NEWTON_STEP * SFA_NEWTON_STEPS
+               + SFA_FIXED) * int(n_found))
