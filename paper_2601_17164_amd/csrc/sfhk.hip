@@ -1100,6 +1100,7 @@ sfhk_status sfhk_sfa_birth(const sfhk_pulse* pulse, const sfhk_ground* gs, int32
     if (!(gs->alpha[i] > 0.0)) return fail(SFHK_E_INVALID, "GTO exponents must be > 0");
     P.alpha[i] = gs->alpha[i];
     P.coef[i] = gs->coef[i];
+    P.cnorm[i] = gs->coef[i] * std::pow(gs->alpha[i], gs->l == 0 ? -2.5 : -3.5);
   }
   hipStream_t st = (hipStream_t)stream;
   hipLaunchKernelGGL(k_sfa_saddle, dim3(blocks_for(n, 256)), dim3(256), 0, st, P, (long long)n, t0, kperp,

@@ -88,6 +88,7 @@ struct SfaParams {
   double e0, omega, n_cycles, cep, ip;
   int mode, l, n_prim;
   double alpha[kSfaMaxPrim], coef[kSfaMaxPrim];
+  double cnorm[kSfaMaxPrim];  // c_j a_j^{-5/2} (s) or c_j a_j^{-7/2} (p), set by the host
 };
 
 struct SfaTerms {
@@ -153,14 +154,6 @@ __device__ inline zd zsqrt(zd a) {
   }
   const double t = ::sqrt(0.5 * (r - a.re));
   return {::fabs(a.im) / (2.0 * t), ::copysign(t, a.im)};
-}
-
-// sin(a) (1 - cosh b) - i cos(a) sinh(b) = sin(a + i 0) - sin(a + i b)
-__device__ inline zd sin_drop(double a, double b) {
-  double sa, ca;
-  ::sincos(a, &sa, &ca);
-  const double sh = ::sinh(0.5 * b);
-  return {-sa * (2.0 * sh * sh), -ca * ::sinh(b)};
 }
 
 __device__ inline SfaTerms sfa_terms(const SfaParams& P, double t0) {
@@ -260,14 +253,17 @@ __global__ __launch_bounds__(256) void k_sfa_weight(SfaParams P, long long n, co
     const double kz = p0[2 * n + j], qz = q0[2 * n + j];
     const SfaTerms a = sfa_terms(P, t0);
     const double cw[3] = {1.0, 0.5, 0.5};
-    double sh[3], ch[3], cm1[3];
+    // sinh, cosh of b_m = w_m t_t and of b_m / 2 (cosh b - 1 = 2 sinh(b/2)^2 without cancellation)
+    double sh[3], ch[3], hs[3], hc[3], cm1[3];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-      const double b = a.om[m] * tt;
-      sh[m] = ::sinh(b);
-      ch[m] = ::cosh(b);
-      const double hb = ::sinh(0.5 * b);
-      cm1[m] = 2.0 * hb * hb;
+      const double e = ::exp(a.om[m] * tt), ie = 1.0 / e;
+      const double eh = ::exp(0.5 * (a.om[m] * tt)), ieh = 1.0 / eh;
+      sh[m] = 0.5 * (e - ie);
+      ch[m] = 0.5 * (e + ie);
+      hs[m] = 0.5 * (eh - ieh);
+      hc[m] = 0.5 * (eh + ieh);
+      cm1[m] = 2.0 * hs[m] * hs[m];
     }
     double a0 = 0.0;
     zd dA = {0.0, 0.0}, ez = {0.0, 0.0}, dP = {0.0, 0.0};
@@ -279,7 +275,10 @@ __global__ __launch_bounds__(256) void k_sfa_weight(SfaParams P, long long n, co
       dP = zadd(dP, zd{-a.K * cw[m] / a.om[m] * a.C[m] * cm1[m], a.K * cw[m] / a.om[m] * a.S[m] * sh[m]});
     }
     // int_{t_s}^{t0} A^2 dt from the antiderivative of each product term; the (m, q) and (q, m)
-    // terms are equal, so the pairs m < q count twice
+    // terms are equal, so the pairs m < q count twice. For a frequency W = w_m -+ w_q, with
+    // alpha = W t0 (+ 2 cep for the sum) = th_m -+ th_q and beta = W t_t = b_m -+ b_q:
+    //   [sin(alpha) - sin(alpha + i beta)] / W = [-sin(alpha) (cosh beta - 1) - i cos(alpha) sinh beta] / W,
+    // with sin, cos of alpha and sinh, cosh of beta (and beta / 2) from the angle-sum formulas.
     zd dQ = {0.0, 0.0};
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
@@ -291,10 +290,16 @@ __global__ __launch_bounds__(256) void k_sfa_weight(SfaParams P, long long n, co
           g = zd{0.0, -tt};  // cos(0 t) integrates to t0 - t_s = -i t_t
         } else {
           const double om = a.om[m] - a.om[q];
-          g = zscale(sin_drop(om * t0, om * tt), 1.0 / om);
+          const double sa = a.S[m] * a.C[q] - a.C[m] * a.S[q], ca = a.C[m] * a.C[q] + a.S[m] * a.S[q];
+          const double shb = sh[m] * ch[q] - ch[m] * sh[q];
+          const double hsb = hs[m] * hc[q] - hc[m] * hs[q];
+          g = zd{-sa * (2.0 * hsb * hsb) / om, -ca * shb / om};
         }
         const double os = a.om[m] + a.om[q];
-        g = zadd(g, zscale(sin_drop(os * t0 + 2.0 * P.cep, os * tt), -1.0 / os));
+        const double sa = a.S[m] * a.C[q] + a.C[m] * a.S[q], ca = a.C[m] * a.C[q] - a.S[m] * a.S[q];
+        const double shb = sh[m] * ch[q] + ch[m] * sh[q];
+        const double hsb = hs[m] * hc[q] + hc[m] * hs[q];
+        g = zadd(g, zd{sa * (2.0 * hsb * hsb) / os, ca * shb / os});
         dQ = zadd(dQ, zscale(g, f));
       }
     }
@@ -315,9 +320,9 @@ __global__ __launch_bounds__(256) void k_sfa_weight(SfaParams P, long long n, co
         const double al = P.alpha[i];
         const zd e = zexp(zscale(k2, -1.0 / (4.0 * al)));
         if (P.l == 0) {
-          sum = zadd(sum, zscale(e, P.coef[i] * ::pow(al, -2.5)));
+          sum = zadd(sum, zscale(e, P.cnorm[i]));
         } else {
-          sum = zadd(sum, zscale(zmul(zd{2.0 * al - kz2.re, -kz2.im}, e), P.coef[i] * ::pow(al, -3.5)));
+          sum = zadd(sum, zscale(zmul(zd{2.0 * al - kz2.re, -kz2.im}, e), P.cnorm[i]));
         }
       }
       const double pi32 = 5.568327996831707845284817982118835702;  // pi^{3/2}
