@@ -225,10 +225,11 @@ def config1_birth_subset(inst: Instance, births, n_per_birth=None) -> Instance:
 
 
 def random_instance(rng: np.random.Generator, seed: int, name: str,
-                    traj_scale: float = 1.0) -> Instance:
+                    traj_scale: float = 1.0, sfa: bool = False) -> Instance:
     """One instance of the uneven batch / serving mix: wavelength U(800, 2000) nm, intensity
     log-uniform in [0.8e14, 3e14] W/cm^2, 2..10 cycles, potential of config 0 or 1 (with its dt,
-    Ip and GTO), N = 64 round(2^U(14, 20) / 64) trajectories (times traj_scale)."""
+    Ip and GTO), N = 64 round(2^U(14, 20) / 64) trajectories (times traj_scale). sfa=True: the
+    same instance with SFA birth samples (sfa_instance) instead of Gaussian ones."""
     lam = rng.uniform(800.0, 2000.0)
     inten = math.exp(rng.uniform(math.log(0.8e14), math.log(3e14)))
     ncyc = int(rng.integers(2, 11))
@@ -237,9 +238,10 @@ def random_instance(rng: np.random.Generator, seed: int, name: str,
     n_birth = int(min(max(2 ** int(math.floor(math.log2(n) / 2)), 64), 1024))
     n_per = int(math.ceil(n / n_birth))
     pulse = Pulse(lam, inten, float(ncyc))
+    make = sfa_instance if sfa else make_instance
     if which == 0:
-        return make_instance(name, SOFTCORE_H, gto_h1s(), pulse, 0.1, n_birth, n_per, seed)
-    return make_instance(name, SCREENED_SAE, gto_p058(), pulse, 0.05, n_birth, n_per, seed)
+        return make(name, SOFTCORE_H, gto_h1s(), pulse, 0.1, n_birth, n_per, seed)
+    return make(name, SCREENED_SAE, gto_p058(), pulse, 0.05, n_birth, n_per, seed)
 
 
 def batch_instances(n=64, seed=3, traj_scale=1.0):
@@ -248,11 +250,12 @@ def batch_instances(n=64, seed=3, traj_scale=1.0):
     return [random_instance(rng, seed * 100003 + i, f"batch{i}", traj_scale) for i in range(n)]
 
 
-def serving_request(req_id: int, traj_scale=1.0) -> Instance:
-    """Request req_id of the serving workload (independent of every other request)."""
+def serving_request(req_id: int, traj_scale=1.0, sfa: bool = False) -> Instance:
+    """Request req_id of the serving workload (independent of every other request); sfa=True
+    gives it SFA birth samples, born on the device when the request is admitted."""
     s = 4000 + int(req_id)
     rng = np.random.Generator(np.random.PCG64(s))
-    return random_instance(rng, s, f"req{req_id}", traj_scale)
+    return random_instance(rng, s, f"req{req_id}", traj_scale, sfa=sfa)
 
 
 def sfa_samples(seed: int, pulse: Pulse, grid: Grid, n_birth: int, n_per_birth: int, ip: float):

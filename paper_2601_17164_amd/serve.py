@@ -48,6 +48,22 @@ class Result:
         return self.finished - self.arrival
 
 
+def _create_job(ctx, inst, precision, stream):
+    """The request's job on `stream`; a request that carries SFA birth samples (``meta`` holds
+    k_perp and the Monte-Carlo weights) gets its initial conditions from the SFA birth step on
+    the device first (sfhk_sfa_birth), in the same stream."""
+    import torch
+    from paper_2601_17164_amd import sfhk
+    if "kperp" not in inst.meta:
+        return sfhk.make_job(ctx, inst, precision=precision, stream=stream)
+    dev = sfhk.to_device(inst, f"cuda:{ctx.device}")
+    f64 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev["t0"].device)
+    b = sfhk.sfa_birth(inst.pulse, inst.ground, dev["t0"], f64(inst.meta["kperp"]),
+                       f64(inst.meta["u"]), inst.meta.get("mode", sfhk.SFHK_BIRTH_GTO), stream)
+    dev.update(q0=b["q0"], p0=b["p0"], w=b["w"])
+    return sfhk.make_job(ctx, inst, dev_arrays=dev, precision=precision, stream=stream)
+
+
 def poisson_arrivals(rate: float, n: int, seed: int) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     return np.cumsum(rng.exponential(1.0 / rate, n))
@@ -135,8 +151,7 @@ class Server:
                     break
                 try:
                     with torch.cuda.stream(adm):
-                        job = sfhk.make_job(self.ctx, req.inst, precision=self.precision,
-                                            stream=adm)
+                        job = _create_job(self.ctx, req.inst, self.precision, adm)
                 except sfhk.SfhkError as e:
                     if e.status == sfhk.SFHK_E_BUDGET and (active or finishing):
                         break  # wait for running requests to free HBM

@@ -69,3 +69,26 @@ def test_serving_with_tight_hbm_budget(S):
     assert ctx.bytes_in_use() == 0
     ref_ctx.close()
     ctx.close()
+
+
+def test_serving_sfa_born_requests(S):
+    """Requests with SFA birth samples: the loop runs the birth step on the device at admission;
+    each result equals the same request born and propagated alone, bit for bit."""
+    sfhk, torch = S
+    from paper_2601_17164_amd import serve
+    ctx = sfhk.Context(0)
+    t = serve.poisson_arrivals(200.0, 6, seed=12)
+    reqs = [serve.Request(k, float(t[k]), I.serving_request(k, traj_scale=1.0 / 128, sfa=True))
+            for k in range(6)]
+    srv = serve.Server(ctx, chunk=800, max_jobs=6,
+                       max_tiles=sum(sfhk.tiles_of(r.inst) for r in reqs), keep_results=True)
+    res = srv.run(reqs)
+    srv.close()
+    assert len(res) == len(reqs)
+    for r in res:
+        job = serve._create_job(ctx, reqs[r.req_id].inst, 0, None)
+        assert job.propagate(0)
+        alone = job.dipole().cpu().numpy()
+        job.close()
+        np.testing.assert_array_equal(r.dipole, alone)
+    ctx.close()
