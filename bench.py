@@ -164,13 +164,19 @@ def mixed_form(step, stream, inst, arrays, ref_spectrum, flops):
 
 
 def _det_drift(job):
-    """|det M - 1| at each trajectory's last evaluated step (the removal step for removed ones):
-    median and max over the job."""
+    """At each trajectory's last evaluated step (the removal step for removed ones): |det M - 1|
+    and the scale-free symplectic defect max|M^T J M - J| / ||M||_F^2, median and max over the
+    job. With the Kay limit at 1e30 |det M - 1| is dominated by the cancellation in det M of
+    large monodromy matrices; the defect is the meaningful figure."""
     from paper_2601_17164_amd import metrics
     y, _, _ = job.trajectories()
-    dr = metrics.det_monodromy_drift(y.cpu().numpy())
-    dr = dr[np.isfinite(dr)]
-    return {"median": float(np.median(dr)), "max": float(np.max(dr))} if dr.size else None
+    y = y.cpu().numpy()
+    out = {}
+    for name, v in (("det", metrics.det_monodromy_drift(y)),
+                    ("symplectic_defect", metrics.symplectic_defect(y))):
+        v = v[np.isfinite(v)]
+        out[name] = {"median": float(np.median(v)), "max": float(np.max(v))} if v.size else None
+    return out
 
 
 def serving_run(ctx, rate, n_req, warmup, precision, chunk, reqs=None, verbose=False):

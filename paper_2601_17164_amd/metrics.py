@@ -43,3 +43,17 @@ def det_monodromy_drift(y) -> np.ndarray:
     y = np.asarray(y)
     M = y[6:42].T.reshape(-1, 6, 6).transpose(0, 2, 1)  # [n, row, column]
     return np.abs(np.linalg.det(M) - 1.0)
+
+
+def symplectic_defect(y) -> np.ndarray:
+    """max |M^T J M - J| / ||M||_F^2 per trajectory from the final states y[43][n], J = [[0, I],
+    [-I, 0]]: the scale-free test of the monodromy (det M = 1 follows from it). |det M - 1| itself
+    is not usable once ||M|| is large, since det M is then a difference of products of order
+    ||M||^6 that cancel to 1."""
+    y = np.asarray(y)
+    M = y[6:42].T.reshape(-1, 6, 6).transpose(0, 2, 1)  # [n, row, column]
+    J = np.zeros((6, 6))
+    J[:3, 3:] = np.eye(3)
+    J[3:, :3] = -np.eye(3)
+    D = np.einsum("nji,jk,nkl->nil", M, J, M) - J
+    return np.max(np.abs(D), axis=(1, 2)) / np.sum(M * M, axis=(1, 2))
