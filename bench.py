@@ -423,7 +423,7 @@ def sfa_results(ctx, stream, reps):
 def main():
     a = _args()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU path (sharding "
+        print(json.dumps({"error": "the library runs one job on one GPU; a multi-GPU path (sharding "
                                    "by birth groups with one reduction of d(t)) is not built",
                           "n_gpus": a.gpus}))
         sys.exit(2)
