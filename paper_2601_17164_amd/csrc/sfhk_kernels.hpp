@@ -235,12 +235,14 @@ __device__ __noinline__ Contrib contribution(const GtoConst* __restrict__ G, dou
 // The dipole integrand is deferred. At a given step few lanes of a wave are near the ground state,
 // and evaluated in place their integrand would cost the whole wave. Instead each such lane appends
 // (q, p, S, w C, n) to a per-wave LDS queue; when the queue cannot take the next step's entries,
-// and at the end of the launch, the wave evaluates up to 64 of them at once. A step's entries are
-// consecutive and in lane order, and the first of them sums the run in that order and stores the
-// tile's partial row for the step; rows of steps without entries keep the zeros they were
-// allocated with. The entries of one step never straddle two evaluations, so the sums do not
-// depend on how the propagation is split into launches or batched. The wave is the whole
-// workgroup, so the queue needs no cross-wave synchronisation.
+// and at the end of the launch, the wave evaluates up to 64 of them at once, one per lane. A
+// step's entries are consecutive lanes in lane order; a segmented scan over the wave (run_sum)
+// sums each run and its last lane stores the tile's partial row for the step; rows of steps
+// without entries keep the zeros they were allocated with. The scan's additions depend only on
+// positions within the run, and the entries of one step never straddle two evaluations, so the
+// sums do not depend on where a run lies in the queue, nor on how the propagation is split into
+// launches or batched. The wave is the whole workgroup, so the queue needs no cross-wave
+// synchronisation.
 constexpr int kQueue = kTile;
 
 struct WorkItem {
@@ -252,8 +254,6 @@ struct QueueEntry {
 };
 struct IntegrandQueue {
   QueueEntry e[kQueue];
-  double2 f[kQueue];
-  double2 fv[kQueue];  // dipole velocity (jobs that ask for it)
 };
 
 typedef __attribute__((address_space(4))) const double* const_dptr;  // scalar (uniform) loads
@@ -302,47 +302,51 @@ __device__ __forceinline__ bool pw_keep(const JobDev& J, double qx, double qy, d
   return (J.pw_mask >> k) & 1;
 }
 
+// sum over the run of equal keys that ends at this lane, for runs of consecutive lanes (run_start
+// = first lane of this lane's run): a Hillis-Steele scan whose additions depend only on positions
+// relative to the run's start, so a run's total does not depend on where the run lies in the wave
+__device__ __forceinline__ double run_sum(double x, int lane, int run_start) {
+#pragma unroll
+  for (int off = 1; off < kQueue; off <<= 1) {
+    const double y = __shfl_up(x, off, 64);
+    if (lane - off >= run_start) x += y;
+  }
+  return x;
+}
+
 // evaluates the qn queued entries (one per lane) and stores their per-step sums; returns this
-// lane's count of evaluated primitives
+// lane's count of evaluated primitives. A step's entries are consecutive lanes (a run); the last
+// lane of the run stores the run's sum.
 __device__ __forceinline__ unsigned int queue_eval(IntegrandQueue& Q, int qn, int lane,
                                                    const JobDev& J, double2* __restrict__ part,
                                                    long long roff, int t0) {
   __syncthreads();
   unsigned int n_eval = 0;
+  Contrib cb = {0.0, 0.0, 0.0, 0.0, 0u};
+  double ns = -1.0;
   if (lane < qn) {
     const QueueEntry x = Q.e[lane];
     const double qx = x.a.x, qy = x.a.y, qz = x.b.x, px = x.b.y, py = x.c.x, pz = x.c.y;
     const double p2 = SFHK_FMA(pz, pz, SFHK_FMA(py, py, px * px));
     const double q2 = SFHK_FMA(qz, qz, SFHK_FMA(qy, qy, qx * qx));
-    Contrib cb = {0.0, 0.0, 0.0, 0.0, 0u};
+    ns = x.e.y;
     if (!J.pw_mask || pw_keep(J, qx, qy, qz, px, py, pz))
       cb = contribution(&J.gto, J.cut, qx, qy, qz, px, py, pz, p2, q2, x.d.x, J.t_a + x.e.y * J.h,
                         x.d.y, x.e.x);
-    Q.f[lane] = make_double2(cb.re, cb.im);
-    Q.fv[lane] = make_double2(cb.vre, cb.vim);
     n_eval = cb.n_eval;
   }
-  __syncthreads();
-  if (lane < qn) {
-    const double ns = Q.e[lane].e.y;
-    if (lane == 0 || Q.e[lane - 1].e.y != ns) {
-      double2 acc = Q.f[lane];
-      for (int j = lane + 1; j < qn && Q.e[j].e.y == ns; ++j) {
-        const double2 v = Q.f[j];
-        acc.x += v.x;
-        acc.y += v.y;
-      }
-      part[roff + ((long long)ns - t0)] = acc;
-      if (J.vel_off) {
-        double2 accv = Q.fv[lane];
-        for (int j = lane + 1; j < qn && Q.e[j].e.y == ns; ++j) {
-          const double2 v = Q.fv[j];
-          accv.x += v.x;
-          accv.y += v.y;
-        }
-        part[J.vel_off + roff + ((long long)ns - t0)] = accv;
-      }
-    }
+  // runs of equal steps: starts as a wave mask, this lane's run start, and whether it ends one
+  const double prev = __shfl_up(ns, 1, 64);
+  const unsigned long long starts =
+      __builtin_amdgcn_ballot_w64(lane < qn && (lane == 0 || prev != ns));
+  const unsigned long long upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+  const int rs = 63 - __clzll(starts & upto);
+  const bool last = lane < qn && (lane == qn - 1 || ((starts >> (lane + 1)) & 1ull));
+  const double sr = run_sum(cb.re, lane, rs), si = run_sum(cb.im, lane, rs);
+  if (last) part[roff + ((long long)ns - t0)] = make_double2(sr, si);
+  if (J.vel_off) {
+    const double vr = run_sum(cb.vre, lane, rs), vi = run_sum(cb.vim, lane, rs);
+    if (last) part[J.vel_off + roff + ((long long)ns - t0)] = make_double2(vr, vi);
   }
   __syncthreads();
   return n_eval;
