@@ -120,11 +120,12 @@ __device__ __forceinline__ void sincos_integrand(double x, double* sp, double* c
   // sin r = r (1 - r^2/3! + r^4/5! - ...), cos r = 1 - r^2/2! + r^4/4! - ...
   double ps = kInvFact14.v[13];
 #pragma unroll
-  for (int k = 11; k >= 3; k -= 2) ps = SFHK_FMA(ps, r2, (k % 4 == 1) ? kInvFact14.v[k] : -kInvFact14.v[k]);
+  for (int k = 11; k >= 3; k -= 2) ps = fma3(ps, r2, (k % 4 == 1) ? kInvFact14.v[k] : -kInvFact14.v[k]);
   const double sr = SFHK_FMA(ps * r2, r, r);
   double pc = -kInvFact14.v[14];
 #pragma unroll
-  for (int k = 12; k >= 2; k -= 2) pc = SFHK_FMA(pc, r2, (k % 4 == 0) ? kInvFact14.v[k] : -kInvFact14.v[k]);
+  for (int k = 12; k >= 4; k -= 2) pc = fma3(pc, r2, (k % 4 == 0) ? kInvFact14.v[k] : -kInvFact14.v[k]);
+  pc = SFHK_FMA(pc, r2, -0.5);  // -1/2!: an inline constant
   const double cr = SFHK_FMA(pc, r2, 1.0);
   const int q = (int)(n - 4.0 * floor(0.25 * n));  // n mod 4, exact for |n| < 2^53
   double s = (q & 1) ? cr : sr;
@@ -159,7 +160,7 @@ __device__ __forceinline__ Elements overlap(const GtoConst& G, double cut, const
     if (re >= -cut) {
       ++n_eval;
       double im = -(pq * G.D[j]);
-      double e = exp(re) * G.N[j];
+      double e = exp_cw_nonpos(re) * G.N[j];
       double s, c;
       sincos_integrand(im, &s, &c);
       cplx E = {e * c, e * s};
