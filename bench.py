@@ -88,6 +88,11 @@ def _args():
                     help="skip the dipole-velocity leg (one propagation with both accumulators)")
     ap.add_argument("--sfa-only", action="store_true",
                     help="time only the SFA birth step (2^20 samples) and print its JSON line")
+    ap.add_argument("--no-softcore", action="store_true",
+                    help="skip the soft-core leg (config 0's atom at config 1's pulse, 2^19 "
+                         "trajectories)")
+    ap.add_argument("--softcore-only", action="store_true",
+                    help="time only the soft-core leg and print its JSON line")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the uneven-batch pass of the default benchmark")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -420,6 +425,36 @@ def sfa_results(ctx, stream, reps):
             "kay_removed": st.kay_removed, "prims_per_step": st.prims_evaluated / max(1, st.steps_evaluated)}
 
 
+def softcore_results(ctx, stream):
+    """The propagate kernel on the soft-core atom at full size (inputs.softcore_full): one
+    untimed launch, then one timed with HIP events on the launch stream. The soft-core instances
+    are half of the batch and serving mix; their kernel is held back by the s-wave dipole
+    element, needed at most steps near the nucleus, and by lanes idle after the Kay test."""
+    import torch
+    from paper_2601_17164_amd import flops, inputs as I, sfhk
+    inst = I.softcore_full()
+    arrays = sfhk.to_device(inst, "cuda:0")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for it in range(2):
+        job = sfhk.make_job(ctx, inst, arrays)
+        ev[0].record(stream)
+        assert job.propagate(0)
+        ev[1].record(stream)
+        st = job.stats(stream)
+        job.close()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1])
+    fl = flops.flops(inst.potential.kind, inst.ground.l, st.steps_evaluated, st.prims_evaluated)
+    return {"workload": "soft-core H (config 0 atom) 1600nm 1.5e14 W/cm2 8-cycle, "
+                        f"{inst.n_birth}x{inst.n_per_birth} trajectories, dt 0.1, FP64",
+            "n_traj": inst.n_traj, "n_steps": inst.grid.n_steps, "kernel_ms": ms,
+            "trajectory_steps": st.steps_evaluated,
+            "trajectory_steps_per_s": st.steps_evaluated / ms * 1e3,
+            "frac_of_fp64_vector_peak": fl / (ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+            "kay_removed_frac": st.kay_removed / inst.n_traj,
+            "prims_per_step": st.prims_evaluated / max(1, st.steps_evaluated)}
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -441,6 +476,13 @@ def main():
         return
     if a.gabor_only:
         gabor_only(a)
+        return
+    if a.softcore_only:
+        import torch
+        from paper_2601_17164_amd import sfhk
+        ctx = sfhk.Context(0)
+        print(json.dumps({"softcore": softcore_results(ctx, torch.cuda.current_stream())}), flush=True)
+        ctx.close()
         return
     import torch
     from paper_2601_17164_amd import flops, inputs as I, sfhk
@@ -529,6 +571,8 @@ def main():
         out["velocity"] = velocity_results(ctx, stream, inst, arrays, float(kern_ms.mean()))
     if not a.no_sfa:
         out["sfa_birth"] = sfa_results(ctx, stream, a.sfa_reps)
+    if not a.no_softcore:
+        out["softcore"] = softcore_results(ctx, stream)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, a.cpu_births, a.cpu_per_birth)
     print(json.dumps(out), flush=True)

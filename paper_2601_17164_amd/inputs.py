@@ -217,6 +217,13 @@ def config1(n_birth=1024, n_per_birth=1024, seed=1, n_out=1 << 15) -> Instance:
                          n_out=n_out)
 
 
+def softcore_full(n_birth=512, n_per_birth=1024, seed=5) -> Instance:
+    """Config 0's atom (soft-core H, s-wave GTO, Ip 0.5) at config 1's pulse (1600 nm,
+    1.5e14 W/cm^2, 8 cycles), dt 0.1: the soft-core kernel at full size, 2^19 trajectories."""
+    return make_instance("soft-core H 1600nm 1.5e14 8cyc", SOFTCORE_H, gto_h1s(),
+                         Pulse(1600.0, 1.5e14, 8.0), 0.1, n_birth, n_per_birth, seed)
+
+
 def config1_birth_subset(inst: Instance, births, n_per_birth=None) -> Instance:
     """Trajectories of the given birth groups (and optionally only the first samples of each)."""
     m = inst.n_per_birth if n_per_birth is None else n_per_birth
