@@ -171,10 +171,9 @@ __device__ __forceinline__ double norm2(double x, double y, double z) {
   return SFHK_FMA(z, z, r2);
 }
 
-// V, g, c at (x, y, z) with r2 = norm2(x, y, z)
+// V, g, c of the central potential at radius^2 r2 = norm2(q)
 template <int KIND>
-__device__ __forceinline__ void pot_gc(const PotParams& P, double x, double y, double z, double r2,
-                                       double& V, double& g, double& c) {
+__device__ __forceinline__ void pot_gc(const PotParams& P, double r2, double& V, double& g, double& c) {
   if constexpr (KIND == POT_SOFTCORE) {
     // V = -Z u, u = (r^2 + a)^(-1/2); dV/dr / r = Z u^3; (V'' - V'/r)/r^2 = -3 Z u^5
     double s = r2 + P.soft2;
@@ -205,16 +204,16 @@ __device__ __forceinline__ void pot_gc(const PotParams& P, double x, double y, d
 }
 
 // kind known only at run time (uniform across the wave): a scalar branch per evaluation
-__device__ __forceinline__ void pot_gc_rt(int kind, const PotParams& P, double x, double y, double z,
-                                          double r2, double& V, double& g, double& c) {
+__device__ __forceinline__ void pot_gc_rt(int kind, const PotParams& P, double r2, double& V,
+                                          double& g, double& c) {
   if (kind == POT_SCREENED)
-    pot_gc<POT_SCREENED>(P, x, y, z, r2, V, g, c);
+    pot_gc<POT_SCREENED>(P, r2, V, g, c);
   else if (kind == POT_SOFTCORE)
-    pot_gc<POT_SOFTCORE>(P, x, y, z, r2, V, g, c);
+    pot_gc<POT_SOFTCORE>(P, r2, V, g, c);
   else if (kind == POT_HARMONIC)
-    pot_gc<POT_HARMONIC>(P, x, y, z, r2, V, g, c);
+    pot_gc<POT_HARMONIC>(P, r2, V, g, c);
   else
-    pot_gc<POT_NONE>(P, x, y, z, r2, V, g, c);
+    pot_gc<POT_NONE>(P, r2, V, g, c);
 }
 
 struct Hess3 {
@@ -260,11 +259,10 @@ struct Traj {
 };
 
 // the (q, p, S) right-hand side; q2 = norm2(q), p2 = norm2(p)
-__device__ __forceinline__ void qps_rhs(int kind, const PotParams& P, const double* q, const double* p,
-                                        double q2, double p2, double E, double* kp, double& kS,
-                                        Hess3& H) {
+__device__ __forceinline__ void qps_rhs(int kind, const PotParams& P, const double* q, double q2,
+                                        double p2, double E, double* kp, double& kS, Hess3& H) {
   double V, g, c;
-  pot_gc_rt(kind, P, q[0], q[1], q[2], q2, V, g, c);
+  pot_gc_rt(kind, P, q2, V, g, c);
   H = hess_from(g, c, q[0], q[1], q[2]);
   kp[0] = -(g * q[0]);
   kp[1] = -(g * q[1]);
@@ -275,7 +273,7 @@ __device__ __forceinline__ void qps_rhs(int kind, const PotParams& P, const doub
 
 __device__ __forceinline__ void qps_rhs(int kind, const PotParams& P, const double* q, const double* p,
                                         double E, double* kp, double& kS, Hess3& H) {
-  qps_rhs(kind, P, q, p, norm2(q[0], q[1], q[2]), norm2(p[0], p[1], p[2]), E, kp, kS, H);
+  qps_rhs(kind, P, q, norm2(q[0], q[1], q[2]), norm2(p[0], p[1], p[2]), E, kp, kS, H);
 }
 
 // q2 = norm2(T.q) and p2 = norm2(T.p) of the state the step starts from (the caller has them)
@@ -286,7 +284,7 @@ __device__ __forceinline__ void rk4_step(int kind, const PotParams& P, Traj& T, 
   {
     double accq[3], accp[3], accS, ysq[3], ysp[3], ysS, kp[3], kS;
     // stage 1
-    qps_rhs(kind, P, T.q, T.p, q2, p2, ea, kp, kS, H1);
+    qps_rhs(kind, P, T.q, q2, p2, ea, kp, kS, H1);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       accq[i] = T.p[i];
