@@ -126,10 +126,18 @@ def cpu_baseline(inst, n_births, n_per):
     t = time.perf_counter()
     r = run_oracle(sub, n_threads=threads)
     dt = time.perf_counter() - t
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": r.steps_evaluated / dt, "unit": "trajectory-steps/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{len(births)} birth groups x {n_per} samples = {sub.n_traj} trajectories "
-                      f"({r.steps_evaluated} trajectory-steps, {dt:.1f} s)"}
+                      f"({r.steps_evaluated} trajectory-steps, {dt:.1f} s)",
+            "per_core": r.steps_evaluated / dt / threads, "cpu_model": model,
+            "host_cpus": os.cpu_count()}
 
 
 def mixed_form(step, stream, inst, arrays, ref_spectrum, flops):
