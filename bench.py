@@ -126,6 +126,10 @@ def cpu_baseline(inst, n_births, n_per):
     t = time.perf_counter()
     r = run_oracle(sub, n_threads=threads)
     dt = time.perf_counter() - t
+    c0 = I.config0()  # the small configuration in full, beside the sample
+    t = time.perf_counter()
+    r0 = run_oracle(c0, n_threads=threads)
+    dt0 = time.perf_counter() - t
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -137,7 +141,9 @@ def cpu_baseline(inst, n_births, n_per):
             "sample": f"{len(births)} birth groups x {n_per} samples = {sub.n_traj} trajectories "
                       f"({r.steps_evaluated} trajectory-steps, {dt:.1f} s)",
             "per_core": r.steps_evaluated / dt / threads, "cpu_model": model,
-            "host_cpus": os.cpu_count()}
+            "host_cpus": os.cpu_count(),
+            "config0_full": {"value": r0.steps_evaluated / dt0, "trajectories": c0.n_traj,
+                             "trajectory_steps": r0.steps_evaluated, "seconds": dt0}}
 
 
 def mixed_form(step, stream, inst, arrays, ref_spectrum, flops):
