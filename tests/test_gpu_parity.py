@@ -165,6 +165,28 @@ def test_config1_full_size_sampled_trajectories(S):
     assert st.kay_removed + st.nonfinite_removed == died.sum()
 
 
+def test_softcore_full_size_sampled_trajectories(S):
+    """The soft-core atom at full size (2^19 trajectories, 17652 steps), launched as the
+    benchmark's soft-core leg launches it: sampled trajectories (removed ones among them) bit for
+    bit against the oracle, and the counters against the per-trajectory removal steps."""
+    sfhk, ctx, torch = S
+    inst = I.softcore_full()
+    g = _gpu_run(S, inst)
+    died = g["death"] >= 0
+    rng = np.random.default_rng(19)
+    idx = np.sort(np.concatenate([rng.choice(np.flatnonzero(died), 8, replace=False),
+                                  rng.choice(np.flatnonzero(~died), 8, replace=False)]))
+    r = run_oracle(inst.subset(idx))
+    np.testing.assert_array_equal(g["death"][idx], r.death)
+    np.testing.assert_array_equal(g["y"][:, idx], r.y_final)
+    st = g["stats"]
+    n0 = np.clip(np.ceil((inst.t0 - inst.grid.t_a) / inst.grid.h - 0.5), 0, inst.grid.n_steps)
+    expect = np.where(died, g["death"] - n0 + 1, inst.grid.n_steps - n0 + 1).sum()
+    assert st.steps_evaluated == expect
+    assert st.kay_removed + st.nonfinite_removed == died.sum()
+    assert 0.2 < died.mean() < 0.4  # the Kay test removes about 28% here
+
+
 def test_chunked_propagation_equals_one_shot(S):
     inst = I.config0(n_birth=16, n_per_birth=40)
     a = _gpu_run(S, inst)
