@@ -105,6 +105,14 @@ MUTANTS = {
     "sincos: reduction drops the pi/2 tail": ("r = fma(-k, SINC_PIO2_3, r);", "r = r;"),
     "sincos: sine series two terms short": ("double ps = inv_fact[17];\n  for (int j = 7;",
                                             "double ps = inv_fact[13];\n  for (int j = 5;"),
+    "skip rule: threshold a quarter of the cut": ("if (creal(ex) < -cut) continue; /* primitive negligible",
+                                                  "if (creal(ex) < -0.25 * cut) continue; /* primitive negligible"),
+    "skip rule: comparison inverted": ("if (creal(ex) < -cut) continue; /* primitive negligible",
+                                       "if (creal(ex) >= -cut) continue; /* primitive negligible"),
+    "velocity skip rule: threshold a quarter of the cut": ("if (creal(ex) < -cut) continue; /* the dipole",
+                                                           "if (creal(ex) < -0.25 * cut) continue; /* the dipole"),
+    "velocity skip rule: comparison inverted": ("if (creal(ex) < -cut) continue; /* the dipole",
+                                                "if (creal(ex) >= -cut) continue; /* the dipole"),
 }
 
 

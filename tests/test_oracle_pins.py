@@ -794,3 +794,77 @@ def test_gabor_edges_and_errors():
     for bad in ((0.0, 0.1), (-1.0, 0.1), (2.0, 0.0)):
         with pytest.raises(ValueError):
             O.gabor(np.ones(10), 0.0, bad[1], bad[0], 0.0, 1.0, 2, 0.5, 2)
+
+
+# ------------------------------------------------------------------------------------------
+# skip rule of the GTO elements (App. C.1, C.2): a primitive whose exponent has real part below
+# -overlap_cut is dropped
+# ------------------------------------------------------------------------------------------
+def _skip_bound(g, gamma, q, p, cut):
+    """Bound on what the skip rule may drop from the dipole element at (q, p): each dropped
+    primitive has |exp(exponent)| < e^{-cut}, so it drops at most
+    e^{-cut} |c_j| (gamma + a_j)^{-5/2} |2 gamma q_z + i p_z| (s) or
+    e^{-cut} |c_j| (gamma + a_j)^{-7/2} |(2 gamma q_z + i p_z)^2 + 2 (gamma + a_j)| (p)."""
+    a = complex(2.0 * gamma * q[2], p[2])
+    tot = 0.0
+    for al, c in zip(g.alpha, g.coef):
+        ga = gamma + al
+        if g.l == 0:
+            tot += abs(c) * ga ** -2.5 * abs(a)
+        else:
+            tot += abs(c) * ga ** -3.5 * abs(a * a + 2.0 * ga)
+    return math.exp(-cut) * tot
+
+
+@pytest.mark.parametrize("gname", ["s", "p"])
+def test_skip_rule_drops_only_primitives_beyond_the_cut(gname):
+    """At phase-space points where some primitives have exponents between -60 and -15 and others
+    are larger, the element at cut = 60 differs from the full sum (cut = 1e9) by less than the
+    e^{-60} bound, while cut = 15 drops terms of size about e^{-15}: the threshold is -cut on the
+    real part of the exponent, and only primitives beyond it are dropped."""
+    g = I.gto_h1s() if gname == "s" else I.gto_p058()
+    G = _ground(g)
+    rng = np.random.default_rng(21)
+    n_between = 0
+    for _ in range(400):
+        q = rng.normal(0, 4.0, 3)
+        p = rng.normal(0, 2.0, 3)
+        p2, q2 = float(p @ p), float(q @ q)
+        re = [-(p2 + 4.0 * al * GAMMA * q2) / (4.0 * (GAMMA + al)) for al in g.alpha]
+        full = O.overlap(G, GAMMA, q, p, cut=1e9)
+        at60 = O.overlap(G, GAMMA, q, p, cut=60.0)
+        assert abs(at60 - full) <= _skip_bound(g, GAMMA, q, p, 60.0) * (1 + 1e-12) + 1e-300
+        fv, v60 = O.overlap_v(G, GAMMA, q, p, cut=1e9), O.overlap_v(G, GAMMA, q, p, cut=60.0)
+        kept = [x for x in re if x >= -60.0]
+        if not kept:
+            assert at60 == 0 and v60 == 0
+        if all(x >= -60.0 for x in re):
+            assert at60 == full and v60 == fv  # nothing beyond the cut: nothing dropped
+        if any(-60.0 < x < -15.0 for x in re) and max(re) > -5.0:
+            n_between += 1
+            # primitives between the two thresholds are kept at 60 and dropped at 15
+            at15 = O.overlap(G, GAMMA, q, p, cut=15.0)
+            assert at15 != at60
+    assert n_between >= 20
+
+
+@pytest.mark.parametrize("case", ["config0", "screened_subset"])
+def test_skip_rule_is_harmless_for_the_dipole(case):
+    """F and V at the workloads' overlap_cut = 60 against the full sum (cut = 1e9): the e^{-60}
+    bound of the rule times the largest Kay-allowed |C| (1e15) is about 1e-11, so the relative
+    L2 difference must stay below 1e-11; a threshold four times smaller (cut = 15) moves F by
+    far more than that, so the workloads do reach primitives beyond the cut."""
+    if case == "config0":
+        inst = I.config0()
+    else:
+        inst = I.config1_birth_subset(I.config1(), list(range(0, 1024, 64)), 16)
+    a = _run(inst, overlap_cut=60.0, velocity=True)
+    b = _run(inst, overlap_cut=1e9, velocity=True)
+    c = _run(inst, overlap_cut=15.0)
+    nb = np.linalg.norm(b.F)
+    assert nb > 0 and np.linalg.norm(b.V) > 0
+    assert np.linalg.norm(a.F - b.F) <= 1e-11 * nb
+    assert np.linalg.norm(a.V - b.V) <= 1e-11 * np.linalg.norm(b.V)
+    assert np.linalg.norm(c.F - b.F) > 1e-9 * nb
+    # the rule never touches the trajectories
+    assert np.array_equal(a.y_final, b.y_final) and np.array_equal(a.death, b.death)
