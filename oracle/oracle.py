@@ -29,17 +29,31 @@ CFLAGS = ["-O2", "-mfma", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shar
           "-std=gnu11", "-Wall", "-Wno-unused-function"]
 
 
+# The same source built with every square root, quotient, exponential, sine and cosine rounded
+# once (-DOR_CORRECTLY_ROUNDED) instead of the rounding contract's sequences.
+LIB_CR = os.environ.get("SFHK_ORACLE_LIB_CR", os.path.join(HERE, "libsfhk_oracle_cr.so"))
+
+
+def _compile(out: str, defines=()) -> None:
+    tmp = out + ".tmp"
+    cmd = ["gcc", *CFLAGS, *[f"-D{d}" for d in defines], "-o", tmp, SRC, "-lquadmath", "-lm",
+           "-lpthread"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc into ``oracle/libsfhk_oracle.so``."""
+    """Compile the oracle with gcc into ``oracle/libsfhk_oracle.so`` (and its correctly rounded
+    build ``oracle/libsfhk_oracle_cr.so``)."""
     if force or not os.path.exists(LIB):
-        tmp = LIB + ".tmp"
-        cmd = ["gcc", *CFLAGS, "-o", tmp, SRC, "-lquadmath", "-lm", "-lpthread"]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, LIB)
+        _compile(LIB)
+    if force or not os.path.exists(LIB_CR):
+        _compile(LIB_CR, ["OR_CORRECTLY_ROUNDED"])
     return LIB
 
 
 _lib = None
+_lib_cr = None
 
 
 class _Potential(ct.Structure):
@@ -54,7 +68,7 @@ class _Ground(ct.Structure):
 
 class _HK(ct.Structure):
     _fields_ = [("gamma", ct.c_double), ("kay_max", ct.c_double), ("overlap_cut", ct.c_double),
-                ("pw_mask", ct.c_int32), ("pw_radius", ct.c_double)]
+                ("pw_mask", ct.c_int32), ("pw_radius", ct.c_double), ("kay_whole", ct.c_int32)]
 
 
 class _Grid(ct.Structure):
@@ -77,49 +91,64 @@ class _Stats(ct.Structure):
                 ("nonfinite_removed", ct.c_int64)]
 
 
-def lib():
-    global _lib
+def lib(correctly_rounded: bool = False):
+    """The oracle's library; correctly_rounded=True: its build with the plain, once-rounded
+    elementary operations."""
+    global _lib, _lib_cr
+    if correctly_rounded:
+        if _lib_cr is None:
+            if not os.path.exists(LIB_CR):
+                build(force=False)
+            _lib_cr = _declare(ct.CDLL(LIB_CR))
+            assert _lib_cr.or_correctly_rounded() == 1
+        return _lib_cr
     if _lib is None:
         if not os.path.exists(LIB):
             build(force=False)
-        L = ct.CDLL(LIB)
-        D, P = ct.c_double, ct.POINTER(ct.c_double)
-        L.or_exp_cr.restype = D
-        L.or_exp_cr.argtypes = [D]
-        L.or_exp_cw.restype = D
-        L.or_exp_cw.argtypes = [D]
-        L.or_rsqrt_c.restype = D
-        L.or_rsqrt_c.argtypes = [D]
-        for nm in ("or_sin_cr", "or_cos_cr"):
-            getattr(L, nm).restype = D
-            getattr(L, nm).argtypes = [D]
-        L.or_sincos_c.argtypes = [D, P, P]
-        L.or_sfa_birth.restype = ct.c_int
-        L.or_sfa_birth.argtypes = [ct.POINTER(_Pulse), ct.POINTER(_Ground), ct.c_int32,
-                                   ct.c_int64, P, P, P, ct.c_int, P, P, P, P]
-        for nm in ("or_field_A", "or_field_E", "or_field_intA"):
-            getattr(L, nm).restype = D
-            getattr(L, nm).argtypes = [D, D, D, D, D]
-        L.or_potential_eval.argtypes = [ct.POINTER(_Potential), P, P, P, P]
-        L.or_hk_det.argtypes = [P, D, P]
-        L.or_overlap.argtypes = [ct.POINTER(_Ground), D, D, P, P, P]
-        L.or_propagate.restype = ct.c_int
-        L.or_propagate.argtypes = [ct.POINTER(_Potential), ct.POINTER(_Ground), ct.POINTER(_HK),
-                                   ct.POINTER(_Grid), ct.c_int64, P, P, P, P, ct.c_int, P, P,
-                                   ct.POINTER(_Diag), ct.POINTER(_Stats)]
-        L.or_overlap_v.argtypes = [ct.POINTER(_Ground), D, D, P, P, P]
-        L.or_gabor.restype = ct.c_int
-        L.or_gabor.argtypes = [P, ct.c_int64, D, D, D, D, D, ct.c_int64, D, ct.c_int64, P, P]
-        L.or_trajectory.restype = ct.c_int
-        L.or_trajectory.argtypes = [ct.POINTER(_Potential), ct.POINTER(_Ground), ct.POINTER(_HK),
-                                    ct.POINTER(_Grid), D, P, P, P, P, P, P, P, P,
-                                    ct.POINTER(ct.c_int8)]
-        L.or_dipole.argtypes = [P, ct.c_int64, P]
-        L.or_resample.argtypes = [P, ct.c_int64, ct.c_int64, P]
-        L.or_spectrum.restype = ct.c_int
-        L.or_spectrum.argtypes = [P, ct.c_int64, D, D, D, ct.c_int64, P, P, P]
-        _lib = L
+        _lib = _declare(ct.CDLL(LIB))
     return _lib
+
+
+def _declare(L):
+    """Set the argument and result types of the oracle's exported functions."""
+    D, P = ct.c_double, ct.POINTER(ct.c_double)
+    L.or_exp_cr.restype = D
+    L.or_exp_cr.argtypes = [D]
+    L.or_exp_cw.restype = D
+    L.or_exp_cw.argtypes = [D]
+    L.or_rsqrt_c.restype = D
+    L.or_rsqrt_c.argtypes = [D]
+    for nm in ("or_sin_cr", "or_cos_cr"):
+        getattr(L, nm).restype = D
+        getattr(L, nm).argtypes = [D]
+    L.or_sincos_c.argtypes = [D, P, P]
+    L.or_sfa_birth.restype = ct.c_int
+    L.or_sfa_birth.argtypes = [ct.POINTER(_Pulse), ct.POINTER(_Ground), ct.c_int32,
+                               ct.c_int64, P, P, P, ct.c_int, P, P, P, P]
+    for nm in ("or_field_A", "or_field_E", "or_field_intA"):
+        getattr(L, nm).restype = D
+        getattr(L, nm).argtypes = [D, D, D, D, D]
+    L.or_potential_eval.argtypes = [ct.POINTER(_Potential), P, P, P, P]
+    L.or_hk_det.argtypes = [P, D, P]
+    L.or_overlap.argtypes = [ct.POINTER(_Ground), D, D, P, P, P]
+    L.or_propagate.restype = ct.c_int
+    L.or_propagate.argtypes = [ct.POINTER(_Potential), ct.POINTER(_Ground), ct.POINTER(_HK),
+                               ct.POINTER(_Grid), ct.c_int64, P, P, P, P, ct.c_int, P, P,
+                               ct.POINTER(_Diag), ct.POINTER(_Stats)]
+    L.or_overlap_v.argtypes = [ct.POINTER(_Ground), D, D, P, P, P]
+    L.or_gabor.restype = ct.c_int
+    L.or_gabor.argtypes = [P, ct.c_int64, D, D, D, D, D, ct.c_int64, D, ct.c_int64, P, P]
+    L.or_trajectory.restype = ct.c_int
+    L.or_trajectory.argtypes = [ct.POINTER(_Potential), ct.POINTER(_Ground), ct.POINTER(_HK),
+                                ct.POINTER(_Grid), D, P, P, P, P, P, P, P, P,
+                                ct.POINTER(ct.c_int8)]
+    L.or_dipole.argtypes = [P, ct.c_int64, P]
+    L.or_resample.argtypes = [P, ct.c_int64, ct.c_int64, P]
+    L.or_spectrum.restype = ct.c_int
+    L.or_spectrum.argtypes = [P, ct.c_int64, D, D, D, ct.c_int64, P, P, P]
+    L.or_correctly_rounded.restype = ct.c_int
+    L.or_correctly_rounded.argtypes = []
+    return L
 
 
 def _p(a):
@@ -202,7 +231,7 @@ class SfaBirth:
 
 
 def sfa_birth(e0, omega, n_cycles, cep, ground: "Ground", t0, kperp, u=None, mode=0,
-              n_threads=0) -> SfaBirth:
+              n_threads=0, correctly_rounded=False) -> SfaBirth:
     """SFA birth step (App. A saddle point and tunnel exit, App. B tunnelling element):
     (t0, k_perp) -> (q0, p0, w, t_t); see ``or_sfa_birth`` in ``sfhk_oracle.h``."""
     t0 = _f64(t0)
@@ -213,7 +242,7 @@ def sfa_birth(e0, omega, n_cycles, cep, ground: "Ground", t0, kperp, u=None, mod
     q0, p0, w2, tt = np.zeros((3, n)), np.zeros((3, n)), np.zeros((2, n)), np.zeros(n)
     g = ground.c()
     pl = _Pulse(float(e0), float(omega), float(n_cycles), float(cep))
-    rc = lib().or_sfa_birth(ct.byref(pl), ct.byref(g), int(mode), n, _p(t0), _p(kperp),
+    rc = lib(correctly_rounded).or_sfa_birth(ct.byref(pl), ct.byref(g), int(mode), n, _p(t0), _p(kperp),
                             None if uu is None else _p(uu), int(n_threads), _p(q0), _p(p0),
                             _p(w2), _p(tt))
     if rc != 0:
@@ -283,11 +312,16 @@ class PropagateResult:
 
 def propagate(pot: Potential, ground: Ground, e_half, t_a, h, n_steps, t0, q0, p0, w=None,
               gamma=0.5, kay_max=1e30, overlap_cut=60.0, n_threads=0,
-              velocity=False, pw_mask=0, pw_radius=3.0) -> PropagateResult:
+              velocity=False, pw_mask=0, pw_radius=3.0,
+              correctly_rounded=False, kay_whole=False) -> PropagateResult:
     """Run the oracle over all trajectories; q0, p0 are [3, n] arrays, w is complex [n] or None.
     velocity=True also accumulates the dipole velocity V(t_n) (App. C.2). pw_mask != 0 keeps
-    only the steps of the selected partial waves near the core (``or_hk`` in sfhk_oracle.h)."""
-    L = lib()
+    only the steps of the selected partial waves near the core (``or_hk`` in sfhk_oracle.h).
+    correctly_rounded=True runs the build whose square roots, quotients and exponentials are
+    the plain operations rounded once. kay_whole=True takes the other reading of the Kay removal:
+    a trajectory that ever exceeds D_t contributes nothing at all (default: it stops contributing
+    from the first step where it does)."""
+    L = lib(correctly_rounded)
     e_half = _f64(e_half)
     if len(e_half) != 2 * n_steps + 1:
         raise ValueError("field table must hold 2*n_steps+1 half-step samples")
@@ -308,7 +342,8 @@ def propagate(pot: Potential, ground: Ground, e_half, t_a, h, n_steps, t0, q0, p
                  death.ctypes.data_as(ct.POINTER(ct.c_int64)), _p(yf), _p(cf))
     st = _Stats()
     grid = _Grid(float(t_a), float(h), int(n_steps), _p(e_half))
-    hk = _HK(float(gamma), float(kay_max), float(overlap_cut), int(pw_mask), float(pw_radius))
+    hk = _HK(float(gamma), float(kay_max), float(overlap_cut), int(pw_mask), float(pw_radius),
+             int(bool(kay_whole)))
     g = ground.c()
     rc = L.or_propagate(ct.byref(pot.c()), ct.byref(g), ct.byref(hk), ct.byref(grid), n,
                         _p(t0), _p(q0), _p(p0), wp, int(n_threads), _p(f),
@@ -333,8 +368,8 @@ class TrajectoryRecord:
 
 def trajectory(pot: Potential, ground: Ground, e_half, t_a, h, n_steps, t0, q0, p0, w=1.0,
                gamma=0.5, kay_max=1e30, overlap_cut=60.0, pw_mask=0,
-               pw_radius=3.0) -> TrajectoryRecord:
-    L = lib()
+               pw_radius=3.0, correctly_rounded=False) -> TrajectoryRecord:
+    L = lib(correctly_rounded)
     e_half = _f64(e_half)
     nb = n_steps + 1
     y = np.zeros((nb, 43))
@@ -346,7 +381,7 @@ def trajectory(pot: Potential, ground: Ground, e_half, t_a, h, n_steps, t0, q0, 
     q0, p0 = _f64(q0), _f64(p0)
     wa = np.array([np.real(w), np.imag(w)], dtype=np.float64)
     grid = _Grid(float(t_a), float(h), int(n_steps), _p(e_half))
-    hk = _HK(float(gamma), float(kay_max), float(overlap_cut), int(pw_mask), float(pw_radius))
+    hk = _HK(float(gamma), float(kay_max), float(overlap_cut), int(pw_mask), float(pw_radius), 0)
     g = ground.c()
     rc = L.or_trajectory(ct.byref(pot.c()), ct.byref(g), ct.byref(hk), ct.byref(grid),
                          float(t0), _p(q0), _p(p0), _p(wa), _p(y), _p(c), _p(f), _p(o), _p(d),

@@ -106,6 +106,33 @@ double or_sin_cr(double x) { return (double)sinq((__float128)x); }
 double or_cos_cr(double x) { return (double)cosq((__float128)x); }
 
 /* ------------------------------------------------------------------------------------------ */
+/* Built with -DOR_CORRECTLY_ROUNDED, every square root, quotient, exponential, sine and       */
+/* cosine on the trajectory path and in the saddle-point solve is the plain operation rounded  */
+/* once (sqrt and / of IEEE-754, exp/sin/cos in binary128 rounded to binary64), instead of the */
+/* rounding contract's sequences above. That build shares nothing with the GPU's choice of     */
+/* sequences; the tests compare the two builds where the problem is well conditioned.          */
+/* ------------------------------------------------------------------------------------------ */
+#ifdef OR_CORRECTLY_ROUNDED
+#define OR_CR 1
+#else
+#define OR_CR 0
+#endif
+int or_correctly_rounded(void) { return OR_CR; }
+static double traj_exp(double x) { return OR_CR ? or_exp_cr(x) : or_exp_cw(x); }
+static void traj_sincos(double x, double* s, double* c) {
+  if (OR_CR) {
+    *s = or_sin_cr(x);
+    *c = or_cos_cr(x);
+  } else {
+    or_sincos_c(x, s, c);
+  }
+}
+/* 1/sqrt(x): two correctly rounded operations, or the contract's sequence */
+static double traj_rsqrt(double x) { return OR_CR ? 1.0 / sqrt(x) : or_rsqrt_c(x); }
+/* sqrt(x) = x / sqrt(x) in the contract; the correctly rounded square root otherwise */
+static double traj_sqrt_from(double x, double rs) { return OR_CR ? sqrt(x) : x * rs; }
+
+/* ------------------------------------------------------------------------------------------ */
 /* sine and cosine of the rounding contract (saddle-point solve of the SFA birth step):        */
 /* Cody-Waite reduction x = k pi/2 + r, k = rint(x 2/pi), with pi/2 split as P1 + P2 + P3      */
 /* (P1, P2 truncated to 33 significant bits, so k P1 and k P2 are exact for |k| < 2^20; P3 the */
@@ -194,7 +221,7 @@ static void pot_gc(const or_potential* pot, const double* q, double* V, double* 
     case 1: { /* soft-core Coulomb: V = -Z u, u = (r^2+a)^(-1/2) */
       double Z = pot->z_inf;
       double s = r2 + pot->soft2;
-      double u = or_rsqrt_c(s);
+      double u = traj_rsqrt(s);
       double u2 = u * u;
       double u3 = u2 * u;
       double u5 = u3 * u2;
@@ -205,20 +232,25 @@ static void pot_gc(const or_potential* pot, const double* q, double* V, double* 
     }
     case 2: { /* screened: V = -Z(r)/rho, Z(r) = z_inf + z_in exp(-r/r_scr), rho = sqrt(r^2+a) */
       double s = r2 + pot->soft2;
-      double ir = or_rsqrt_c(s);           /* 1/rho */
+      double ir = traj_rsqrt(s);           /* 1/rho */
       double inv_r = 0.0, r = 0.0;
       if (r2 > 0.0) {
-        inv_r = or_rsqrt_c(r2);
-        r = r2 * inv_r;
+        if (OR_CR) {
+          r = sqrt(r2);
+          inv_r = 1.0 / r;
+        } else {
+          inv_r = or_rsqrt_c(r2);
+          r = r2 * inv_r;
+        }
       }
       double ir2 = ir * ir;
       double ir3 = ir2 * ir;
       double inv_rs = 1.0 / pot->r_scr;
-      double e = or_exp_cw(-(r * inv_rs));
+      double e = traj_exp(OR_CR ? -(r / pot->r_scr) : -(r * inv_rs));
       double ez = pot->z_in * e;            /* z_in exp(-r/r_scr) */
       double Z = pot->z_inf + ez;
-      double d1 = ez * inv_rs;              /* -Z'(r) */
-      double d2 = d1 * inv_rs;              /*  Z''(r) */
+      double d1 = OR_CR ? ez / pot->r_scr : ez * inv_rs;   /* -Z'(r) */
+      double d2 = OR_CR ? d1 / pot->r_scr : d1 * inv_rs;   /*  Z''(r) */
       *V = -(Z * ir);
       /* V'(r) = d1/rho + Z r / rho^3 */
       double vp = fma(Z * r, ir3, d1 * ir);
@@ -388,13 +420,13 @@ static cpx csqrt_principal(cpx z, double mod) {
     r.im = 0.0;
     return r;
   }
-  double rw = or_rsqrt_c(w);
-  double t = w * rw;
+  double rw = OR_CR ? 0.0 : or_rsqrt_c(w);
+  double t = traj_sqrt_from(w, rw);
   if (z.re >= 0.0) {
     r.re = t;
-    r.im = (0.5 * z.im) * rw;
+    r.im = OR_CR ? (0.5 * z.im) / t : (0.5 * z.im) * rw;
   } else {
-    r.re = (0.5 * fabs(z.im)) * rw;
+    r.re = OR_CR ? (0.5 * fabs(z.im)) / t : (0.5 * fabs(z.im)) * rw;
     r.im = copysign(t, z.im);
   }
   return r;
@@ -557,7 +589,7 @@ static void run_traj(const or_potential* pot, const or_ground* gs, const or_hk* 
       break;
     }
     cpx dz = {det[0], det[1]};
-    double mod = a2 > 0.0 ? a2 * or_rsqrt_c(a2) : 0.0; /* |det G| */
+    double mod = a2 > 0.0 ? traj_sqrt_from(a2, OR_CR ? 0.0 : or_rsqrt_c(a2)) : 0.0; /* |det G| */
     cpx c = csqrt_principal(dz, mod);
     double dot = fma(c.im, cprev.im, c.re * cprev.re);
     if (sgn * dot < 0.0) sgn = -sgn;
@@ -631,7 +663,17 @@ static void* worker(void* arg) {
     double p0[3] = {jb->p0[j], jb->p0[N + j], jb->p0[2 * N + j]};
     double complex w = jb->w ? (jb->w[j] + I * jb->w[N + j]) : default_weight(q0, p0, N);
     traj_out to;
-    run_traj(jb->pot, jb->gs, jb->hk, jb->g, jb->t0[j], q0, p0, w, &sk, &to);
+    if (jb->hk->kay_whole) {
+      /* the other reading of the Kay removal: a first pass finds whether the trajectory is
+       * removed at any step; a removed one contributes nothing, a kept one is run again into
+       * the accumulators */
+      sink none;
+      memset(&none, 0, sizeof(none));
+      run_traj(jb->pot, jb->gs, jb->hk, jb->g, jb->t0[j], q0, p0, w, &none, &to);
+      if (to.death < 0) run_traj(jb->pot, jb->gs, jb->hk, jb->g, jb->t0[j], q0, p0, w, &sk, &to);
+    } else {
+      run_traj(jb->pot, jb->gs, jb->hk, jb->g, jb->t0[j], q0, p0, w, &sk, &to);
+    }
     jb->st.steps_evaluated += to.evaluated;
     if (to.death >= 0) {
       if (to.nonfinite)
@@ -843,7 +885,7 @@ int or_spectrum(const double* d, int64_t n, double t_first, double dt, double ta
 /* exp_cw for sinh and cosh, sincos_c, rsqrt_c, one operation per step as written.              */
 /* ------------------------------------------------------------------------------------------ */
 static double sinh_c(double x) {
-  double e = or_exp_cw(x);
+  double e = traj_exp(x);
   return 0.5 * (e - 1.0 / e);
 }
 
@@ -863,7 +905,7 @@ static void sfa_setup(const or_pulse* pl, double t0, sfa_terms* a) {
   a->om[1] = pl->omega + W;
   a->om[2] = pl->omega - W;
   a->K = pl->e0 / (2.0 * pl->omega);
-  for (int m = 0; m < 3; ++m) or_sincos_c(a->om[m] * t0 + pl->cep, &a->S[m], &a->C[m]);
+  for (int m = 0; m < 3; ++m) traj_sincos(a->om[m] * t0 + pl->cep, &a->S[m], &a->C[m]);
 }
 
 static double sfa_im_a(const sfa_terms* a, double tau) {
@@ -877,7 +919,7 @@ static double sfa_im_a(const sfa_terms* a, double tau) {
 static void sfa_im_a_d(const sfa_terms* a, double tau, double* v, double* dv) {
   double sh[3], ch[3];
   for (int m = 0; m < 3; ++m) {
-    double e = or_exp_cw(a->om[m] * tau);
+    double e = traj_exp(a->om[m] * tau);
     double ie = 1.0 / e;
     sh[m] = 0.5 * (e - ie);
     ch[m] = 0.5 * (e + ie);
@@ -897,7 +939,7 @@ static int sfa_saddle(const or_pulse* pl, double ip, double t0, double kx, doubl
   sfa_terms a;
   sfa_setup(pl, t0, &a);
   double kap2 = 2.0 * ip + (kx * kx + ky * ky);
-  double kap = kap2 * or_rsqrt_c(kap2);
+  double kap = traj_sqrt_from(kap2, OR_CR ? 0.0 : or_rsqrt_c(kap2));
   double dtau = 0.25 / a.om[1];
   double lo = 0.0, hi = 0.0, ahi = 0.0;
   int found = 0;

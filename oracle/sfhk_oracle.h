@@ -42,13 +42,18 @@ typedef struct {
  * partial-wave filter of the returning trajectories (Sec. III.A): pw_mask = 0 keeps every step;
  * otherwise a step's term counts when r < pw_radius and l = |q x p| lies in a selected band,
  * bit k (k = 0..6) for l in [k - 1/2, k + 1/2) (s, p, d, ... waves; k = 0 is [0, 1/2)), bit 7
- * for l >= 13/2, or, with bit 8, when r >= pw_radius. */
+ * for l >= 13/2, or, with bit 8, when r >= pw_radius.
+ * kay_whole selects the reading of the Kay removal (the paper removes trajectories with
+ * |C|^2 > D_t without saying from when): 0, a trajectory stops contributing from the first step
+ * where |det G| > D_t and keeps its earlier terms; 1, a trajectory that exceeds D_t at any step
+ * is removed entirely and contributes nothing (found by a first pass over the trajectory). */
 typedef struct {
   double gamma;
   double kay_max;
   double overlap_cut;
   int32_t pw_mask;
   double pw_radius;
+  int32_t kay_whole;
 } or_hk;
 
 /* Time grid: t_n = t_a + n h, n = 0..n_steps. The field table holds E_z(t_a + m h / 2),

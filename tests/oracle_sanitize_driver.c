@@ -49,7 +49,7 @@ static int run_case(const char* name, const or_potential* pot, const or_ground* 
       }
     }
   q0[1 * n + 3] = NAN; /* a non-finite sample: removed and counted, not an error */
-  or_hk hk = {0.5, 1e30, 60.0, 0x1FF ^ 0x80, 3.0};
+  or_hk hk = {0.5, 1e30, 60.0, 0x1FF ^ 0x80, 3.0, 0};
   or_grid grid = {t_a, h, ns, e_half};
   double* f = calloc((size_t)(2 * (ns + 1)), sizeof(double));
   int64_t *n0 = malloc(sizeof(int64_t) * (size_t)n), *death = malloc(sizeof(int64_t) * (size_t)n);

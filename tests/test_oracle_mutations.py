@@ -51,15 +51,15 @@ MUTANTS = {
     "contract exp drops the ln2 tail": ("r = fma(-k, EXPC_LN2_LO, r);", "r = r;"),
     "contract exp one degree short": ("double p = inv_fact[13];\n  for (int n = 12;",
                                       "double p = inv_fact[12];\n  for (int n = 11;"),
-    "screened exponent scale": ("double e = or_exp_cw(-(r * inv_rs));",
-                                "double e = or_exp_cw(-(r * inv_rs * 0.5));"),
+    "screened exponent scale": ("-(r / pot->r_scr) : -(r * inv_rs));",
+                                "-(r / pot->r_scr) : -(r * inv_rs * 0.5));"),
     "screened 1/r^2 in the Hessian": ("*c = (vpp - *g) * (inv_r * inv_r);",
                                       "*c = (vpp - *g) * inv_r;"),
     "rsqrt: one Newton step short": ("for (int it = 0; it < 3; ++it)", "for (int it = 0; it < 2; ++it)"),
     "rsqrt: tiny arguments unscaled": ("return rsqrt_core(x * 0x1p1000) * 0x1p500;",
                                        "return rsqrt_core(x);"),
-    "principal sqrt: imaginary part halved twice": ("r.im = (0.5 * z.im) * rw;",
-                                                    "r.im = (0.25 * z.im) * rw;"),
+    "principal sqrt: imaginary part halved twice": ("(0.5 * z.im) / t : (0.5 * z.im) * rw;",
+                                                    "(0.5 * z.im) / t : (0.25 * z.im) * rw;"),
     "SFA: crossing sign ignored in the bisection": ("if ((up ? v : -v) < kap)", "if (v < kap)"),
     "SFA: Newton derivative without w_m": ("*dv = -(a->K * (a->C[0] * a->om[0] * ch[0] +",
                                            "*dv = -(a->K * (a->C[0] * ch[0] +"),
@@ -111,6 +111,7 @@ MUTANTS = {
                                        "if (creal(ex) >= -cut) continue; /* primitive negligible"),
     "velocity skip rule: threshold a quarter of the cut": ("if (creal(ex) < -cut) continue; /* the dipole",
                                                            "if (creal(ex) < -0.25 * cut) continue; /* the dipole"),
+    "Kay whole-removal reading ignored": ("if (to.death < 0) run_traj(", "run_traj("),
     "velocity skip rule: comparison inverted": ("if (creal(ex) < -cut) continue; /* the dipole",
                                                 "if (creal(ex) >= -cut) continue; /* the dipole"),
 }

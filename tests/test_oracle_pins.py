@@ -868,3 +868,30 @@ def test_skip_rule_is_harmless_for_the_dipole(case):
     assert np.linalg.norm(c.F - b.F) > 1e-9 * nb
     # the rule never touches the trajectories
     assert np.array_equal(a.y_final, b.y_final) and np.array_equal(a.death, b.death)
+
+
+# ------------------------------------------------------------------------------------------
+# the two readings of the Kay removal (Sec. III.A)
+# ------------------------------------------------------------------------------------------
+def test_kay_whole_removal_is_the_dipole_of_the_survivors():
+    """Reading 'remove entirely': a trajectory that exceeds D_t at any step contributes nothing.
+    Its dipole must equal the streaming dipole of the subset of trajectories that are never
+    removed, and the two readings count the same removals; with no limit they coincide."""
+    inst = I.config0(n_birth=16, n_per_birth=16)
+    n = inst.n_traj
+    w = np.exp(1j * np.sum(inst.p0 * inst.q0, axis=0)) / n
+    stream = _run(inst, w=w)
+    whole = _run(inst, w=w, kay_whole=True)
+    assert whole.kay_removed == stream.kay_removed > 0
+    assert np.array_equal(whole.death, stream.death)
+    keep = np.nonzero(stream.death < 0)[0]
+    surv = _run(inst.subset(keep), w=w[keep])
+    scale = np.max(np.abs(surv.F))
+    assert scale > 0
+    assert np.max(np.abs(whole.F - surv.F)) <= 1e-14 * scale
+    assert np.max(np.abs(whole.F - stream.F)) > 1e-3 * np.max(np.abs(stream.F))
+    # a limit no trajectory reaches: both readings keep every trajectory
+    big = _run(inst, w=w, kay_max=1e300)
+    big_w = _run(inst, w=w, kay_max=1e300, kay_whole=True)
+    assert big.kay_removed == 0 and big.nonfinite_removed == 0
+    assert np.array_equal(big.F, big_w.F, equal_nan=True)
