@@ -112,9 +112,10 @@ def copy_probe(nbytes):
     print(json.dumps({"copy_probe_bytes": n * 8}), flush=True)
 
 
-def cpu_baseline(inst, n_births, n_per):
+def cpu_baseline(inst, n_births, n_per, ctx=None):
     """Oracle trajectory-steps/s on a bounded sample: n_births birth groups spread evenly over
-    the pulse, the first n_per samples of each."""
+    the pulse, the first n_per samples of each. With a context, the device also propagates the
+    same sample and its F is compared with the oracle's (relative L2)."""
     from oracle import oracle as O  # test infrastructure: the CPU-baseline leg only
     from tests.common import run_oracle
     O.build(force=False)
@@ -130,6 +131,17 @@ def cpu_baseline(inst, n_births, n_per):
     t = time.perf_counter()
     r0 = run_oracle(c0, n_threads=threads)
     dt0 = time.perf_counter() - t
+    parity = None
+    if ctx is not None:
+        import torch
+        from paper_2601_17164_amd import sfhk
+        job = sfhk.make_job(ctx, sub)
+        assert job.propagate(0)
+        _, f = job.dipole(want_f=True)
+        F = (f[0] + 1j * f[1]).cpu().numpy()
+        torch.cuda.synchronize()
+        job.close()
+        parity = float(np.linalg.norm(F - r.F) / np.linalg.norm(r.F))
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -142,6 +154,7 @@ def cpu_baseline(inst, n_births, n_per):
                       f"({r.steps_evaluated} trajectory-steps, {dt:.1f} s)",
             "per_core": r.steps_evaluated / dt / threads, "cpu_model": model,
             "host_cpus": os.cpu_count(),
+            "gpu_vs_oracle_rel_l2_F": parity,
             "config0_full": {"value": r0.steps_evaluated / dt0, "trajectories": c0.n_traj,
                              "trajectory_steps": r0.steps_evaluated, "seconds": dt0}}
 
@@ -588,7 +601,7 @@ def main():
     if not a.no_softcore:
         out["softcore"] = softcore_results(ctx, stream)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(inst, a.cpu_births, a.cpu_per_birth)
+        out["cpu_baseline"] = cpu_baseline(inst, a.cpu_births, a.cpu_per_birth, ctx)
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -169,7 +169,8 @@ sfhk_status sfhk_propagate(sfhk_job* job, int64_t max_steps, void* stream);
 
 /* Propagate several jobs of one context with one kernel launch per (precision, potential kind)
  * present (jobs may differ in size, pulse, potential and precision). Same semantics per job as
- * sfhk_propagate; returns SFHK_E_NOT_DONE if any job is unfinished. */
+ * sfhk_propagate; returns SFHK_E_NOT_DONE if any job is unfinished. The jobs must be distinct
+ * (SFHK_E_INVALID if one is listed twice). */
 sfhk_status sfhk_propagate_many(sfhk_job* const* jobs, int32_t n_jobs, int64_t max_steps,
                                 void* stream);
 
@@ -188,7 +189,8 @@ sfhk_status sfhk_propagate_many(sfhk_job* const* jobs, int32_t n_jobs, int64_t m
 typedef struct sfhk_batch sfhk_batch;
 sfhk_status sfhk_batch_create(sfhk_ctx* ctx, int32_t max_jobs, int64_t max_tiles, int64_t max_steps,
                               int32_t workers_per_cu, sfhk_batch** out);
-/* Stage the unfinished tiles of jobs[0..n_jobs): the table is written to one of two pinned
+/* Stage the unfinished tiles of jobs[0..n_jobs) (distinct jobs; SFHK_E_INVALID if one is listed
+ * twice): the table is written to one of two pinned
  * staging sets, used in turn, and copied asynchronously on `stream`. The call waits only until
  * the replay issued after the previous use of that set has completed, so a caller can stage the
  * next replay while the current one runs (the host stays at most one replay ahead). */

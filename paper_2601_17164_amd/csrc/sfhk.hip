@@ -201,6 +201,13 @@ sfhk_status launch_propagate(int precision, int kind, const JobDev* descs, const
   return SFHK_OK;
 }
 
+// a job listed twice would have its tiles queued twice: two workgroups racing on one tile's state
+bool has_duplicates(sfhk_job* const* jobs, int n_jobs) {
+  std::vector<const sfhk_job*> v(jobs, jobs + n_jobs);
+  std::sort(v.begin(), v.end());
+  return std::adjacent_find(v.begin(), v.end()) != v.end();
+}
+
 int segment_of(int precision, int kind) { return (precision == SFHK_FP32_MIXED ? kKinds : 0) + kind; }
 
 }  // namespace
@@ -611,6 +618,7 @@ sfhk_status sfhk_propagate_many(sfhk_job* const* jobs, int32_t n_jobs, int64_t m
   sfhk_ctx* ctx = jobs[0] ? jobs[0]->ctx : nullptr;
   for (int i = 0; i < n_jobs; ++i)
     if (!jobs[i] || jobs[i]->ctx != ctx) return fail(SFHK_E_INVALID, "jobs must be non-NULL and share one context");
+  if (has_duplicates(jobs, n_jobs)) return fail(SFHK_E_INVALID, "a job is listed more than once");
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
   // one launch over the unfinished tiles of every job, ordered by steps left (longest first)
@@ -790,6 +798,7 @@ sfhk_status sfhk_batch_set_jobs(sfhk_batch* b, sfhk_job* const* jobs, int32_t n_
   if (n_jobs > b->max_jobs) return fail(SFHK_E_INVALID, "more jobs than the batch was created for");
   for (int i = 0; i < n_jobs; ++i)
     if (!jobs[i] || jobs[i]->ctx != b->ctx) return fail(SFHK_E_INVALID, "jobs must be non-NULL and share the batch's context");
+  if (has_duplicates(jobs, n_jobs)) return fail(SFHK_E_INVALID, "a job is listed more than once");
   HIP_TRY(hipSetDevice(b->ctx->device));
   hipStream_t st = (hipStream_t)stream;
   struct Item {
@@ -893,40 +902,80 @@ sfhk_status sfhk_velocity(sfhk_job* job, double* v_out, double* vf_out, void* st
   return reduce_rows(job, true, v_out, vf_out, stream);
 }
 
+}  // extern "C"
+
+namespace {
+
+// The spectrum's working memory for n samples zero-padded to n_fft: windowed samples xw[n_fft],
+// twiddles tw[n_fft], and one row of partial sums per span of samples, part[n_spans][n_fft/2+1].
+// Spans are whole chunks of kDftChunk samples, at most kDftMaxSpans of them.
+struct SpectrumPlan {
+  long long nk, span;
+  int n_spans;
+  size_t xw_off, tw_off, part_off, bytes;  // offsets into one workspace, 256-byte aligned
+};
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+SpectrumPlan spectrum_plan(long long n, long long n_fft) {
+  SpectrumPlan P{};
+  P.nk = n_fft / 2 + 1;
+  const long long chunks = (n + kDftChunk - 1) / kDftChunk;
+  const long long per = (chunks + kDftMaxSpans - 1) / kDftMaxSpans;
+  P.span = per * kDftChunk;
+  P.n_spans = (int)((n + P.span - 1) / P.span);
+  P.xw_off = 0;
+  P.tw_off = align256((size_t)n_fft * sizeof(double));
+  P.part_off = P.tw_off + align256((size_t)n_fft * sizeof(double2));
+  P.bytes = P.part_off + align256((size_t)P.n_spans * P.nk * sizeof(double2));
+  return P;
+}
+
+sfhk_status spectrum_check(const double* d, int64_t n, int64_t n_fft, double dt, double tau_h) {
+  if (!d || n < 1 || n_fft < n || n_fft > (1LL << 31) || !(dt > 0.0) || !(tau_h > 0.0))
+    return fail(SFHK_E_INVALID, "spectrum: need d, 1 <= n <= n_fft <= 2^31, dt > 0, tau_h > 0");
+  return SFHK_OK;
+}
+
+// the window, the partial transforms and their fixed-order sum, in the workspace `ws`
+sfhk_status spectrum_launch(const double* d, long long n, double t_first, double dt, double tau_h,
+                            long long n_fft, double* omega_out, double* power_out, double* x_out,
+                            hipStream_t st, const SpectrumPlan& P, char* ws) {
+  double* xw = (double*)(ws + P.xw_off);
+  double2* tw = (double2*)(ws + P.tw_off);
+  double2* part = (double2*)(ws + P.part_off);
+  hipLaunchKernelGGL(k_window, dim3(blocks_for(n_fft, 256)), dim3(256), 0, st, d, n, n_fft,
+                     t_first, dt, tau_h, xw, tw);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_dft_partial, dim3(blocks_for(P.nk, 256), P.n_spans), dim3(256), 0, st,
+                     (const double*)xw, (const double2*)tw, n, n_fft, P.span, part);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_dft_final, dim3(blocks_for(P.nk, 256)), dim3(256), 0, st,
+                     (const double2*)part, P.n_spans, n_fft, t_first, dt, omega_out, power_out,
+                     x_out);
+  HIP_TRY(hipGetLastError());
+  return SFHK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 sfhk_status sfhk_spectrum(const double* d, int64_t n, double t_first, double dt, double tau_h,
                           int64_t n_fft, double* omega_out, double* power_out, double* x_out,
                           void* stream) {
   TraceRange trace_("sfhk_spectrum");
   if (n_fft == 0) n_fft = n;
-  if (!d || n < 1 || n_fft < n || n_fft > (1LL << 31) || !(dt > 0.0) || !(tau_h > 0.0))
-    return fail(SFHK_E_INVALID, "spectrum: need d, 1 <= n <= n_fft <= 2^31, dt > 0, tau_h > 0");
+  sfhk_status rc = spectrum_check(d, n, n_fft, dt, tau_h);
+  if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
-  const long long nk = n_fft / 2 + 1;
-  // spans of samples per block row: whole chunks, at most kDftMaxSpans rows
-  const long long chunks = (n + kDftChunk - 1) / kDftChunk;
-  const long long per = (chunks + kDftMaxSpans - 1) / kDftMaxSpans;
-  const long long span = per * kDftChunk;
-  const int n_spans = (int)((n + span - 1) / span);
-  double* xw = nullptr;
-  double2* tw = nullptr;
-  double2* part = nullptr;
-  HIP_TRY(hipMallocAsync((void**)&xw, n_fft * sizeof(double), st));
-  HIP_TRY(hipMallocAsync((void**)&tw, n_fft * sizeof(double2), st));
-  HIP_TRY(hipMallocAsync((void**)&part, (size_t)n_spans * nk * sizeof(double2), st));
-  hipLaunchKernelGGL(k_window, dim3(blocks_for(n_fft, 256)), dim3(256), 0, st, d, (long long)n,
-                     (long long)n_fft, t_first, dt, tau_h, xw, tw);
-  HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_dft_partial, dim3(blocks_for(nk, 256), n_spans), dim3(256), 0, st,
-                     (const double*)xw, (const double2*)tw, (long long)n, (long long)n_fft, span,
-                     part);
-  HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_dft_final, dim3(blocks_for(nk, 256)), dim3(256), 0, st,
-                     (const double2*)part, n_spans, (long long)n_fft, t_first, dt, omega_out,
-                     power_out, x_out);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipFreeAsync(part, st));
-  HIP_TRY(hipFreeAsync(xw, st));
-  HIP_TRY(hipFreeAsync(tw, st));
+  const SpectrumPlan P = spectrum_plan(n, n_fft);
+  char* ws = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&ws, P.bytes, st));
+  rc = spectrum_launch(d, n, t_first, dt, tau_h, n_fft, omega_out, power_out, x_out, st, P, ws);
+  hipError_t fe = hipFreeAsync(ws, st);
+  if (rc) return rc;
+  HIP_TRY(fe);
   return SFHK_OK;
 }
 

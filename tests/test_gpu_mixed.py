@@ -95,6 +95,38 @@ def test_mixed_config1_subset_spectral_error(S):
     _check_against_oracle(S, "config1-subset", inst)
 
 
+# At the soft-core workload's own Kay limit D_t = 1e30 neither precision is stable against
+# rounding: the FP64 spectrum moves by O(1) (E_dB > 0) when the samples move by one ulp. The
+# stated error of the mixed form there is relative to that floor: its E_dB against the FP64 oracle
+# exceeds the FP64 one-ulp E_dB by at most FLOOR_MARGIN_DB in each band (measured +3.5 / +1.4 dB).
+# The screened workload is the counter-example that bounds this statement: on 16 birth groups x 16
+# samples its FP64 spectrum is stable (one-ulp floor -45 / -44 dB), yet the mixed form is at
+# +71 / +74 dB, because a few trajectories stretched far enough for det G to lose every FP32 digit
+# (relative error ~ lam^2 2^-24) are still below D_t there and carry huge spurious prefactors.
+FLOOR_MARGIN_DB = 6.0
+
+
+@pytest.mark.parametrize("case", ["config0"])
+def test_mixed_at_the_workload_kay_limit_is_within_the_fp64_rounding_floor(S, case):
+    inst = I.config0()
+    assert inst.kay_max == 1e30
+    r = run_oracle(inst)
+    moved = inst.subset(np.arange(inst.n_traj))
+    moved.q0 = np.nextafter(inst.q0, np.inf)
+    r1 = run_oracle(moved)
+    d_ref, d_ulp = O.dipole(r.F), O.dipole(r1.F)
+    if inst.n_out:
+        d_ref, d_ulp = O.resample(d_ref, inst.n_out), O.resample(d_ulp, inst.n_out)
+    g = _run(S, inst)
+    mix = _spectral(inst, g["d"], d_ref)
+    floor = _spectral(inst, d_ulp, d_ref)
+    print(f"[{case}, D_t = 1e30] mixed vs FP64 oracle: "
+          f"{ {b: round(e['E_dB'], 2) for b, e in mix.items()} }; FP64 one-ulp floor: "
+          f"{ {b: round(e['E_dB'], 2) for b, e in floor.items()} }", flush=True)
+    for band in mix:
+        assert mix[band]["E_dB"] <= floor[band]["E_dB"] + FLOOR_MARGIN_DB, band
+
+
 def test_mixed_volkov_closed_form(S):
     """Laser-only motion in the mixed form: M = [[I, tau I], [0, I]] and C = (1 - i gamma tau)^{3/2}
     to FP32 accuracy, with every step on the FP32 path (r_fp64 = 0)."""
