@@ -254,6 +254,23 @@ sfhk_status sfhk_spectrum(const double* d, int64_t n, double t_first, double dt,
                           int64_t n_fft, double* omega_out, double* power_out, double* x_out,
                           void* stream);
 
+/* sfhk_spectrum for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same arguments and the same
+ * results, bit for bit, but its working memory (the windowed samples, the twiddle table and the
+ * per-span partial sums) is a fixed device array of the library, SFHK_SPECTRUM_NOALLOC_BYTES per
+ * GPU, which each GPU the library runs on holds until the process ends; the call allocates and
+ * frees nothing and needs no clearing of that array (every byte it reads it has written first).
+ * Limit: n_fft <= SFHK_SPECTRUM_NOALLOC_MAX_FFT (n_fft = 0: n); SFHK_E_INVALID beyond, or as
+ * sfhk_spectrum. The first call on a device looks up that device's copy of the array
+ * (SFHK_E_DEVICE if the lookup fails). Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (on different streams, or from different host threads without ordering)
+ * race and give wrong results; order them on one stream. */
+#define SFHK_SPECTRUM_NOALLOC_MAX_FFT 65536
+#define SFHK_SPECTRUM_NOALLOC_BYTES 35128320
+sfhk_status sfhk_spectrum_noalloc(const double* d, int64_t n, double t_first, double dt,
+                                  double tau_h, int64_t n_fft, double* omega_out,
+                                  double* power_out, double* x_out, void* stream);
+
 /* Counters of the job (synchronises `stream` first). */
 sfhk_status sfhk_job_stats(sfhk_job* job, sfhk_stats* out, void* stream);
 

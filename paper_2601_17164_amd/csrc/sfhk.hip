@@ -957,7 +957,35 @@ sfhk_status spectrum_launch(const double* d, long long n, double t_first, double
   return SFHK_OK;
 }
 
+// Working memory of sfhk_spectrum_noalloc: one copy per GPU, held until the process ends. In host
+// code `scratch` only names the symbol; its device address on each GPU comes from
+// hipGetSymbolAddress (scratch_ptr below), and only that address is passed to kernels.
+constexpr size_t kNoAllocBytes = SFHK_SPECTRUM_NOALLOC_BYTES;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mu;
+std::vector<char*> g_scratch_ptr;  // per device, nullptr until looked up
+
+// the current device's address of `scratch` (looked up once per device, with it current)
+sfhk_status scratch_ptr(char** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SFHK_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SFHK_OK;
+}
+
 }  // namespace
+
+static_assert(SFHK_SPECTRUM_NOALLOC_MAX_FFT % 2 == 0, "max n_fft");
 
 extern "C" {
 
@@ -977,6 +1005,24 @@ sfhk_status sfhk_spectrum(const double* d, int64_t n, double t_first, double dt,
   if (rc) return rc;
   HIP_TRY(fe);
   return SFHK_OK;
+}
+
+sfhk_status sfhk_spectrum_noalloc(const double* d, int64_t n, double t_first, double dt,
+                                  double tau_h, int64_t n_fft, double* omega_out,
+                                  double* power_out, double* x_out, void* stream) {
+  TraceRange trace_("sfhk_spectrum_noalloc");
+  if (n_fft == 0) n_fft = n;
+  sfhk_status rc = spectrum_check(d, n, n_fft, dt, tau_h);
+  if (rc) return rc;
+  if (n_fft > SFHK_SPECTRUM_NOALLOC_MAX_FFT)
+    return fail(SFHK_E_INVALID, "spectrum_noalloc: n_fft above SFHK_SPECTRUM_NOALLOC_MAX_FFT");
+  const SpectrumPlan P = spectrum_plan(n, n_fft);
+  if (P.bytes > kNoAllocBytes)  // cannot happen for n <= n_fft <= the maximum; kept as a guard
+    return fail(SFHK_E_INVALID, "spectrum_noalloc: working memory above its fixed size");
+  char* ws = nullptr;
+  if ((rc = scratch_ptr(&ws))) return rc;
+  return spectrum_launch(d, n, t_first, dt, tau_h, n_fft, omega_out, power_out, x_out,
+                         (hipStream_t)stream, P, ws);
 }
 
 sfhk_status sfhk_job_stats(sfhk_job* job, sfhk_stats* out, void* stream) {

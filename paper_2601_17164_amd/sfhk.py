@@ -93,6 +93,8 @@ _SIGS = {
     "sfhk_job_restore": (ct.c_int, [_VP, _VP, _VP]),
     "sfhk_spectrum": (ct.c_int, [_VP, ct.c_int64, ct.c_double, ct.c_double, ct.c_double,
                                  ct.c_int64, _VP, _VP, _VP, _VP]),
+    "sfhk_spectrum_noalloc": (ct.c_int, [_VP, ct.c_int64, ct.c_double, ct.c_double, ct.c_double,
+                                         ct.c_int64, _VP, _VP, _VP, _VP]),
     "sfhk_job_stats": (ct.c_int, [_VP, ct.POINTER(_Stats), _VP]),
     "sfhk_job_trajectories": (ct.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "sfhk_batch_create": (ct.c_int, [_VP, ct.c_int32, ct.c_int64, ct.c_int64, ct.c_int32,
@@ -381,6 +383,28 @@ def spectrum(d: torch.Tensor, t_first: float, dt: float, tau_h: float, n_fft: in
     _check(lib().sfhk_spectrum(_dptr(d), n, float(t_first), float(dt), float(tau_h), nf,
                                _dptr(om), _dptr(pw), _dptr(x), _stream_ptr(stream)),
            "sfhk_spectrum")
+    return om, pw, torch.view_as_complex(x)
+
+
+SPECTRUM_NOALLOC_MAX_FFT = 65536
+
+
+def spectrum_noalloc(d: torch.Tensor, t_first: float, dt: float, tau_h: float, n_fft: int = 0,
+                     out=None, stream=None):
+    """sfhk_spectrum_noalloc: the same transform as ``spectrum`` in the library's fixed working
+    memory (the library allocates nothing; n_fft <= SPECTRUM_NOALLOC_MAX_FFT). ``out`` may give
+    the (omega, power, X as [nk, 2]) tensors to write; returns (omega, power, X complex)."""
+    n = int(d.shape[0])
+    nf = int(n_fft) if n_fft else n
+    nk = nf // 2 + 1
+    if out is None:
+        out = (torch.empty(nk, dtype=torch.float64, device=d.device),
+               torch.empty(nk, dtype=torch.float64, device=d.device),
+               torch.empty(nk, 2, dtype=torch.float64, device=d.device))
+    om, pw, x = out
+    _check(lib().sfhk_spectrum_noalloc(_dptr(d), n, float(t_first), float(dt), float(tau_h), nf,
+                                       _dptr(om), _dptr(pw), _dptr(x), _stream_ptr(stream)),
+           "sfhk_spectrum_noalloc")
     return om, pw, torch.view_as_complex(x)
 
 
