@@ -175,7 +175,8 @@ def mixed_form(step, stream, inst, arrays, ref_spectrum, flops):
     drift = _det_drift(job)
     job.close()
     kms = ev[0].elapsed_time(ev[1])
-    fl = flops.flops(inst.potential.kind, inst.ground.l, st.steps_evaluated, st.prims_evaluated)
+    fl = flops.flops(inst.potential.kind, inst.ground.l, st.steps_evaluated, st.prims_evaluated,
+                     st.integrands_evaluated)
     om_r, _, x_r = ref_spectrum
     band = lambda xx: metrics.spectral_report(om_r.cpu().numpy(), xx.cpu().numpy(),
                                               x_r.cpu().numpy(), inst.ground.ip, inst.pulse.up,
@@ -440,7 +441,8 @@ def sfa_results(ctx, stream, reps):
     birth_ms = ev[0].elapsed_time(ev[1]) / reps
     prop_ms = ev[2].elapsed_time(ev[3])
     tt = b["tt"].cpu().numpy()
-    fl = flops.flops(inst.potential.kind, inst.ground.l, st.steps_evaluated, st.prims_evaluated)
+    fl = flops.flops(inst.potential.kind, inst.ground.l, st.steps_evaluated, st.prims_evaluated,
+                     st.integrands_evaluated)
     return {"workload": "screened-SAE 1600nm 1.5e14 W/cm2 8-cycle, 1024x1024 SFA births "
                         "(GTO tunnelling element), dt 0.05",
             "n": inst.n_traj, "birth_kernel_ms": birth_ms, "births_per_s": inst.n_traj / birth_ms * 1e3,
@@ -471,7 +473,8 @@ def softcore_results(ctx, stream):
         job.close()
     torch.cuda.synchronize()
     ms = ev[0].elapsed_time(ev[1])
-    fl = flops.flops(inst.potential.kind, inst.ground.l, st.steps_evaluated, st.prims_evaluated)
+    fl = flops.flops(inst.potential.kind, inst.ground.l, st.steps_evaluated, st.prims_evaluated,
+                     st.integrands_evaluated)
     return {"workload": "soft-core H (config 0 atom) 1600nm 1.5e14 W/cm2 8-cycle, "
                         f"{inst.n_birth}x{inst.n_per_birth} trajectories, dt 0.1, FP64",
             "n_traj": inst.n_traj, "n_steps": inst.grid.n_steps, "kernel_ms": ms,
@@ -556,7 +559,8 @@ def main():
     kern_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
     lat_ms = np.array([marks[k].elapsed_time(marks[k + 1]) for k in range(a.steps)])
     s0 = stats[0]
-    fl = flops.flops(inst.potential.kind, inst.ground.l, s0.steps_evaluated, s0.prims_evaluated)
+    fl = flops.flops(inst.potential.kind, inst.ground.l, s0.steps_evaluated, s0.prims_evaluated,
+                     s0.integrands_evaluated)
     achieved = fl / (kern_ms.mean() * 1e-3) / 1e12
     out = {
         "metric": "HK trajectory-steps/s (3D, w/ monodromy) at 1 GPU; p50/p99 spectrum latency",

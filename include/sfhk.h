@@ -83,7 +83,7 @@ typedef struct {
  *   n_out        0: dipole on the step grid (n_steps + 1 points); > 0: linearly resampled onto
  *                t_k = t_a + k (n_steps h) / n_out, k = 0..n_out-1
  *   velocity     1: also accumulate the dipole velocity (App. C.2; read with sfhk_velocity); its
- *                partial rows double the job's partial-row memory. 0: dipole only
+ *                accumulators double the job's accumulator memory. 0: dipole only
  *   pw_mask      partial-wave filter of the returning trajectories (Sec. III.A). 0: every step
  *                counts. Otherwise a step's dipole (and velocity) term counts only when
  *                r < pw_radius and l = |q x p| lies in a selected band: bit k (k = 0..6) for
@@ -116,6 +116,8 @@ typedef struct {
   int64_t tiles_done;
   int64_t prims_evaluated;   /* GTO primitives evaluated in the dipole integrand (the rest were
                                 skipped by overlap_cut) */
+  int64_t integrands_evaluated; /* (trajectory, t_n) pairs whose dipole integrand was evaluated
+                                   (not every primitive skipped) */
 } sfhk_stats;
 
 typedef struct sfhk_ctx sfhk_ctx;

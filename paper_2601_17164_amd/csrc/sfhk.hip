@@ -79,13 +79,12 @@ struct sfhk_job {
   long long* perm = nullptr;   // [n_pad] sorted slot -> original index (-1: padding)
   WorkItem* work = nullptr;    // [n_tiles] (0, t): this job's tiles, longest first
   double* dbuf = nullptr;      // [n_steps+1] dipole on the step grid
-  double2* gsum = nullptr;     // [n_groups][n_steps+1]
   size_t bytes = 0;
   std::vector<void*> allocs;
   hipEvent_t last_use = nullptr;  // recorded after every piece of work issued on the job
   std::vector<int> tile_n0_host;
   long long steps_done = 0;    // steps requested so far (uniform across tiles)
-  long long part_elems = 0;    // complex entries of the partial rows
+  long long acc_words = 0;     // 64-bit words of the exact accumulators (dipole and velocity)
   uint64_t fingerprint = 0;    // of the inputs that define the propagation (checkpoint matching)
   bool done = false;
 };
@@ -118,27 +117,22 @@ struct sfhk_batch {
 
 namespace {
 
-size_t footprint_parts(long long n_traj, long long n_steps, long long n_out, int velocity,
-                       const std::vector<int>* tile_n0, long long* part_elems) {
-  long long n_pad = (n_traj + kTile - 1) / kTile * kTile;
-  long long n_tiles = n_pad / kTile;
-  long long pe = 0;
-  if (tile_n0) {
-    for (int a : *tile_n0) pe += n_steps - a + 1;
-  } else {
-    pe = n_tiles * (n_steps + 1);  // upper bound
-  }
-  if (velocity) pe *= 2;  // the dipole velocity's rows follow the dipole's
-  if (part_elems) *part_elems = pe;
-  long long n_groups = (n_tiles + kReduceGroup - 1) / kReduceGroup;
+// 64-bit words of a job's exact accumulators: two per step (Re, Im) for the dipole, two more for
+// the dipole velocity
+long long accumulator_words(long long n_steps, int velocity) {
+  return (n_steps + 1) * 2 * sfhk_exact::kExactWords * (velocity ? 2 : 1);
+}
+
+size_t footprint_bytes(long long n_traj, long long n_steps, int velocity) {
+  const long long n_pad = (n_traj + kTile - 1) / kTile * kTile;
+  const long long n_tiles = n_pad / kTile;
   size_t b = 0;
   b += (size_t)n_pad * kNY * 8 + (size_t)n_pad * 5 * 8 + (size_t)n_pad * 8 * 2;  // y, aux, n0+death, perm
-  b += (size_t)n_tiles * (4 * 3 + 8 + sizeof(WorkItem));
-  b += (size_t)pe * 16;
-  b += (size_t)(2 * n_steps + 1) * 8;
-  b += (size_t)(n_steps + 1) * 8 + (size_t)n_groups * (n_steps + 1) * 16;
+  b += (size_t)n_tiles * (4 * 3 + sizeof(WorkItem));                             // tile arrays, work list
+  b += (size_t)accumulator_words(n_steps, velocity) * 8;
+  b += (size_t)(2 * n_steps + 1) * 8;  // field table
+  b += (size_t)(n_steps + 1) * 8;      // dipole on the step grid
   b += 64;
-  (void)n_out;
   return b;
 }
 
@@ -219,7 +213,7 @@ constexpr size_t kCkptAlign = 256;
 
 struct CkptHeader {
   uint64_t magic;
-  int64_t n_traj, n_pad, n_tiles, n_steps, part_elems, steps_done;
+  int64_t n_traj, n_pad, n_tiles, n_steps, acc_words, steps_done;
   int32_t kind, precision, done, reserved;
   uint64_t fingerprint;  // of the job's potential, ground state, grid and method parameters
 };
@@ -237,7 +231,7 @@ std::vector<std::pair<void*, size_t>> ckpt_sections(sfhk_job* j) {
           {H.tile_next, nt * sizeof(int)},
           {H.tile_last, nt * sizeof(int)},
           {H.counters, 8 * sizeof(unsigned long long)},
-          {H.part, (size_t)j->part_elems * sizeof(double2)}};
+          {H.acc, (size_t)j->acc_words * sizeof(long long)}};
 }
 
 size_t ckpt_bytes(sfhk_job* j) {
@@ -316,7 +310,8 @@ size_t sfhk_job_footprint(int64_t n_traj, int64_t n_steps, int64_t n_out, int32_
                           int32_t velocity) {
   (void)precision;
   if (n_traj < 1 || n_steps < 1) return 0;
-  return footprint_parts(n_traj, n_steps, n_out, velocity != 0, nullptr, nullptr);
+  (void)n_out;
+  return footprint_bytes(n_traj, n_steps, velocity != 0);
 }
 
 int64_t sfhk_job_n_out(const sfhk_job* job) {
@@ -426,16 +421,12 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
     for (int t = 0; t < n_tiles; ++t) tile_n0[t] = n0s[(long long)t * kTile];
   }
   std::vector<int> tile_next(n_tiles), tile_last(n_tiles);
-  std::vector<long long> row_off(n_tiles);
-  long long off = 0;
   for (int t = 0; t < n_tiles; ++t) {
     tile_next[t] = tile_n0[t];
     tile_last[t] = tile_n0[t] - 1;
-    row_off[t] = off;
-    off += NS - tile_n0[t] + 1;
   }
-  long long part_elems = 0;
-  const size_t need = footprint_parts(N, NS, params->n_out, params->velocity != 0, &tile_n0, &part_elems);
+  const long long acc_words = accumulator_words(NS, params->velocity != 0);
+  const size_t need = footprint_bytes(N, NS, params->velocity != 0);
   bool over = false;
   size_t left = 0;
   {
@@ -458,7 +449,7 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   j->n_out = params->n_out;
   j->bytes = bytes;
   j->tile_n0_host = tile_n0;
-  j->part_elems = part_elems;
+  j->acc_words = acc_words;
   // fast range of the screened potential: 2^-1000 <= r^2 <= 2^999 and 0 <= a <= 2^999 keep r^2
   // and r^2 + a within the square root's core range
   const double r2_fast = (pot->kind == SFHK_POT_SCREENED && pot->soft2 >= 0.0 && pot->soft2 <= 0x1p999)
@@ -482,7 +473,6 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   H.gto.vel = params->velocity;
   H.pw_mask = params->pw_mask;
   H.pw_r2 = params->pw_mask ? params->pw_radius * params->pw_radius : 0.0;
-  H.vel_off = params->velocity ? part_elems / 2 : 0;
   H.gto.two_gamma = 2.0 * g;
   H.gto.ip = ground->ip;
   H.gto.Amin = H.gto.A[0];
@@ -531,14 +521,13 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   if ((rc = job_alloc(j, &e_half, 2 * (size_t)NS + 1, st)) || (rc = job_alloc(j, &H.y, (size_t)n_pad * kNY, st)) ||
       (rc = job_alloc(j, &H.aux, (size_t)n_pad * 5, st)) || (rc = job_alloc(j, &H.death, (size_t)n_pad, st)) ||
       (rc = job_alloc(j, &H.tile_next, (size_t)n_tiles, st)) || (rc = job_alloc(j, &H.tile_last, (size_t)n_tiles, st)) ||
-      (rc = job_alloc(j, &H.row_off, (size_t)n_tiles, st)) || (rc = job_alloc(j, &H.part, (size_t)part_elems, st)) ||
+      (rc = job_alloc(j, &H.acc, (size_t)acc_words, st)) ||
       (rc = job_alloc(j, &H.counters, 8, st)) || (rc = job_alloc(j, &j->work, (size_t)n_tiles, st)) ||
-      (rc = job_alloc(j, &j->dbuf, (size_t)NS + 1, st)) ||
-      (rc = job_alloc(j, &j->gsum, (size_t)((n_tiles + kReduceGroup - 1) / kReduceGroup) * (NS + 1), st)) ||
-      (rc = job_alloc(j, &j->dev, 1, st)))
+      (rc = job_alloc(j, &j->dbuf, (size_t)NS + 1, st)) || (rc = job_alloc(j, &j->dev, 1, st)))
     return cleanup(rc);
   if (!in_order && (rc = job_alloc(j, &j->perm, (size_t)n_pad, st))) return cleanup(rc);
   H.e_half = e_half;
+  H.acc_v = params->velocity ? H.acc + acc_words / 2 : nullptr;
   TRY_C(hipMemcpyAsync(e_half, grid->e_half, (2 * (size_t)NS + 1) * sizeof(double), hipMemcpyDeviceToDevice, st));
   if (!in_order) {  // the sorted order replaces the caller order k_birth wrote
     TRY_C(hipMemcpyAsync(j->perm, perm.data(), n_pad * sizeof(long long), hipMemcpyHostToDevice, st));
@@ -547,12 +536,11 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   }
   TRY_C(hipMemcpyAsync(H.tile_next, tile_next.data(), n_tiles * sizeof(int), hipMemcpyHostToDevice, st));
   TRY_C(hipMemcpyAsync(H.tile_last, tile_last.data(), n_tiles * sizeof(int), hipMemcpyHostToDevice, st));
-  TRY_C(hipMemcpyAsync(H.row_off, row_off.data(), n_tiles * sizeof(long long), hipMemcpyHostToDevice, st));
   std::vector<WorkItem> work(n_tiles);
   for (int t = 0; t < n_tiles; ++t) work[t] = {0, t};
   TRY_C(hipMemcpyAsync(j->work, work.data(), n_tiles * sizeof(WorkItem), hipMemcpyHostToDevice, st));
   TRY_C(hipMemsetAsync(H.counters, 0, 8 * sizeof(unsigned long long), st));
-  TRY_C(hipMemsetAsync(H.part, 0, (size_t)part_elems * sizeof(double2), st));  // rows without integrands stay 0
+  TRY_C(hipMemsetAsync(H.acc, 0, (size_t)acc_words * sizeof(long long), st));  // exact sums start at 0
   TRY_C(hipMemcpyAsync(j->dev, &H, sizeof(JobDev), hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL(k_init, dim3(blocks_for(n_pad, 256)), dim3(256), 0, st, H, j->perm, N, q0, p0, w);
   TRY_C(hipGetLastError());
@@ -867,22 +855,17 @@ int32_t sfhk_batch_workers(const sfhk_batch* b) { return b ? b->n_workers : 0; }
 
 int32_t sfhk_job_is_done(const sfhk_job* job) { return job && job->done ? 1 : 0; }
 
-// fixed-order sum of one set of partial rows (the dipole's, or the velocity's at part + vel_off)
+// the dipole (or the dipole velocity) from the job's exact per-step accumulators
 static sfhk_status reduce_rows(sfhk_job* job, bool velocity, double* d_out, double* f_out, void* stream) {
   if (!job || !d_out) return fail(SFHK_E_INVALID, "NULL argument");
   if (!job->done) return fail(SFHK_E_NOT_DONE, "job is not finished");
-  if (velocity && !job->host.vel_off) return fail(SFHK_E_INVALID, "job was created without velocity");
+  if (velocity && !job->host.acc_v) return fail(SFHK_E_INVALID, "job was created without velocity");
   HIP_TRY(hipSetDevice(job->ctx->device));
   hipStream_t st = (hipStream_t)stream;
-  JobDev H = job->host;
-  if (velocity) H.part = job->host.part + job->host.vel_off;
-  const int n_groups = (H.n_tiles + kReduceGroup - 1) / kReduceGroup;
-  dim3 g1(blocks_for(H.n_steps + 1, 256), n_groups);
-  hipLaunchKernelGGL(k_reduce_groups, g1, dim3(256), 0, st, H, job->gsum);
-  HIP_TRY(hipGetLastError());
+  const JobDev& H = job->host;
   double* d_step = job->n_out > 0 ? job->dbuf : d_out;
-  hipLaunchKernelGGL(k_reduce_final, dim3(blocks_for(H.n_steps + 1, 256)), dim3(256), 0, st,
-                     H.n_steps, n_groups, (const double2*)job->gsum, d_step, f_out);
+  hipLaunchKernelGGL(k_acc_final, dim3(blocks_for(H.n_steps + 1, 256)), dim3(256), 0, st,
+                     (const long long*)(velocity ? H.acc_v : H.acc), H.n_steps, d_step, f_out);
   HIP_TRY(hipGetLastError());
   if (job->n_out > 0) {
     hipLaunchKernelGGL(k_resample, dim3(blocks_for(job->n_out, 256)), dim3(256), 0, st,
@@ -1039,6 +1022,7 @@ sfhk_status sfhk_job_stats(sfhk_job* job, sfhk_stats* out, void* stream) {
   out->nonfinite_removed = (int64_t)c[2];
   out->steps_fp64 = (int64_t)c[3];
   out->prims_evaluated = (int64_t)c[4];
+  out->integrands_evaluated = (int64_t)c[5];
   out->tiles_total = job->host.n_tiles;
   out->tiles_done = job->host.n_tiles - unfinished_tiles(job, job->steps_done);
   return SFHK_OK;
@@ -1074,7 +1058,7 @@ sfhk_status sfhk_job_checkpoint(sfhk_job* job, void* dst, void* stream) {
   h.n_pad = job->host.n_pad;
   h.n_tiles = job->host.n_tiles;
   h.n_steps = job->host.n_steps;
-  h.part_elems = job->part_elems;
+  h.acc_words = job->acc_words;
   h.steps_done = job->steps_done;
   h.kind = job->kind;
   h.precision = job->precision;
@@ -1104,7 +1088,7 @@ sfhk_status sfhk_job_restore(sfhk_job* job, const void* src, void* stream) {
   HIP_TRY(hipStreamSynchronize(st));
   if (h.magic != kCkptMagic || h.n_traj != job->n_traj || h.n_pad != job->host.n_pad ||
       h.n_tiles != job->host.n_tiles || h.n_steps != job->host.n_steps ||
-      h.part_elems != job->part_elems || h.kind != job->kind || h.precision != job->precision ||
+      h.acc_words != job->acc_words || h.kind != job->kind || h.precision != job->precision ||
       h.fingerprint != job->fingerprint || h.steps_done < 0)
     return fail(SFHK_E_INVALID, "checkpoint does not match this job (other inputs or not a checkpoint)");
   size_t off = kCkptAlign;

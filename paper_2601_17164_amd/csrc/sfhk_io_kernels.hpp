@@ -1,5 +1,5 @@
 // sfhk_io_kernels.hpp -- the kernels around the propagation (gfx950): birth steps and initial
-// state of a job, the fixed-order reduction of the partial rows into the dipole, resampling, the
+// state of a job, the dipole from the per-step exact accumulators, resampling, the
 // per-trajectory state in caller order, the Hann-windowed Fourier transform, and the exported
 // contract functions. Included by sfhk.hip after sfhk_kernels.hpp (device layout and the
 // propagation kernels).
@@ -81,41 +81,21 @@ __global__ void k_init(JobDev J, const long long* __restrict__ perm, long long n
 }
 
 // ------------------------------------------------------------------------------------------------
-// reduction of the partial rows (fixed order) and the dipole
+// the dipole from the per-step exact accumulators
 // ------------------------------------------------------------------------------------------------
-__global__ void k_reduce_groups(JobDev J, double2* __restrict__ gsum) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  const int g = blockIdx.y;
-  if (n > J.n_steps) return;
-  const int t_lo = g * kReduceGroup;
-  const int t_hi = min(J.n_tiles, t_lo + kReduceGroup);
-  double sr = 0.0, si = 0.0;
-  for (int t = t_lo; t < t_hi; ++t) {
-    const int a = J.tile_n0[t];
-    if (a > n) break;  // tiles are sorted by birth step
-    if (n <= J.tile_last[t]) {
-      double2 v = J.part[J.row_off[t] + (n - a)];
-      sr += v.x;
-      si += v.y;
-    }
-  }
-  gsum[(long long)g * (J.n_steps + 1) + n] = make_double2(sr, si);
-}
-
-__global__ void k_reduce_final(int n_steps, int n_groups, const double2* __restrict__ gsum,
-                               double* __restrict__ d, double* __restrict__ f_out) {
+// F(t_n) = the exact sum of the step's integrands, rounded once to binary64; d = -2 Re F (Eq. 2:
+// "+ c.c." with the leading minus); f_out (nullable) = [Re F][Im F] on the step grid
+__global__ void k_acc_final(const long long* __restrict__ acc, int n_steps, double* __restrict__ d,
+                            double* __restrict__ f_out) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n > n_steps) return;
-  double sr = 0.0, si = 0.0;
-  for (int g = 0; g < n_groups; ++g) {
-    double2 v = gsum[(long long)g * (n_steps + 1) + n];
-    sr += v.x;
-    si += v.y;
-  }
-  d[n] = -2.0 * sr;
+  const int64_t* a = (const int64_t*)acc + (long long)n * (2 * sfhk_exact::kExactWords);
+  const double re = sfhk_exact::round_total(a);
+  const double im = sfhk_exact::round_total(a + sfhk_exact::kExactWords);
+  d[n] = -2.0 * re;
   if (f_out) {
-    f_out[n] = sr;
-    f_out[n_steps + 1 + n] = si;
+    f_out[n] = re;
+    f_out[n_steps + 1 + n] = im;
   }
 }
 

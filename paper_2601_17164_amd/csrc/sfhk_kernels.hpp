@@ -7,24 +7,24 @@
 //   sorted trajectories 64t..64t+63, so tiles are ordered longest first;
 //   state y[43][n_pad] (SoA, FP64): q(3) p(3) M(6 columns of Q(3) P(3)) S; aux[5][n_pad]:
 //   C_prev (re, im), w (re, im), branch sign; n0[n_pad], death[n_pad] (int32);
-//   one partial row per tile: F_tile(t_n) for n = tile_n0 .. n_steps (complex FP64), zero when
-//   the job is created; the propagate kernel stores a step's entry when some lane of the tile had
-//   a dipole integrand at that step.
-// Reduction order is fixed (tile order inside groups of 64 tiles, then group order), so the dipole
-// is bitwise reproducible for a given input.
+//   one exact accumulator per step for Re F and one for Im F (sfhk_exact_sum.hpp: 68 64-bit
+//   words each, zero when the job is created), and two more per step for the dipole velocity:
+//   each tile adds, per step, the sum of its lanes' integrands with integer atomics.
+// The accumulated totals are exact and do not depend on the order of the additions, so the dipole
+// is bitwise reproducible for a given input however the tiles are scheduled, chunked or batched.
 #pragma once
 #include <hip/hip_runtime.h>
 
 #include "../../include/sfhk.h"
 #include "sfhk_device.hpp"
 #include "sfhk_device_f32.hpp"
+#include "sfhk_exact_sum.hpp"
 
 using namespace sfhk;
 
 namespace {
 
 constexpr int kTile = 64;           // trajectories per tile = lanes per wave
-constexpr int kReduceGroup = 64;    // tiles per first-level reduction group
 constexpr int kNY = 43;
 
 // ------------------------------------------------------------------------------------------------
@@ -62,14 +62,22 @@ struct JobDev {
   int* tile_n0;
   int* tile_next;
   int* tile_last;
-  long long* row_off;
-  double2* part;
-  long long vel_off;  // dipole velocity: its partial rows start at part + vel_off (0: none)
+  long long* acc;      // [n_steps + 1][2][kExactWords]: exact sums of Re F, Im F per step
+  long long* acc_v;    // the same for the dipole velocity (nullptr: not accumulated)
   int pw_mask;        // partial-wave filter (0: every step counts), see pw_keep
   double pw_r2;       // its radius, squared
   unsigned long long* counters;  // steps_evaluated, kay_removed, nonfinite_removed, steps_fp64,
                                  // GTO primitives evaluated
 };
+
+// values that are the same in every lane of the wave (per-tile bookkeeping): kept in scalar
+// registers so the step loop's control runs on the scalar unit
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long uniform_i64(long long v) {
+  const unsigned int lo = __builtin_amdgcn_readfirstlane((unsigned int)(unsigned long long)v);
+  const unsigned int hi = __builtin_amdgcn_readfirstlane((unsigned int)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
 
 // ------------------------------------------------------------------------------------------------
 // wave-level sum (butterfly: every lane ends with the same, order-independent-by-symmetry value)
@@ -86,8 +94,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 // ------------------------------------------------------------------------------------------------
 // Every primitive is skipped when p^2 A_j + q^2 B_j > cut for all j. Since A_j >= A_min and
 // B_j >= B_min, p^2 A_min + q^2 B_min > cut (1 + 1e-12) implies it; the margin covers rounding.
-__device__ __forceinline__ bool overlap_all_skipped(const GtoConst& G, double p2, double q2) {
-  return SFHK_FMA(p2, G.Amin, q2 * G.Bmin) > G.cut_hi;
+__device__ __forceinline__ bool overlap_all_skipped(double amin, double bmin, double cut_hi,
+                                                    double p2, double q2) {
+  return SFHK_FMA(p2, amin, q2 * bmin) > cut_hi;
 }
 
 // sin and cos of x for the dipole integrand (held to the oracle at a relative tolerance, not bit
@@ -148,7 +157,13 @@ struct Elements {
   cplx o, ov;
 };
 
-__device__ __forceinline__ Elements overlap(const GtoConst& G, double cut, const double* q,
+// the GTO constants seen through the constant address space: with a wave-uniform pointer their
+// reads are scalar loads
+typedef const __attribute__((address_space(4))) GtoConst& gto_cref;
+typedef const __attribute__((address_space(4))) GtoConst* gto_cptr;
+
+template <typename GREF>
+__device__ __forceinline__ Elements overlap(GREF G, double cut, const double* q,
                                             const double* p, double p2, double q2,
                                             unsigned int& n_eval) {
   double pq = SFHK_FMA(p[2], q[2], SFHK_FMA(p[1], q[1], p[0] * q[0]));
@@ -206,13 +221,16 @@ struct Contrib {
   unsigned int n_eval;
 };
 
-__device__ __noinline__ Contrib contribution(const GtoConst* __restrict__ G, double cut, double qx,
+__device__ __noinline__ Contrib contribution(const GtoConst* Gv, double cut, double qx,
                                              double qy, double qz, double px, double py, double pz,
                                              double p2, double q2, double S, double tn, double wcr,
                                              double wci) {
+  // every lane passes the same constants: read through a uniform pointer in the constant address
+  // space they are scalar loads, instead of a vector load and a wait per primitive
+  const gto_cptr __restrict__ G = (gto_cptr)uniform_i64((long long)Gv);
   const double q[3] = {qx, qy, qz}, p[3] = {px, py, pz};
   unsigned int n_eval = 0;
-  const Elements el = overlap(*G, cut, q, p, p2, q2, n_eval);
+  const Elements el = overlap<gto_cref>(*G, cut, q, p, p2, q2, n_eval);
   Contrib r = {0.0, 0.0, 0.0, 0.0, n_eval};
   if (el.o.re != 0.0 || el.o.im != 0.0 || el.ov.re != 0.0 || el.ov.im != 0.0) {
     const double ph = S - G->ip * tn;
@@ -238,11 +256,11 @@ __device__ __noinline__ Contrib contribution(const GtoConst* __restrict__ G, dou
 // (q, p, S, w C, n) to a per-wave LDS queue; when the queue cannot take the next step's entries,
 // and at the end of the launch, the wave evaluates up to 64 of them at once, one per lane. A
 // step's entries are consecutive lanes in lane order; a segmented scan over the wave (run_sum)
-// sums each run and its last lane stores the tile's partial row for the step; rows of steps
-// without entries keep the zeros they were allocated with. The scan's additions depend only on
-// positions within the run, and the entries of one step never straddle two evaluations, so the
-// sums do not depend on where a run lies in the queue, nor on how the propagation is split into
-// launches or batched. The wave is the whole workgroup, so the queue needs no cross-wave
+// sums each run and its last lane adds the sum to the step's exact accumulators. The scan's
+// additions depend only on positions within the run, and the entries of one step never straddle
+// two evaluations, so a run's sum does not depend on where it lies in the queue, nor on how the
+// propagation is split into launches or batched; the accumulators' totals do not depend on the
+// order of the additions. The wave is the whole workgroup, so the queue needs no cross-wave
 // synchronisation.
 constexpr int kQueue = kTile;
 
@@ -258,15 +276,6 @@ struct IntegrandQueue {
 };
 
 typedef __attribute__((address_space(4))) const double* const_dptr;  // scalar (uniform) loads
-
-// values that are the same in every lane of the wave (per-tile bookkeeping): kept in scalar
-// registers so the step loop's control runs on the scalar unit
-__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ long long uniform_i64(long long v) {
-  const unsigned int lo = __builtin_amdgcn_readfirstlane((unsigned int)(unsigned long long)v);
-  const unsigned int hi = __builtin_amdgcn_readfirstlane((unsigned int)((unsigned long long)v >> 32));
-  return (long long)(((unsigned long long)hi << 32) | lo);
-}
 
 // position of this lane among the set bits of the wave mask m
 __device__ __forceinline__ int lanes_below(unsigned long long m) {
@@ -290,17 +299,17 @@ __device__ __forceinline__ void queue_push(IntegrandQueue& Q, int idx, double qx
 // d, ... for k = 0, 1, 2, ...; bit 7 for l >= 13/2). A step's terms count when r^2 < pw_r2 and the
 // band's bit is set, or, beyond the radius, when bit 8 is set. r^2 and l^2 are formed by one fixed
 // sequence and compared with the squared edges, so the decision is reproducible bit for bit.
-__device__ __forceinline__ bool pw_keep(const JobDev& J, double qx, double qy, double qz, double px,
-                                        double py, double pz) {
+__device__ __forceinline__ bool pw_keep(int pw_mask, double pw_r2, double qx, double qy, double qz,
+                                        double px, double py, double pz) {
   const double r2 = SFHK_FMA(qz, qz, SFHK_FMA(qy, qy, qx * qx));
-  if (!(r2 < J.pw_r2)) return (J.pw_mask >> 8) & 1;
+  if (!(r2 < pw_r2)) return (pw_mask >> 8) & 1;
   const double cx = SFHK_FMA(qy, pz, -(qz * py));
   const double cy = SFHK_FMA(qz, px, -(qx * pz));
   const double cz = SFHK_FMA(qx, py, -(qy * px));
   const double l2 = SFHK_FMA(cz, cz, SFHK_FMA(cy, cy, cx * cx));
   int k = 0;
   while (k < 7 && !(l2 < (k + 0.5) * (k + 0.5))) ++k;
-  return (J.pw_mask >> k) & 1;
+  return (pw_mask >> k) & 1;
 }
 
 // sum over the run of equal keys that ends at this lane, for runs of consecutive lanes (run_start
@@ -315,12 +324,66 @@ __device__ __forceinline__ double run_sum(double x, int lane, int run_start) {
   return x;
 }
 
-// evaluates the qn queued entries (one per lane) and stores their per-step sums; returns this
-// lane's count of evaluated primitives. A step's entries are consecutive lanes (a run); the last
-// lane of the run stores the run's sum.
+// global-memory view of an accumulator: its atomics then count only as vector-memory operations, so
+// waiting for LDS results does not wait for them
+typedef __attribute__((address_space(1))) unsigned long long* acc_gptr;
+
+// adds one value to an exact accumulator (sfhk_exact_sum.hpp) with integer atomics
+__device__ __forceinline__ void acc_add(long long* __restrict__ a, double v) {
+  const sfhk_exact::Slices sl = sfhk_exact::slices_of(v);
+  const acc_gptr w = (acc_gptr)a;
+  if (sl.flag) {
+    __hip_atomic_fetch_or(w + sfhk_exact::kExactFlag, (unsigned long long)sl.flag, __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+  if (sl.n == 0) return;
+  __hip_atomic_fetch_add(w + sl.bin, (unsigned long long)sl.s[0], __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_add(w + sl.bin + 1, (unsigned long long)sl.s[1], __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  if (sl.n == 3)
+    __hip_atomic_fetch_add(w + sl.bin + 2, (unsigned long long)sl.s[2], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// adds (re, im) to step n's pair of accumulators
+__device__ __forceinline__ void acc_add_step(long long* __restrict__ acc, long long n, double re,
+                                             double im) {
+  long long* a = acc + n * (2 * sfhk_exact::kExactWords);
+  acc_add(a, re);
+  acc_add(a + sfhk_exact::kExactWords, im);
+}
+
+// the job's values the queue evaluation needs, read once per tile: the accumulators' atomics could
+// alias the descriptor as far as the compiler knows, and re-reading it after them would wait for
+// them to complete
+struct QueueCtx {
+  const GtoConst* gto;
+  long long* acc;
+  long long* acc_v;
+  double cut, t_a, h, pw_r2;
+  int pw_mask;
+};
+
+__device__ __forceinline__ QueueCtx queue_ctx(const JobDev& J) {
+  QueueCtx c;
+  c.gto = &J.gto;
+  c.acc = J.acc;
+  c.acc_v = J.acc_v;
+  c.cut = J.cut;
+  c.t_a = J.t_a;
+  c.h = J.h;
+  c.pw_r2 = J.pw_r2;
+  c.pw_mask = J.pw_mask;
+  return c;
+}
+
+// evaluates the qn queued entries (one per lane) and adds their per-step sums to the job's
+// accumulators; returns this lane's count of evaluated primitives. A step's entries are
+// consecutive lanes (a run); the last lane of the run adds the run's sum.
 __device__ __forceinline__ unsigned int queue_eval(IntegrandQueue& Q, int qn, int lane,
-                                                   const JobDev& J, double2* __restrict__ part,
-                                                   long long roff, int t0) {
+                                                   const QueueCtx& J) {
   __syncthreads();
   unsigned int n_eval = 0;
   Contrib cb = {0.0, 0.0, 0.0, 0.0, 0u};
@@ -331,8 +394,8 @@ __device__ __forceinline__ unsigned int queue_eval(IntegrandQueue& Q, int qn, in
     const double p2 = SFHK_FMA(pz, pz, SFHK_FMA(py, py, px * px));
     const double q2 = SFHK_FMA(qz, qz, SFHK_FMA(qy, qy, qx * qx));
     ns = x.e.y;
-    if (!J.pw_mask || pw_keep(J, qx, qy, qz, px, py, pz))
-      cb = contribution(&J.gto, J.cut, qx, qy, qz, px, py, pz, p2, q2, x.d.x, J.t_a + x.e.y * J.h,
+    if (!J.pw_mask || pw_keep(J.pw_mask, J.pw_r2, qx, qy, qz, px, py, pz))
+      cb = contribution(J.gto, J.cut, qx, qy, qz, px, py, pz, p2, q2, x.d.x, J.t_a + x.e.y * J.h,
                         x.d.y, x.e.x);
     n_eval = cb.n_eval;
   }
@@ -344,10 +407,10 @@ __device__ __forceinline__ unsigned int queue_eval(IntegrandQueue& Q, int qn, in
   const int rs = 63 - __clzll(starts & upto);
   const bool last = lane < qn && (lane == qn - 1 || ((starts >> (lane + 1)) & 1ull));
   const double sr = run_sum(cb.re, lane, rs), si = run_sum(cb.im, lane, rs);
-  if (last) part[roff + ((long long)ns - t0)] = make_double2(sr, si);
-  if (J.vel_off) {
+  if (last) acc_add_step(J.acc, (long long)ns, sr, si);
+  if (J.acc_v) {
     const double vr = run_sum(cb.vre, lane, rs), vi = run_sum(cb.vim, lane, rs);
-    if (last) part[J.vel_off + roff + ((long long)ns - t0)] = make_double2(vr, vi);
+    if (last) acc_add_step(J.acc_v, (long long)ns, vr, vi);
   }
   __syncthreads();
   return n_eval;
@@ -384,17 +447,17 @@ __device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const 
   int death = death_in;
   bool alive = death_in == -1;
 
-  const int t0 = uniform_i32(J.tile_n0[tile]);
-  const long long roff = uniform_i64(J.row_off[tile]);
-  double2* __restrict__ part = J.part;
   const const_dptr eh = (const_dptr)J.e_half;
   const PotParams P = J.pot;
   const int kind = KIND >= 0 ? KIND : J.kind;
   const double gamma = J.gamma, inv4g = J.inv4g, kay2 = J.kay2;
   const double h = J.h, h2 = J.h2, h6 = J.h6;
+  const QueueCtx QC = queue_ctx(J);
+  const double amin = J.gto.Amin, bmin = J.gto.Bmin, cut_hi = J.gto.cut_hi;
 
   int qn = 0;  // queued integrands (wave-uniform)
   unsigned int kay = 0, nonfin = 0, prims = 0;
+  int ents = 0;  // queued integrand entries evaluated (wave-uniform)
   int n = n_begin;
   double ea = eh[2 * n];
   for (; n <= n_stop; ++n) {
@@ -426,12 +489,13 @@ __device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const 
     // |p|^2 and |q|^2 of the state at t_n: the skip bound below and the RK4's first stage use them
     const double p2 = norm2(T.p[0], T.p[1], T.p[2]);
     const double q2 = norm2(T.q[0], T.q[1], T.q[2]);
-    const bool need = contrib && !overlap_all_skipped(J.gto, p2, q2);
+    const bool need = contrib && !overlap_all_skipped(amin, bmin, cut_hi, p2, q2);
     const unsigned long long m = __builtin_amdgcn_ballot_w64(need);
     if (m) {
       const int k = __popcll(m);
       if (qn + k > kQueue) {
-        prims += queue_eval(Q, qn, lane, J, part, roff, t0);
+        ents += qn;
+        prims += queue_eval(Q, qn, lane, QC);
         qn = 0;
       }
       if (need)
@@ -449,7 +513,10 @@ __device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const 
       break;
     }
   }
-  if (qn > 0) prims += queue_eval(Q, qn, lane, J, part, roff, t0);
+  if (qn > 0) {
+    ents += qn;
+    prims += queue_eval(Q, qn, lane, QC);
+  }
   // n is now one past the last step processed
   double* yw = J.y;
 #pragma unroll
@@ -484,6 +551,7 @@ __device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const 
     atomicAdd(&J.counters[1], (unsigned long long)ka);
     atomicAdd(&J.counters[2], (unsigned long long)nf);
     atomicAdd(&J.counters[4], (unsigned long long)pr);
+    atomicAdd(&J.counters[5], (unsigned long long)ents);
   }
 }
 
@@ -535,9 +603,6 @@ __device__ __forceinline__ void run_tile_mixed(const JobDev& J, const int tile, 
   int death = death_in;
   bool alive = death_in == -1;
 
-  const int t0 = uniform_i32(J.tile_n0[tile]);
-  const long long roff = uniform_i64(J.row_off[tile]);
-  double2* __restrict__ part = J.part;
   const const_dptr eh = (const_dptr)J.e_half;
   const PotParams P = J.pot;
   const PotParamsF PF = {(float)P.z_inf, (float)P.z_in, (float)P.soft2, (float)P.omega_ho,
@@ -545,6 +610,7 @@ __device__ __forceinline__ void run_tile_mixed(const JobDev& J, const int tile, 
   const int kind = KIND >= 0 ? KIND : J.kind;
   const double kay2 = J.kay2;
   const double h = J.h, h2 = J.h2, h6 = J.h6;
+  const QueueCtx QC = queue_ctx(J);
   const float hf = (float)h, h2f = (float)h2, h6f = (float)h6;
   const float gammaf = (float)J.gamma, inv4gf = (float)J.inv4g;
   const float aminf = (float)J.gto.Amin, bminf = (float)J.gto.Bmin;
@@ -553,6 +619,7 @@ __device__ __forceinline__ void run_tile_mixed(const JobDev& J, const int tile, 
 
   int qn = 0;  // queued integrands (wave-uniform)
   unsigned int kay = 0, nonfin = 0, prims = 0, steps64 = 0;
+  int ents = 0;  // queued integrand entries evaluated (wave-uniform)
   int n = n_begin;
   double ea = eh[2 * n];
   for (; n <= n_stop; ++n) {
@@ -587,7 +654,8 @@ __device__ __forceinline__ void run_tile_mixed(const JobDev& J, const int tile, 
     if (m) {
       const int k = __popcll(m);
       if (qn + k > kQueue) {
-        prims += queue_eval(Q, qn, lane, J, part, roff, t0);
+        ents += qn;
+        prims += queue_eval(Q, qn, lane, QC);
         qn = 0;
       }
       if (need)
@@ -629,7 +697,10 @@ __device__ __forceinline__ void run_tile_mixed(const JobDev& J, const int tile, 
       break;
     }
   }
-  if (qn > 0) prims += queue_eval(Q, qn, lane, J, part, roff, t0);
+  if (qn > 0) {
+    ents += qn;
+    prims += queue_eval(Q, qn, lane, QC);
+  }
   double* yw = J.y;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -662,6 +733,7 @@ __device__ __forceinline__ void run_tile_mixed(const JobDev& J, const int tile, 
     atomicAdd(&J.counters[2], (unsigned long long)nf);
     atomicAdd(&J.counters[3], (unsigned long long)s64);
     atomicAdd(&J.counters[4], (unsigned long long)pr);
+    atomicAdd(&J.counters[5], (unsigned long long)ents);
   }
 }
 

@@ -13,9 +13,11 @@ branch, the GTO dipole element of App. C.1, the phase and the per-step sum of Eq
   HK prefactor: G (45), det G (64), |det|^2 (3), |det| = |det|^2 rsqrt(|det|^2) (2),
       principal sqrt: w (2), rsqrt w (1), sqrt w (1), Im/(2 sqrt w) (2); branch dot product and
       sign (4), C (2)                                                       = 126
-  GTO element, per step: |p|^2, |q|^2, p.q (15), 2 gamma q_z (1), the final complex product (6) = 22
+  skip test of the GTO element, per step: |p|^2, |q|^2 (10) and the bound p^2 A + q^2 B (3) = 13
+  per evaluated integrand (a step of a lane with some primitive within the cut): p.q (5),
+      2 gamma q_z (1), the element's final complex product (6), the phase Ip t_n - S, its sincos
+      and the product w C O e^{i phase} (24), the complex accumulation (2)            = 38
   GTO element, per evaluated primitive: s-wave 12, p-wave 19
-  phase Ip t_n - S, sincos and the product w C O e^{i phase}: 24; complex accumulation: 2
 
 A step that removes the trajectory (Kay) evaluates less than this; such steps are under 1e-4 of
 all steps on the benchmark workloads, so every evaluated step is priced at the full count.
@@ -26,20 +28,22 @@ RHS = {0: 30, 1: 39, 2: 62, 3: 33}
 RK4_QPS = 85
 MONODROMY = 828
 HK = 126
-GTO_FIXED = 22
+SKIP_TEST = 13
+INTEGRAND = 38
 GTO_PRIM = {0: 12, 1: 19}
-PHASE = 24
-ACCUM = 2
 
 
 def fixed_per_step(pot_kind: int) -> int:
-    """FP64 operations per trajectory-step excluding the GTO primitives."""
-    return 4 * RHS[pot_kind] + RK4_QPS + MONODROMY + HK + GTO_FIXED + PHASE + ACCUM
+    """FP64 operations of every trajectory-step (integrand and primitives excluded)."""
+    return 4 * RHS[pot_kind] + RK4_QPS + MONODROMY + HK + SKIP_TEST
 
 
-def flops(pot_kind: int, l: int, steps_evaluated: int, prims_evaluated: int) -> int:
-    """Algorithmic FP64 operations of a propagation that evaluated the given counts."""
-    return fixed_per_step(pot_kind) * int(steps_evaluated) + GTO_PRIM[l] * int(prims_evaluated)
+def flops(pot_kind: int, l: int, steps_evaluated: int, prims_evaluated: int,
+          integrands_evaluated: int) -> int:
+    """Algorithmic FP64 operations of a propagation that evaluated the given counts (steps, GTO
+    primitives, and steps whose dipole integrand was evaluated)."""
+    return (fixed_per_step(pot_kind) * int(steps_evaluated) + INTEGRAND * int(integrands_evaluated)
+            + GTO_PRIM[l] * int(prims_evaluated))
 
 
 # SFA birth step, saddle-point kernel (same convention; exp, sin, cos, 1/sqrt count 1):

@@ -18,7 +18,8 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsfhk.so")
+# SFHK_LIB may name another build of the library (for side-by-side timing of two builds)
+LIB_PATH = os.environ.get("SFHK_LIB", os.path.join(HERE, "libsfhk.so"))
 
 SFHK_OK, SFHK_E_INVALID, SFHK_E_NOMEM, SFHK_E_DEVICE, SFHK_E_NOT_DONE, SFHK_E_BUDGET = (
     0, -1, -2, -3, -4, -5)
@@ -65,7 +66,8 @@ class _Stats(ct.Structure):
     _fields_ = [("n_traj", ct.c_int64), ("n_steps", ct.c_int64), ("steps_evaluated", ct.c_int64),
                 ("steps_fp64", ct.c_int64), ("kay_removed", ct.c_int64),
                 ("nonfinite_removed", ct.c_int64), ("tiles_total", ct.c_int64),
-                ("tiles_done", ct.c_int64), ("prims_evaluated", ct.c_int64)]
+                ("tiles_done", ct.c_int64), ("prims_evaluated", ct.c_int64),
+                ("integrands_evaluated", ct.c_int64)]
 
 
 _lib = None
@@ -202,10 +204,11 @@ class Stats:
     tiles_total: int
     tiles_done: int
     prims_evaluated: int
+    integrands_evaluated: int
 
 
 class Job:
-    """sfhk_job: one SFHK instance (its trajectories' state, partial sums and field table live in
+    """sfhk_job: one SFHK instance (its trajectories' state, dipole sums and field table live in
     HBM until the job is closed)."""
 
     def __init__(self, ctx: Context, potential, ground, grid_t_a: float, grid_h: float,
@@ -281,7 +284,7 @@ class Job:
                "sfhk_job_stats")
         return Stats(s.n_traj, s.n_steps, s.steps_evaluated, s.steps_fp64, s.kay_removed,
                      s.nonfinite_removed, s.tiles_total, s.tiles_done,
-                     s.prims_evaluated)
+                     s.prims_evaluated, s.integrands_evaluated)
 
     def checkpoint(self, stream=None) -> torch.Tensor:
         """The job's propagation state as a device byte tensor (sfhk_job_checkpoint)."""

@@ -40,3 +40,15 @@ def test_status_strings_without_a_device():
     lib.sfhk_status_string.restype = ct.c_char_p
     assert lib.sfhk_status_string(0) == b"ok"
     assert lib.sfhk_status_string(-5) == b"HBM budget exceeded"
+
+
+def test_job_footprint_of_the_benchmark_workload():
+    """A job's device memory (state, tiles, field table and the per-step exact accumulators of the
+    dipole) is known before it is created; the 2^20-trajectory, 35303-step workload fits in 1 GB:
+    43 doubles of state per trajectory (361 MB) plus small per-trajectory and per-step terms."""
+    from paper_2601_17164_amd import sfhk
+    n, ns = 1 << 20, 35303
+    f = sfhk.job_footprint(n, ns)
+    assert 43 * 8 * n < f <= 1_000_000_000
+    fv = sfhk.job_footprint(n, ns, velocity=True)
+    assert fv - f == (ns + 1) * 2 * 68 * 8

@@ -166,8 +166,8 @@ def test_velocity_errors_and_footprint(S):
     vj.close()
     n, ns = inst.n_traj, inst.grid.n_steps
     f0, f1 = sfhk.job_footprint(n, ns), sfhk.job_footprint(n, ns, velocity=True)
-    tiles = (n + 63) // 64
-    assert f1 - f0 == tiles * (ns + 1) * 16
+    # the velocity's exact accumulators: two per step of 68 64-bit words
+    assert f1 - f0 == (ns + 1) * 2 * 68 * 8
 
 
 def test_length_and_velocity_forms_agree_for_sfa_births(S):
