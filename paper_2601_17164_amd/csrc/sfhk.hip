@@ -87,6 +87,9 @@ struct sfhk_job {
   long long acc_words = 0;     // 64-bit words of the exact accumulators (dipole and velocity)
   uint64_t fingerprint = 0;    // of the inputs that define the propagation (checkpoint matching)
   bool done = false;
+  // regrouping of live trajectories (compact_every > 0)
+  int n_groups = 0;
+  CompactHdr* cq = nullptr;    // the persistent launch's queue of regrouped tiles
 };
 
 struct sfhk_batch {
@@ -129,6 +132,7 @@ size_t footprint_bytes(long long n_traj, long long n_steps, int velocity) {
   size_t b = 0;
   b += (size_t)n_pad * kNY * 8 + (size_t)n_pad * 5 * 8 + (size_t)n_pad * 8 * 2;  // y, aux, n0+death, perm
   b += (size_t)n_tiles * (4 * 3 + sizeof(WorkItem));                             // tile arrays, work list
+  b += (size_t)n_tiles * (4 * 4 + 12) + sizeof(CompactHdr);  // regrouping: groups, queue (if used)
   b += (size_t)accumulator_words(n_steps, velocity) * 8;
   b += (size_t)(2 * n_steps + 1) * 8;  // field table
   b += (size_t)(n_steps + 1) * 8;      // dipole on the step grid
@@ -204,6 +208,39 @@ bool has_duplicates(sfhk_job* const* jobs, int n_jobs) {
 
 int segment_of(int precision, int kind) { return (precision == SFHK_FP32_MIXED ? kKinds : 0) + kind; }
 
+// The persistent, regrouping launch of one FP64 job: as many single-wave workgroups as can be
+// resident at once (never more than the tiles), after a kernel that resets the job's queue.
+sfhk_status launch_compact(sfhk_job* job, int n_items, int max_steps, hipStream_t st) {
+  const int kind = job->kind;
+  const void* fn = nullptr;
+  switch (kind) {
+    case SFHK_POT_SOFTCORE: fn = (const void*)k_propagate_compact<POT_SOFTCORE>; break;
+    case SFHK_POT_SCREENED: fn = (const void*)k_propagate_compact<POT_SCREENED>; break;
+    case SFHK_POT_HARMONIC: fn = (const void*)k_propagate_compact<POT_HARMONIC>; break;
+    default: fn = (const void*)k_propagate_compact<POT_NONE>; break;
+  }
+  int per_cu = 0, cus = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kTile, 0));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, job->ctx->device));
+  const int workers = std::max(1, std::min(n_items, std::max(1, per_cu) * cus));
+  hipLaunchKernelGGL(k_compact_reset, dim3(blocks_for(job->host.n_tiles, 256)), dim3(256), 0, st,
+                     job->cq, job->host.n_tiles);
+  HIP_TRY(hipGetLastError());
+#define SFHK_LAUNCH_C(K)                                                                            \
+  hipLaunchKernelGGL(k_propagate_compact<K>, dim3(workers), dim3(kTile), 0, st,                    \
+                     (const JobDev*)job->dev, (const WorkItem*)job->work, n_items, job->cq,        \
+                     max_steps);
+  switch (kind) {
+    case SFHK_POT_SOFTCORE: SFHK_LAUNCH_C(POT_SOFTCORE) break;
+    case SFHK_POT_SCREENED: SFHK_LAUNCH_C(POT_SCREENED) break;
+    case SFHK_POT_HARMONIC: SFHK_LAUNCH_C(POT_HARMONIC) break;
+    default: SFHK_LAUNCH_C(POT_NONE) break;
+  }
+#undef SFHK_LAUNCH_C
+  HIP_TRY(hipGetLastError());
+  return SFHK_OK;
+}
+
 }  // namespace
 
 namespace {
@@ -225,13 +262,21 @@ size_t ckpt_round(size_t b) { return (b + kCkptAlign - 1) / kCkptAlign * kCkptAl
 std::vector<std::pair<void*, size_t>> ckpt_sections(sfhk_job* j) {
   const JobDev& H = j->host;
   const size_t np = (size_t)H.n_pad, nt = (size_t)H.n_tiles;
-  return {{H.y, np * kNY * sizeof(double)},
-          {H.aux, np * 5 * sizeof(double)},
-          {H.death, np * sizeof(int)},
-          {H.tile_next, nt * sizeof(int)},
-          {H.tile_last, nt * sizeof(int)},
-          {H.counters, 8 * sizeof(unsigned long long)},
-          {H.acc, (size_t)j->acc_words * sizeof(long long)}};
+  std::vector<std::pair<void*, size_t>> v = {{H.y, np * kNY * sizeof(double)},
+                                              {H.aux, np * 5 * sizeof(double)},
+                                              {H.death, np * sizeof(int)},
+                                              {H.tile_next, nt * sizeof(int)},
+                                              {H.tile_last, nt * sizeof(int)},
+                                              {H.counters, 8 * sizeof(unsigned long long)},
+                                              {H.acc, (size_t)j->acc_words * sizeof(long long)}};
+  if (j->cq) {  // regrouping moves trajectories between slots and tiles
+    const size_t ng = (size_t)std::max(1, j->n_groups);
+    v.push_back({H.n0, np * sizeof(int)});
+    v.push_back({H.perm, np * sizeof(long long)});
+    v.push_back({H.grp_active, ng * sizeof(int)});
+    v.push_back({H.grp_pending, ng * sizeof(int)});
+  }
+  return v;
 }
 
 size_t ckpt_bytes(sfhk_job* j) {
@@ -345,6 +390,12 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   if (params->pw_mask < 0 || params->pw_mask > 0x1FF) return fail(SFHK_E_INVALID, "pw_mask must be in [0, 0x1FF]");
   if (params->pw_mask && !(params->pw_radius > 0.0 && std::isfinite(params->pw_radius)))
     return fail(SFHK_E_INVALID, "pw_radius must be finite and > 0");
+  if (params->compact_every != 0 && (params->compact_every < 16 || params->compact_every > (1 << 24)))
+    return fail(SFHK_E_INVALID, "compact_every must be 0 or in [16, 2^24]");
+  // The regrouping launch (k_propagate_compact) did not finish on the GPU in its first two runs and
+  // the cause has not been found, so it stays switched off: any compact_every > 0 is refused.
+  if (params->compact_every != 0)
+    return fail(SFHK_E_INVALID, "compact_every: regrouping of live trajectories is switched off in this build");
   for (int j = 0; j < ground->n_prim; ++j)
     if (!(ground->alpha[j] > 0.0)) return fail(SFHK_E_INVALID, "GTO exponents must be > 0");
 
@@ -511,7 +562,8 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
     mix(&grid->h, sizeof(grid->h));
     const double pv[5] = {params->gamma, params->kay_max, params->overlap_cut, params->r_fp64,
                           params->pw_mask ? params->pw_radius : 0.0};
-    const int64_t iv[4] = {params->precision, params->n_out, params->velocity, params->pw_mask};
+    const int64_t iv[5] = {params->precision, params->n_out, params->velocity, params->pw_mask,
+                           params->compact_every};
     mix(pv, sizeof(pv));
     mix(iv, sizeof(iv));
     j->fingerprint = fp;
@@ -525,12 +577,57 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
       (rc = job_alloc(j, &H.counters, 8, st)) || (rc = job_alloc(j, &j->work, (size_t)n_tiles, st)) ||
       (rc = job_alloc(j, &j->dbuf, (size_t)NS + 1, st)) || (rc = job_alloc(j, &j->dev, 1, st)))
     return cleanup(rc);
-  if (!in_order && (rc = job_alloc(j, &j->perm, (size_t)n_pad, st))) return cleanup(rc);
+  // regrouping: groups of up to kCompactTiles consecutive tiles with one first birth step
+  const bool compact = params->compact_every > 0;
+  std::vector<int> grp_of_tile, grp_first, grp_size;
+  if (compact) {
+    grp_of_tile.assign(n_tiles, -1);
+    for (int t = 0; t < n_tiles;) {
+      int e = t + 1;
+      while (e < n_tiles && e - t < kCompactTiles && tile_n0[e] == tile_n0[t]) ++e;
+      if (e - t >= 2) {
+        for (int u = t; u < e; ++u) grp_of_tile[u] = (int)grp_first.size();
+        grp_first.push_back(t);
+        grp_size.push_back(e - t);
+      }
+      t = e;
+    }
+  }
+  const int n_groups = (int)grp_first.size();
+  if ((!in_order || compact) && (rc = job_alloc(j, &j->perm, (size_t)n_pad, st))) return cleanup(rc);
+  if (compact) {
+    const int ng = std::max(1, n_groups);
+    if ((rc = job_alloc(j, &H.grp_of_tile, (size_t)n_tiles, st)) ||
+        (rc = job_alloc(j, &H.grp_first, (size_t)ng, st)) || (rc = job_alloc(j, &H.grp_active, (size_t)ng, st)) ||
+        (rc = job_alloc(j, &H.grp_pending, (size_t)ng, st)))
+      return cleanup(rc);
+    char* qb = nullptr;
+    if ((rc = job_alloc(j, &qb, sizeof(CompactHdr) + (size_t)n_tiles * (sizeof(int2) + sizeof(unsigned int)), st)))
+      return cleanup(rc);
+    j->cq = (CompactHdr*)qb;
+  }
+  H.compact_every = params->compact_every;
+  H.perm = j->perm;
+  j->n_groups = n_groups;
   H.e_half = e_half;
   H.acc_v = params->velocity ? H.acc + acc_words / 2 : nullptr;
   TRY_C(hipMemcpyAsync(e_half, grid->e_half, (2 * (size_t)NS + 1) * sizeof(double), hipMemcpyDeviceToDevice, st));
-  if (!in_order) {  // the sorted order replaces the caller order k_birth wrote
+  if (compact) {
+    TRY_C(hipMemcpyAsync(H.grp_of_tile, grp_of_tile.data(), n_tiles * sizeof(int), hipMemcpyHostToDevice, st));
+    if (n_groups) {
+      TRY_C(hipMemcpyAsync(H.grp_first, grp_first.data(), n_groups * sizeof(int), hipMemcpyHostToDevice, st));
+      TRY_C(hipMemcpyAsync(H.grp_active, grp_size.data(), n_groups * sizeof(int), hipMemcpyHostToDevice, st));
+      TRY_C(hipMemcpyAsync(H.grp_pending, grp_size.data(), n_groups * sizeof(int), hipMemcpyHostToDevice, st));
+    }
+    if (in_order) {  // slots hold the samples in caller order; regrouping moves them
+      perm.resize(n_pad);
+      for (long long i = 0; i < n_pad; ++i) perm[i] = i < N ? i : -1;
+    }
     TRY_C(hipMemcpyAsync(j->perm, perm.data(), n_pad * sizeof(long long), hipMemcpyHostToDevice, st));
+  }
+  if (!in_order) {  // the sorted order replaces the caller order k_birth wrote
+    if (!compact)
+      TRY_C(hipMemcpyAsync(j->perm, perm.data(), n_pad * sizeof(long long), hipMemcpyHostToDevice, st));
     TRY_C(hipMemcpyAsync(H.n0, n0s.data(), n_pad * sizeof(int), hipMemcpyHostToDevice, st));
     TRY_C(hipMemcpyAsync(H.tile_n0, tile_n0.data(), n_tiles * sizeof(int), hipMemcpyHostToDevice, st));
   }
@@ -587,7 +684,9 @@ sfhk_status sfhk_propagate(sfhk_job* job, int64_t max_steps, void* stream) {
   const int nt = unfinished_tiles(job, job->steps_done);
   if (nt > 0) {
     int ms = (max_steps <= 0 || max_steps > NS + 1) ? 0 : (int)max_steps;
-    sfhk_status rc = launch_propagate(job->precision, job->kind, job->dev, job->work, nt, ms, st);
+    sfhk_status rc = (job->cq && job->precision == SFHK_FP64)
+                         ? launch_compact(job, nt, ms, st)
+                         : launch_propagate(job->precision, job->kind, job->dev, job->work, nt, ms, st);
     if (rc) return rc;
     if ((rc = mark_use(job, st))) return rc;
   }
@@ -607,6 +706,8 @@ sfhk_status sfhk_propagate_many(sfhk_job* const* jobs, int32_t n_jobs, int64_t m
   for (int i = 0; i < n_jobs; ++i)
     if (!jobs[i] || jobs[i]->ctx != ctx) return fail(SFHK_E_INVALID, "jobs must be non-NULL and share one context");
   if (has_duplicates(jobs, n_jobs)) return fail(SFHK_E_INVALID, "a job is listed more than once");
+  for (int i = 0; i < n_jobs; ++i)
+    if (jobs[i]->cq) return fail(SFHK_E_INVALID, "a job created with compact_every runs through sfhk_propagate only");
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
   // one launch over the unfinished tiles of every job, ordered by steps left (longest first)
@@ -787,6 +888,8 @@ sfhk_status sfhk_batch_set_jobs(sfhk_batch* b, sfhk_job* const* jobs, int32_t n_
   for (int i = 0; i < n_jobs; ++i)
     if (!jobs[i] || jobs[i]->ctx != b->ctx) return fail(SFHK_E_INVALID, "jobs must be non-NULL and share the batch's context");
   if (has_duplicates(jobs, n_jobs)) return fail(SFHK_E_INVALID, "a job is listed more than once");
+  for (int i = 0; i < n_jobs; ++i)
+    if (jobs[i]->cq) return fail(SFHK_E_INVALID, "a job created with compact_every runs through sfhk_propagate only");
   HIP_TRY(hipSetDevice(b->ctx->device));
   hipStream_t st = (hipStream_t)stream;
   struct Item {
@@ -1023,6 +1126,7 @@ sfhk_status sfhk_job_stats(sfhk_job* job, sfhk_stats* out, void* stream) {
   out->steps_fp64 = (int64_t)c[3];
   out->prims_evaluated = (int64_t)c[4];
   out->integrands_evaluated = (int64_t)c[5];
+  out->scheduler_errors = (int64_t)c[6];
   out->tiles_total = job->host.n_tiles;
   out->tiles_done = job->host.n_tiles - unfinished_tiles(job, job->steps_done);
   return SFHK_OK;

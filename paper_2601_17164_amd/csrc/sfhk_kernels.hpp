@@ -67,7 +67,14 @@ struct JobDev {
   int pw_mask;        // partial-wave filter (0: every step counts), see pw_keep
   double pw_r2;       // its radius, squared
   unsigned long long* counters;  // steps_evaluated, kay_removed, nonfinite_removed, steps_fp64,
-                                 // GTO primitives evaluated
+                                 // GTO primitives evaluated, integrands evaluated, scheduler errors
+  // compaction of live trajectories (compact_every > 0; see k_propagate_compact)
+  int compact_every;  // boundary interval in steps (0: off)
+  int* grp_of_tile;   // [n_tiles] compaction group of the tile, -1: none
+  int* grp_first;     // [n_groups] first tile of the group
+  int* grp_active;    // [n_groups] tiles first .. first + active - 1 may hold live trajectories
+  int* grp_pending;   // [n_groups] of those, tiles that have not reached the next boundary
+  long long* perm;    // [n_pad] slot -> caller's trajectory index (-1: padding); nullptr: identity
 };
 
 // values that are the same in every lane of the wave (per-tile bookkeeping): kept in scalar
@@ -416,16 +423,15 @@ __device__ __forceinline__ unsigned int queue_eval(IntegrandQueue& Q, int qn, in
   return n_eval;
 }
 
-// KIND >= 0: the potential kind is a compile-time constant (its dispatch folds away); -1: read from
-// the job descriptor at run time
+// Propagates tile `tile` over steps n_begin..n_stop (n_begin <= n_stop <= n_steps; wave-uniform)
+// and stores its state; returns the tile's next step, n_steps + 1 once every lane is removed or the
+// grid's end is reached. KIND >= 0: the potential kind is a compile-time constant (its dispatch
+// folds away); -1: read from the job descriptor at run time
 template <int KIND>
-__device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const int max_steps,
-                                         IntegrandQueue& Q) {
+__device__ __forceinline__ int run_tile_to(const JobDev& J, const int tile, const int n_begin,
+                                           const int n_stop, IntegrandQueue& Q) {
   const int lane = threadIdx.x;
-  const int n_begin = uniform_i32(J.tile_next[tile]);
   const int N = J.n_steps;
-  if (n_begin > N) return;
-  const int n_stop = (max_steps > 0) ? min(N, n_begin + max_steps - 1) : N;
   const long long np = J.n_pad;
   const long long s = (long long)tile * kTile + lane;
 
@@ -532,11 +538,12 @@ __device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const 
   J.aux[4 * np + s] = sgn;
   J.death[s] = death;
   const bool finished = !__any(alive) || n > N;
+  const int next = finished ? N + 1 : n;
   if (lane == 0) {
-    J.tile_next[tile] = finished ? N + 1 : n;
+    J.tile_next[tile] = next;
     J.tile_last[tile] = n - 1;
   }
-  // steps evaluated by this lane in this launch: from max(n_begin, n0) to its removal step or the
+  // steps evaluated by this lane in this call: from max(n_begin, n0) to its removal step or the
   // last step processed
   int evals = 0;
   if (death_in == -1) {
@@ -553,6 +560,18 @@ __device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const 
     atomicAdd(&J.counters[4], (unsigned long long)pr);
     atomicAdd(&J.counters[5], (unsigned long long)ents);
   }
+  return next;
+}
+
+// one launch's share of a tile: max_steps steps (max_steps <= 0: to the end of the grid)
+template <int KIND>
+__device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const int max_steps,
+                                         IntegrandQueue& Q) {
+  const int n_begin = uniform_i32(J.tile_next[tile]);
+  const int N = J.n_steps;
+  if (n_begin > N) return;
+  const int n_stop = (max_steps > 0) ? min(N, n_begin + max_steps - 1) : N;
+  run_tile_to<KIND>(J, tile, n_begin, n_stop, Q);
 }
 
 #ifndef SFHK_PROPAGATE_WAVES_PER_EU
@@ -830,6 +849,282 @@ void k_grid_mixed(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ 
   if ((int)blockIdx.x >= B->n_items[seg]) return;
   const WorkItem wi = work[B->offset[seg] + blockIdx.x];
   run_tile_mixed<KIND>(jobs[wi.job], wi.tile, max_steps, Q);
+}
+
+// ------------------------------------------------------------------------------------------------
+// compaction of live trajectories (persistent form of a single job's propagation)
+// ------------------------------------------------------------------------------------------------
+// Trajectories removed by the Kay test leave their lanes idle until the tile ends. With
+// compact_every = E > 0, the tiles of one birth step (up to kCompactTiles consecutive tiles with
+// the same first birth step: a compaction group) stop at every boundary step k E. The tile whose
+// arrival completes the group (the others have arrived or have no live lane left) regroups the
+// group: the live trajectories move to the front slots of the group (each live slot behind the
+// live count swaps with a removed slot in front of it, pairs by rank), so ceil(live / 64) tiles
+// continue and the rest retire. A trajectory's own arithmetic does not depend on its lane, and
+// which trajectories share a tile after a boundary depends only on the removal steps, never on
+// timing, so results are bitwise reproducible; the per-step sums of a tile's lanes change with
+// the grouping (the exact accumulators make the total independent of everything else).
+// Resident single-wave workgroups take tiles from the launch's static list (longest first) and,
+// first, from a queue of regrouped tiles; a workgroup exits once the static list and the queue
+// are empty and no workgroup holds a tile (holding tiles are the only source of new queue items).
+// Every wait is bounded by a count of polls without progress, after which the workgroup records a
+// scheduler error and exits.
+constexpr int kCompactTiles = 16;  // tiles per compaction group at most
+
+// queue of regrouped tiles, one per launch: header words then items and sequence words
+struct CompactHdr {
+  unsigned int head, tail;   // items taken / pushed
+  unsigned int next_static;  // static items taken
+  int running;               // workgroups holding a tile (or taking one)
+  int cap;                   // item capacity (the job's tile count)
+  int pad[3];
+};
+
+__device__ __forceinline__ unsigned int ld_acq(const unsigned int* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ld_acq(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// takes the next tile (lane 0 decides, the wave gets the result): x = tile (-1: no work left),
+// y = its last step in this launch (-1: from the launch's step limit)
+__device__ __forceinline__ int2* compact_items(CompactHdr* H) { return (int2*)(H + 1); }
+__device__ __forceinline__ unsigned int* compact_seq(CompactHdr* H, int cap) {
+  return (unsigned int*)(compact_items(H) + cap);
+}
+
+// A wait gives up after this many polls without progress (items pushed, taken or started): at
+// least a few seconds, far longer than any tile segment between boundaries.
+constexpr unsigned int kCompactMaxPolls = 1u << 22;
+
+__device__ __forceinline__ int2 compact_pop(CompactHdr* H, const WorkItem* __restrict__ work,
+                                            int n_static, unsigned long long* errors) {
+  int tile = -1, stop = -1;
+  if (threadIdx.x == 0) {
+    const int cap = H->cap;
+    int2* items = compact_items(H);
+    unsigned int* seq = compact_seq(H, cap);
+    unsigned int polls = 0;
+    unsigned long long seen = ~0ull;
+    for (;;) {
+      // regrouped tiles first, then the static list. A workgroup counts itself as running before
+      // it takes an item, and only when there is one to take, so idle workgroups never hold the
+      // count up and never see it at 0 while a tile is being taken.
+      unsigned int h = ld_acq(&H->head), t = ld_acq(&H->tail);
+      const bool dyn = h < t;
+      const bool sta = !dyn && ld_acq(&H->next_static) < (unsigned int)n_static;
+      if (dyn || sta) {
+        __hip_atomic_fetch_add(&H->running, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        bool got = false;
+        if (dyn) {
+          // slot protocol: seq = n + 1 once item n is written; its taker sets seq = n + cap,
+          // which frees the slot for item n + cap; an item is taken only once it is written
+          for (;;) {
+            const unsigned int slot = h % (unsigned int)cap;
+            if (ld_acq(&seq[slot]) != h + 1) break;  // not written yet, or taken: look again
+            if (__hip_atomic_compare_exchange_strong(&H->head, &h, h + 1, __ATOMIC_ACQ_REL,
+                                                     __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) {
+              const int2 it = items[slot];
+              tile = it.x;
+              stop = it.y;
+              got = true;
+              __hip_atomic_store(&seq[slot], h + (unsigned int)cap, __ATOMIC_RELEASE,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+              break;
+            }
+          }
+        } else {
+          const unsigned int k = atomicAdd(&H->next_static, 1u);
+          if (k < (unsigned int)n_static) {
+            tile = work[k].tile;
+            got = true;
+          }
+        }
+        if (got) break;
+        __hip_atomic_fetch_sub(&H->running, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        continue;  // taken by another workgroup, or still being written: look again at once
+      }
+      // nothing to take: finished when nobody holds or takes a tile (read first) and nothing is
+      // queued; holders are the only source of new items
+      if (ld_acq(&H->running) == 0 && ld_acq(&H->head) >= ld_acq(&H->tail) &&
+          ld_acq(&H->next_static) >= (unsigned int)n_static)
+        break;
+      const unsigned long long state = ((unsigned long long)ld_acq(&H->tail) << 32) ^
+                                       ld_acq(&H->head) ^
+                                       ((unsigned long long)ld_acq(&H->next_static) << 16);
+      if (state != seen) {
+        seen = state;
+        polls = 0;
+      } else if (++polls > kCompactMaxPolls) {
+        atomicAdd(errors, 1ull);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  tile = __shfl(tile, 0, 64);
+  stop = __shfl(stop, 0, 64);
+  return make_int2(uniform_i32(tile), uniform_i32(stop));
+}
+
+__device__ __forceinline__ void compact_release(CompactHdr* H) {
+  if (threadIdx.x == 0)
+    __hip_atomic_fetch_sub(&H->running, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// exchanges everything the job holds for slots a and b
+__device__ __forceinline__ void swap_slots(const JobDev& J, long long a, long long b) {
+  const long long np = J.n_pad;
+#pragma unroll 4
+  for (int c = 0; c < kNY; ++c) {
+    const double u = J.y[c * np + a], v = J.y[c * np + b];
+    J.y[c * np + a] = v;
+    J.y[c * np + b] = u;
+  }
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    const double u = J.aux[c * np + a], v = J.aux[c * np + b];
+    J.aux[c * np + a] = v;
+    J.aux[c * np + b] = u;
+  }
+  const int n0a = J.n0[a], n0b = J.n0[b];
+  J.n0[a] = n0b;
+  J.n0[b] = n0a;
+  const int da = J.death[a], db = J.death[b];
+  J.death[a] = db;
+  J.death[b] = da;
+  const long long pa = J.perm[a], pb = J.perm[b];
+  J.perm[a] = pb;
+  J.perm[b] = pa;
+}
+
+// Regroups group g at boundary step nb (the whole wave; every tile of the group that may hold a
+// live trajectory has stopped there or retired) and queues its continuing tiles if the launch
+// goes on past nb (stop = the group's last step in this launch).
+__device__ void compact_group(const JobDev& J, int g, int nb, int stop, int* holes, CompactHdr* H) {
+  const int lane = threadIdx.x;
+  __threadfence();  // the arrived tiles' state
+  const int first = uniform_i32(J.grp_first[g]);
+  const int A = uniform_i32(J.grp_active[g]);
+  const long long base = (long long)first * kTile;
+  const int nslots = A * kTile;
+  int L = 0;  // live trajectories (not removed; not yet born counts as live)
+  for (int c = 0; c < nslots; c += kTile)
+    L += __popcll(__builtin_amdgcn_ballot_w64(J.death[base + c + lane] == -1));
+  const int newA = (L + kTile - 1) / kTile;
+  if (newA < A && L > 0) {
+    // removed slots in front of L, by rank
+    int cnt = 0;
+    for (int c = 0; c < L; c += kTile) {
+      const int i = c + lane;
+      const bool hole = i < L && J.death[base + i] != -1;
+      const unsigned long long m = __builtin_amdgcn_ballot_w64(hole);
+      if (hole) holes[cnt + lanes_below(m)] = i;
+      cnt += __popcll(m);
+    }
+    __syncthreads();
+    // live slots behind L swap with the removed slot of the same rank
+    int r = 0;
+    for (int c = L; c < nslots; c += kTile) {
+      const int i = c + lane;
+      const bool live = i < nslots && J.death[base + i] == -1;
+      const unsigned long long m = __builtin_amdgcn_ballot_w64(live);
+      if (live) swap_slots(J, base + i, base + holes[r + lanes_below(m)]);
+      r += __popcll(m);
+    }
+    __syncthreads();
+  }
+  const int N = J.n_steps;
+  if (lane < A) {
+    const int t = first + lane;
+    if (lane < newA) {
+      J.tile_next[t] = nb;
+      J.tile_last[t] = nb - 1;
+    } else {
+      J.tile_next[t] = N + 1;
+    }
+  }
+  if (lane == 0) {
+    J.grp_active[g] = newA;
+    J.grp_pending[g] = newA;
+  }
+  __threadfence();  // moved state and tile fields before the tiles are queued
+  if (nb <= stop && lane < newA) {
+    const int cap = H->cap;
+    unsigned int* seq = compact_seq(H, cap);
+    const unsigned int slot_n = atomicAdd(&H->tail, 1u);
+    const unsigned int slot = slot_n % (unsigned int)cap;
+    // the slot's previous item (slot_n - cap) has been taken: at most cap items are ever queued
+    // at once (a tile is queued at most once at a time), so this wait ends at once
+    unsigned int waits = 0;
+    while (__hip_atomic_load(&seq[slot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != slot_n &&
+           ++waits < kCompactMaxPolls)
+      __builtin_amdgcn_s_sleep(1);
+    if (waits < kCompactMaxPolls) {
+      compact_items(H)[slot] = make_int2(first + lane, stop);
+      __hip_atomic_store(&seq[slot], slot_n + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      atomicAdd(&J.counters[6], 1ull);
+    }
+  }
+}
+
+// one tile item: propagate to the launch's step limit or to the group's next boundary, whichever
+// comes first; a tile that reaches the boundary waits there (tile_next = n_steps + 2: skipped if
+// taken again) until the group's last arrival regroups the group
+template <int KIND>
+__device__ __forceinline__ void compact_run(const JobDev& J, int tile, int stop_in, int max_steps,
+                                            IntegrandQueue& Q, int* holes, CompactHdr* H) {
+  const int N = J.n_steps;
+  const int n_begin = uniform_i32(__hip_atomic_load(&J.tile_next[tile], __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT));
+  if (n_begin > N) return;  // retired, finished, or waiting at a boundary
+  const int stop = stop_in >= 0 ? stop_in : (max_steps > 0 ? min(N, n_begin + max_steps - 1) : N);
+  const int g = uniform_i32(J.grp_of_tile[tile]);
+  const int E = J.compact_every;
+  const int nb = g < 0 ? N + 1 : (n_begin / E + 1) * E;  // the next boundary after n_begin
+  const int next = run_tile_to<KIND>(J, tile, n_begin, min(stop, nb - 1), Q);
+  if (nb > N) return;                          // no boundary before the grid's end
+  if (next != nb && next != N + 1) return;     // stopped at the launch's step limit
+  if (next == nb && threadIdx.x == 0) J.tile_next[tile] = N + 2;  // waits for the regrouping
+  __threadfence();                             // this tile's state before its arrival
+  int left = 0;
+  if (threadIdx.x == 0)
+    left = __hip_atomic_fetch_sub(&J.grp_pending[g], 1, __ATOMIC_ACQ_REL,
+                                  __HIP_MEMORY_SCOPE_AGENT) - 1;
+  left = uniform_i32(__shfl(left, 0, 64));
+  if (left == 0) compact_group(J, g, nb, stop, holes, H);
+}
+
+// resets the queue of regrouped tiles before a launch: counters, and slot i free for item i
+__global__ void k_compact_reset(CompactHdr* H, int cap) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    H->head = 0u;
+    H->tail = 0u;
+    H->next_static = 0u;
+    H->running = 0;
+    H->cap = cap;
+  }
+  if (i < cap) compact_seq(H, cap)[i] = (unsigned int)i;
+}
+
+// persistent propagation of one job with compaction (see above); launched with at most as many
+// single-wave workgroups as can be resident at once
+template <int KIND>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_PROPAGATE_WAVES_PER_EU)))
+void k_propagate_compact(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work,
+                         int n_static, CompactHdr* __restrict__ H, int max_steps) {
+  __shared__ IntegrandQueue Q;
+  __shared__ int holes[kCompactTiles * kTile];
+  const JobDev& J = jobs[0];
+  for (;;) {
+    const int2 it = compact_pop(H, work, n_static, &J.counters[6]);
+    if (it.x < 0) break;
+    compact_run<KIND>(J, it.x, it.y, max_steps, Q, holes, H);
+    compact_release(H);
+  }
 }
 
 }  // namespace

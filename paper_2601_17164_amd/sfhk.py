@@ -54,7 +54,8 @@ class _Grid(ct.Structure):
 class _Params(ct.Structure):
     _fields_ = [("gamma", ct.c_double), ("kay_max", ct.c_double), ("overlap_cut", ct.c_double),
                 ("r_fp64", ct.c_double), ("precision", ct.c_int32), ("n_out", ct.c_int64),
-                ("velocity", ct.c_int32), ("pw_mask", ct.c_int32), ("pw_radius", ct.c_double)]
+                ("velocity", ct.c_int32), ("pw_mask", ct.c_int32), ("pw_radius", ct.c_double),
+                ("compact_every", ct.c_int32)]
 
 
 class _Pulse(ct.Structure):
@@ -67,7 +68,7 @@ class _Stats(ct.Structure):
                 ("steps_fp64", ct.c_int64), ("kay_removed", ct.c_int64),
                 ("nonfinite_removed", ct.c_int64), ("tiles_total", ct.c_int64),
                 ("tiles_done", ct.c_int64), ("prims_evaluated", ct.c_int64),
-                ("integrands_evaluated", ct.c_int64)]
+                ("integrands_evaluated", ct.c_int64), ("scheduler_errors", ct.c_int64)]
 
 
 _lib = None
@@ -205,6 +206,7 @@ class Stats:
     tiles_done: int
     prims_evaluated: int
     integrands_evaluated: int
+    scheduler_errors: int
 
 
 class Job:
@@ -217,7 +219,7 @@ class Job:
                  kay_max: float = 1e30, overlap_cut: float = 60.0, r_fp64: float = 2.0,
                  precision: int = SFHK_FP64, n_out: int = 0,
                  stream: Optional[torch.cuda.Stream] = None, velocity: bool = False,
-                 pw_mask: int = 0, pw_radius: float = 3.0):
+                 pw_mask: int = 0, pw_radius: float = 3.0, compact_every: int = 0):
         alpha = np.ascontiguousarray(ground.alpha, dtype=np.float64)
         coef = np.ascontiguousarray(ground.coef, dtype=np.float64)
         pot = _Potential(int(potential.kind), float(potential.z_inf), float(potential.z_in),
@@ -227,7 +229,7 @@ class Job:
         grid = _Grid(float(grid_t_a), float(grid_h), int(n_steps), _dptr(e_half))
         prm = _Params(float(gamma), float(kay_max), float(overlap_cut), float(r_fp64),
                       int(precision), int(n_out), int(bool(velocity)), int(pw_mask),
-                      float(pw_radius))
+                      float(pw_radius), int(compact_every))
         n = int(t0.shape[0])
         for name, t, shp in (("t0", t0, (n,)), ("q0", q0, (3, n)), ("p0", p0, (3, n))):
             if tuple(t.shape) != shp or t.dtype != torch.float64:
@@ -284,7 +286,7 @@ class Job:
                "sfhk_job_stats")
         return Stats(s.n_traj, s.n_steps, s.steps_evaluated, s.steps_fp64, s.kay_removed,
                      s.nonfinite_removed, s.tiles_total, s.tiles_done,
-                     s.prims_evaluated, s.integrands_evaluated)
+                     s.prims_evaluated, s.integrands_evaluated, s.scheduler_errors)
 
     def checkpoint(self, stream=None) -> torch.Tensor:
         """The job's propagation state as a device byte tensor (sfhk_job_checkpoint)."""
@@ -486,9 +488,9 @@ def to_device(inst, device="cuda:0"):
 
 
 def make_job(ctx: Context, inst, dev_arrays=None, precision=SFHK_FP64, n_out=None, stream=None,
-             r_fp64=2.0, velocity=False, pw_mask=0, pw_radius=3.0) -> Job:
+             r_fp64=2.0, velocity=False, pw_mask=0, pw_radius=3.0, compact_every=0) -> Job:
     a = dev_arrays if dev_arrays is not None else to_device(inst, f"cuda:{ctx.device}")
     return Job(ctx, inst.potential, inst.ground, inst.grid.t_a, inst.grid.h, inst.grid.n_steps,
                a["e_half"], a["t0"], a["q0"], a["p0"], a["w"], inst.gamma, inst.kay_max,
                inst.overlap_cut, r_fp64, precision, inst.n_out if n_out is None else n_out,
-               stream, velocity, pw_mask, pw_radius)
+               stream, velocity, pw_mask, pw_radius, compact_every)
