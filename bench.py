@@ -77,8 +77,11 @@ def _args():
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--serve-warmup", type=int, default=20)
     ap.add_argument("--serve-chunk", type=int, default=1024)
+    ap.add_argument("--default-requests", type=int, default=100,
+                    help="measured requests per rate in the default line's serving sweep")
+    ap.add_argument("--default-serve-warmup", type=int, default=10)
     ap.add_argument("--no-serving", action="store_true",
-                    help="skip the short serving run of the default benchmark")
+                    help="skip the serving sweep (--rates, both forms) of the default benchmark")
     ap.add_argument("--no-sfa", action="store_true",
                     help="skip the SFA birth step leg (birth kernel timing, SFA-born propagation)")
     ap.add_argument("--sfa-reps", type=int, default=5)
@@ -234,6 +237,25 @@ def serving_run(ctx, rate, n_req, warmup, precision, chunk, reqs=None, verbose=F
     if verbose:
         print(json.dumps(summ), flush=True)
     return summ
+
+
+def serving_sweep(ctx, a):
+    """The serving loop at each offered rate of --rates, in both forms, with --default-requests
+    measured requests after --default-serve-warmup warm-up ones (the default line's leg)."""
+    from paper_2601_17164_amd import inputs as I
+    n = a.default_serve_warmup + a.default_requests
+    reqs = [I.serving_request(k) for k in range(n)]
+    runs = []
+    for prec in (0, 1):
+        for rate in [float(x) for x in a.rates.split(",")]:
+            r = serving_run(ctx, rate, a.default_requests, a.default_serve_warmup, prec,
+                            a.serve_chunk, reqs)
+            runs.append({k: r[k] for k in ("precision", "offered_rate", "served_rate", "requests",
+                                           "p50_ms", "p99_ms", "trajectory_steps_per_s",
+                                           "max_active", "max_queued")})
+            print(json.dumps({"serving_progress": runs[-1]}), file=sys.stderr, flush=True)
+    return {"requests_per_rate": a.default_requests, "warmup": a.default_serve_warmup,
+            "chunk": a.serve_chunk, "runs": runs}
 
 
 def run_serve(a):
@@ -594,8 +616,7 @@ def main():
     if not a.no_mixed:
         out["fp32_mixed"] = mixed_form(step, stream, inst, arrays, spec, flops)
     if not a.no_serving:
-        out["serving"] = {name: serving_run(ctx, 5.0, 30, 2, prec, a.serve_chunk)
-                          for prec, name in ((0, "fp64"), (1, "fp32_mixed"))}
+        out["serving"] = serving_sweep(ctx, a)
     if not a.no_batch:
         out["batch"] = batch_results(ctx, a.batch_size)
     if not a.no_velocity:
