@@ -34,7 +34,7 @@ def kernel_source_hash() -> str:
     """sha256 of the sources the FP64 propagate kernel is compiled from (the host runtime in
     sfhk.hip does not enter)."""
     h = hashlib.sha256()
-    for f in ("sfhk_kernels.hpp", "sfhk_device.hpp"):
+    for f in ("sfhk_kernels.hpp", "sfhk_device.hpp", "sfhk_exact_sum.hpp"):
         with open(os.path.join(ROOT, "paper_2601_17164_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
