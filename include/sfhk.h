@@ -63,14 +63,32 @@ typedef struct {
   double ip;
 } sfhk_ground;
 
+/* A linearly polarised sin^2 pulse along z (Sec. II.B field; App. A): vector potential
+ * A(t) = -(e0/omega) cos^2(pi t/T) sin(omega t + cep) for |t| <= T/2 (else 0),
+ * T = 2 pi n_cycles / omega, and field E = -dA/dt. */
+typedef struct {
+  double e0, omega, n_cycles, cep;
+} sfhk_pulse;
+
 /* Time grid and laser field (Sec. II.B field, linear polarisation along z): t_n = t_a + n h,
- * n = 0..n_steps. e_half is a DEVICE array of 2*n_steps + 1 values E_z(t_a + m h / 2), read during
- * sfhk_job_create (copied; the caller may free it afterwards). */
+ * n = 0..n_steps. The propagation reads E_z at the half steps t_a + m h/2, m = 0..2 n_steps:
+ *  - pulse given, e_half NULL: the library tabulates the pulse's field on the device, in the fixed
+ *    sequence T = ((2 pi) n_cycles) / omega, t = t_a + m (h / 2); E = 0 where |t| > T/2, else
+ *    (s1, c1) = sincos(pi t / T), (sx, cx) = sincos(omega t + cep),
+ *    E = (e0 c1^2) cx - ((e0 pi) / (omega T)) (2 s1 c1) sx (each product as written), with the
+ *    sine and cosine of sfhk_traj_sincos, so that an independent evaluation of the same sequence
+ *    gives the same table bit for bit; within 1e-15 e0 of the field's exact values;
+ *  - e_half given (a DEVICE array of 2 n_steps + 1 values, copied during sfhk_job_create; the caller
+ *    may free it afterwards): that table is used; if pulse is also given, the table must agree with
+ *    the pulse's within 1e-9 e0 at every half step (else SFHK_E_INVALID), so a job cannot run in a
+ *    field other than the pulse its births (sfhk_sfa_birth) were drawn from.
+ * pulse is a HOST pointer read during sfhk_job_create. */
 typedef struct {
   double t_a;
   double h;
   int64_t n_steps;
   const double* e_half;
+  const sfhk_pulse* pulse;
 } sfhk_grid;
 
 /* Method parameters:
@@ -342,13 +360,9 @@ sfhk_status sfhk_traj_sincos(const double* x, double* s, double* c, int64_t n, v
  * SFA birth step (App. A: the continuum wave packet right after tunnelling, the saddle-point
  * equation, the tunnel exit and the action under the barrier; App. B: tunnelling elements).
  *
- * The pulse: linear polarisation along z, A(t) = -(e0/omega) cos^2(pi t/T) sin(omega t + cep),
- * T = 2 pi n_cycles / omega, E = -dA/dt (Sec. II.B field; the same pulse the field table of
- * sfhk_grid tabulates). n_cycles must exceed 1.
+ * The pulse is the sfhk_pulse of sfhk_grid (the same description a job's field is tabulated
+ * from); n_cycles must exceed 1 here.
  */
-typedef struct {
-  double e0, omega, n_cycles, cep;
-} sfhk_pulse;
 
 typedef enum {
   SFHK_BIRTH_GTO = 0,      /* Eq. A.2 with the GTO tunnelling element of App. B.1 */

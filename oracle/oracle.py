@@ -146,6 +146,7 @@ def _declare(L):
     L.or_resample.argtypes = [P, ct.c_int64, ct.c_int64, P]
     L.or_spectrum.restype = ct.c_int
     L.or_spectrum.argtypes = [P, ct.c_int64, D, D, D, ct.c_int64, P, P, P]
+    L.or_field_table_c.argtypes = [D, D, D, D, D, D, ct.c_int64, P]
     L.or_correctly_rounded.restype = ct.c_int
     L.or_correctly_rounded.argtypes = []
     return L
@@ -256,6 +257,15 @@ def field_A(t, e0, omega, T, cep=0.0):
 
 def field_E(t, e0, omega, T, cep=0.0):
     return np.array([lib().or_field_E(float(x), e0, omega, T, cep) for x in np.atleast_1d(t)])
+
+
+def field_table_c(e0, omega, n_cycles, cep, t_a, h, n_steps, correctly_rounded=False):
+    """E_z(t_a + m h/2), m = 0..2 n_steps, in the fixed sequence of ``or_field_table_c`` (the
+    table the device tabulates from the same pulse)."""
+    out = np.zeros(2 * int(n_steps) + 1)
+    lib(correctly_rounded).or_field_table_c(float(e0), float(omega), float(n_cycles), float(cep),
+                                           float(t_a), float(h), int(n_steps), _p(out))
+    return out
 
 
 def field_intA(t, e0, omega, T, cep=0.0):

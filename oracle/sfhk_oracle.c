@@ -194,6 +194,29 @@ double or_field_E(double t, double e0, double omega, double T, double cep) {
          (e0 * M_PI / (omega * T)) * sin(2.0 * M_PI * t / T) * sin(omega * t + cep);
 }
 
+/* the field table in the fixed sequence stated in sfhk_oracle.h (E = -dA/dt with the sin^2
+ * envelope; sin(2 pi t/T) written as 2 sin(pi t/T) cos(pi t/T)) */
+void or_field_table_c(double e0, double omega, double n_cycles, double cep, double t_a, double h,
+                      int64_t n_steps, double* e_half) {
+  const double T = ((2.0 * M_PI) * n_cycles) / omega;
+  const double half_T = 0.5 * T;
+  const double h2 = 0.5 * h;
+  const double k = (e0 * M_PI) / (omega * T);
+  for (int64_t m = 0; m <= 2 * n_steps; ++m) {
+    const double t = t_a + (double)m * h2;
+    if (!(fabs(t) <= half_T)) {
+      e_half[m] = 0.0;
+      continue;
+    }
+    double s1, c1, sx, cx;
+    traj_sincos((M_PI * t) / T, &s1, &c1);
+    traj_sincos(omega * t + cep, &sx, &cx);
+    const double a = (e0 * (c1 * c1)) * cx;
+    const double b = (k * (2.0 * (s1 * c1))) * sx;
+    e_half[m] = a - b;
+  }
+}
+
 /* antiderivative of cos^2(pi t/T) sin(omega t + cep): cos^2 = (1 + cos(W t))/2, W = 2 pi/T */
 static double cos2sin_antideriv(double t, double omega, double T, double cep) {
   double W = 2.0 * M_PI / T;

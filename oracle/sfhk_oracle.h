@@ -103,6 +103,14 @@ void or_sincos_c(double x, double* s, double* c);
  *   A(t) = -(E0/omega) cos^2(pi t/T) sin(omega t + cep) for |t| <= T/2, else 0. */
 double or_field_A(double t, double e0, double omega, double T, double cep);
 double or_field_E(double t, double e0, double omega, double T, double cep);
+/* The field table E_z(t_a + m h/2), m = 0..2 n_steps, of the sin^2 pulse (e0, omega, n_cycles,
+ * cep) evaluated in a fixed operation sequence with the contract sine and cosine (or_sincos_c), so
+ * that an independent implementation of the same sequence gives the same table bit for bit:
+ * T = ((2 pi) n_cycles) / omega, t = t_a + m (h / 2); E = 0 where |t| > T/2, otherwise
+ * (s1, c1) = sincos(pi t / T), (sx, cx) = sincos(omega t + cep),
+ * E = (e0 c1^2) cx - ((e0 pi) / (omega T)) (2 s1 c1) sx, the two products evaluated as written. */
+void or_field_table_c(double e0, double omega, double n_cycles, double cep, double t_a, double h,
+                      int64_t n_steps, double* e_half);
 /* int_{-T/2}^{t} A(t') dt' (closed form; requires omega T != 2 pi). */
 double or_field_intA(double t, double e0, double omega, double T, double cep);
 

@@ -374,7 +374,11 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   if (!(params->gamma > 0.0)) return fail(SFHK_E_INVALID, "gamma must be > 0");
   if (!(grid->h > 0.0)) return fail(SFHK_E_INVALID, "h must be > 0");
   if (grid->n_steps < 1 || grid->n_steps > (1LL << 30)) return fail(SFHK_E_INVALID, "n_steps out of range");
-  if (!grid->e_half) return fail(SFHK_E_INVALID, "e_half is NULL");
+  if (!grid->e_half && !grid->pulse) return fail(SFHK_E_INVALID, "the grid needs e_half or a pulse");
+  if (const sfhk_pulse* pl = grid->pulse)
+    if (!(std::isfinite(pl->e0) && pl->omega > 0.0 && std::isfinite(pl->omega) && pl->n_cycles > 0.0 &&
+          std::isfinite(pl->n_cycles) && std::isfinite(pl->cep)))
+      return fail(SFHK_E_INVALID, "pulse: need finite e0 and cep, omega > 0, n_cycles > 0");
   if (n_traj < 1 || n_traj > (1LL << 31)) return fail(SFHK_E_INVALID, "n_traj out of range");
   if (ground->l != 0 && ground->l != 1) return fail(SFHK_E_INVALID, "ground-state l must be 0 or 1");
   if (ground->n_prim < 1 || ground->n_prim > SFHK_MAX_PRIM || !ground->alpha || !ground->coef)
@@ -560,6 +564,7 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
     mix(ground->coef, sizeof(double) * (size_t)ground->n_prim);
     mix(&grid->t_a, sizeof(grid->t_a));
     mix(&grid->h, sizeof(grid->h));
+    if (grid->pulse) mix(grid->pulse, sizeof(*grid->pulse));
     const double pv[5] = {params->gamma, params->kay_max, params->overlap_cut, params->r_fp64,
                           params->pw_mask ? params->pw_radius : 0.0};
     const int64_t iv[5] = {params->precision, params->n_out, params->velocity, params->pw_mask,
@@ -611,7 +616,24 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   j->n_groups = n_groups;
   H.e_half = e_half;
   H.acc_v = params->velocity ? H.acc + acc_words / 2 : nullptr;
-  TRY_C(hipMemcpyAsync(e_half, grid->e_half, (2 * (size_t)NS + 1) * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (grid->e_half)
+    TRY_C(hipMemcpyAsync(e_half, grid->e_half, (2 * (size_t)NS + 1) * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (const sfhk_pulse* pl = grid->pulse) {
+    // tabulate the pulse's field, or check the given table against it (flags[0] = mismatch)
+    TRY_C(hipMemsetAsync(flags, 0, sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(k_field_table, dim3(blocks_for(2 * (long long)NS + 1, 256)), dim3(256), 0, st,
+                       pl->e0, pl->omega, pl->n_cycles, pl->cep, grid->t_a, grid->h, (long long)NS,
+                       grid->e_half ? nullptr : e_half, grid->e_half ? e_half : nullptr, flags,
+                       1e-9 * std::fabs(pl->e0));
+    TRY_C(hipGetLastError());
+    if (grid->e_half) {
+      unsigned long long mismatch = 0;
+      TRY_C(hipMemcpyAsync(&mismatch, flags, sizeof(mismatch), hipMemcpyDeviceToHost, st));
+      TRY_C(hipStreamSynchronize(st));
+      if (mismatch)
+        return cleanup(fail(SFHK_E_INVALID, "e_half differs from the pulse's field by more than 1e-9 e0"));
+    }
+  }
   if (compact) {
     TRY_C(hipMemcpyAsync(H.grp_of_tile, grp_of_tile.data(), n_tiles * sizeof(int), hipMemcpyHostToDevice, st));
     if (n_groups) {

@@ -352,6 +352,34 @@ __global__ __launch_bounds__(256) void k_sfa_weight(SfaParams P, long long n, co
 }
 
 // the contract sine and cosine, exported for bitwise checks
+// The field table of a sin^2 pulse (Sec. II.B field, E = -dA/dt as in App. A) in the fixed
+// sequence stated with sfhk_grid: out[m] = E_z(t_a + m h/2), m = 0..2 n_steps (out nullable); with
+// `given`, any |given[m] - E| above tol (or a NaN) sets *mismatch.
+__global__ __launch_bounds__(256) void k_field_table(double e0, double omega, double n_cycles,
+                                                     double cep, double t_a, double h,
+                                                     long long n_steps, double* __restrict__ out,
+                                                     const double* __restrict__ given,
+                                                     unsigned long long* __restrict__ mismatch,
+                                                     double tol) {
+  const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m > 2 * n_steps) return;
+  const double T = ((2.0 * M_PI) * n_cycles) / omega;
+  const double half_T = 0.5 * T;
+  const double k = (e0 * M_PI) / (omega * T);
+  const double t = t_a + (double)m * (0.5 * h);
+  double e = 0.0;
+  if (fabs(t) <= half_T) {
+    double s1, c1, sx, cx;
+    sincos_c((M_PI * t) / T, &s1, &c1);
+    sincos_c(omega * t + cep, &sx, &cx);
+    const double a = (e0 * (c1 * c1)) * cx;
+    const double b = (k * (2.0 * (s1 * c1))) * sx;
+    e = a - b;
+  }
+  if (out) out[m] = e;
+  if (given && !(fabs(given[m] - e) <= tol)) atomicOr(mismatch, 1ull);
+}
+
 __global__ __launch_bounds__(256) void k_traj_sincos(const double* __restrict__ x, double* __restrict__ s,
                                                      double* __restrict__ c, long long n) {
   const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;

@@ -116,19 +116,6 @@ def time_grid(pulse: Pulse, dt: float) -> Grid:
     return Grid(-0.5 * T, T / n, n)
 
 
-def field_table(pulse: Pulse, grid: Grid) -> np.ndarray:
-    """E_z at t_a + m h/2, m = 0..2 n_steps, for A(t) = -(E0/w) cos^2(pi t/T) sin(w t + cep)
-    and E = -dA/dt (the laser field is an input of the method)."""
-    T, w, e0, cep = pulse.duration, pulse.omega, pulse.e0, pulse.cep
-    m = np.arange(2 * grid.n_steps + 1, dtype=np.float64)
-    t = grid.t_a + m * (0.5 * grid.h)
-    inside = np.abs(t) <= 0.5 * T
-    c = np.cos(np.pi * t / T)
-    e = e0 * c * c * np.cos(w * t + cep) - (e0 * np.pi / (w * T)) * np.sin(
-        2.0 * np.pi * t / T) * np.sin(w * t + cep)
-    return np.where(inside, e, 0.0)
-
-
 def birth_times(grid: Grid, n_birth: int) -> np.ndarray:
     """Midpoints of n_birth equal bins over the pulse."""
     T = grid.h * grid.n_steps
@@ -151,13 +138,16 @@ def gaussian_samples(seed: int, n_birth: int, n_per_birth: int, gamma: float):
 
 @dataclass
 class Instance:
-    """One SFHK problem: potential, ground state, pulse, grid, field table and samples."""
+    """One SFHK problem: potential, ground state, pulse, grid and samples. The laser field of the
+    pulse is tabulated by the library (or, on the test side, by the oracle); e_half gives an explicit
+    table E_z(t_a + m h/2), m = 0..2 n_steps, instead (test cases with a field other than the
+    pulse's, such as none)."""
     name: str
     potential: Potential
     ground: Ground
     pulse: Pulse
     grid: Grid
-    e_half: np.ndarray
+    e_half: Optional[np.ndarray]
     t0: np.ndarray
     q0: np.ndarray
     p0: np.ndarray
@@ -196,11 +186,10 @@ class Instance:
 def make_instance(name, potential, ground, pulse, dt, n_birth, n_per_birth, seed, gamma=0.5,
                   kay_max=1e30, n_out=0, overlap_cut=60.0) -> Instance:
     grid = time_grid(pulse, dt)
-    e_half = field_table(pulse, grid)
     tb = birth_times(grid, n_birth)
     t0 = np.repeat(tb, n_per_birth)
     q0, p0 = gaussian_samples(seed, n_birth, n_per_birth, gamma)
-    return Instance(name, potential, ground, pulse, grid, e_half, t0, q0, p0, None, gamma,
+    return Instance(name, potential, ground, pulse, grid, None, t0, q0, p0, None, gamma,
                     kay_max, overlap_cut, n_out, n_birth, n_per_birth, seed)
 
 
@@ -290,10 +279,9 @@ def sfa_instance(name, potential, ground, pulse, dt, n_birth, n_per_birth, seed,
     """An instance whose initial conditions come from the SFA birth step: t0, k_perp and u are
     here (``meta``); q0, p0 and w are zero until the birth step fills them."""
     grid = time_grid(pulse, dt)
-    e_half = field_table(pulse, grid)
     t0, kperp, u = sfa_samples(seed, pulse, grid, n_birth, n_per_birth, ground.ip)
     n = t0.shape[0]
-    return Instance(name, potential, ground, pulse, grid, e_half, t0, np.zeros((3, n)),
+    return Instance(name, potential, ground, pulse, grid, None, t0, np.zeros((3, n)),
                     np.zeros((3, n)), np.zeros(n, dtype=np.complex128), gamma, kay_max,
                     overlap_cut, n_out, n_birth, n_per_birth, seed,
                     meta=dict(kperp=kperp, u=u, mode=mode))

@@ -46,9 +46,14 @@ class _Ground(ct.Structure):
                 ("coef", ct.POINTER(ct.c_double)), ("ip", ct.c_double)]
 
 
+class _Pulse(ct.Structure):
+    _fields_ = [("e0", ct.c_double), ("omega", ct.c_double), ("n_cycles", ct.c_double),
+                ("cep", ct.c_double)]
+
+
 class _Grid(ct.Structure):
     _fields_ = [("t_a", ct.c_double), ("h", ct.c_double), ("n_steps", ct.c_int64),
-                ("e_half", ct.c_void_p)]
+                ("e_half", ct.c_void_p), ("pulse", ct.POINTER(_Pulse))]
 
 
 class _Params(ct.Structure):
@@ -56,11 +61,6 @@ class _Params(ct.Structure):
                 ("r_fp64", ct.c_double), ("precision", ct.c_int32), ("n_out", ct.c_int64),
                 ("velocity", ct.c_int32), ("pw_mask", ct.c_int32), ("pw_radius", ct.c_double),
                 ("compact_every", ct.c_int32)]
-
-
-class _Pulse(ct.Structure):
-    _fields_ = [("e0", ct.c_double), ("omega", ct.c_double), ("n_cycles", ct.c_double),
-                ("cep", ct.c_double)]
 
 
 class _Stats(ct.Structure):
@@ -214,19 +214,31 @@ class Job:
     HBM until the job is closed)."""
 
     def __init__(self, ctx: Context, potential, ground, grid_t_a: float, grid_h: float,
-                 n_steps: int, e_half: torch.Tensor, t0: torch.Tensor, q0: torch.Tensor,
+                 n_steps: int, e_half: Optional[torch.Tensor], t0: torch.Tensor, q0: torch.Tensor,
                  p0: torch.Tensor, w: Optional[torch.Tensor] = None, gamma: float = 0.5,
                  kay_max: float = 1e30, overlap_cut: float = 60.0, r_fp64: float = 2.0,
                  precision: int = SFHK_FP64, n_out: int = 0,
                  stream: Optional[torch.cuda.Stream] = None, velocity: bool = False,
-                 pw_mask: int = 0, pw_radius: float = 3.0, compact_every: int = 0):
+                 pw_mask: int = 0, pw_radius: float = 3.0, compact_every: int = 0,
+                 pulse=None):
+        """``e_half`` is the field at the half steps (device, 2 n_steps + 1 values) or None;
+        ``pulse`` (e0, omega, n_cycles, cep) has the library tabulate the field, or check the given
+        table against it. At least one of the two is needed."""
         alpha = np.ascontiguousarray(ground.alpha, dtype=np.float64)
         coef = np.ascontiguousarray(ground.coef, dtype=np.float64)
         pot = _Potential(int(potential.kind), float(potential.z_inf), float(potential.z_in),
                          float(potential.r_scr), float(potential.soft2), float(potential.omega_ho))
         gs = _Ground(int(ground.l), len(alpha), alpha.ctypes.data_as(ct.POINTER(ct.c_double)),
                      coef.ctypes.data_as(ct.POINTER(ct.c_double)), float(ground.ip))
-        grid = _Grid(float(grid_t_a), float(grid_h), int(n_steps), _dptr(e_half))
+        pl = None
+        if pulse is not None:
+            pl = _Pulse(float(pulse.e0), float(pulse.omega), float(pulse.n_cycles),
+                        float(pulse.cep))
+        if e_half is not None and (tuple(e_half.shape) != (2 * int(n_steps) + 1,)
+                                   or e_half.dtype != torch.float64):
+            raise ValueError("e_half must be float64 of shape (2 n_steps + 1,)")
+        grid = _Grid(float(grid_t_a), float(grid_h), int(n_steps), _dptr(e_half),
+                     ct.pointer(pl) if pl is not None else None)
         prm = _Params(float(gamma), float(kay_max), float(overlap_cut), float(r_fp64),
                       int(precision), int(n_out), int(bool(velocity)), int(pw_mask),
                       float(pw_radius), int(compact_every))
@@ -478,13 +490,15 @@ def sfa_birth(pulse, ground, t0: torch.Tensor, kperp: torch.Tensor,
 # convenience: one instance (see inputs.Instance) end to end on the device
 # ------------------------------------------------------------------------------------------------
 def to_device(inst, device="cuda:0"):
-    """Upload an instance's field table and samples (float64) to the device."""
+    """Upload an instance's samples (float64) and its explicit field table, if it has one, to the
+    device (a pulse instance's field is tabulated by the library)."""
     dev = torch.device(device)
     f = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
     w = None
     if inst.w is not None:
         w = f(np.stack([np.real(inst.w), np.imag(inst.w)]))
-    return dict(e_half=f(inst.e_half), t0=f(inst.t0), q0=f(inst.q0), p0=f(inst.p0), w=w)
+    e = f(inst.e_half) if inst.e_half is not None else None
+    return dict(e_half=e, t0=f(inst.t0), q0=f(inst.q0), p0=f(inst.p0), w=w)
 
 
 def make_job(ctx: Context, inst, dev_arrays=None, precision=SFHK_FP64, n_out=None, stream=None,
@@ -493,4 +507,5 @@ def make_job(ctx: Context, inst, dev_arrays=None, precision=SFHK_FP64, n_out=Non
     return Job(ctx, inst.potential, inst.ground, inst.grid.t_a, inst.grid.h, inst.grid.n_steps,
                a["e_half"], a["t0"], a["q0"], a["p0"], a["w"], inst.gamma, inst.kay_max,
                inst.overlap_cut, r_fp64, precision, inst.n_out if n_out is None else n_out,
-               stream, velocity, pw_mask, pw_radius, compact_every)
+               stream, velocity, pw_mask, pw_radius, compact_every,
+               pulse=inst.pulse if inst.e_half is None else None)

@@ -21,8 +21,19 @@ def oracle_ground(g: I.Ground) -> O.Ground:
     return O.Ground(g.l, g.alpha, g.coef, g.ip)
 
 
+def pulse_table(pulse: I.Pulse, grid: I.Grid) -> np.ndarray:
+    """The oracle's field table of the pulse on the grid (E_z at the half steps)."""
+    return O.field_table_c(pulse.e0, pulse.omega, pulse.n_cycles, pulse.cep, grid.t_a, grid.h,
+                           grid.n_steps)
+
+
+def e_half(inst: I.Instance) -> np.ndarray:
+    """The instance's explicit field table, else the oracle's table of its pulse."""
+    return inst.e_half if inst.e_half is not None else pulse_table(inst.pulse, inst.grid)
+
+
 def run_oracle(inst: I.Instance, n_threads: int = 0, kay_max=None) -> O.PropagateResult:
-    return O.propagate(oracle_potential(inst.potential), oracle_ground(inst.ground), inst.e_half,
+    return O.propagate(oracle_potential(inst.potential), oracle_ground(inst.ground), e_half(inst),
                        inst.grid.t_a, inst.grid.h, inst.grid.n_steps, inst.t0, inst.q0, inst.p0,
                        inst.w, inst.gamma, inst.kay_max if kay_max is None else kay_max,
                        inst.overlap_cut, n_threads)

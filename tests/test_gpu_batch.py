@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from paper_2601_17164_amd import inputs as I
-from tests.common import require_gpu
+from tests.common import pulse_table, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -112,7 +112,7 @@ def _kind_instances():
     own kernel instance."""
     pulse = I.Pulse(800.0, 1e14, 2.0)
     grid = I.time_grid(pulse, 0.1)
-    e = I.field_table(pulse, grid)
+    e = pulse_table(pulse, grid)
     rng = np.random.default_rng(5)
     n = 96
     t0 = np.sort(grid.t_a + rng.integers(0, grid.n_steps, n) * grid.h)

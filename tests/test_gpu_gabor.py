@@ -9,7 +9,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2601_17164_amd import inputs as I
-from tests.common import oracle_ground, oracle_potential, require_gpu
+from tests.common import e_half, oracle_ground, oracle_potential, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -49,7 +49,7 @@ def test_wave_packet_ragged_grid(S):
 
 
 def _oracle_velocity(inst):
-    r = O.propagate(oracle_potential(inst.potential), oracle_ground(inst.ground), inst.e_half,
+    r = O.propagate(oracle_potential(inst.potential), oracle_ground(inst.ground), e_half(inst),
                     inst.grid.t_a, inst.grid.h, inst.grid.n_steps, inst.t0, inst.q0, inst.p0,
                     inst.w, inst.gamma, inst.kay_max, inst.overlap_cut, 0, velocity=True)
     return -2.0 * r.V.real

@@ -10,7 +10,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2601_17164_amd import inputs as I, metrics
-from tests.common import rel_l2, require_gpu, run_oracle
+from tests.common import pulse_table, rel_l2, require_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -132,7 +132,7 @@ def test_mixed_volkov_closed_form(S):
     to FP32 accuracy, with every step on the FP32 path (r_fp64 = 0)."""
     pulse = I.Pulse(800.0, 1e14, 2.0)
     grid = I.time_grid(pulse, 0.05)
-    e = I.field_table(pulse, grid)
+    e = pulse_table(pulse, grid)
     inst = I.Instance("volkov", I.Potential(I.POT_NONE, 0, 0, 1, 0, 0), I.gto_h1s(), pulse, grid,
                       e, np.array([grid.t_a + 100 * grid.h]), np.array([[3.0], [-2.0], [2.5]]),
                       np.array([[0.1], [0.2], [-0.3]]))

@@ -12,7 +12,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2601_17164_amd import inputs as I
-from tests.common import rel_l2, require_gpu, run_oracle
+from tests.common import e_half, pulse_table, rel_l2, require_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -208,7 +208,7 @@ def test_against_the_correctly_rounded_oracle(S, case):
 
 def _oracle_args(inst):
     from tests.common import oracle_ground, oracle_potential
-    return (oracle_potential(inst.potential), oracle_ground(inst.ground), inst.e_half,
+    return (oracle_potential(inst.potential), oracle_ground(inst.ground), e_half(inst),
             inst.grid.t_a, inst.grid.h, inst.grid.n_steps, inst.t0, inst.q0, inst.p0, inst.w,
             inst.gamma, inst.kay_max, inst.overlap_cut)
 
@@ -370,7 +370,7 @@ def test_volkov_and_oscillator_closed_forms_through_gpu(S):
     oscillator with omega = 2 gamma: C = exp(-3 i omega tau / 2)."""
     pulse = I.Pulse(800.0, 1e14, 2.0)
     grid = I.time_grid(pulse, 0.05)
-    e = I.field_table(pulse, grid)
+    e = pulse_table(pulse, grid)
     q0 = np.array([[0.3], [-0.2], [0.5]])
     p0 = np.array([[0.1], [0.2], [-0.3]])
     t0 = np.array([grid.t_a + 100 * grid.h])

@@ -8,7 +8,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2601_17164_amd import inputs as I
-from tests.common import oracle_ground, oracle_potential, rel_l2, require_gpu
+from tests.common import e_half, oracle_ground, oracle_potential, rel_l2, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -27,7 +27,7 @@ def S():
 
 
 def _oracle(inst, mask, velocity=False):
-    return O.propagate(oracle_potential(inst.potential), oracle_ground(inst.ground), inst.e_half,
+    return O.propagate(oracle_potential(inst.potential), oracle_ground(inst.ground), e_half(inst),
                        inst.grid.t_a, inst.grid.h, inst.grid.n_steps, inst.t0, inst.q0, inst.p0,
                        inst.w, inst.gamma, inst.kay_max, inst.overlap_cut, 0, velocity=velocity,
                        pw_mask=mask, pw_radius=3.0)

@@ -13,7 +13,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2601_17164_amd import inputs as I
-from tests.common import oracle_ground, oracle_potential, rel_l2
+from tests.common import e_half, oracle_ground, oracle_potential, pulse_table, rel_l2
 
 GAMMA = 0.5
 
@@ -37,7 +37,7 @@ def test_volkov_and_oscillator_agree_to_rounding():
     square root goes through the contract's rsqrt in one build and sqrt and / in the other)."""
     pulse = I.Pulse(800.0, 1e14, 2.0)
     grid = I.time_grid(pulse, 0.05)
-    e = I.field_table(pulse, grid)
+    e = pulse_table(pulse, grid)
     q0, p0 = np.array([0.3, -0.2, 0.5]), np.array([0.1, 0.2, -0.3])
     g = oracle_ground(I.gto_h1s())
     a, b = _both(O.trajectory, pot=O.Potential("none"), ground=g, e_half=e, t_a=grid.t_a,
@@ -72,7 +72,7 @@ def test_kepler_orbit_agrees_to_rounding():
 
 
 def _run(inst, kay, cr):
-    return O.propagate(oracle_potential(inst.potential), oracle_ground(inst.ground), inst.e_half,
+    return O.propagate(oracle_potential(inst.potential), oracle_ground(inst.ground), e_half(inst),
                        inst.grid.t_a, inst.grid.h, inst.grid.n_steps, inst.t0, inst.q0, inst.p0,
                        inst.w, inst.gamma, kay, inst.overlap_cut, velocity=True,
                        correctly_rounded=cr)

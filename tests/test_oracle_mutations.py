@@ -25,6 +25,9 @@ MUTANTS = {
                                     "double inv4g = 1.0 / (2.0 * gamma);"),
     "gamma dq/dp0 term doubled": ("-(gamma * M_QP(m, i, k))", "-(2.0 * gamma * M_QP(m, i, k))"),
     "Hessian force sign": ("kP[i] = -t;", "kP[i] = t;"),
+    "field table: sign of the envelope term": ("e_half[m] = a - b;", "e_half[m] = a + b;"),
+    "field table: envelope frequency doubled": ("traj_sincos((M_PI * t) / T, &s1, &c1);",
+                                                "traj_sincos((2.0 * M_PI * t) / T, &s1, &c1);"),
     "field dropped from the action": ("L = fma(-q[2], E, L);", "L = L;"),
     "field force sign": ("k[5] = -fma(g, q[2], E);", "k[5] = -fma(g, q[2], -E);"),
     "RK4 weight of k3": ("acc = fma(2.0, k3[i], acc);", "acc = acc + k3[i];"),

@@ -14,6 +14,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2601_17164_amd import inputs as I
+from tests.common import e_half, pulse_table
 
 GAMMA = 0.5
 
@@ -102,16 +103,31 @@ def test_field_closed_forms():
         assert abs(O.field_intA(tt, e0, w, T)[0] - quad) < 1e-12 * e0 / w * T
 
 
-def test_field_table_matches_oracle_field():
-    inst = I.config0()
-    g = inst.grid
+@pytest.mark.parametrize("which", ["config0", "config1", "cep"])
+def test_field_table_matches_oracle_field(which):
+    """The field table in the library's fixed sequence (the oracle's copy of that sequence) is the
+    pulse's field E = -dA/dt at the half steps, within 2e-15 e0, and zero outside the pulse."""
+    if which == "config1":
+        inst = I.config1(4, 4)
+    else:
+        inst = I.config0()
+    p, g = inst.pulse, inst.grid
+    if which == "cep":
+        p = I.Pulse(p.wavelength_nm, p.intensity_wcm2, p.n_cycles, cep=1.1)
     m = np.arange(2 * g.n_steps + 1)
     t = g.t_a + m * (0.5 * g.h)
-    p = inst.pulse
-    ref = O.field_E(t, p.e0, p.omega, p.duration)
-    assert np.max(np.abs(inst.e_half - ref)) < 1e-15
+    ref = O.field_E(t, p.e0, p.omega, p.duration, p.cep)
+    e = pulse_table(p, g)
+    assert np.max(np.abs(e - ref)) < 2e-15 * p.e0
+    # outside the pulse the table holds zeros (a grid reaching past its end)
+    wide = I.Grid(-0.75 * p.duration, g.h, int(np.ceil(1.5 * p.duration / g.h)))
+    ew = pulse_table(p, wide)
+    tw = wide.t_a + 0.5 * wide.h * np.arange(ew.size)
+    assert np.all(ew[np.abs(tw) > 0.5 * p.duration] == 0.0)
+    assert np.max(np.abs(ew - O.field_E(tw, p.e0, p.omega, p.duration, p.cep))) < 2e-15 * p.e0
+    if which == "cep":
+        return
     # the field integrates to zero over the pulse (A(t_a) = A(t_b) = 0): Simpson on the table
-    e = inst.e_half
     simpson = (g.h / 6.0) * np.sum(e[0:-1:2] + 4 * e[1::2] + e[2::2])
     assert abs(simpson) < 1e-8
 
@@ -225,7 +241,7 @@ def test_volkov_motion_and_prefactor():
     [0, I]], C = (1 - i gamma tau)^{3/2} continued through the branch cut at gamma tau = sqrt 3."""
     pulse = I.Pulse(800.0, 1e14, 2.0)
     grid = I.time_grid(pulse, 0.05)
-    e = I.field_table(pulse, grid)
+    e = pulse_table(pulse, grid)
     T, w, e0 = pulse.duration, pulse.omega, pulse.e0
     q0 = np.array([0.3, -0.2, 0.5])
     p0 = np.array([0.1, 0.2, -0.3])
@@ -347,7 +363,7 @@ def test_kepler_invariants():
 def test_lz_conserved_with_field():
     inst = I.config0()
     g = inst.grid
-    rec = O.trajectory(_pot(I.SOFTCORE_H), _ground(inst.ground), inst.e_half, g.t_a, g.h,
+    rec = O.trajectory(_pot(I.SOFTCORE_H), _ground(inst.ground), e_half(inst), g.t_a, g.h,
                        g.n_steps, g.t_a, np.array([20.0, 15.0, 10.0]), np.array([0.3, -0.2, 0.1]),
                        gamma=GAMMA)
     y = rec.y[rec.alive]
@@ -361,7 +377,7 @@ def test_lz_conserved_with_field():
 def test_monodromy_vs_finite_differences_and_symplectic():
     inst = I.config0()
     g = inst.grid
-    e = inst.e_half
+    e = e_half(inst)
     t0 = g.t_a + 400 * g.h
     z0 = np.array([5.0, 3.0, 8.0, 0.1, -0.2, 0.3])
     nst = 900
@@ -551,7 +567,7 @@ def _small_c0(nb=8, ns=4):
 
 def _run(inst, **kw):
     g = inst.grid
-    return O.propagate(_pot(inst.potential), _ground(inst.ground), inst.e_half, g.t_a, g.h,
+    return O.propagate(_pot(inst.potential), _ground(inst.ground), e_half(inst), g.t_a, g.h,
                        g.n_steps, inst.t0, inst.q0, inst.p0, w=kw.pop("w", inst.w),
                        gamma=inst.gamma, kay_max=kw.pop("kay_max", inst.kay_max), **kw)
 
@@ -608,7 +624,7 @@ def test_kay_removal_is_on_the_modulus_of_C_squared():
     j = int(np.argmax(r.death >= 0))  # first removed trajectory
     assert r.death[j] >= 0
     for dt_kay in (1e30, 1e12):
-        rec = O.trajectory(_pot(inst.potential), _ground(inst.ground), inst.e_half, g.t_a, g.h,
+        rec = O.trajectory(_pot(inst.potential), _ground(inst.ground), e_half(inst), g.t_a, g.h,
                            g.n_steps, inst.t0[j], inst.q0[:, j], inst.p0[:, j], gamma=GAMMA,
                            kay_max=dt_kay)
         n0 = int(np.argmax(rec.alive))
@@ -715,7 +731,7 @@ def test_partial_wave_masks_partition_the_dipole():
     base = dict(pot=_pot(inst.potential), G=_ground(inst.ground))
 
     def run(mask):
-        return O.propagate(base["pot"], base["G"], inst.e_half, inst.grid.t_a, inst.grid.h,
+        return O.propagate(base["pot"], base["G"], e_half(inst), inst.grid.t_a, inst.grid.h,
                            inst.grid.n_steps, inst.t0, inst.q0, inst.p0, pw_mask=mask,
                            pw_radius=3.0, n_threads=1).F
     full = run(0)
@@ -734,7 +750,7 @@ def test_partial_wave_decisions_from_the_recorded_path():
     G, pot = _ground(inst.ground), _pot(inst.potential)
     checked = 0
     for j in range(inst.n_traj):
-        args = (pot, G, inst.e_half, inst.grid.t_a, inst.grid.h, inst.grid.n_steps, inst.t0[j],
+        args = (pot, G, e_half(inst), inst.grid.t_a, inst.grid.h, inst.grid.n_steps, inst.t0[j],
                 inst.q0[:, j], inst.p0[:, j])
         rec = O.trajectory(*args, overlap_cut=1e9)
         filt = O.trajectory(*args, overlap_cut=1e9, pw_mask=PW_P, pw_radius=3.0)
