@@ -19,6 +19,7 @@
 #include "sfhk_io_kernels.hpp"
 #include "sfhk_sfa_kernels.hpp"
 #include "sfhk_gabor_kernels.hpp"
+#include "sfhk_host.hpp"
 
 namespace {
 
@@ -201,9 +202,7 @@ sfhk_status launch_propagate(int precision, int kind, const JobDev* descs, const
 
 // a job listed twice would have its tiles queued twice: two workgroups racing on one tile's state
 bool has_duplicates(sfhk_job* const* jobs, int n_jobs) {
-  std::vector<const sfhk_job*> v(jobs, jobs + n_jobs);
-  std::sort(v.begin(), v.end());
-  return std::adjacent_find(v.begin(), v.end()) != v.end();
+  return sfhk_host::has_duplicates((const void* const*)jobs, n_jobs);
 }
 
 int segment_of(int precision, int kind) { return (precision == SFHK_FP32_MIXED ? kKinds : 0) + kind; }
@@ -245,18 +244,9 @@ sfhk_status launch_compact(sfhk_job* job, int n_items, int max_steps, hipStream_
 
 namespace {
 
-constexpr uint64_t kCkptMagic = 0x54504b434b484653ull;  // "SFHKCKPT"
-constexpr size_t kCkptAlign = 256;
-
-struct CkptHeader {
-  uint64_t magic;
-  int64_t n_traj, n_pad, n_tiles, n_steps, acc_words, steps_done;
-  int32_t kind, precision, done, reserved;
-  uint64_t fingerprint;  // of the job's potential, ground state, grid and method parameters
-};
-static_assert(sizeof(CkptHeader) <= kCkptAlign, "checkpoint header");
-
-size_t ckpt_round(size_t b) { return (b + kCkptAlign - 1) / kCkptAlign * kCkptAlign; }
+using sfhk_host::CkptHeader;
+using sfhk_host::kCkptAlign;
+using sfhk_host::kCkptMagic;
 
 // (device pointer of the job, bytes) of every section after the header, in checkpoint order
 std::vector<std::pair<void*, size_t>> ckpt_sections(sfhk_job* j) {
@@ -279,10 +269,35 @@ std::vector<std::pair<void*, size_t>> ckpt_sections(sfhk_job* j) {
   return v;
 }
 
+// offsets of the sections in a checkpoint; returns its size
+size_t ckpt_offsets(sfhk_job* j, std::vector<std::pair<void*, size_t>>& secs, std::vector<size_t>& off) {
+  secs = ckpt_sections(j);
+  std::vector<size_t> bytes(secs.size());
+  for (size_t i = 0; i < secs.size(); ++i) bytes[i] = secs[i].second;
+  return sfhk_host::ckpt_layout(bytes, off);
+}
+
 size_t ckpt_bytes(sfhk_job* j) {
-  size_t b = kCkptAlign;
-  for (const auto& sec : ckpt_sections(j)) b += ckpt_round(sec.second);
-  return b;
+  std::vector<std::pair<void*, size_t>> secs;
+  std::vector<size_t> off;
+  return ckpt_offsets(j, secs, off);
+}
+
+// the header a checkpoint of this job carries
+CkptHeader ckpt_header(const sfhk_job* job) {
+  CkptHeader h{};
+  h.magic = kCkptMagic;
+  h.n_traj = job->n_traj;
+  h.n_pad = job->host.n_pad;
+  h.n_tiles = job->host.n_tiles;
+  h.n_steps = job->host.n_steps;
+  h.acc_words = job->acc_words;
+  h.steps_done = job->steps_done;
+  h.kind = job->kind;
+  h.precision = job->precision;
+  h.done = job->done ? 1 : 0;
+  h.fingerprint = job->fingerprint;
+  return h;
 }
 
 }  // namespace
@@ -466,20 +481,12 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
     std::vector<int> n0h(N);
     TRY_C(hipMemcpyAsync(n0h.data(), H.n0, N * sizeof(int), hipMemcpyDeviceToHost, st));
     TRY_C(hipStreamSynchronize(st));
-    std::vector<long long> next(NS + 2, 0);
-    for (long long i = 0; i < N; ++i) ++next[n0h[i] + 1];
-    for (int k = 0; k <= NS; ++k) next[k + 1] += next[k];
-    perm.assign(n_pad, -1);
-    for (long long i = 0; i < N; ++i) perm[next[n0h[i]]++] = i;
-    n0s.assign(n_pad, NS + 1);
-    for (long long s = 0; s < N; ++s) n0s[s] = n0h[perm[s]];
-    for (int t = 0; t < n_tiles; ++t) tile_n0[t] = n0s[(long long)t * kTile];
+    if (!sfhk_host::birth_sort(n0h.data(), N, NS, n_pad, perm, n0s))
+      return cleanup(fail(SFHK_E_DEVICE, "birth steps out of range"));
+    sfhk_host::tile_first_steps(n0s, kTile, tile_n0);
   }
-  std::vector<int> tile_next(n_tiles), tile_last(n_tiles);
-  for (int t = 0; t < n_tiles; ++t) {
-    tile_next[t] = tile_n0[t];
-    tile_last[t] = tile_n0[t] - 1;
-  }
+  std::vector<int> tile_next, tile_last;
+  sfhk_host::tile_progress(tile_n0, tile_next, tile_last);
   const long long acc_words = accumulator_words(NS, params->velocity != 0);
   const size_t need = footprint_bytes(N, NS, params->velocity != 0);
   bool over = false;
@@ -685,15 +692,16 @@ void sfhk_job_destroy(sfhk_job* job) {
 
 // number of tiles that still have steps left after `done` steps have been requested
 static int unfinished_tiles(const sfhk_job* j, long long done) {
-  const int NS = j->host.n_steps;
-  // tiles are sorted by birth step ascending: a tile with birth a is finished once a + done > NS
-  const std::vector<int>& a = j->tile_n0_host;
-  int lo = 0, hi = (int)a.size();
-  while (lo < hi) {
-    int mid = (lo + hi) / 2;
-    if ((long long)a[mid] + done <= NS) lo = mid + 1; else hi = mid;
-  }
-  return lo;
+  return sfhk_host::unfinished_tiles(j->tile_n0_host, j->host.n_steps, done);
+}
+
+// the longest-first work list over the unfinished tiles of the jobs, grouped by kernel segment
+static std::vector<sfhk_host::Item> work_items(sfhk_job* const* jobs, int n_jobs) {
+  std::vector<sfhk_host::JobProgress> jp((size_t)n_jobs);
+  for (int i = 0; i < n_jobs; ++i)
+    jp[(size_t)i] = {&jobs[i]->tile_n0_host, jobs[i]->host.n_steps, jobs[i]->steps_done,
+                     jobs[i]->done, segment_of(jobs[i]->precision, jobs[i]->kind)};
+  return sfhk_host::work_items(jp);
 }
 
 sfhk_status sfhk_propagate(sfhk_job* job, int64_t max_steps, void* stream) {
@@ -732,25 +740,9 @@ sfhk_status sfhk_propagate_many(sfhk_job* const* jobs, int32_t n_jobs, int64_t m
     if (jobs[i]->cq) return fail(SFHK_E_INVALID, "a job created with compact_every runs through sfhk_propagate only");
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
-  // one launch over the unfinished tiles of every job, ordered by steps left (longest first)
-  struct Item {
-    long long left;
-    int job, tile, seg;
-  };
-  std::vector<Item> items;
-  for (int i = 0; i < n_jobs; ++i) {
-    sfhk_job* j = jobs[i];
-    if (j->done) continue;
-    const int NS = j->host.n_steps;
-    const int nt = unfinished_tiles(j, j->steps_done);
-    for (int t = 0; t < nt; ++t)
-      items.push_back({NS + 1 - (j->tile_n0_host[t] + j->steps_done), i, t,
-                       segment_of(j->precision, j->kind)});
-  }
-  // one launch per (precision, potential kind) kernel, each ordered longest first
-  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
-    return a.seg != b.seg ? a.seg < b.seg : a.left > b.left;
-  });
+  // one launch per (precision, potential kind) kernel over the unfinished tiles of every job,
+  // each ordered by steps left (longest first)
+  const std::vector<sfhk_host::Item> items = work_items(jobs, n_jobs);
   if (!items.empty()) {
     HIP_TRY(hipStreamSynchronize(st));  // the staging buffers of the previous call are free
     if (ctx->many_desc_cap < (size_t)n_jobs) {
@@ -914,31 +906,14 @@ sfhk_status sfhk_batch_set_jobs(sfhk_batch* b, sfhk_job* const* jobs, int32_t n_
     if (jobs[i]->cq) return fail(SFHK_E_INVALID, "a job created with compact_every runs through sfhk_propagate only");
   HIP_TRY(hipSetDevice(b->ctx->device));
   hipStream_t st = (hipStream_t)stream;
-  struct Item {
-    long long left;
-    int job, tile, seg;
-  };
-  std::vector<Item> items;
-  for (int i = 0; i < n_jobs; ++i) {
-    sfhk_job* j = jobs[i];
-    if (j->done) continue;
-    const int NS = j->host.n_steps;
-    const int nt = unfinished_tiles(j, j->steps_done);
-    for (int t = 0; t < nt; ++t)
-      items.push_back({NS + 1 - (j->tile_n0_host[t] + j->steps_done), i, t,
-                       segment_of(j->precision, j->kind)});
-  }
+  const std::vector<sfhk_host::Item> items = work_items(jobs, n_jobs);
   if ((long long)items.size() > b->max_items) return fail(SFHK_E_INVALID, "more unfinished tiles than the batch was created for");
-  std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) {
-    return x.seg != y.seg ? x.seg < y.seg : x.left > y.left;
-  });
   // the other staging set than the latest one; its copies were followed by a replay (or by
   // nothing) recorded in done[s]
   const int s = b->cur ^ 1;
   if (b->done_recorded[s]) HIP_TRY(hipEventSynchronize(b->done[s]));
   BatchDev bd{};
-  for (const Item& it : items) bd.n_items[it.seg]++;
-  for (int g = 1; g < kSegs; ++g) bd.offset[g] = bd.offset[g - 1] + bd.n_items[g - 1];
+  sfhk_host::segment_table(items, kSegs, bd.n_items, bd.offset);
   for (int i = 0; i < n_jobs; ++i) b->desc_host[s][i] = jobs[i]->host;
   for (size_t k = 0; k < items.size(); ++k) b->work_host[s][k] = {items[k].job, items[k].tile};
   *b->bdev_host[s] = bd;
@@ -1017,26 +992,11 @@ namespace {
 // The spectrum's working memory for n samples zero-padded to n_fft: windowed samples xw[n_fft],
 // twiddles tw[n_fft], and one row of partial sums per span of samples, part[n_spans][n_fft/2+1].
 // Spans are whole chunks of kDftChunk samples, at most kDftMaxSpans of them.
-struct SpectrumPlan {
-  long long nk, span;
-  int n_spans;
-  size_t xw_off, tw_off, part_off, bytes;  // offsets into one workspace, 256-byte aligned
-};
-
-size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+using sfhk_host::SpectrumPlan;
+static_assert(sizeof(double2) == 2 * sizeof(double), "complex layout of the workspace");
 
 SpectrumPlan spectrum_plan(long long n, long long n_fft) {
-  SpectrumPlan P{};
-  P.nk = n_fft / 2 + 1;
-  const long long chunks = (n + kDftChunk - 1) / kDftChunk;
-  const long long per = (chunks + kDftMaxSpans - 1) / kDftMaxSpans;
-  P.span = per * kDftChunk;
-  P.n_spans = (int)((n + P.span - 1) / P.span);
-  P.xw_off = 0;
-  P.tw_off = align256((size_t)n_fft * sizeof(double));
-  P.part_off = P.tw_off + align256((size_t)n_fft * sizeof(double2));
-  P.bytes = P.part_off + align256((size_t)P.n_spans * P.nk * sizeof(double2));
-  return P;
+  return sfhk_host::spectrum_plan(n, n_fft, kDftChunk, kDftMaxSpans);
 }
 
 sfhk_status spectrum_check(const double* d, int64_t n, int64_t n_fft, double dt, double tau_h) {
@@ -1178,25 +1138,14 @@ sfhk_status sfhk_job_checkpoint(sfhk_job* job, void* dst, void* stream) {
   if (!job || !dst) return fail(SFHK_E_INVALID, "NULL argument");
   HIP_TRY(hipSetDevice(job->ctx->device));
   hipStream_t st = (hipStream_t)stream;
-  CkptHeader h{};
-  h.magic = kCkptMagic;
-  h.n_traj = job->n_traj;
-  h.n_pad = job->host.n_pad;
-  h.n_tiles = job->host.n_tiles;
-  h.n_steps = job->host.n_steps;
-  h.acc_words = job->acc_words;
-  h.steps_done = job->steps_done;
-  h.kind = job->kind;
-  h.precision = job->precision;
-  h.done = job->done ? 1 : 0;
-  h.fingerprint = job->fingerprint;
+  const CkptHeader h = ckpt_header(job);
   char* out = (char*)dst;
   HIP_TRY(hipMemcpyAsync(out, &h, sizeof(h), hipMemcpyHostToDevice, st));
-  size_t off = kCkptAlign;
-  for (const auto& sec : ckpt_sections(job)) {
-    HIP_TRY(hipMemcpyAsync(out + off, sec.first, sec.second, hipMemcpyDeviceToDevice, st));
-    off += ckpt_round(sec.second);
-  }
+  std::vector<std::pair<void*, size_t>> secs;
+  std::vector<size_t> off;
+  ckpt_offsets(job, secs, off);
+  for (size_t i = 0; i < secs.size(); ++i)
+    HIP_TRY(hipMemcpyAsync(out + off[i], secs[i].first, secs[i].second, hipMemcpyDeviceToDevice, st));
   sfhk_status rc = mark_use(job, st);
   if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(st));  // the header above lives on this call's stack
@@ -1212,16 +1161,13 @@ sfhk_status sfhk_job_restore(sfhk_job* job, const void* src, void* stream) {
   const char* in = (const char*)src;
   HIP_TRY(hipMemcpyAsync(&h, in, sizeof(h), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  if (h.magic != kCkptMagic || h.n_traj != job->n_traj || h.n_pad != job->host.n_pad ||
-      h.n_tiles != job->host.n_tiles || h.n_steps != job->host.n_steps ||
-      h.acc_words != job->acc_words || h.kind != job->kind || h.precision != job->precision ||
-      h.fingerprint != job->fingerprint || h.steps_done < 0)
+  if (!sfhk_host::ckpt_matches(h, ckpt_header(job)))
     return fail(SFHK_E_INVALID, "checkpoint does not match this job (other inputs or not a checkpoint)");
-  size_t off = kCkptAlign;
-  for (const auto& sec : ckpt_sections(job)) {
-    HIP_TRY(hipMemcpyAsync(sec.first, in + off, sec.second, hipMemcpyDeviceToDevice, st));
-    off += ckpt_round(sec.second);
-  }
+  std::vector<std::pair<void*, size_t>> secs;
+  std::vector<size_t> off;
+  ckpt_offsets(job, secs, off);
+  for (size_t i = 0; i < secs.size(); ++i)
+    HIP_TRY(hipMemcpyAsync(secs[i].first, in + off[i], secs[i].second, hipMemcpyDeviceToDevice, st));
   sfhk_status rc = mark_use(job, st);
   if (rc) return rc;
   job->steps_done = h.steps_done;
