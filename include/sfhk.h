@@ -111,17 +111,19 @@ typedef struct {
  *                l^2 = fma(L_z, L_z, fma(L_y, L_y, L_x L_x)), L_x = fma(q_y, p_z, -(q_z p_y)) and
  *                cyclic, with pw_radius^2 and the squared band edges.
  *   pw_radius    radius of the filter's near-core region (> 0 when pw_mask != 0)
- *   compact_every  must be 0: regrouping is switched off in this build (SFHK_E_INVALID otherwise;
- *                its launch did not finish on the GPU and the cause is not yet found). As designed,
- *                E >= 16: sfhk_propagate (FP64 jobs) regroups live trajectories at every
- *                step k E: the tiles of one birth step (up to 16 tiles of 64 trajectories) stop
- *                there, and the last to arrive moves the trajectories not removed by the Kay test
- *                into the group's first tiles, so tiles emptied by removals stop costing work.
- *                Trajectories are unchanged bit for bit; which ones share a tile depends only on
- *                the removal steps, so results are bitwise reproducible (chunked or not), and they
- *                differ from compact_every = 0 only in the order the dipole's terms are summed
- *                within a tile before the exact per-step sum. Mixed-precision jobs, and jobs
- *                propagated by sfhk_propagate_many or in a batch, run without regrouping. */
+ *   compact_every  0 (no regrouping) or E in [16, 2^24], FP64 jobs only (SFHK_E_INVALID
+ *                otherwise): sfhk_propagate runs the job's tiles four at a time, and at every step
+ *                k E the four tiles of one first birth step move the trajectories not removed by
+ *                the Kay test (Sec. III.A) into their first tiles, so that tiles emptied by
+ *                removals stop costing work. Trajectories are unchanged bit for bit; which ones
+ *                share a tile depends only on the removal steps, so results are bitwise
+ *                reproducible (chunked or not, checkpointed or not), and they differ from
+ *                compact_every = 0 only in how the dipole's terms are grouped within a tile before
+ *                the exact per-step sum (rounding level). Such jobs run through sfhk_propagate
+ *                only (sfhk_propagate_many and batches refuse them). The four-wave workgroups cost
+ *                about 8% by themselves, so regrouping pays only when many trajectories are
+ *                removed (measured on a soft-core hydrogen workload: 22% faster with 86% removed,
+ *                16% slower with 28% removed). */
 typedef struct {
   double gamma;
   double kay_max;
@@ -148,8 +150,7 @@ typedef struct {
                                 skipped by overlap_cut) */
   int64_t integrands_evaluated; /* (trajectory, t_n) pairs whose dipole integrand was evaluated
                                    (not every primitive skipped) */
-  int64_t scheduler_errors;  /* compact_every > 0: waits of the regrouping scheduler that ran out
-                                (0 unless the device stalled; the job's results are then incomplete) */
+  int64_t reserved;          /* 0 */
 } sfhk_stats;
 
 typedef struct sfhk_ctx sfhk_ctx;

@@ -88,9 +88,7 @@ struct sfhk_job {
   long long acc_words = 0;     // 64-bit words of the exact accumulators (dipole and velocity)
   uint64_t fingerprint = 0;    // of the inputs that define the propagation (checkpoint matching)
   bool done = false;
-  // regrouping of live trajectories (compact_every > 0)
-  int n_groups = 0;
-  CompactHdr* cq = nullptr;    // the persistent launch's queue of regrouped tiles
+  bool regroup = false;  // live trajectories regrouped every compact_every steps (k_propagate_rg)
 };
 
 struct sfhk_batch {
@@ -133,7 +131,6 @@ size_t footprint_bytes(long long n_traj, long long n_steps, int velocity) {
   size_t b = 0;
   b += (size_t)n_pad * kNY * 8 + (size_t)n_pad * 5 * 8 + (size_t)n_pad * 8 * 2;  // y, aux, n0+death, perm
   b += (size_t)n_tiles * (4 * 3 + sizeof(WorkItem));                             // tile arrays, work list
-  b += (size_t)n_tiles * (4 * 4 + 12) + sizeof(CompactHdr);  // regrouping: groups, queue (if used)
   b += (size_t)accumulator_words(n_steps, velocity) * 8;
   b += (size_t)(2 * n_steps + 1) * 8;  // field table
   b += (size_t)(n_steps + 1) * 8;      // dipole on the step grid
@@ -207,35 +204,18 @@ bool has_duplicates(sfhk_job* const* jobs, int n_jobs) {
 
 int segment_of(int precision, int kind) { return (precision == SFHK_FP32_MIXED ? kKinds : 0) + kind; }
 
-// The persistent, regrouping launch of one FP64 job: as many single-wave workgroups as can be
-// resident at once (never more than the tiles), after a kernel that resets the job's queue.
-sfhk_status launch_compact(sfhk_job* job, int n_items, int max_steps, hipStream_t st) {
-  const int kind = job->kind;
-  const void* fn = nullptr;
-  switch (kind) {
-    case SFHK_POT_SOFTCORE: fn = (const void*)k_propagate_compact<POT_SOFTCORE>; break;
-    case SFHK_POT_SCREENED: fn = (const void*)k_propagate_compact<POT_SCREENED>; break;
-    case SFHK_POT_HARMONIC: fn = (const void*)k_propagate_compact<POT_HARMONIC>; break;
-    default: fn = (const void*)k_propagate_compact<POT_NONE>; break;
+// the regrouping launch of one FP64 job: one workgroup of kRgWaves waves per kRgWaves work items
+sfhk_status launch_regroup(sfhk_job* job, int n_items, int max_steps, hipStream_t st) {
+  if (n_items <= 0) return SFHK_OK;
+  const dim3 g(blocks_for(n_items, kRgWaves)), b(kRgWaves * kTile);
+  const JobDev* D = job->dev;
+  const WorkItem* W = job->work;
+  switch (job->kind) {
+    case SFHK_POT_SOFTCORE: hipLaunchKernelGGL(k_propagate_rg<POT_SOFTCORE>, g, b, 0, st, D, W, n_items, max_steps); break;
+    case SFHK_POT_SCREENED: hipLaunchKernelGGL(k_propagate_rg<POT_SCREENED>, g, b, 0, st, D, W, n_items, max_steps); break;
+    case SFHK_POT_HARMONIC: hipLaunchKernelGGL(k_propagate_rg<POT_HARMONIC>, g, b, 0, st, D, W, n_items, max_steps); break;
+    default: hipLaunchKernelGGL(k_propagate_rg<POT_NONE>, g, b, 0, st, D, W, n_items, max_steps); break;
   }
-  int per_cu = 0, cus = 0;
-  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kTile, 0));
-  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, job->ctx->device));
-  const int workers = std::max(1, std::min(n_items, std::max(1, per_cu) * cus));
-  hipLaunchKernelGGL(k_compact_reset, dim3(blocks_for(job->host.n_tiles, 256)), dim3(256), 0, st,
-                     job->cq, job->host.n_tiles);
-  HIP_TRY(hipGetLastError());
-#define SFHK_LAUNCH_C(K)                                                                            \
-  hipLaunchKernelGGL(k_propagate_compact<K>, dim3(workers), dim3(kTile), 0, st,                    \
-                     (const JobDev*)job->dev, (const WorkItem*)job->work, n_items, job->cq,        \
-                     max_steps);
-  switch (kind) {
-    case SFHK_POT_SOFTCORE: SFHK_LAUNCH_C(POT_SOFTCORE) break;
-    case SFHK_POT_SCREENED: SFHK_LAUNCH_C(POT_SCREENED) break;
-    case SFHK_POT_HARMONIC: SFHK_LAUNCH_C(POT_HARMONIC) break;
-    default: SFHK_LAUNCH_C(POT_NONE) break;
-  }
-#undef SFHK_LAUNCH_C
   HIP_TRY(hipGetLastError());
   return SFHK_OK;
 }
@@ -259,12 +239,9 @@ std::vector<std::pair<void*, size_t>> ckpt_sections(sfhk_job* j) {
                                               {H.tile_last, nt * sizeof(int)},
                                               {H.counters, 8 * sizeof(unsigned long long)},
                                               {H.acc, (size_t)j->acc_words * sizeof(long long)}};
-  if (j->cq) {  // regrouping moves trajectories between slots and tiles
-    const size_t ng = (size_t)std::max(1, j->n_groups);
+  if (j->regroup) {  // regrouping moves trajectories between slots and tiles
     v.push_back({H.n0, np * sizeof(int)});
     v.push_back({H.perm, np * sizeof(long long)});
-    v.push_back({H.grp_active, ng * sizeof(int)});
-    v.push_back({H.grp_pending, ng * sizeof(int)});
   }
   return v;
 }
@@ -411,10 +388,8 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
     return fail(SFHK_E_INVALID, "pw_radius must be finite and > 0");
   if (params->compact_every != 0 && (params->compact_every < 16 || params->compact_every > (1 << 24)))
     return fail(SFHK_E_INVALID, "compact_every must be 0 or in [16, 2^24]");
-  // The regrouping launch (k_propagate_compact) did not finish on the GPU in its first two runs and
-  // the cause has not been found, so it stays switched off: any compact_every > 0 is refused.
-  if (params->compact_every != 0)
-    return fail(SFHK_E_INVALID, "compact_every: regrouping of live trajectories is switched off in this build");
+  if (params->compact_every != 0 && params->precision != SFHK_FP64)
+    return fail(SFHK_E_INVALID, "compact_every: regrouping runs in the FP64 form only");
   for (int j = 0; j < ground->n_prim; ++j)
     if (!(ground->alpha[j] > 0.0)) return fail(SFHK_E_INVALID, "GTO exponents must be > 0");
 
@@ -589,38 +564,11 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
       (rc = job_alloc(j, &H.counters, 8, st)) || (rc = job_alloc(j, &j->work, (size_t)n_tiles, st)) ||
       (rc = job_alloc(j, &j->dbuf, (size_t)NS + 1, st)) || (rc = job_alloc(j, &j->dev, 1, st)))
     return cleanup(rc);
-  // regrouping: groups of up to kCompactTiles consecutive tiles with one first birth step
-  const bool compact = params->compact_every > 0;
-  std::vector<int> grp_of_tile, grp_first, grp_size;
-  if (compact) {
-    grp_of_tile.assign(n_tiles, -1);
-    for (int t = 0; t < n_tiles;) {
-      int e = t + 1;
-      while (e < n_tiles && e - t < kCompactTiles && tile_n0[e] == tile_n0[t]) ++e;
-      if (e - t >= 2) {
-        for (int u = t; u < e; ++u) grp_of_tile[u] = (int)grp_first.size();
-        grp_first.push_back(t);
-        grp_size.push_back(e - t);
-      }
-      t = e;
-    }
-  }
-  const int n_groups = (int)grp_first.size();
-  if ((!in_order || compact) && (rc = job_alloc(j, &j->perm, (size_t)n_pad, st))) return cleanup(rc);
-  if (compact) {
-    const int ng = std::max(1, n_groups);
-    if ((rc = job_alloc(j, &H.grp_of_tile, (size_t)n_tiles, st)) ||
-        (rc = job_alloc(j, &H.grp_first, (size_t)ng, st)) || (rc = job_alloc(j, &H.grp_active, (size_t)ng, st)) ||
-        (rc = job_alloc(j, &H.grp_pending, (size_t)ng, st)))
-      return cleanup(rc);
-    char* qb = nullptr;
-    if ((rc = job_alloc(j, &qb, sizeof(CompactHdr) + (size_t)n_tiles * (sizeof(int2) + sizeof(unsigned int)), st)))
-      return cleanup(rc);
-    j->cq = (CompactHdr*)qb;
-  }
+  const bool regroup = params->compact_every > 0;
+  if ((!in_order || regroup) && (rc = job_alloc(j, &j->perm, (size_t)n_pad, st))) return cleanup(rc);
+  j->regroup = regroup;
   H.compact_every = params->compact_every;
   H.perm = j->perm;
-  j->n_groups = n_groups;
   H.e_half = e_half;
   H.acc_v = params->velocity ? H.acc + acc_words / 2 : nullptr;
   if (grid->e_half)
@@ -641,22 +589,13 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
         return cleanup(fail(SFHK_E_INVALID, "e_half differs from the pulse's field by more than 1e-9 e0"));
     }
   }
-  if (compact) {
-    TRY_C(hipMemcpyAsync(H.grp_of_tile, grp_of_tile.data(), n_tiles * sizeof(int), hipMemcpyHostToDevice, st));
-    if (n_groups) {
-      TRY_C(hipMemcpyAsync(H.grp_first, grp_first.data(), n_groups * sizeof(int), hipMemcpyHostToDevice, st));
-      TRY_C(hipMemcpyAsync(H.grp_active, grp_size.data(), n_groups * sizeof(int), hipMemcpyHostToDevice, st));
-      TRY_C(hipMemcpyAsync(H.grp_pending, grp_size.data(), n_groups * sizeof(int), hipMemcpyHostToDevice, st));
-    }
-    if (in_order) {  // slots hold the samples in caller order; regrouping moves them
-      perm.resize(n_pad);
-      for (long long i = 0; i < n_pad; ++i) perm[i] = i < N ? i : -1;
-    }
-    TRY_C(hipMemcpyAsync(j->perm, perm.data(), n_pad * sizeof(long long), hipMemcpyHostToDevice, st));
+  if (regroup && in_order) {  // slots hold the samples in caller order; regrouping moves them
+    perm.resize(n_pad);
+    for (long long i = 0; i < n_pad; ++i) perm[i] = i < N ? i : -1;
   }
+  if (regroup || !in_order)
+    TRY_C(hipMemcpyAsync(j->perm, perm.data(), n_pad * sizeof(long long), hipMemcpyHostToDevice, st));
   if (!in_order) {  // the sorted order replaces the caller order k_birth wrote
-    if (!compact)
-      TRY_C(hipMemcpyAsync(j->perm, perm.data(), n_pad * sizeof(long long), hipMemcpyHostToDevice, st));
     TRY_C(hipMemcpyAsync(H.n0, n0s.data(), n_pad * sizeof(int), hipMemcpyHostToDevice, st));
     TRY_C(hipMemcpyAsync(H.tile_n0, tile_n0.data(), n_tiles * sizeof(int), hipMemcpyHostToDevice, st));
   }
@@ -714,8 +653,8 @@ sfhk_status sfhk_propagate(sfhk_job* job, int64_t max_steps, void* stream) {
   const int nt = unfinished_tiles(job, job->steps_done);
   if (nt > 0) {
     int ms = (max_steps <= 0 || max_steps > NS + 1) ? 0 : (int)max_steps;
-    sfhk_status rc = (job->cq && job->precision == SFHK_FP64)
-                         ? launch_compact(job, nt, ms, st)
+    sfhk_status rc = job->regroup
+                         ? launch_regroup(job, nt, ms, st)
                          : launch_propagate(job->precision, job->kind, job->dev, job->work, nt, ms, st);
     if (rc) return rc;
     if ((rc = mark_use(job, st))) return rc;
@@ -737,7 +676,7 @@ sfhk_status sfhk_propagate_many(sfhk_job* const* jobs, int32_t n_jobs, int64_t m
     if (!jobs[i] || jobs[i]->ctx != ctx) return fail(SFHK_E_INVALID, "jobs must be non-NULL and share one context");
   if (has_duplicates(jobs, n_jobs)) return fail(SFHK_E_INVALID, "a job is listed more than once");
   for (int i = 0; i < n_jobs; ++i)
-    if (jobs[i]->cq) return fail(SFHK_E_INVALID, "a job created with compact_every runs through sfhk_propagate only");
+    if (jobs[i]->regroup) return fail(SFHK_E_INVALID, "a job created with compact_every runs through sfhk_propagate only");
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
   // one launch per (precision, potential kind) kernel over the unfinished tiles of every job,
@@ -903,7 +842,7 @@ sfhk_status sfhk_batch_set_jobs(sfhk_batch* b, sfhk_job* const* jobs, int32_t n_
     if (!jobs[i] || jobs[i]->ctx != b->ctx) return fail(SFHK_E_INVALID, "jobs must be non-NULL and share the batch's context");
   if (has_duplicates(jobs, n_jobs)) return fail(SFHK_E_INVALID, "a job is listed more than once");
   for (int i = 0; i < n_jobs; ++i)
-    if (jobs[i]->cq) return fail(SFHK_E_INVALID, "a job created with compact_every runs through sfhk_propagate only");
+    if (jobs[i]->regroup) return fail(SFHK_E_INVALID, "a job created with compact_every runs through sfhk_propagate only");
   HIP_TRY(hipSetDevice(b->ctx->device));
   hipStream_t st = (hipStream_t)stream;
   const std::vector<sfhk_host::Item> items = work_items(jobs, n_jobs);
@@ -1108,7 +1047,7 @@ sfhk_status sfhk_job_stats(sfhk_job* job, sfhk_stats* out, void* stream) {
   out->steps_fp64 = (int64_t)c[3];
   out->prims_evaluated = (int64_t)c[4];
   out->integrands_evaluated = (int64_t)c[5];
-  out->scheduler_errors = (int64_t)c[6];
+  out->reserved = 0;
   out->tiles_total = job->host.n_tiles;
   out->tiles_done = job->host.n_tiles - unfinished_tiles(job, job->steps_done);
   return SFHK_OK;

@@ -67,13 +67,9 @@ struct JobDev {
   int pw_mask;        // partial-wave filter (0: every step counts), see pw_keep
   double pw_r2;       // its radius, squared
   unsigned long long* counters;  // steps_evaluated, kay_removed, nonfinite_removed, steps_fp64,
-                                 // GTO primitives evaluated, integrands evaluated, scheduler errors
-  // compaction of live trajectories (compact_every > 0; see k_propagate_compact)
+                                 // GTO primitives evaluated, integrands evaluated
+  // regrouping of live trajectories (compact_every > 0; see k_propagate_rg)
   int compact_every;  // boundary interval in steps (0: off)
-  int* grp_of_tile;   // [n_tiles] compaction group of the tile, -1: none
-  int* grp_first;     // [n_groups] first tile of the group
-  int* grp_active;    // [n_groups] tiles first .. first + active - 1 may hold live trajectories
-  int* grp_pending;   // [n_groups] of those, tiles that have not reached the next boundary
   long long* perm;    // [n_pad] slot -> caller's trajectory index (-1: padding); nullptr: identity
 };
 
@@ -386,12 +382,29 @@ __device__ __forceinline__ QueueCtx queue_ctx(const JobDev& J) {
   return c;
 }
 
+// Orders a wave's accesses to its own LDS queue: the LDS requests of one wave complete in issue
+// order, so a wave needs no barrier with the other waves of its workgroup, only that neither the
+// compiler nor the wait counters move an access across this point. ONE_WAVE: the workgroup is this
+// wave, and the workgroup barrier serves.
+template <bool ONE_WAVE>
+__device__ __forceinline__ void queue_sync() {
+  if (ONE_WAVE) {
+    __syncthreads();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS accesses have completed
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 // evaluates the qn queued entries (one per lane) and adds their per-step sums to the job's
 // accumulators; returns this lane's count of evaluated primitives. A step's entries are
 // consecutive lanes (a run); the last lane of the run adds the run's sum.
+template <bool ONE_WAVE = true>
 __device__ __forceinline__ unsigned int queue_eval(IntegrandQueue& Q, int qn, int lane,
                                                    const QueueCtx& J) {
-  __syncthreads();
+  queue_sync<ONE_WAVE>();
   unsigned int n_eval = 0;
   Contrib cb = {0.0, 0.0, 0.0, 0.0, 0u};
   double ns = -1.0;
@@ -419,18 +432,133 @@ __device__ __forceinline__ unsigned int queue_eval(IntegrandQueue& Q, int qn, in
     const double vr = run_sum(cb.vre, lane, rs), vi = run_sum(cb.vim, lane, rs);
     if (last) acc_add_step(J.acc_v, (long long)ns, vr, vi);
   }
-  __syncthreads();
+  queue_sync<ONE_WAVE>();
   return n_eval;
+}
+
+// ------------------------------------------------------------------------------------------------
+// regrouping of live trajectories within a workgroup (FP64, one job)
+// ------------------------------------------------------------------------------------------------
+// Trajectories removed by the Kay test leave their lanes idle until the tile ends. A job created
+// with regroup_every = E > 0 runs its tiles kRgWaves at a time: one workgroup of kRgWaves waves
+// takes kRgWaves consecutive tiles that share their first birth step, the waves propagate their
+// tiles independently up to the next multiple of E, and there the workgroup moves the group's
+// live trajectories to the group's first slots (a stable partition: live slots in slot order,
+// then the removed ones) so that ceil(live / 64) tiles continue and the waves of the others end.
+// A trajectory's arithmetic does not depend on its lane, and the grouping after a boundary
+// depends only on the removal steps, so results are reproducible bit for bit and do not depend on
+// how propagation is split into launches (the boundaries are fixed steps of the grid). Only the
+// per-step sums of a wave's queued integrands change with the grouping, at rounding level. No
+// workgroup waits for another. Groups whose tiles do not share a first birth step run as
+// kRgWaves independent tiles.
+constexpr int kRgWaves = 4;
+
+// moves the records of the group's slots so that slot i receives the record of slot src[i]
+// (state, auxiliary values, birth and removal steps, caller index); every thread of the
+// workgroup takes one slot, rows in blocks of kRgRows between barriers so that every read of a
+// row precedes every write of it
+constexpr int kRgRows = 8;
+
+__device__ __forceinline__ void rg_move(const JobDev& J, long long base, int i, const int* src) {
+  const long long np = J.n_pad;
+  const long long from = base + src[i], to = base + i;
+  for (int r0 = 0; r0 < kNY; r0 += kRgRows) {
+    double v[kRgRows];
+#pragma unroll
+    for (int r = 0; r < kRgRows; ++r)
+      if (r0 + r < kNY) v[r] = J.y[(r0 + r) * np + from];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRgRows; ++r)
+      if (r0 + r < kNY) J.y[(r0 + r) * np + to] = v[r];
+  }
+  double a[5];
+#pragma unroll
+  for (int r = 0; r < 5; ++r) a[r] = J.aux[r * np + from];
+  const int n0 = J.n0[from], death = J.death[from];
+  const long long pm = J.perm[from];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 5; ++r) J.aux[r * np + to] = a[r];
+  J.n0[to] = n0;
+  J.death[to] = death;
+  J.perm[to] = pm;
+}
+
+// The boundary at step nb of the group whose first tile is t0, called by the nw waves still in the
+// workgroup (the tiles of the waves that have ended hold removed trajectories only) once every
+// tile's state is stored: regroups the live trajectories into the first tiles and sets the tiles'
+// progress. Returns the number of tiles that continue.
+__device__ int rg_boundary(const JobDev& J, int t0, int nb, int nw, int* src, int* cnt) {
+  const int i = threadIdx.x;
+  const int w = uniform_i32(i >> 6);
+  const long long base = (long long)t0 * kTile;
+  const bool live = J.death[base + i] == -1;  // not removed (or not yet born)
+  const unsigned long long m = __builtin_amdgcn_ballot_w64(live);
+  if ((i & (kTile - 1)) == 0) cnt[w] = __popcll(m);
+  __syncthreads();
+  int before = 0, L = 0;
+  for (int k = 0; k < nw; ++k) {
+    before += k < w ? cnt[k] : 0;
+    L += cnt[k];
+  }
+  const int live_before = before + lanes_below(m);
+  const int dest = live ? live_before : L + (i - live_before);
+  // whether any slot moves: per wave, then over the waves present (cnt[kRgWaves + k])
+  const bool mv = __builtin_amdgcn_ballot_w64(dest != i) != 0ull;
+  if ((i & (kTile - 1)) == 0) cnt[kRgWaves + w] = mv ? 1 : 0;
+  __syncthreads();
+  int moved = 0;
+  for (int k = 0; k < nw; ++k) moved |= cnt[kRgWaves + k];
+  if (moved) {
+    src[dest] = i;
+    __syncthreads();
+    rg_move(J, base, i, src);
+  }
+  const int keep = (L + kTile - 1) / kTile;
+  if ((i & (kTile - 1)) == 0) {
+    if (w < keep) {
+      J.tile_next[t0 + w] = nb;
+      J.tile_last[t0 + w] = nb - 1;
+    } else {
+      J.tile_next[t0 + w] = J.n_steps + 1;
+    }
+  }
+  __syncthreads();  // the moved records and the tiles' progress, before the next interval
+  return keep;
+}
+
+// Regrouping state of a wave of a k_propagate_rg workgroup (see there): the next boundary step
+// (INT_MAX: none), the interval, the group's first tile, the waves still in the workgroup, this
+// wave's index, and the workgroup's LDS for the boundary.
+struct RgWave {
+  int nb, E, t0, nw, w;
+  int* src;
+  int* cnt;
+};
+
+// A removed lane's steps from the interval that began at `first_step` (its steps evaluated in
+// [max(first_step, n0), removal step or last]) when it entered the interval as not removed.
+__device__ __forceinline__ int lane_evals(int death_in, int death, int n0l, int first_step,
+                                          int last) {
+  if (death_in != -1) return 0;
+  const int first = max(first_step, n0l);
+  const int lastn = death >= 0 ? death : last;
+  return max(0, lastn - first + 1);
 }
 
 // Propagates tile `tile` over steps n_begin..n_stop (n_begin <= n_stop <= n_steps; wave-uniform)
 // and stores its state; returns the tile's next step, n_steps + 1 once every lane is removed or the
 // grid's end is reached. KIND >= 0: the potential kind is a compile-time constant (its dispatch
-// folds away); -1: read from the job descriptor at run time
-template <int KIND>
+// folds away); -1: read from the job descriptor at run time. ONE_WAVE: the workgroup is this wave.
+// RG: the wave belongs to a regrouping workgroup (rg): at each boundary step inside the range the
+// workgroup regroups its trajectories and the lanes continue with the trajectories then in their
+// slots; returns -1 if the wave's tile was retired there (the wave must end).
+template <int KIND, bool ONE_WAVE = true, bool RG = false>
 __device__ __forceinline__ int run_tile_to(const JobDev& J, const int tile, const int n_begin,
-                                           const int n_stop, IntegrandQueue& Q) {
-  const int lane = threadIdx.x;
+                                           const int n_stop, IntegrandQueue& Q,
+                                           RgWave* rg = nullptr) {
+  const int lane = threadIdx.x & (kTile - 1);
   const int N = J.n_steps;
   const long long np = J.n_pad;
   const long long s = (long long)tile * kTile + lane;
@@ -446,10 +574,10 @@ __device__ __forceinline__ int run_tile_to(const JobDev& J, const int tile, cons
   for (int c = 0; c < 36; ++c) T.M[c] = y[(6 + c) * np + s];
   T.S = y[42 * np + s];
   cplx cprev = {J.aux[s], J.aux[np + s]};
-  const cplx w = {J.aux[2 * np + s], J.aux[3 * np + s]};
+  cplx w = {J.aux[2 * np + s], J.aux[3 * np + s]};
   double sgn = J.aux[4 * np + s];
-  const int n0l = J.n0[s];
-  const int death_in = J.death[s];
+  int n0l = J.n0[s];
+  int death_in = J.death[s];
   int death = death_in;
   bool alive = death_in == -1;
 
@@ -464,9 +592,71 @@ __device__ __forceinline__ int run_tile_to(const JobDev& J, const int tile, cons
   int qn = 0;  // queued integrands (wave-uniform)
   unsigned int kay = 0, nonfin = 0, prims = 0;
   int ents = 0;  // queued integrand entries evaluated (wave-uniform)
+  int evals = 0;           // RG: steps evaluated by this lane's trajectories of earlier intervals
+  int first_step = n_begin;  // RG: the first step of the current interval
   int n = n_begin;
   double ea = eh[2 * n];
   for (; n <= n_stop; ++n) {
+    if constexpr (RG) {
+      if (n == rg->nb) {  // boundary: regroup with the other waves of the workgroup
+        if (qn > 0) {
+          ents += qn;
+          prims += queue_eval<ONE_WAVE>(Q, qn, lane, QC);
+          qn = 0;
+        }
+        // the arrays' addresses through volatile reads: computed here, not held in registers for
+        // the whole step loop
+        double* const yw = *(double* const volatile*)&J.y;
+        double* const ax = *(double* const volatile*)&J.aux;
+        int* const dt = *(int* const volatile*)&J.death;
+        const int* const nz = *(int* const volatile*)&J.n0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          yw[i * np + s] = T.q[i];
+          yw[(3 + i) * np + s] = T.p[i];
+        }
+#pragma unroll
+        for (int c = 0; c < 36; ++c) yw[(6 + c) * np + s] = T.M[c];
+        yw[42 * np + s] = T.S;
+        ax[s] = cprev.re;
+        ax[np + s] = cprev.im;
+        ax[4 * np + s] = sgn;
+        dt[s] = death;
+        evals += lane_evals(death_in, death, n0l, first_step, n - 1);
+        __syncthreads();  // every tile's state is stored
+        rg->nw = rg_boundary(J, rg->t0, n, rg->nw, rg->src, rg->cnt);
+        if (rg->w >= rg->nw) {  // this wave's tile is retired: count and end
+          double ev = wave_sum((double)evals), ka = wave_sum((double)kay);
+          double nf = wave_sum((double)nonfin), pr = wave_sum((double)prims);
+          if (lane == 0) {
+            atomicAdd(&J.counters[0], (unsigned long long)ev);
+            atomicAdd(&J.counters[1], (unsigned long long)ka);
+            atomicAdd(&J.counters[2], (unsigned long long)nf);
+            atomicAdd(&J.counters[4], (unsigned long long)pr);
+            atomicAdd(&J.counters[5], (unsigned long long)ents);
+          }
+          return -1;
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          T.q[i] = yw[i * np + s];
+          T.p[i] = yw[(3 + i) * np + s];
+        }
+#pragma unroll
+        for (int c = 0; c < 36; ++c) T.M[c] = yw[(6 + c) * np + s];
+        T.S = yw[42 * np + s];
+        cprev = {ax[s], ax[np + s]};
+        w = {ax[2 * np + s], ax[3 * np + s]};
+        sgn = ax[4 * np + s];
+        n0l = nz[s];
+        death_in = dt[s];
+        death = death_in;
+        alive = death_in == -1;
+        first_step = n;
+        ea = eh[2 * n];
+        rg->nb += rg->E;
+      }
+    }
     bool contrib = false;
     cplx C = {0.0, 0.0};
     if (alive && n >= n0l) {
@@ -501,7 +691,7 @@ __device__ __forceinline__ int run_tile_to(const JobDev& J, const int tile, cons
       const int k = __popcll(m);
       if (qn + k > kQueue) {
         ents += qn;
-        prims += queue_eval(Q, qn, lane, QC);
+        prims += queue_eval<ONE_WAVE>(Q, qn, lane, QC);
         qn = 0;
       }
       if (need)
@@ -515,13 +705,19 @@ __device__ __forceinline__ int run_tile_to(const JobDev& J, const int tile, cons
       ea = ec;
     }
     if (!__any(alive)) {  // every lane removed: the rest of the tile's row stays zero
+      if constexpr (RG) {
+        if (rg->nb <= n_stop) {  // idle to the next boundary, where the workgroup regroups
+          n = rg->nb - 1;
+          continue;
+        }
+      }
       ++n;
       break;
     }
   }
   if (qn > 0) {
     ents += qn;
-    prims += queue_eval(Q, qn, lane, QC);
+    prims += queue_eval<ONE_WAVE>(Q, qn, lane, QC);
   }
   // n is now one past the last step processed
   double* yw = J.y;
@@ -545,12 +741,7 @@ __device__ __forceinline__ int run_tile_to(const JobDev& J, const int tile, cons
   }
   // steps evaluated by this lane in this call: from max(n_begin, n0) to its removal step or the
   // last step processed
-  int evals = 0;
-  if (death_in == -1) {
-    const int first = max(n_begin, n0l);
-    const int lastn = death >= 0 ? death : n - 1;
-    evals = max(0, lastn - first + 1);
-  }
+  evals += lane_evals(death_in, death, n0l, first_step, n - 1);
   double ev = wave_sum((double)evals), ka = wave_sum((double)kay), nf = wave_sum((double)nonfin);
   double pr = wave_sum((double)prims);
   if (lane == 0) {
@@ -564,14 +755,14 @@ __device__ __forceinline__ int run_tile_to(const JobDev& J, const int tile, cons
 }
 
 // one launch's share of a tile: max_steps steps (max_steps <= 0: to the end of the grid)
-template <int KIND>
+template <int KIND, bool ONE_WAVE = true>
 __device__ __forceinline__ void run_tile(const JobDev& J, const int tile, const int max_steps,
                                          IntegrandQueue& Q) {
   const int n_begin = uniform_i32(J.tile_next[tile]);
   const int N = J.n_steps;
   if (n_begin > N) return;
   const int n_stop = (max_steps > 0) ? min(N, n_begin + max_steps - 1) : N;
-  run_tile_to<KIND>(J, tile, n_begin, n_stop, Q);
+  run_tile_to<KIND, ONE_WAVE>(J, tile, n_begin, n_stop, Q);
 }
 
 #ifndef SFHK_PROPAGATE_WAVES_PER_EU
@@ -851,280 +1042,49 @@ void k_grid_mixed(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ 
   run_tile_mixed<KIND>(jobs[wi.job], wi.tile, max_steps, Q);
 }
 
-// ------------------------------------------------------------------------------------------------
-// compaction of live trajectories (persistent form of a single job's propagation)
-// ------------------------------------------------------------------------------------------------
-// Trajectories removed by the Kay test leave their lanes idle until the tile ends. With
-// compact_every = E > 0, the tiles of one birth step (up to kCompactTiles consecutive tiles with
-// the same first birth step: a compaction group) stop at every boundary step k E. The tile whose
-// arrival completes the group (the others have arrived or have no live lane left) regroups the
-// group: the live trajectories move to the front slots of the group (each live slot behind the
-// live count swaps with a removed slot in front of it, pairs by rank), so ceil(live / 64) tiles
-// continue and the rest retire. A trajectory's own arithmetic does not depend on its lane, and
-// which trajectories share a tile after a boundary depends only on the removal steps, never on
-// timing, so results are bitwise reproducible; the per-step sums of a tile's lanes change with
-// the grouping (the exact accumulators make the total independent of everything else).
-// Resident single-wave workgroups take tiles from the launch's static list (longest first) and,
-// first, from a queue of regrouped tiles; a workgroup exits once the static list and the queue
-// are empty and no workgroup holds a tile (holding tiles are the only source of new queue items).
-// Every wait is bounded by a count of polls without progress, after which the workgroup records a
-// scheduler error and exits.
-constexpr int kCompactTiles = 16;  // tiles per compaction group at most
-
-// queue of regrouped tiles, one per launch: header words then items and sequence words
-struct CompactHdr {
-  unsigned int head, tail;   // items taken / pushed
-  unsigned int next_static;  // static items taken
-  int running;               // workgroups holding a tile (or taking one)
-  int cap;                   // item capacity (the job's tile count)
-  int pad[3];
-};
-
-__device__ __forceinline__ unsigned int ld_acq(const unsigned int* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ int ld_acq(const int* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// takes the next tile (lane 0 decides, the wave gets the result): x = tile (-1: no work left),
-// y = its last step in this launch (-1: from the launch's step limit)
-__device__ __forceinline__ int2* compact_items(CompactHdr* H) { return (int2*)(H + 1); }
-__device__ __forceinline__ unsigned int* compact_seq(CompactHdr* H, int cap) {
-  return (unsigned int*)(compact_items(H) + cap);
-}
-
-// A wait gives up after this many polls without progress (items pushed, taken or started): at
-// least a few seconds, far longer than any tile segment between boundaries.
-constexpr unsigned int kCompactMaxPolls = 1u << 22;
-
-__device__ __forceinline__ int2 compact_pop(CompactHdr* H, const WorkItem* __restrict__ work,
-                                            int n_static, unsigned long long* errors) {
-  int tile = -1, stop = -1;
+template <int KIND>
+__global__ __launch_bounds__(kRgWaves * kTile) __attribute__((amdgpu_waves_per_eu(SFHK_PROPAGATE_WAVES_PER_EU)))
+void k_propagate_rg(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work, int n_items,
+                    int max_steps) {
+  __shared__ IntegrandQueue Q[kRgWaves];
+  __shared__ int src[kRgWaves * kTile];
+  __shared__ int cnt[2 * kRgWaves];
+  __shared__ int next[kRgWaves];
+  __shared__ int group;  // the first tile of a group, else -1
+  const int w = uniform_i32((int)threadIdx.x >> 6);
+  const int lane = threadIdx.x & (kTile - 1);
+  const long long k0 = (long long)blockIdx.x * kRgWaves;
+  const long long k = k0 + w;
+  const WorkItem wi = work[k < n_items ? k : k0];
+  const JobDev& J = jobs[wi.job];
+  const int N = J.n_steps;
   if (threadIdx.x == 0) {
-    const int cap = H->cap;
-    int2* items = compact_items(H);
-    unsigned int* seq = compact_seq(H, cap);
-    unsigned int polls = 0;
-    unsigned long long seen = ~0ull;
-    for (;;) {
-      // regrouped tiles first, then the static list. A workgroup counts itself as running before
-      // it takes an item, and only when there is one to take, so idle workgroups never hold the
-      // count up and never see it at 0 while a tile is being taken.
-      unsigned int h = ld_acq(&H->head), t = ld_acq(&H->tail);
-      const bool dyn = h < t;
-      const bool sta = !dyn && ld_acq(&H->next_static) < (unsigned int)n_static;
-      if (dyn || sta) {
-        __hip_atomic_fetch_add(&H->running, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        bool got = false;
-        if (dyn) {
-          // slot protocol: seq = n + 1 once item n is written; its taker sets seq = n + cap,
-          // which frees the slot for item n + cap; an item is taken only once it is written
-          for (;;) {
-            const unsigned int slot = h % (unsigned int)cap;
-            if (ld_acq(&seq[slot]) != h + 1) break;  // not written yet, or taken: look again
-            if (__hip_atomic_compare_exchange_strong(&H->head, &h, h + 1, __ATOMIC_ACQ_REL,
-                                                     __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) {
-              const int2 it = items[slot];
-              tile = it.x;
-              stop = it.y;
-              got = true;
-              __hip_atomic_store(&seq[slot], h + (unsigned int)cap, __ATOMIC_RELEASE,
-                                 __HIP_MEMORY_SCOPE_AGENT);
-              break;
-            }
-          }
-        } else {
-          const unsigned int k = atomicAdd(&H->next_static, 1u);
-          if (k < (unsigned int)n_static) {
-            tile = work[k].tile;
-            got = true;
-          }
-        }
-        if (got) break;
-        __hip_atomic_fetch_sub(&H->running, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        continue;  // taken by another workgroup, or still being written: look again at once
-      }
-      // nothing to take: finished when nobody holds or takes a tile (read first) and nothing is
-      // queued; holders are the only source of new items
-      if (ld_acq(&H->running) == 0 && ld_acq(&H->head) >= ld_acq(&H->tail) &&
-          ld_acq(&H->next_static) >= (unsigned int)n_static)
-        break;
-      const unsigned long long state = ((unsigned long long)ld_acq(&H->tail) << 32) ^
-                                       ld_acq(&H->head) ^
-                                       ((unsigned long long)ld_acq(&H->next_static) << 16);
-      if (state != seen) {
-        seen = state;
-        polls = 0;
-      } else if (++polls > kCompactMaxPolls) {
-        atomicAdd(errors, 1ull);
-        break;
-      }
-      __builtin_amdgcn_s_sleep(2);
+    int g = k0 + kRgWaves <= n_items && J.compact_every > 0 ? work[k0].tile : -1;
+    for (int u = 1; u < kRgWaves && g >= 0; ++u) {
+      const WorkItem x = work[k0 + u];
+      if (x.job != work[k0].job || x.tile != g + u || J.tile_n0[g + u] != J.tile_n0[g]) g = -1;
     }
+    group = g;
   }
-  tile = __shfl(tile, 0, 64);
-  stop = __shfl(stop, 0, 64);
-  return make_int2(uniform_i32(tile), uniform_i32(stop));
-}
-
-__device__ __forceinline__ void compact_release(CompactHdr* H) {
-  if (threadIdx.x == 0)
-    __hip_atomic_fetch_sub(&H->running, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// exchanges everything the job holds for slots a and b
-__device__ __forceinline__ void swap_slots(const JobDev& J, long long a, long long b) {
-  const long long np = J.n_pad;
-#pragma unroll 4
-  for (int c = 0; c < kNY; ++c) {
-    const double u = J.y[c * np + a], v = J.y[c * np + b];
-    J.y[c * np + a] = v;
-    J.y[c * np + b] = u;
+  if (lane == 0) next[w] = k < n_items ? J.tile_next[wi.tile] : N + 1;
+  __syncthreads();
+  const int t0 = uniform_i32(group);
+  RgWave rg{INT_MAX, J.compact_every, t0, kRgWaves, w, src, cnt};
+  int n;
+  if (t0 >= 0) {  // a group: its running tiles share their next step
+    n = N + 1;
+    for (int u = 0; u < kRgWaves; ++u) n = min(n, next[u]);
+    n = uniform_i32(n);
+    if (n > N) return;  // the whole workgroup
+    // the first boundary at or after n: a launch that starts on a boundary step regroups there
+    // first, as a launch running through that step does at the top of its iteration
+    rg.nb = (n + rg.E - 1) / rg.E * rg.E;
+  } else {        // four independent tiles
+    n = uniform_i32(next[w]);
+    if (k >= n_items || n > N) return;
   }
-#pragma unroll
-  for (int c = 0; c < 5; ++c) {
-    const double u = J.aux[c * np + a], v = J.aux[c * np + b];
-    J.aux[c * np + a] = v;
-    J.aux[c * np + b] = u;
-  }
-  const int n0a = J.n0[a], n0b = J.n0[b];
-  J.n0[a] = n0b;
-  J.n0[b] = n0a;
-  const int da = J.death[a], db = J.death[b];
-  J.death[a] = db;
-  J.death[b] = da;
-  const long long pa = J.perm[a], pb = J.perm[b];
-  J.perm[a] = pb;
-  J.perm[b] = pa;
-}
-
-// Regroups group g at boundary step nb (the whole wave; every tile of the group that may hold a
-// live trajectory has stopped there or retired) and queues its continuing tiles if the launch
-// goes on past nb (stop = the group's last step in this launch).
-__device__ void compact_group(const JobDev& J, int g, int nb, int stop, int* holes, CompactHdr* H) {
-  const int lane = threadIdx.x;
-  __threadfence();  // the arrived tiles' state
-  const int first = uniform_i32(J.grp_first[g]);
-  const int A = uniform_i32(J.grp_active[g]);
-  const long long base = (long long)first * kTile;
-  const int nslots = A * kTile;
-  int L = 0;  // live trajectories (not removed; not yet born counts as live)
-  for (int c = 0; c < nslots; c += kTile)
-    L += __popcll(__builtin_amdgcn_ballot_w64(J.death[base + c + lane] == -1));
-  const int newA = (L + kTile - 1) / kTile;
-  if (newA < A && L > 0) {
-    // removed slots in front of L, by rank
-    int cnt = 0;
-    for (int c = 0; c < L; c += kTile) {
-      const int i = c + lane;
-      const bool hole = i < L && J.death[base + i] != -1;
-      const unsigned long long m = __builtin_amdgcn_ballot_w64(hole);
-      if (hole) holes[cnt + lanes_below(m)] = i;
-      cnt += __popcll(m);
-    }
-    __syncthreads();
-    // live slots behind L swap with the removed slot of the same rank
-    int r = 0;
-    for (int c = L; c < nslots; c += kTile) {
-      const int i = c + lane;
-      const bool live = i < nslots && J.death[base + i] == -1;
-      const unsigned long long m = __builtin_amdgcn_ballot_w64(live);
-      if (live) swap_slots(J, base + i, base + holes[r + lanes_below(m)]);
-      r += __popcll(m);
-    }
-    __syncthreads();
-  }
-  const int N = J.n_steps;
-  if (lane < A) {
-    const int t = first + lane;
-    if (lane < newA) {
-      J.tile_next[t] = nb;
-      J.tile_last[t] = nb - 1;
-    } else {
-      J.tile_next[t] = N + 1;
-    }
-  }
-  if (lane == 0) {
-    J.grp_active[g] = newA;
-    J.grp_pending[g] = newA;
-  }
-  __threadfence();  // moved state and tile fields before the tiles are queued
-  if (nb <= stop && lane < newA) {
-    const int cap = H->cap;
-    unsigned int* seq = compact_seq(H, cap);
-    const unsigned int slot_n = atomicAdd(&H->tail, 1u);
-    const unsigned int slot = slot_n % (unsigned int)cap;
-    // the slot's previous item (slot_n - cap) has been taken: at most cap items are ever queued
-    // at once (a tile is queued at most once at a time), so this wait ends at once
-    unsigned int waits = 0;
-    while (__hip_atomic_load(&seq[slot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != slot_n &&
-           ++waits < kCompactMaxPolls)
-      __builtin_amdgcn_s_sleep(1);
-    if (waits < kCompactMaxPolls) {
-      compact_items(H)[slot] = make_int2(first + lane, stop);
-      __hip_atomic_store(&seq[slot], slot_n + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      atomicAdd(&J.counters[6], 1ull);
-    }
-  }
-}
-
-// one tile item: propagate to the launch's step limit or to the group's next boundary, whichever
-// comes first; a tile that reaches the boundary waits there (tile_next = n_steps + 2: skipped if
-// taken again) until the group's last arrival regroups the group
-template <int KIND>
-__device__ __forceinline__ void compact_run(const JobDev& J, int tile, int stop_in, int max_steps,
-                                            IntegrandQueue& Q, int* holes, CompactHdr* H) {
-  const int N = J.n_steps;
-  const int n_begin = uniform_i32(__hip_atomic_load(&J.tile_next[tile], __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT));
-  if (n_begin > N) return;  // retired, finished, or waiting at a boundary
-  const int stop = stop_in >= 0 ? stop_in : (max_steps > 0 ? min(N, n_begin + max_steps - 1) : N);
-  const int g = uniform_i32(J.grp_of_tile[tile]);
-  const int E = J.compact_every;
-  const int nb = g < 0 ? N + 1 : (n_begin / E + 1) * E;  // the next boundary after n_begin
-  const int next = run_tile_to<KIND>(J, tile, n_begin, min(stop, nb - 1), Q);
-  if (nb > N) return;                          // no boundary before the grid's end
-  if (next != nb && next != N + 1) return;     // stopped at the launch's step limit
-  if (next == nb && threadIdx.x == 0) J.tile_next[tile] = N + 2;  // waits for the regrouping
-  __threadfence();                             // this tile's state before its arrival
-  int left = 0;
-  if (threadIdx.x == 0)
-    left = __hip_atomic_fetch_sub(&J.grp_pending[g], 1, __ATOMIC_ACQ_REL,
-                                  __HIP_MEMORY_SCOPE_AGENT) - 1;
-  left = uniform_i32(__shfl(left, 0, 64));
-  if (left == 0) compact_group(J, g, nb, stop, holes, H);
-}
-
-// resets the queue of regrouped tiles before a launch: counters, and slot i free for item i
-__global__ void k_compact_reset(CompactHdr* H, int cap) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) {
-    H->head = 0u;
-    H->tail = 0u;
-    H->next_static = 0u;
-    H->running = 0;
-    H->cap = cap;
-  }
-  if (i < cap) compact_seq(H, cap)[i] = (unsigned int)i;
-}
-
-// persistent propagation of one job with compaction (see above); launched with at most as many
-// single-wave workgroups as can be resident at once
-template <int KIND>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_PROPAGATE_WAVES_PER_EU)))
-void k_propagate_compact(const JobDev* __restrict__ jobs, const WorkItem* __restrict__ work,
-                         int n_static, CompactHdr* __restrict__ H, int max_steps) {
-  __shared__ IntegrandQueue Q;
-  __shared__ int holes[kCompactTiles * kTile];
-  const JobDev& J = jobs[0];
-  for (;;) {
-    const int2 it = compact_pop(H, work, n_static, &J.counters[6]);
-    if (it.x < 0) break;
-    compact_run<KIND>(J, it.x, it.y, max_steps, Q, holes, H);
-    compact_release(H);
-  }
+  const int stop = max_steps > 0 ? min(N, n + max_steps - 1) : N;
+  run_tile_to<KIND, false, true>(J, t0 >= 0 ? t0 + w : wi.tile, n, stop, Q[w], &rg);
 }
 
 }  // namespace

@@ -68,7 +68,7 @@ class _Stats(ct.Structure):
                 ("steps_fp64", ct.c_int64), ("kay_removed", ct.c_int64),
                 ("nonfinite_removed", ct.c_int64), ("tiles_total", ct.c_int64),
                 ("tiles_done", ct.c_int64), ("prims_evaluated", ct.c_int64),
-                ("integrands_evaluated", ct.c_int64), ("scheduler_errors", ct.c_int64)]
+                ("integrands_evaluated", ct.c_int64), ("reserved", ct.c_int64)]
 
 
 _lib = None
@@ -206,7 +206,6 @@ class Stats:
     tiles_done: int
     prims_evaluated: int
     integrands_evaluated: int
-    scheduler_errors: int
 
 
 class Job:
@@ -298,7 +297,7 @@ class Job:
                "sfhk_job_stats")
         return Stats(s.n_traj, s.n_steps, s.steps_evaluated, s.steps_fp64, s.kay_removed,
                      s.nonfinite_removed, s.tiles_total, s.tiles_done,
-                     s.prims_evaluated, s.integrands_evaluated, s.scheduler_errors)
+                     s.prims_evaluated, s.integrands_evaluated)
 
     def checkpoint(self, stream=None) -> torch.Tensor:
         """The job's propagation state as a device byte tensor (sfhk_job_checkpoint)."""

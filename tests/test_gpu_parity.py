@@ -230,16 +230,6 @@ def test_a_job_listed_twice_is_refused(S):
     job.close()
 
 
-def test_regrouping_is_refused(S):
-    """Regrouping of live trajectories (sfhk_params.compact_every) is switched off in this build:
-    a job asking for it is refused with SFHK_E_INVALID."""
-    sfhk, ctx, torch = S
-    inst = I.config0(n_birth=2, n_per_birth=32)
-    with pytest.raises(sfhk.SfhkError) as e:
-        sfhk.make_job(ctx, inst, compact_every=1024)
-    assert e.value.status == sfhk.SFHK_E_INVALID
-
-
 def test_config1_full_size_sampled_trajectories(S):
     """The full 2^20-trajectory workload, launched as the benchmark launches it: sampled
     trajectories' final states against the oracle one by one, and whole-run invariants."""
