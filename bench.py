@@ -71,6 +71,12 @@ def _args():
                     help="instead: the 64-instance uneven batch in one graph-captured launch per "
                          "precision (FP64 and FP32-mixed), autotuned launch form")
     ap.add_argument("--batch-size", type=int, default=64)
+    ap.add_argument("--batch-sweep", action="store_true",
+                    help="instead: every launch form of the autotuner on the full batch, the "
+                         "tuner's trial beside it, and the batch split by potential kind")
+    ap.add_argument("--batch-forms", default="",
+                    help="with --batch-sweep: only these forms (';'-separated, as the tuner names "
+                         "them, e.g. 'workers=0,chunk=0;workers=8,chunk=0')")
     ap.add_argument("--serve", action="store_true",
                     help="instead: the serving sweep (Poisson arrivals at --rates, FP64 and mixed)")
     ap.add_argument("--rates", default="5,10,20,50")
@@ -314,10 +320,63 @@ def batch_results(ctx, batch_size):
         out[name] = {"value": steps / wall, "seconds": wall, "trajectory_steps": steps,
                      "replays": replays, "workers_per_cu": tuned["workers_per_cu"],
                      "chunk": tuned["chunk"], "autotune_rates": tuned["rates"],
+                     "autotune_confirm_rates": tuned.get("confirm_rates"),
                      "fp64_step_fraction": sum(x.steps_fp64 for x in st) / max(1, steps)}
         for j in jobs:
             j.close()
         b.close()
+    return out
+
+
+def _batch_rate(ctx, insts, arrays, prec, workers, chunk):
+    """trajectory-steps/s of one batch of `insts` in one launch form (all replays to the end)"""
+    import torch
+    from paper_2601_17164_amd import sfhk
+    jobs = [sfhk.make_job(ctx, x, arr, precision=prec) for x, arr in zip(insts, arrays)]
+    b = sfhk.Batch(ctx, len(jobs), sum(sfhk.tiles_of(x) for x in insts), chunk, workers)
+    b.set_jobs(jobs)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    while not b.run():
+        pass
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    steps = sum(j.stats().steps_evaluated for j in jobs)
+    for j in jobs:
+        j.close()
+    b.close()
+    return steps, steps / wall
+
+
+def batch_sweep(ctx, batch_size, forms=None):
+    """The autotuner's candidates on the full uneven batch, beside the tuner's own trial rates
+    (does the scaled-down trial rank the forms as the full batch does?), and the batch split by
+    potential kind: each kind's instances alone in hardware dispatch, with the work-weighted
+    combination of the two rates that the whole batch can be expected to reach."""
+    from paper_2601_17164_amd import autotune, inputs as I, sfhk
+    insts = I.batch_instances(batch_size, seed=3)
+    arrays = [sfhk.to_device(x, "cuda:0") for x in insts]
+    out = {"instances": len(insts)}
+    for prec, name in ((0, "fp64"), (1, "fp32_mixed")):
+        trial = autotune.tune(ctx, prec, use_cache=False, verbose=True)
+        full = {}
+        for form in (forms or autotune.forms()):
+            w, k = autotune.parse(form)
+            full[form] = _batch_rate(ctx, insts, arrays, prec, w, k)[1]
+            print(json.dumps({"batch_sweep": name, "form": form, "full": full[form],
+                              "trial": trial["rates"][form]}), flush=True)
+        kinds = {}
+        for kind in sorted({x.potential.kind for x in insts}):
+            sel = [i for i, x in enumerate(insts) if x.potential.kind == kind]
+            steps, rate = _batch_rate(ctx, [insts[i] for i in sel], [arrays[i] for i in sel], prec,
+                                      0, 0)
+            kinds[str(kind)] = {"instances": len(sel), "trajectory_steps": steps, "rate": rate}
+        tot = sum(v["trajectory_steps"] for v in kinds.values())
+        mix = tot / sum(v["trajectory_steps"] / v["rate"] for v in kinds.values())
+        out[name] = {"chosen": autotune.choose(trial["rates"]), "trial": trial["rates"],
+                     "full": full, "by_kind": kinds, "work_weighted_rate": mix}
+        print(json.dumps({"batch_sweep": name, "by_kind": kinds, "work_weighted_rate": mix}),
+              flush=True)
     return out
 
 
@@ -550,6 +609,13 @@ def main():
         return
     if a.batch:
         run_batch(a)
+        return
+    if a.batch_sweep:
+        from paper_2601_17164_amd import sfhk
+        ctx = sfhk.Context(0)
+        forms = [f for f in a.batch_forms.split(";") if f] or None
+        print(json.dumps({"batch_sweep": batch_sweep(ctx, a.batch_size, forms)}), flush=True)
+        ctx.close()
         return
     if a.serve:
         run_serve(a)

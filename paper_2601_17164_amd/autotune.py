@@ -1,8 +1,13 @@
 """Autotuner of the batched propagation: chooses the launch form (persistent queue with a given
 number of resident workgroups per compute unit, or hardware dispatch of one workgroup per tile)
-and the step chunk for a precision, by timing short trials of each candidate through the C ABI on
-a scaled-down batch drawn from the uneven-batch distribution (16 instances with a quarter of their
-trajectories: 1/16 of the 64-instance batch's work, large enough for its tail effects to show).
+and the step chunk for a precision, by timing trials of the candidates through the C ABI on
+batches drawn from the uneven-batch distribution, in two stages:
+  1. every candidate (WORKERS x CHUNKS) on a small batch: 16 instances with a quarter of their
+     trajectories (1/16 of the 64-instance batch's work);
+  2. for each resident-workgroup count, its best chunk from stage 1, again on a batch of the full
+     batch's shape: 64 instances with half their trajectories. The small batch ranks the chunks
+     as the full batch does but not the forms (it has too few long tiles for the tails of the
+     persistent forms to even out), so the form is chosen on the second.
 Results are cached per device name and precision in a JSON file.
 """
 from __future__ import annotations
@@ -17,11 +22,21 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "autotune_cache.json")
 
 WORKERS = (0, 4, 8, 16)          # 0 = hardware dispatch
-CHUNKS = (0, 2048)               # 0 = to the end in one replay
-# a persistent form must beat the best hardware-dispatch form by this factor on the scaled-down
-# trial: it calls the tile loop out of line, and near-ties on the small trial have not carried
-# over to full-size batches
+CHUNKS = (0, 256, 1024, 4096)    # steps per replay; 0 = to the end in one replay
+# on a small trial a persistent form must beat the best hardware-dispatch form by this factor:
+# near-ties there have not carried over to full-size batches (stage 2 compares with no margin)
 PERSISTENT_MARGIN = 1.05
+
+
+def forms():
+    """Every candidate launch form, as the keys of the rates the tuner reports."""
+    return [f"workers={w},chunk={k}" for w in WORKERS for k in CHUNKS]
+
+
+def parse(form: str):
+    """(workers_per_cu, chunk) of a form key"""
+    w, k = (int(v.split("=")[1]) for v in form.split(","))
+    return w, k
 
 
 def _trial(sfhk, ctx, arrays_list, insts, precision, workers, chunk, torch):
@@ -41,21 +56,33 @@ def _trial(sfhk, ctx, arrays_list, insts, precision, workers, chunk, torch):
     return steps / dt
 
 
-def choose(rates: dict) -> str:
+def choose(rates: dict, margin: float = PERSISTENT_MARGIN) -> str:
     """The fastest candidate, with hardware dispatch kept unless a persistent form is faster by
-    PERSISTENT_MARGIN."""
+    `margin`."""
     best = max(rates, key=rates.get)
     hw = [k for k in rates if k.startswith("workers=0,")]
     if hw and not best.startswith("workers=0,"):
         best_hw = max(hw, key=rates.get)
-        if rates[best] < PERSISTENT_MARGIN * rates[best_hw]:
+        if rates[best] < margin * rates[best_hw]:
             return best_hw
     return best
 
 
+def finalists(rates: dict) -> list:
+    """For each resident-workgroup count, its form with the best rate."""
+    out = {}
+    for form, r in rates.items():
+        w, _ = parse(form)
+        if w not in out or r > rates[out[w]]:
+            out[w] = form
+    return [out[w] for w in sorted(out)]
+
+
 def tune(ctx, precision: int = 0, n_instances: int = 16, traj_scale: float = 1.0 / 4,
-         seed: int = 77, use_cache: bool = True, verbose: bool = False) -> dict:
-    """Returns {"workers_per_cu": w, "chunk": k, "rates": {...}} for this device and precision."""
+         seed: int = 77, use_cache: bool = True, verbose: bool = False,
+         confirm_instances: int = 64, confirm_scale: float = 0.5) -> dict:
+    """Returns {"workers_per_cu": w, "chunk": k, "rates": {stage 1}, "confirm_rates": {stage 2}}
+    for this device and precision (confirm_instances = 0: stage 1 only)."""
     import torch
     from . import inputs as I, sfhk
     dev = torch.cuda.get_device_name(ctx.device)
@@ -73,16 +100,28 @@ def tune(ctx, precision: int = 0, n_instances: int = 16, traj_scale: float = 1.0
     arrays_list = [sfhk.to_device(x, f"cuda:{ctx.device}") for x in insts]
     _trial(sfhk, ctx, arrays_list, insts, precision, 8, 0, torch)  # warm-up
     rates = {}
-    for w in WORKERS:
-        for k in CHUNKS:
-            r = _trial(sfhk, ctx, arrays_list, insts, precision, w, k, torch)
-            rates[f"workers={w},chunk={k}"] = r
-            if verbose:
-                print(f"autotune precision={precision} workers_per_cu={w} chunk={k}: "
-                      f"{r:.4e} trajectory-steps/s", flush=True)
+    for form in forms():
+        w, k = parse(form)
+        r = _trial(sfhk, ctx, arrays_list, insts, precision, w, k, torch)
+        rates[form] = r
+        if verbose:
+            print(f"autotune precision={precision} workers_per_cu={w} chunk={k}: "
+                  f"{r:.4e} trajectory-steps/s", flush=True)
     best = choose(rates)
-    w, k = (int(v.split("=")[1]) for v in best.split(","))
-    res = {"workers_per_cu": w, "chunk": k, "rates": rates}
+    confirm = {}
+    if confirm_instances > 0:
+        big = I.batch_instances(confirm_instances, seed=seed, traj_scale=confirm_scale)
+        big_arrays = [sfhk.to_device(x, f"cuda:{ctx.device}") for x in big]
+        for form in finalists(rates):
+            fw, fk = parse(form)
+            confirm[form] = _trial(sfhk, ctx, big_arrays, big, precision, fw, fk, torch)
+            if verbose:
+                print(f"autotune precision={precision} stage 2 workers_per_cu={fw} chunk={fk}: "
+                      f"{confirm[form]:.4e} trajectory-steps/s", flush=True)
+        del big_arrays
+        best = choose(confirm, margin=1.0)
+    w, k = parse(best)
+    res = {"workers_per_cu": w, "chunk": k, "rates": rates, "confirm_rates": confirm}
     cache[key] = res
     try:
         with open(CACHE, "w") as f:
