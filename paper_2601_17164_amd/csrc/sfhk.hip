@@ -115,6 +115,16 @@ struct sfhk_batch {
   int cur = 0;  // set of the latest staging
   std::vector<sfhk_job*> jobs;
   bool staged = false;
+  // hardware-dispatch form: the graph's kernel node of each segment, whose grid is resized to the
+  // segment's staged tile count before each replay (grid_update), so that no replay dispatches
+  // the workgroups of the batch's whole capacity for a segment that holds few tiles or none
+  bool grid_update = false;
+  hipGraphNode_t seg_node[kSegs] = {};
+  const void* seg_fn[kSegs] = {};
+  const JobDev* arg_desc = nullptr;
+  const WorkItem* arg_work = nullptr;
+  const BatchDev* arg_bdev = nullptr;
+  int arg_ms = 0;
 };
 
 namespace {
@@ -829,6 +839,41 @@ sfhk_status sfhk_batch_create(sfhk_ctx* ctx, int32_t max_jobs, int64_t max_tiles
   TRY_B(le);
   TRY_B(ce);
   TRY_B(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  if (workers_per_cu == 0) {  // find each segment's kernel node (else the grids stay at capacity)
+    const void* fns[kSegs] = {
+        (const void*)k_grid_fp64<POT_NONE>,      (const void*)k_grid_fp64<POT_SOFTCORE>,
+        (const void*)k_grid_fp64<POT_SCREENED>,  (const void*)k_grid_fp64<POT_HARMONIC>,
+        (const void*)k_grid_mixed<POT_NONE>,     (const void*)k_grid_mixed<POT_SOFTCORE>,
+        (const void*)k_grid_mixed<POT_SCREENED>, (const void*)k_grid_mixed<POT_HARMONIC>};
+    static_assert(POT_NONE == 0 && POT_SOFTCORE == 1 && POT_SCREENED == 2 && POT_HARMONIC == 3 &&
+                      kSegs == 8, "segment order");
+    size_t nn = 0;
+    int found = 0;
+    if (hipGraphGetNodes(b->graph, nullptr, &nn) == hipSuccess && nn > 0) {
+      std::vector<hipGraphNode_t> nodes(nn);
+      if (hipGraphGetNodes(b->graph, nodes.data(), &nn) == hipSuccess) {
+        for (hipGraphNode_t nd : nodes) {
+          hipGraphNodeType ty;
+          hipKernelNodeParams kp{};
+          if (hipGraphNodeGetType(nd, &ty) != hipSuccess || ty != hipGraphNodeTypeKernel ||
+              hipGraphKernelNodeGetParams(nd, &kp) != hipSuccess)
+            continue;
+          for (int g = 0; g < kSegs; ++g)
+            if (kp.func == fns[g] && !b->seg_node[g]) {
+              b->seg_node[g] = nd;
+              b->seg_fn[g] = fns[g];
+              ++found;
+            }
+        }
+      }
+    }
+    b->arg_desc = b->desc;
+    b->arg_work = b->work;
+    b->arg_bdev = b->bdev;
+    b->arg_ms = ms;
+    b->grid_update = found == kSegs;
+    (void)hipGetLastError();  // a failed lookup only keeps the grids at capacity
+  }
 #undef TRY_B
   *out = b;
   return SFHK_OK;
@@ -853,6 +898,25 @@ sfhk_status sfhk_batch_set_jobs(sfhk_batch* b, sfhk_job* const* jobs, int32_t n_
   if (b->done_recorded[s]) HIP_TRY(hipEventSynchronize(b->done[s]));
   BatchDev bd{};
   sfhk_host::segment_table(items, kSegs, bd.n_items, bd.offset);
+  if (b->grid_update) {
+    // the next replay dispatches exactly each segment's tiles (one workgroup when it has none:
+    // the kernel's own bound check ends it); replays already launched keep their grids
+    void* args[4] = {(void*)&b->arg_desc, (void*)&b->arg_work, (void*)&b->arg_bdev, (void*)&b->arg_ms};
+    for (int g = 0; g < kSegs; ++g) {
+      hipKernelNodeParams kp{};
+      kp.func = const_cast<void*>(b->seg_fn[g]);
+      kp.gridDim = dim3((unsigned)std::max(1, bd.n_items[g]));
+      kp.blockDim = dim3(kTile);
+      kp.sharedMemBytes = 0;
+      kp.kernelParams = args;
+      kp.extra = nullptr;
+      const hipError_t e = hipGraphExecKernelNodeSetParams(b->exec, b->seg_node[g], &kp);
+      if (e != hipSuccess) {  // grids of mixed sizes: nothing may run until a staging succeeds
+        b->staged = false;
+        return fail(SFHK_E_DEVICE, std::string("hipGraphExecKernelNodeSetParams: ") + hipGetErrorString(e));
+      }
+    }
+  }
   for (int i = 0; i < n_jobs; ++i) b->desc_host[s][i] = jobs[i]->host;
   for (size_t k = 0; k < items.size(); ++k) b->work_host[s][k] = {items[k].job, items[k].tile};
   *b->bdev_host[s] = bd;
