@@ -183,3 +183,27 @@ def test_regrouped_full_size_sampled_trajectories(S):
     expect = np.where(died, g["death"] - n0 + 1, inst.grid.n_steps - n0 + 1).sum()
     assert st.steps_evaluated == expect
     assert st.kay_removed + st.nonfinite_removed == died.sum()
+
+
+def test_regrouping_with_velocity_and_partial_waves(S):
+    """The dipole velocity's accumulators and the partial-wave filter under regrouping: V and F
+    agree with the unregrouped job at rounding level, trajectories bit for bit."""
+    sfhk, ctx, torch = S
+    inst = _softcore_groups((20, 260))
+    out = {}
+    for every in (0, 128):
+        job = sfhk.make_job(ctx, inst, compact_every=every, velocity=True, pw_mask=0x1FD,
+                            pw_radius=3.0)
+        assert job.propagate(0)
+        _, f = job.dipole(want_f=True)
+        _, vf = job.velocity(want_v=True)
+        y, _, death = job.trajectories()
+        torch.cuda.synchronize()
+        out[every] = ((f[0] + 1j * f[1]).cpu().numpy(), (vf[0] + 1j * vf[1]).cpu().numpy(),
+                      y.cpu().numpy(), death.cpu().numpy())
+        job.close()
+    (f0, v0, y0, d0), (f1, v1, y1, d1) = out[0], out[128]
+    np.testing.assert_array_equal(y1, y0)
+    np.testing.assert_array_equal(d1, d0)
+    assert np.linalg.norm(f0) > 0 and np.linalg.norm(v0) > 0
+    assert rel_l2(f1, f0) < 1e-13 and rel_l2(v1, v0) < 1e-13
