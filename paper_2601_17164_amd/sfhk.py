@@ -222,7 +222,9 @@ class Job:
                  pulse=None):
         """``e_half`` is the field at the half steps (device, 2 n_steps + 1 values) or None;
         ``pulse`` (e0, omega, n_cycles, cep) has the library tabulate the field, or check the given
-        table against it. At least one of the two is needed."""
+        table against it. At least one of the two is needed. ``compact_every`` > 0 (FP64 only)
+        regroups the trajectories left by the Kay test every that many steps
+        (sfhk_params.compact_every); such a job runs through ``propagate`` only."""
         alpha = np.ascontiguousarray(ground.alpha, dtype=np.float64)
         coef = np.ascontiguousarray(ground.coef, dtype=np.float64)
         pot = _Potential(int(potential.kind), float(potential.z_inf), float(potential.z_in),
