@@ -1208,7 +1208,7 @@ sfhk_status sfhk_gabor(const double* d, int64_t n, double t_first, double dt, do
   if (n_w > INT32_MAX || n_c * n_w > INT32_MAX) return fail(SFHK_E_INVALID, "output grid too large");
   if (n_c == 0 || n_w == 0) return SFHK_OK;
   if (!power_out || (n > 0 && !d)) return fail(SFHK_E_INVALID, "NULL array");
-  dim3 grid((unsigned)((n_w + kGaborThreads - 1) / kGaborThreads), (unsigned)n_c);
+  dim3 grid((unsigned)((n_w + kGaborFreqPerBlock - 1) / kGaborFreqPerBlock), (unsigned)n_c);
   hipLaunchKernelGGL(k_gabor, grid, dim3(kGaborThreads), 0, (hipStream_t)stream, d, (long long)n, t_first,
                      dt, sigma, tc_first, tc_step, w_step, (long long)n_w, power_out, (double2*)g_out);
   HIP_TRY(hipGetLastError());
