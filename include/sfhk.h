@@ -236,13 +236,14 @@ sfhk_status sfhk_batch_run(sfhk_batch* batch, void* stream);
 int32_t sfhk_batch_workers(const sfhk_batch* batch);
 void sfhk_batch_destroy(sfhk_batch* batch);
 
-/* Reduce the job's per-tile partial sums in a fixed order into F(t_n) = sum_j f_j(t_n) and write
- * d_out = -2 Re F (Eq. 2: "+ c.c." with the leading minus) on the job's output grid (n_out points,
+/* Round the job's exact per-step sums once into F(t_n) = sum_j f_j(t_n) (every term was added as
+ * an integer into fixed-point accumulators, so F is the correctly rounded sum of the step's terms
+ * as grouped within each tile, whatever the order of the tiles) and write d_out = -2 Re F (Eq. 2: "+ c.c." with the leading minus) on the job's output grid (n_out points,
  * or n_steps + 1 when n_out = 0). f_out (nullable) receives F on the step grid as
  * [2][n_steps+1] (re block then im block). Requires a finished job (else SFHK_E_NOT_DONE). */
 sfhk_status sfhk_dipole(sfhk_job* job, double* d_out, double* f_out, void* stream);
 
-/* The dipole velocity of a job created with velocity = 1 (App. C.2): the fixed-order sum
+/* The dipole velocity of a job created with velocity = 1 (App. C.2): the exact per-step sum
  * V(t_n) = sum_j w_j C_j(t_n) <psi0|k_z|p_t,q_t,gamma> e^{i(S_j - Ip t_n)} over the same
  * trajectories, steps and removal rule as F, and v_out = -2 Re V on the job's output grid
  * (as d_out of sfhk_dipole); vf_out (nullable) receives V as [2][n_steps+1]. The velocity element
