@@ -220,3 +220,23 @@ def test_sfa_born_screened_subset_matches_oracle(S):
     e = rel_l2(F, ref.F)
     print(f"SFA-born screened subset: rel-L2 of F {e:.3e}", flush=True)
     assert e <= 1e-9
+
+
+def test_sfa_born_config1_birth_groups(S):
+    """SFA-born config 1 on 16 whole birth groups (births 0, 64, ..., 960 with all 1024 samples:
+    16384 trajectories born by the device over the whole pulse): initial states and final states
+    bit for bit, removal steps, and F on the step grid within the FP64 bar of the oracle's births
+    propagated by the oracle (App. A birth step, Eq. 2)."""
+    sfhk, torch = S
+    full = I.sfa_config1(n_out=0)
+    idx = np.concatenate([b * 1024 + np.arange(1024) for b in range(0, 1024, 64)])
+    inst = full.subset(idx)
+    print(f"SFA-born config 1 birth groups: {inst.n_traj} trajectories", flush=True)
+    born = oracle_sfa_births(inst)
+    ref = run_oracle(born)
+    F, y, death = _gpu_end_to_end(sfhk, torch, inst, 0)
+    np.testing.assert_array_equal(y, ref.y_final)
+    np.testing.assert_array_equal(death, ref.death)
+    e = rel_l2(F, ref.F)
+    print(f"SFA-born config 1, 16 x 1024: rel-L2 of F {e:.3e}", flush=True)
+    assert e <= 1e-9
