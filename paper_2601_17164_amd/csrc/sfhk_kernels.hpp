@@ -106,9 +106,10 @@ __device__ __forceinline__ bool overlap_all_skipped(double amin, double bmin, do
 // for bit). Reduction x = n pi/2 + r with the two-part constant pi/2 = C1 + C2 and fused
 // multiply-adds (|r| <= pi/4, error about |n| 2e-33), Taylor polynomials in r^2 to degree 13 (sin)
 // and 14 (cos), truncation below 3e-14, then the quadrant. Accurate for |x| < 2^52; beyond that,
-// and for a NaN or an infinity, both are NaN. The integrand's arguments stay far below: an evaluated primitive has
-// p^2 A_j + q^2 B_j <= overlap_cut, so |p.q| <= overlap_cut / sqrt(A_min B_min), and the phase
-// S - Ip t is an action of order 10^4 at most.
+// and for a NaN or an infinity, both are NaN. The integrand's arguments, phi - D_j p.q, stay far
+// below: an evaluated primitive has p^2 A_j + q^2 B_j <= overlap_cut, so
+// |p.q| <= overlap_cut / sqrt(A_min B_min), and the phase phi = S - Ip t is an action of order
+// 10^4 at most.
 struct InvFactorials14 {
   double v[15];
   constexpr InvFactorials14() : v() {
@@ -155,7 +156,9 @@ __device__ __forceinline__ void sincos_integrand(double x, double* sp, double* c
 //   s-wave: O = a sum_j N_j E_j,                   Ov = -2 i a sum_j alpha_j N_j E_j
 //   p-wave: O = sum_j N_j E_j (a^2 + 2 (g + a_j)),  Ov = 2 i sum_j N_j E_j (2 g (g + a_j) - a_j a^2)
 // (the printed velocity forms times 2 and 4 i gamma, the ratio of the two elements' written-out
-// constants, so that the real part taken by "+ c.c." is the same for both forms).
+// constants, so that the real part taken by "+ c.c." is the same for both forms). Both come out
+// times the phase e^{i phi}, which enters each primitive's angle: E_j e^{i phi} =
+// N_j e^{Re_j} e^{i (phi - D_j p.q)}, one sincos per primitive and none for the phase alone.
 struct Elements {
   cplx o, ov;
 };
@@ -167,7 +170,7 @@ typedef const __attribute__((address_space(4))) GtoConst* gto_cptr;
 
 template <typename GREF>
 __device__ __forceinline__ Elements overlap(GREF G, double cut, const double* q,
-                                            const double* p, double p2, double q2,
+                                            const double* p, double p2, double q2, double phi,
                                             unsigned int& n_eval) {
   double pq = SFHK_FMA(p[2], q[2], SFHK_FMA(p[1], q[1], p[0] * q[0]));
   cplx a = {G.two_gamma * q[2], p[2]};
@@ -177,7 +180,7 @@ __device__ __forceinline__ Elements overlap(GREF G, double cut, const double* q,
     double re = -SFHK_FMA(p2, G.A[j], q2 * G.B[j]);
     if (re >= -cut) {
       ++n_eval;
-      double im = -(pq * G.D[j]);
+      double im = SFHK_FMA(-pq, G.D[j], phi);
       double e = exp_cw_nonpos(re) * G.N[j];
       double s, c;
       sincos_integrand(im, &s, &c);
@@ -233,20 +236,15 @@ __device__ __noinline__ Contrib contribution(const GtoConst* Gv, double cut, dou
   const gto_cptr __restrict__ G = (gto_cptr)uniform_i64((long long)Gv);
   const double q[3] = {qx, qy, qz}, p[3] = {px, py, pz};
   unsigned int n_eval = 0;
-  const Elements el = overlap<gto_cref>(*G, cut, q, p, p2, q2, n_eval);
-  Contrib r = {0.0, 0.0, 0.0, 0.0, n_eval};
-  if (el.o.re != 0.0 || el.o.im != 0.0 || el.ov.re != 0.0 || el.ov.im != 0.0) {
-    const double ph = S - G->ip * tn;
-    double sp, cp;
-    sincos_integrand(ph, &sp, &cp);
-    const cplx f = cmul(cplx{wcr, wci}, cmul(el.o, cplx{cp, sp}));
-    r.re = f.re;
-    r.im = f.im;
-    if (G->vel) {
-      const cplx fv = cmul(cplx{wcr, wci}, cmul(el.ov, cplx{cp, sp}));
-      r.vre = fv.re;
-      r.vim = fv.im;
-    }
+  const double phi = S - G->ip * tn;
+  const Elements el = overlap<gto_cref>(*G, cut, q, p, p2, q2, phi, n_eval);
+  const cplx w = {wcr, wci};
+  const cplx f = cmul(w, el.o);
+  Contrib r = {f.re, f.im, 0.0, 0.0, n_eval};
+  if (G->vel) {
+    const cplx fv = cmul(w, el.ov);
+    r.vre = fv.re;
+    r.vim = fv.im;
   }
   return r;
 }
