@@ -181,10 +181,16 @@ size_t sfhk_job_footprint(int64_t n_traj, int64_t n_steps, int64_t n_out, int32_
  * M = I and S = 0. t0 must lie in [t_a, t_a + n_steps h]. Reads t0 synchronously (the host orders
  * trajectories by birth step); the other inputs are read on `stream` before the call returns its
  * status, after which the caller may free all inputs.
- * Errors: SFHK_E_INVALID (gamma <= 0, h <= 0, n_steps < 1, n_traj < 1, l not 0/1, n_prim not in
- * 1..SFHK_MAX_PRIM, precision unknown, n_out < 0, t0 outside the grid, NULL pointers),
- * SFHK_E_BUDGET, SFHK_E_NOMEM, SFHK_E_DEVICE. Non-finite samples are not errors: the trajectory
- * is removed at its birth step and counted in nonfinite_removed. */
+ * Errors: SFHK_E_INVALID (NULL pointers; gamma <= 0; kay_max not > 0 (+inf allowed: no
+ * removal); overlap_cut not >= 0 (+inf allowed: no skipping); r_fp64 not >= 0 in the mixed form;
+ * h <= 0; n_steps not in 1..2^30; n_traj not in 1..2^31; neither e_half nor a pulse; a pulse with
+ * a non-finite e0 or cep, or omega or n_cycles not > 0; e_half given with a pulse but more than
+ * 1e-9 e0 away from its field; unknown potential kind; r_scr <= 0 for the screened potential; l not
+ * 0/1; n_prim not in 1..SFHK_MAX_PRIM or an exponent <= 0; precision unknown; n_out < 0; velocity
+ * not 0/1; pw_mask outside [0, 0x1FF] or pw_radius not finite and > 0 with a mask; compact_every
+ * not 0 or in [16, 2^24], or given with the mixed form; t0 outside the grid), SFHK_E_BUDGET,
+ * SFHK_E_NOMEM, SFHK_E_DEVICE. NaN parameters fail these tests. Non-finite samples are not
+ * errors: the trajectory is removed at its birth step and counted in nonfinite_removed. */
 sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk_ground* ground,
                             const sfhk_grid* grid, const sfhk_params* params, int64_t n_traj,
                             const double* t0, const double* q0, const double* p0, const double* w,
@@ -323,7 +329,7 @@ const char* sfhk_status_string(sfhk_status s);
 
 /* The two elementary functions of the trajectory arithmetic, exported so their operation
  * sequences can be checked against an independent implementation (DEVICE pointers, y[i] = f(x[i])
- * for i < n, asynchronous on `stream`; SFHK_E_INVALID for NULL pointers or n < 0).
+ * for i < n, asynchronous on `stream`; SFHK_E_INVALID for NULL pointers or n outside [0, 2^31)).
  *
  * sfhk_traj_exp: exp as evaluated inside the screened potential. Cody-Waite reduction
  * x = k ln2 + r (ln2 split into a 32-significant-bit head and a rounded tail, both applied with

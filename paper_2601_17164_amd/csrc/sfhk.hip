@@ -374,6 +374,11 @@ sfhk_status sfhk_job_create(sfhk_ctx* ctx, const sfhk_potential* pot, const sfhk
   if (!ctx || !pot || !ground || !grid || !params || !t0 || !q0 || !p0 || !out)
     return fail(SFHK_E_INVALID, "NULL argument");
   if (!(params->gamma > 0.0)) return fail(SFHK_E_INVALID, "gamma must be > 0");
+  if (!(params->kay_max > 0.0)) return fail(SFHK_E_INVALID, "kay_max must be > 0 (+inf: no Kay removal)");
+  if (!(params->overlap_cut >= 0.0))
+    return fail(SFHK_E_INVALID, "overlap_cut must be >= 0 (+inf: no primitive skipped)");
+  if (params->precision == SFHK_FP32_MIXED && !(params->r_fp64 >= 0.0))
+    return fail(SFHK_E_INVALID, "r_fp64 must be >= 0");
   if (!(grid->h > 0.0)) return fail(SFHK_E_INVALID, "h must be > 0");
   if (grid->n_steps < 1 || grid->n_steps > (1LL << 30)) return fail(SFHK_E_INVALID, "n_steps out of range");
   if (!grid->e_half && !grid->pulse) return fail(SFHK_E_INVALID, "the grid needs e_half or a pulse");
@@ -1179,7 +1184,7 @@ sfhk_status sfhk_job_restore(sfhk_job* job, const void* src, void* stream) {
 }
 
 static sfhk_status traj_fn(int which, const double* x, double* y, int64_t n, void* stream) {
-  if (!x || !y || n < 0) return fail(SFHK_E_INVALID, "NULL pointer or negative count");
+  if (!x || !y || n < 0 || n > INT32_MAX) return fail(SFHK_E_INVALID, "NULL pointer or bad count");
   if (n == 0) return SFHK_OK;
   hipLaunchKernelGGL(k_traj_fn, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, which, x,
                      y, (long long)n);

@@ -424,6 +424,19 @@ def test_budget_and_invalid_arguments(S):
         sfhk.make_job(ctx, bad2)
     assert ei.value.status == sfhk.SFHK_E_INVALID
     assert sfhk.job_footprint(inst.n_traj, inst.grid.n_steps) > 43 * 8 * inst.n_traj
+    # method parameters outside their domain (NaN included) are refused, not run
+    before = ctx.bytes_in_use()
+    for field, value in (("kay_max", 0.0), ("kay_max", -1e30), ("kay_max", float("nan")),
+                         ("overlap_cut", -1.0), ("overlap_cut", float("nan"))):
+        bad = I.Instance(**{**inst.__dict__, field: value})
+        with pytest.raises(sfhk.SfhkError) as ei:
+            sfhk.make_job(ctx, bad)
+        assert ei.value.status == sfhk.SFHK_E_INVALID, (field, value)
+    for r in (-1.0, float("nan")):
+        with pytest.raises(sfhk.SfhkError) as ei:
+            sfhk.make_job(ctx, inst, precision=sfhk.SFHK_FP32_MIXED, r_fp64=r)
+        assert ei.value.status == sfhk.SFHK_E_INVALID, r
+    assert ctx.bytes_in_use() == before  # refusals leave no job behind
 
 
 def test_cancel_mid_job_releases_its_memory(S):
