@@ -318,6 +318,22 @@ def test_ragged_sizes_and_edge_births(S, n_traj):
     _assert_parity(f"ragged-{n_traj}", g, r)
 
 
+@pytest.mark.parametrize("n_steps", [1, 2, 3])
+def test_tiny_grids(S, n_steps):
+    """Grids of one to three steps around the pulse's centre (the library tabulates the field at
+    the 2 n_steps + 1 half steps from the pulse), 65 trajectories born at every step of the grid:
+    two tiles, the second with one lane, births at the last step evaluated once."""
+    from dataclasses import replace
+    base = I.config0()
+    grid = I.Grid(-0.05 * n_steps, 0.1, n_steps)
+    inst = replace(base.subset(np.arange(65)), grid=grid, e_half=None)
+    inst.t0 = grid.t_a + grid.h * (np.arange(65) % (n_steps + 1))
+    r = run_oracle(inst)
+    g = _gpu_run(S, inst)
+    assert len(g["d"]) == n_steps + 1
+    _assert_parity(f"grid-{n_steps}", g, r)
+
+
 def test_nonfinite_sample_is_removed_and_counted(S):
     inst = I.config0(n_birth=4, n_per_birth=16)
     q0 = inst.q0.copy()
