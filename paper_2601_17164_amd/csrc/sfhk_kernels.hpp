@@ -945,8 +945,11 @@ __device__ __forceinline__ void run_tile_mixed(const JobDev& J, const int tile, 
   }
 }
 
+// Three waves per SIMD (168 VGPRs): the FP32 step's dependency chains leave the VALU idle at two
+// waves, and the register allocation this forces moves 160-272 B per lane to scratch, mostly
+// around the rarely taken FP64 step (screened workload 366 -> 326 ms; four waves: 360 ms).
 #ifndef SFHK_MIXED_WAVES_PER_EU
-#define SFHK_MIXED_WAVES_PER_EU 2
+#define SFHK_MIXED_WAVES_PER_EU 3
 #endif
 template <int KIND>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SFHK_MIXED_WAVES_PER_EU)))
