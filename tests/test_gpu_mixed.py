@@ -95,6 +95,29 @@ def test_mixed_config1_subset_spectral_error(S):
     _check_against_oracle(S, "config1-subset", inst)
 
 
+def test_mixed_velocity_within_the_stated_bound(S):
+    """The dipole-velocity accumulation of the mixed form (App. C.2; same integrand path as the
+    dipole) against the FP64 oracle's V at D_t = 1e4 on config 0: the spectrum of -2 Re V within
+    the config-0 bound in both bands, as the dipole's."""
+    sfhk, ctx, torch = S
+    from tests.common import e_half, oracle_ground, oracle_potential
+    inst = I.config0()
+    inst.kay_max = KAY_MIXED
+    ref = O.propagate(oracle_potential(inst.potential), oracle_ground(inst.ground), e_half(inst),
+                      inst.grid.t_a, inst.grid.h, inst.grid.n_steps, inst.t0, inst.q0, inst.p0,
+                      inst.w, inst.gamma, inst.kay_max, inst.overlap_cut, 0, velocity=True)
+    job = sfhk.make_job(ctx, inst, precision=MIXED, velocity=True)
+    assert job.propagate(0)
+    v = job.velocity().cpu().numpy()
+    d = job.dipole().cpu().numpy()
+    job.close()
+    for name, got, want in (("velocity", v, -2.0 * ref.V.real), ("dipole", d, O.dipole(ref.F))):
+        rep = _spectral(inst, got, want)
+        print(f"[config0 mixed, D_t = 1e4] {name}: {rep}", flush=True)
+        for band, e in rep.items():
+            assert e["E_dB"] is not None and e["E_dB"] <= E_DB_MAX["config0"], (name, band, e)
+
+
 # At the soft-core workload's own Kay limit D_t = 1e30 neither precision is stable against
 # rounding: the FP64 spectrum moves by O(1) (E_dB > 0) when the samples move by one ulp. The
 # stated error of the mixed form there is relative to that floor: its E_dB against the FP64 oracle
