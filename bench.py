@@ -115,6 +115,16 @@ def _args():
     return ap.parse_args()
 
 
+def _device_info():
+    """The GPU the line was measured on (boxes of one model differ by a few % in sustained FP64
+    clock, so the figures are read together with this)."""
+    import torch
+    pr = torch.cuda.get_device_properties(0)
+    return {"name": pr.name, "arch": getattr(pr, "gcnArchName", None),
+            "compute_units": pr.multi_processor_count,
+            "memory_gib": round(pr.total_memory / 2 ** 30, 1)}
+
+
 def _ints(text):
     """comma-separated integers (empty: none)"""
     return [int(x) for x in text.split(",") if x.strip()]
@@ -711,6 +721,7 @@ def main():
                      "flop_per_launch": fl},
         "stats": {"kay_removed": s0.kay_removed, "nonfinite_removed": s0.nonfinite_removed,
                   "prims_per_step": s0.prims_evaluated / max(1, s0.steps_evaluated)},
+        "device": _device_info(),
     }
     if not a.no_mixed:
         out["fp32_mixed"] = mixed_form(step, stream, inst, arrays, spec, flops)
