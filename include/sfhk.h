@@ -123,7 +123,7 @@ typedef struct {
  *                only (sfhk_propagate_many and batches refuse them). The four-wave workgroups cost
  *                about 8% by themselves, so regrouping pays only when many trajectories are
  *                removed (measured on a soft-core hydrogen workload: 22% faster with 86% removed,
- *                16% slower with 28% removed). */
+ *                14-16% slower with 28% removed). */
 typedef struct {
   double gamma;
   double kay_max;
