@@ -95,6 +95,39 @@ def test_mixed_config1_subset_spectral_error(S):
     _check_against_oracle(S, "config1-subset", inst)
 
 
+# The mixed form's accuracy envelope on the paper's initial conditions (SFA births at the tunnel
+# exit, App. A; the oracle's births on both sides), as E_dB against the FP64 oracle at the same
+# Kay limit D_t: the FP32 state and monodromy resolve trajectories stretched by up to a few
+# hundred, which D_t <= 1e8 keeps; beyond ~1e10 the spectrum is carried by trajectories with
+# |det G| of 1e12-1e16 whose FP32 integration errors are amplified to O(1).
+SFA_ENVELOPE = [("config0", 1e4, -90.0), ("config0", 1e6, -35.0),
+                ("config1-subset", 1e4, -110.0), ("config1-subset", 1e6, -60.0),
+                ("config1-subset", 1e8, -40.0)]
+
+
+@pytest.mark.parametrize("name,kay,bound", SFA_ENVELOPE)
+def test_mixed_on_sfa_born_trajectories(S, name, kay, bound):
+    from tests.common import oracle_sfa_births
+    if name == "config0":
+        inst = I.sfa_config0()
+    else:
+        full = I.sfa_config1()
+        inst = full.subset(np.concatenate([b * 1024 + np.arange(32) for b in range(0, 1024, 32)]))
+    inst = oracle_sfa_births(inst)
+    inst.kay_max = kay
+    r = run_oracle(inst)
+    d_ref = O.dipole(r.F)
+    if inst.n_out:
+        d_ref = O.resample(d_ref, inst.n_out)
+    g = _run(S, inst)
+    rep = _spectral(inst, g["d"], d_ref)
+    print(f"[{name} SFA-born, D_t = {kay:.0e}] mixed vs FP64 oracle: "
+          f"{ {b: round(e['E_dB'], 1) for b, e in rep.items()} }; removed {r.kay_removed}"
+          f"/{inst.n_traj}", flush=True)
+    for band, e in rep.items():
+        assert e["E_dB"] is not None and e["E_dB"] <= bound, (band, e)
+
+
 def test_mixed_velocity_within_the_stated_bound(S):
     """The dipole-velocity accumulation of the mixed form (App. C.2; same integrand path as the
     dipole) against the FP64 oracle's V at D_t = 1e4 on config 0: the spectrum of -2 Re V within
