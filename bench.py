@@ -544,8 +544,10 @@ def sfa_results(ctx, stream, reps):
     tt = b["tt"].cpu().numpy()
     fl = flops.flops(inst.potential.kind, inst.ground.l, st.steps_evaluated, st.prims_evaluated,
                      st.integrands_evaluated)
+    envelope = mixed_envelope(ctx, inst, dev, stream)
     return {"workload": "screened-SAE 1600nm 1.5e14 W/cm2 8-cycle, 1024x1024 SFA births "
                         "(GTO tunnelling element), dt 0.05",
+            "mixed_vs_fp64_by_kay_limit": envelope,
             "n": inst.n_traj, "birth_kernel_ms": birth_ms, "births_per_s": inst.n_traj / birth_ms * 1e3,
             "no_saddle": no_saddle, **sfa_saddle_work(inst, tt),
             "propagate_kernel_ms": prop_ms,
@@ -553,6 +555,36 @@ def sfa_results(ctx, stream, reps):
             "trajectory_steps_per_s": st.steps_evaluated / prop_ms * 1e3,
             "propagate_fp64_frac": fl / (prop_ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
             "kay_removed": st.kay_removed, "prims_per_step": st.prims_evaluated / max(1, st.steps_evaluated)}
+
+
+def mixed_envelope(ctx, inst, dev, stream, limits=(1e6, 1e8, 1e30)):
+    """The FP32-mixed form against the FP64 kernel (which matches the FP64 oracle to 1e-9) on the
+    SFA-born trajectories at several Kay limits: E_dB over the plateau and cutoff bands of the
+    2^15-point spectrum, and the trajectories the Kay test removed. The FP32 state resolves
+    trajectories stretched by up to a few hundred, which limits of 1e6 to 1e8 keep."""
+    from dataclasses import replace
+    import torch
+    from paper_2601_17164_amd import metrics, sfhk
+    T = inst.grid.h * inst.grid.n_steps
+    dt_out = T / inst.n_out
+    out = {}
+    for kay in limits:
+        ik = replace(inst, kay_max=kay)
+        spec, removed = {}, 0
+        for prec in (0, 1):
+            job = sfhk.make_job(ctx, ik, dev, precision=prec)
+            assert job.propagate(0)
+            om, _, x = sfhk.spectrum(job.dipole(), inst.grid.t_a, dt_out, T / 2)
+            if prec == 0:
+                removed = job.stats(stream).kay_removed
+            job.close()
+            spec[prec] = (om.cpu().numpy(), x.cpu().numpy())
+        torch.cuda.synchronize()
+        rep = metrics.spectral_report(spec[0][0], spec[1][1], spec[0][1], inst.ground.ip,
+                                      inst.pulse.up, inst.pulse.omega)
+        out[f"{kay:.0e}"] = {"kay_removed": removed,
+                             **{band: round(e["E_dB"], 2) for band, e in rep.items()}}
+    return out
 
 
 def softcore_results(ctx, stream, regroup=(1024,), kay_max=None):

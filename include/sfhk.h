@@ -47,10 +47,11 @@ typedef enum { SFHK_POT_NONE = 0, SFHK_POT_SOFTCORE = 1, SFHK_POT_SCREENED = 2, 
 /* SFHK_FP64: every step in FP64 under the rounding contract. SFHK_FP32_MIXED: position, momentum
  * and monodromy integrated in FP32 away from the nucleus (steps that start at r < r_fp64 in FP64),
  * the action, the HK square root and branch, the dipole integrand and the per-step sums in FP64.
- * The FP32 state resolves trajectories stretched by up to a few hundred: with the Kay limit at
- * kay_max <= 1e8 its spectra stay within about -40 dB of the FP64 ones on the screened-potential
- * workload (measured on SFA-born samples); with larger limits the contributions of strongly
- * stretched trajectories, which FP32 cannot integrate, make the difference O(1). */
+ * The FP32 state resolves trajectories stretched by up to a few hundred: on the screened-potential
+ * workload with SFA-born samples its spectra stay within -40 dB of the FP64 ones in the plateau
+ * and cutoff bands up to kay_max = 1e6 (at 1e8: -43 dB plateau, -16 dB cutoff); with larger
+ * limits the contributions of strongly stretched trajectories, which FP32 cannot integrate, make
+ * the difference O(1). */
 typedef enum { SFHK_FP64 = 0, SFHK_FP32_MIXED = 1 } sfhk_precision;
 
 typedef struct {
