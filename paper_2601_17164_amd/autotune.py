@@ -21,7 +21,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "autotune_cache.json")
 
-WORKERS = (0, 4, 8, 16)          # 0 = hardware dispatch
+# resident workgroups per compute unit (0 = hardware dispatch); 8 and 12 fill the wave slots of
+# the FP64 (two waves per SIMD) and the FP32-mixed (three) kernels
+WORKERS = (0, 4, 8, 12, 16)
 CHUNKS = (0, 256, 1024, 4096)    # steps per replay; 0 = to the end in one replay
 # on a small trial a persistent form must beat the best hardware-dispatch form by this factor:
 # near-ties there have not carried over to full-size batches (stage 2 compares with no margin)
