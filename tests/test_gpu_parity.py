@@ -206,6 +206,36 @@ def test_against_the_correctly_rounded_oracle(S, case):
     assert e <= TOL
 
 
+def test_sfa_born_config1_at_its_own_kay_limit_against_the_correctly_rounded_oracle(S):
+    """The paper's initial conditions (SFA births at the tunnel exit, App. A; the oracle's births)
+    for config 1, 32 birth groups x 32 samples, at the workload's own Kay limit D_t = 1e30: this
+    input set is well conditioned (moving every q0 by one ulp moves its spectrum by -135 dB), so
+    any FP64 evaluation of the method should agree closely. The device path (bit for bit the
+    contract oracle) against the build with once-rounded square roots, quotients, exponentials,
+    sines and cosines: F within 1e-5 relative L2 (measured 8.6e-7, the rounding differences of
+    some 10^9 operations per trajectory amplified by the stretched trajectories that carry the
+    dipole), and the 2^15-point spectrum within -100 dB in the plateau and cutoff bands."""
+    from tests.common import oracle_sfa_births
+    from paper_2601_17164_amd import metrics
+    full = I.sfa_config1()
+    inst = oracle_sfa_births(full.subset(np.concatenate(
+        [b * 1024 + np.arange(32) for b in range(0, 1024, 32)])))
+    assert inst.kay_max == 1e30
+    r = O.propagate(*_oracle_args(inst), correctly_rounded=True)
+    g = _gpu_run(S, inst)
+    e = rel_l2(g["F"], r.F)
+    T = inst.grid.h * inst.grid.n_steps
+    dt = T / inst.n_out
+    om, _, x_r = O.spectrum(O.resample(O.dipole(r.F), inst.n_out), inst.grid.t_a, dt, T / 2)
+    _, _, x_g = O.spectrum(g["d"], inst.grid.t_a, dt, T / 2)
+    rep = metrics.spectral_report(om, x_g, x_r, inst.ground.ip, inst.pulse.up, inst.pulse.omega)
+    print(f"SFA-born config 1 at D_t = 1e30 vs the correctly rounded oracle: rel-L2(F) {e:.2e}, "
+          f"{ {b: round(v['E_dB'], 1) for b, v in rep.items()} }", flush=True)
+    assert e <= 1e-5
+    for band, v in rep.items():
+        assert v["E_dB"] <= -100.0, (band, v)
+
+
 def _oracle_args(inst):
     from tests.common import oracle_ground, oracle_potential
     return (oracle_potential(inst.potential), oracle_ground(inst.ground), e_half(inst),
