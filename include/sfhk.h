@@ -244,7 +244,9 @@ sfhk_status sfhk_batch_create(sfhk_ctx* ctx, int32_t max_jobs, int64_t max_tiles
  * the replay issued after the previous use of that set has completed, so a caller can stage the
  * next replay while the current one runs (the host stays at most one replay ahead). */
 sfhk_status sfhk_batch_set_jobs(sfhk_batch* batch, sfhk_job* const* jobs, int32_t n_jobs, void* stream);
-/* One graph replay on `stream`. SFHK_OK when every staged job has finished, else SFHK_E_NOT_DONE. */
+/* One graph replay on `stream`. SFHK_OK when every staged job has finished (at once for an empty
+ * table), else SFHK_E_NOT_DONE; SFHK_E_INVALID, with nothing launched, when no table is staged
+ * (sfhk_batch_set_jobs not called yet, or its last call failed). */
 sfhk_status sfhk_batch_run(sfhk_batch* batch, void* stream);
 /* Resident workgroups of the persistent form (0 for hardware dispatch). */
 int32_t sfhk_batch_workers(const sfhk_batch* batch);

@@ -940,8 +940,11 @@ sfhk_status sfhk_batch_set_jobs(sfhk_batch* b, sfhk_job* const* jobs, int32_t n_
 sfhk_status sfhk_batch_run(sfhk_batch* b, void* stream) {
   TraceRange trace_("sfhk_batch_run");
   if (!b) return fail(SFHK_E_INVALID, "batch is NULL");
+  if (!b->staged)
+    return fail(SFHK_E_INVALID, "no job table is staged (sfhk_batch_set_jobs has not been called, "
+                                "or its last call failed)");
+  if (b->jobs.empty()) return SFHK_OK;
   HIP_TRY(hipSetDevice(b->ctx->device));
-  if (!b->staged || b->jobs.empty()) return SFHK_OK;
   HIP_TRY(hipGraphLaunch(b->exec, (hipStream_t)stream));
   for (sfhk_job* j : b->jobs) HIP_TRY(hipEventRecord(j->last_use, (hipStream_t)stream));
   // the latest staging set is refilled only after this replay: at most one replay ahead

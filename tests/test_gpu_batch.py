@@ -151,3 +151,16 @@ def test_all_potential_kinds_in_one_batch_and_one_call(S, precision):
     for job, ref in zip(jobs, alone):
         np.testing.assert_array_equal(job.dipole().cpu().numpy(), ref)
         job.close()
+
+
+def test_a_replay_needs_a_staged_table(S):
+    """Before any sfhk_batch_set_jobs (or after a failed one) a replay is refused rather than
+    reported finished; an empty table is finished at once."""
+    sfhk, ctx, torch = S
+    b = sfhk.Batch(ctx, 2, 16, 0, 0)
+    with pytest.raises(sfhk.SfhkError) as ei:
+        b.run()
+    assert ei.value.status == sfhk.SFHK_E_INVALID
+    b.set_jobs([])
+    assert b.run()
+    b.close()
