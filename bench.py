@@ -591,9 +591,10 @@ def softcore_results(ctx, stream, regroup=(1024,), kay_max=None):
     """The propagate kernel on the soft-core atom at full size (inputs.softcore_full): per form
     (plain, and regrouped every E steps for E in `regroup`) one untimed launch, then one timed with
     HIP events on the launch stream. The soft-core instances are half of the batch and serving
-    mix; their kernel is held back by the s-wave dipole element, needed at most steps near the
-    nucleus, and by lanes idle after the Kay test (28% of the trajectories are removed), which
-    regrouping (sfhk_params.compact_every) gives back."""
+    mix; on these Gaussian samples, placed inside the potential, their kernel is held back by the
+    s-wave dipole element, needed at most steps near the nucleus, and by lanes idle after the Kay
+    test (28% of the trajectories are removed), which regrouping (sfhk_params.compact_every) gives
+    back. `sfa_born`: the same atom, pulse and sizes with SFA births at the tunnel exit."""
     import torch
     from paper_2601_17164_amd import flops, inputs as I, sfhk
     inst = I.softcore_full()
@@ -602,7 +603,7 @@ def softcore_results(ctx, stream, regroup=(1024,), kay_max=None):
         inst = replace(inst, kay_max=kay_max)
     arrays = sfhk.to_device(inst, "cuda:0")
 
-    def timed(every):
+    def timed(every, inst=inst, arrays=arrays):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         for it in range(2):
             job = sfhk.make_job(ctx, inst, arrays, compact_every=every)
@@ -636,6 +637,19 @@ def softcore_results(ctx, stream, regroup=(1024,), kay_max=None):
         out["form"] = "plain"
     out["plain"] = plain
     out.update(forms)
+    # the same atom, pulse and sizes with the paper's initial conditions: SFA births at the tunnel
+    # exit (sfhk_sfa_birth on the device) instead of Gaussian samples placed inside the potential
+    sfa = I.softcore_sfa_full()
+    if kay_max is not None:
+        from dataclasses import replace
+        sfa = replace(sfa, kay_max=kay_max)
+    dev = sfhk.to_device(sfa, "cuda:0")
+    b = sfhk.sfa_birth(sfa.pulse, sfa.ground, dev["t0"], torch.from_numpy(sfa.meta["kperp"]).cuda(),
+                       torch.from_numpy(sfa.meta["u"]).cuda(), sfhk.SFHK_BIRTH_GTO, stream)
+    dev.update(q0=b["q0"], p0=b["p0"], w=b["w"])
+    out["sfa_born"] = {"workload": "soft-core H 1600nm 1.5e14 W/cm2 8-cycle, "
+                                   f"{sfa.n_birth}x{sfa.n_per_birth} SFA births, dt 0.1, FP64",
+                       **timed(0, sfa, dev)}
     return out
 
 

@@ -293,6 +293,12 @@ def sfa_config0(n_birth=64, n_per_birth=32, seed=10, mode=0) -> Instance:
                         Pulse(800.0, 1e14, 2.0), 0.1, n_birth, n_per_birth, seed, mode)
 
 
+def softcore_sfa_full(n_birth=512, n_per_birth=1024, seed=12, mode=0) -> Instance:
+    """The soft-core probe's atom, pulse and sizes (softcore_full) born by the SFA step."""
+    return sfa_instance("softcore-H 1600nm 1.5e14 8cyc sfa", SOFTCORE_H, gto_h1s(),
+                        Pulse(1600.0, 1.5e14, 8.0), 0.1, n_birth, n_per_birth, seed, mode)
+
+
 def sfa_config1(n_birth=1024, n_per_birth=1024, seed=11, mode=0, n_out=1 << 15) -> Instance:
     """Config 1 (screened SAE, 1600 nm, 1.5e14 W/cm^2, 8 cycles, dt 0.05) born by the SFA step."""
     return sfa_instance("screened-SAE 1600nm 1.5e14 8cyc sfa", SCREENED_SAE, gto_p058(),
