@@ -243,6 +243,42 @@ def test_sfa_born_config1_birth_groups(S):
     assert e <= 1e-9
 
 
+def test_sfa_born_softcore_full_size_sampled_trajectories(S):
+    """The soft-core atom at full size (2^19 trajectories, 17652 steps) born by the device's SFA
+    step and propagated as the benchmark's soft-core leg does (Kay limit 1e30): sampled final
+    states, removed trajectories among them, bit for bit against the oracle's births propagated by
+    the oracle, and the step counter against the removal steps of every trajectory."""
+    sfhk, torch = S
+    full = I.softcore_sfa_full()
+    print(f"SFA-born soft-core, {full.n_traj} trajectories x {full.grid.n_steps} steps",
+          flush=True)
+    dev = sfhk.to_device(full)
+    b = sfhk.sfa_birth(full.pulse, full.ground, dev["t0"], _dev(torch, full.meta["kperp"]),
+                       _dev(torch, full.meta["u"]), 0)
+    dev.update(q0=b["q0"], p0=b["p0"], w=b["w"])
+    ctx = sfhk.Context(0)
+    job = sfhk.make_job(ctx, full, dev_arrays=dev)
+    assert job.propagate(0)
+    st = job.stats()
+    y, _, death = job.trajectories()
+    torch.cuda.synchronize()
+    y, death = y.cpu().numpy(), death.cpu().numpy()
+    job.close()
+    ctx.close()
+    died = death >= 0
+    assert 0 < died.sum() < 0.01 * full.n_traj  # SFA births: about 0.15% removed
+    rng = np.random.default_rng(23)
+    idx = np.sort(np.concatenate([rng.choice(np.flatnonzero(died), 6, replace=False),
+                                  rng.choice(np.flatnonzero(~died), 18, replace=False)]))
+    ref = run_oracle(oracle_sfa_births(full.subset(idx)))
+    np.testing.assert_array_equal(death[idx], ref.death)
+    np.testing.assert_array_equal(y[:, idx], ref.y_final)
+    n0 = np.clip(np.ceil((full.t0 - full.grid.t_a) / full.grid.h - 0.5), 0, full.grid.n_steps)
+    expect = np.where(died, death - n0 + 1, full.grid.n_steps - n0 + 1).sum()
+    assert st.steps_evaluated == expect
+    assert st.kay_removed + st.nonfinite_removed == died.sum()
+
+
 def test_sfa_born_config1_full_size_against_the_correctly_rounded_oracle(S):
     """All 2^20 SFA-born trajectories of config 1 born and propagated on the device at the
     workload's Kay limit D_t = 1e30, then 256 seeded samples of them against the oracle's build
