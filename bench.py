@@ -66,7 +66,7 @@ def _args():
                     help="skip the FP32-mixed pass over the same inputs")
     ap.add_argument("--cpu-births", type=int, default=64,
                     help="birth groups (spread over the pulse) in the oracle's sample")
-    ap.add_argument("--cpu-per-birth", type=int, default=256)
+    ap.add_argument("--cpu-per-birth", type=int, default=384)
     ap.add_argument("--batch", action="store_true",
                     help="instead: the 64-instance uneven batch in one graph-captured launch per "
                          "precision (FP64 and FP32-mixed), autotuned launch form")
